@@ -1,0 +1,171 @@
+/*
+ * mithra.h -- C ABI of the MI355X boosted-frame FEL particle-in-cell step.
+ *
+ * The operation is the time step of the MITHRA 2.0 manual (arXiv
+ * 2009.13645), ch. 3 "Methodology", in the bunch rest frame:
+ *   - NSFD finite-difference update of the vector potential A and the
+ *     scalar potential phi (sec. "FDTD for Wave Equation", eqs. NSFDtrick,
+ *     NSFDCoefficient, updateEquation; sec. "FDTD for Scalar Potential");
+ *   - Mur absorbing boundaries of first or second order (sec. "Boundary
+ *     Truncation");
+ *   - E and B at the vertices and trilinear gather (sec. "Field
+ *     Evaluation", eq. fieldInterpolation);
+ *   - Boris push in the total field, the static undulator field being
+ *     evaluated in the lab frame and Lorentz-boosted (sec. "Update
+ *     Algorithm", eq. BorisScheme; sec. "Static Undulator Field", eqs.
+ *     undulatorField, fringingField, LorentzTransformR2L,
+ *     LorentzTransformElectric, LorentzTransformMagnetic);
+ *   - charge-conserving zigzag current deposition and cloud-in-cell charge
+ *     (sec. "Current Deposition").
+ *
+ * Memory: the caller owns all device memory.  `mithra_footprint_bytes`
+ * gives the exact arena size; `mithra_init_grid` borrows an arena of at
+ * least that size (any device allocation aligned to 256 bytes, e.g. a
+ * torch uint8 tensor) for the handle's lifetime, and enqueues all work on
+ * the caller's HIP stream.  Host arrays passed in are copied; host arrays
+ * passed out are written synchronously.
+ *
+ * Errors: every call returns MITHRA_OK (0) or a negative code; the
+ * handle keeps a message readable with `mithra_last_error`.  One thread
+ * per handle; handles are independent.
+ *
+ * Units: SI.  The mesh is given in the boosted frame: node (i,j,k) sits at
+ * (x0 + i dx, y0 + j dy, z0 + k dz); arrays are [nz][ny][nx], x fastest.
+ */
+#ifndef MITHRA_H_
+#define MITHRA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MITHRA_OK 0
+#define MITHRA_EINVAL (-1)   /* descriptor or argument out of range */
+#define MITHRA_ENOMEM (-2)   /* arena smaller than the footprint */
+#define MITHRA_EDEVICE (-3)  /* a HIP call failed */
+#define MITHRA_ESTATE (-4)   /* call not allowed in the handle's state */
+#define MITHRA_ENUMERIC (-5) /* non-finite value detected in the run */
+
+/* Field ids of the manual's field sampling (sec. "FIELD", field list):
+ * Ex Ey Ez Bx By Bz Ax Ay Az Jx Jy Jz F(phi) Q(rho). */
+enum mithra_field_id {
+    MITHRA_FIELD_EX = 0, MITHRA_FIELD_EY, MITHRA_FIELD_EZ,
+    MITHRA_FIELD_BX, MITHRA_FIELD_BY, MITHRA_FIELD_BZ,
+    MITHRA_FIELD_AX, MITHRA_FIELD_AY, MITHRA_FIELD_AZ,
+    MITHRA_FIELD_JX, MITHRA_FIELD_JY, MITHRA_FIELD_JZ,
+    MITHRA_FIELD_PHI, MITHRA_FIELD_RHO
+};
+
+enum mithra_dtype { MITHRA_DTYPE_F32 = 0, MITHRA_DTYPE_F64 = 1 };
+
+/* Run descriptor.  Parameter names follow the manual's MESH group
+ * (mesh resolution, truncation order, space charge, solver, bunch time
+ * step) and UNDULATOR group (undulator parameter, period, length,
+ * polarization angle), with the mesh already in the boosted frame. */
+typedef struct mithra_grid_desc {
+    int32_t nx, ny, nz;          /* nodes per axis, >= 6 each */
+    int32_t truncation_order;    /* Mur order: 1 or 2 */
+    int32_t space_charge;        /* 1: solve for phi; 0: phi = 0 */
+    int32_t solver;              /* 0: NSFD (only NSFD is built) */
+    int32_t n_sub;               /* bunch sub-steps per field step, dt_b = dt / n_sub, >= 1 */
+    int32_t field_precision;     /* 32 or 64: storage of potentials, sources, E, B */
+    int32_t compensated;         /* 1 (with 32): two-sum compensated current/charge sums */
+    int32_t und_type;            /* 0 planar, 1 helical */
+    int32_t n_periods;           /* undulator length in periods, >= 1 */
+    int32_t k_plane;             /* node plane of the radiated-power diagnostic, 1..nz-2 */
+    int32_t tile[3];             /* sort tile, cells per axis, each 1..64 */
+    int32_t record_power;        /* 1: radiated power through k_plane every step */
+    int64_t max_particles;       /* capacity reserved in the arena */
+    double dx, dy, dz;           /* boosted-frame spacings (m); NSFD needs (dz/dx)^2+(dz/dy)^2 < 1 */
+    double x0, y0, z0;           /* position of node (0,0,0) (m) */
+    double gamma;                /* beam Lorentz factor in the lab, > 1 */
+    double K;                    /* undulator parameter, > 0 */
+    double lambda_u;             /* undulator period, lab frame (m) */
+    double pol_angle_deg;        /* planar field direction: 0 = along y */
+    double z_entrance;           /* boosted-frame z of the undulator entrance at t = 0 (m) */
+} mithra_grid_desc;
+
+typedef struct mithra_engine *mithra_handle;
+
+/* Exact device bytes of the run's arena: potentials (3 time levels),
+ * sources (2 sets, plus compensation terms), vertex fields, particle
+ * state (2 buffers), sort scratch and diagnostics.  Returns 0 for an
+ * invalid descriptor.  Pure function; no device call. */
+size_t mithra_footprint_bytes(const mithra_grid_desc *d, int64_t n_particles);
+
+/* Validate `d`, derive the boost (gamma0 from the undulator, dt = dz/c,
+ * dt_b = dt/n_sub) and the NSFD and Mur coefficients, carve `dev_arena`
+ * and zero the fields.  `hip_stream` is a hipStream_t (NULL = default
+ * stream).  On success *out is a new handle.  Errors: EINVAL (bad
+ * descriptor: sizes, NSFD condition, precision, tiles, key range),
+ * ENOMEM (arena_bytes < footprint or misaligned), EDEVICE. */
+int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size_t arena_bytes,
+                     void *hip_stream, mithra_handle *out);
+
+/* Load n macro-electrons (ids 0..n-1 in input order).  Host arrays n x 3
+ * row-major, copied: xyz = boosted-frame positions at t = dt/2 (m),
+ * u = gamma*beta at t = 0.  q_macro = charge per macro-particle (C,
+ * negative for electrons).  Deposits the first current from the backward
+ * drift r - c dt u/gamma -> r and the charge at r, and sorts.  Errors:
+ * EINVAL (n <= 0, n > max_particles, non-finite input), ESTATE (after a
+ * step), EDEVICE. */
+int mithra_load_bunch(mithra_handle h, int64_t n, const double *xyz, const double *u,
+                      double q_macro);
+
+/* Enqueue n_steps PIC steps on the stream and return without waiting.
+ * A non-finite value seen by the diagnostics is reported as ENUMERIC by
+ * the next read.  Errors: ESTATE (no bunch loaded), EDEVICE. */
+int mithra_step(mithra_handle h, int64_t n_steps);
+
+/* Copy one field to host memory after synchronising the stream.  After n
+ * completed steps: A and J at t_n, phi and rho at t_{n+1/2}, E and B at
+ * t_{n-1/2} (the fields of the last push; evaluated at all nodes whose
+ * neighbours are inside the box, zero on the boundary).  J_l(i,j,k) is
+ * the edge current between nodes (i,j,k) and (i,j,k)+e_l.  Layout
+ * [nz][ny][nx]; dtype converts on request; bytes must equal
+ * nx*ny*nz*sizeof(dtype).  Errors: EINVAL, ENUMERIC, EDEVICE. */
+int mithra_read_fields(mithra_handle h, int field_id, int dtype, void *host_out, size_t bytes);
+
+/* Copy the particles in id order after synchronising the stream:
+ * xyz (n x 3, m) at t_{n+1/2}, u (n x 3) at t_n.  Optional (nullable):
+ * cell[id] = linear node index of the cell corner (-1 outside the active
+ * region 1 <= cell <= n-3 on every axis) and sort_perm[rank] = id of the
+ * current sort order (ascending tile-major key, ties by id).  Any pointer
+ * may be NULL.  Errors: ESTATE, ENUMERIC, EDEVICE. */
+int mithra_read_particles(mithra_handle h, double *xyz, double *u, int32_t *cell,
+                          int32_t *sort_perm);
+
+/* Lab-frame radiated power (W) through node plane k_plane at the latest
+ * step: the boosted-frame E and B of the last push are transformed to
+ * the lab and the Poynting flux is summed over the plane's interior
+ * nodes (the manual's radiation-power output; its formula is not
+ * printed).  Synchronises.  Errors: EINVAL (plane), ESTATE, EDEVICE. */
+int mithra_radiated_power(mithra_handle h, int32_t k_plane, double *p_lab_W);
+
+/* Per-step history of the power through the descriptor's k_plane
+ * (record_power = 1): copies min(n, steps done) values, oldest first,
+ * and returns the count (or a negative code). */
+int64_t mithra_power_history(mithra_handle h, double *out, int64_t n);
+
+/* |<exp(i k_r z)>| over particles in active cells, k_r = 2 pi gamma0
+ * beta0 / lambda_u (resonant boosted wavenumber).  Synchronises. */
+int mithra_bunching(mithra_handle h, double *b);
+
+/* Derived constants: out[0..7] = gamma0, beta0, dt, dt_b, NSFD A,
+ * q_macro, steps done, particles. */
+int mithra_constants(mithra_handle h, double *out8);
+
+/* Message of the last error on this handle (never NULL). */
+const char *mithra_last_error(mithra_handle h);
+
+/* Release the host-side state.  The arena stays the caller's. */
+int mithra_destroy(mithra_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MITHRA_H_ */

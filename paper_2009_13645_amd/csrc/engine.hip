@@ -1,0 +1,720 @@
+// engine.hip -- host engine and C ABI (include/mithra.h) of the MI355X
+// boosted-frame PIC step.  It validates the run descriptor, derives the
+// boost and the NSFD/Mur coefficients, carves the caller's device arena,
+// and enqueues the step pipeline on the caller's stream:
+//
+//   sweep (A, phi; clears the stale source set) -> Mur -> vertex E,B on the
+//   active-particle box -> bookkeeping -> gather/push/deposit -> bin+sort ->
+//   radiated power -> bookkeeping (step counter, particle buffer).
+//
+// Every kernel reads the step number from device memory, so one step is
+// captured once into a HIP graph and replayed for the following steps.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mithra.h"
+#include "mithra_dev.hpp"
+
+namespace mithra {
+hipError_t launch_sweep(const RunDev &R, int shape, hipStream_t st);
+int sweep_shape_count();
+void sweep_shape_dims(int shape, int *tx, int *ty, int *tz);
+hipError_t launch_mur(const RunDev &R, hipStream_t st);
+hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStream_t st);
+hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st);
+hipError_t launch_push_deposit(const RunDev &R, hipStream_t st);
+hipError_t launch_load_deposit(const RunDev &R, hipStream_t st);
+hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st);
+hipError_t launch_sort(const RunDev &R, hipStream_t st);
+int sort_passes(uint32_t key_inactive);
+int64_t sort_blocks(int64_t n);
+
+// --- bookkeeping kernels (single thread) -----------------------------------
+
+// after the vertex fields of step s: empty the deposit box of set (s+1)&1
+// (its stale entries were cleared by the sweep) and the active-cell box
+__global__ void k_book_mid(Ctl *ctl)
+{
+    const int set = (int)((ctl->step + 1) & 1);
+    for (int a = 0; a < 3; ++a) {
+        ctl->dep_lo[set][a] = 0x7fffffff;
+        ctl->dep_hi[set][a] = -1;
+        ctl->cell_lo[a] = 0x7fffffff;
+        ctl->cell_hi[a] = -1;
+    }
+    ctl->n_active = 0;
+}
+
+__global__ void k_book_end(Ctl *ctl, int advance)
+{
+    ctl->pbuf ^= 1;
+    ctl->nsort += 1;
+    if (advance)
+        ctl->step += 1;
+}
+
+__global__ void k_book_load(Ctl *ctl)
+{
+    for (int a = 0; a < 3; ++a) {
+        ctl->cell_lo[a] = 0x7fffffff;
+        ctl->cell_hi[a] = -1;
+    }
+    ctl->n_active = 0;
+}
+
+}  // namespace mithra
+
+using namespace mithra;
+
+static const int64_t kPowerCap = 1 << 16;
+static const int kBunchBlocks = 256;
+
+struct Layout {
+    size_t ctl, pot, src, src_lo, eb, pr, pid, key_by_id, slot_of_id, cell_by_id, key_sorted, sk, sv, hist, power,
+        scratch, total;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static Layout make_layout(const mithra_grid_desc *d, int64_t cap)
+{
+    Layout L{};
+    const size_t nn = (size_t)d->nx * d->ny * d->nz;
+    const size_t pf = d->field_precision == 32 ? 4 : 8;
+    const size_t c = (size_t)(cap > 0 ? cap : 1);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.ctl = take(sizeof(Ctl));
+    L.pot = take(12 * nn * pf);
+    L.src = take(8 * nn * pf);
+    L.src_lo = (d->compensated && d->field_precision == 32) ? take(8 * nn * pf) : (size_t)-1;
+    L.eb = take(6 * nn * pf);
+    L.pr = take(12 * c * 8);
+    L.pid = take(2 * c * 4);
+    L.key_by_id = take(c * 4);
+    L.slot_of_id = take(c * 4);
+    L.cell_by_id = take(c * 4);
+    L.key_sorted = take(c * 4);
+    L.sk = take(2 * c * 4);
+    L.sv = take(2 * c * 4);
+    L.hist = take(256 * (size_t)sort_blocks((int64_t)c) * 4);
+    L.power = take((size_t)kPowerCap * 8);
+    L.scratch = take((size_t)(3 * kBunchBlocks + 8) * 8);
+    L.total = off;
+    return L;
+}
+
+struct mithra_engine {
+    mithra_grid_desc d;
+    RunDev R;
+    Layout L;
+    char *arena = nullptr;
+    hipStream_t stream = nullptr;
+    int64_t steps = 0;
+    bool loaded = false;
+    int sweep_shape = 0;
+    int32_t *cell_by_id = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int use_graph = 1;
+    std::string err;
+};
+
+static int fail(mithra_handle h, int code, const char *fmt, ...)
+{
+    if (h) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        h->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(h, call)                                                                         \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(h, MITHRA_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+static double gamma0_of(const mithra_grid_desc *d)
+{
+    return d->und_type == 1 ? d->gamma / std::sqrt(1.0 + d->K * d->K) : d->gamma / std::sqrt(1.0 + 0.5 * d->K * d->K);
+}
+
+static const char *validate(const mithra_grid_desc *d)
+{
+    if (!d)
+        return "null descriptor";
+    if (d->nx < 6 || d->ny < 6 || d->nz < 6)
+        return "each of nx, ny, nz must be >= 6";
+    if ((double)d->nx * d->ny * d->nz > 4.0e9)
+        return "grid too large";
+    if (d->truncation_order != 1 && d->truncation_order != 2)
+        return "truncation_order must be 1 or 2";
+    if (d->space_charge != 0 && d->space_charge != 1)
+        return "space_charge must be 0 or 1";
+    if (d->solver != 0)
+        return "only the NSFD solver (0) is built";
+    if (d->n_sub < 1 || d->n_sub > 1024)
+        return "n_sub must be in 1..1024";
+    if (d->field_precision != 32 && d->field_precision != 64)
+        return "field_precision must be 32 or 64";
+    if (d->compensated != 0 && d->compensated != 1)
+        return "compensated must be 0 or 1";
+    if (d->compensated && d->field_precision != 32)
+        return "compensated accumulation applies to field_precision 32 only";
+    if (d->und_type != 0 && d->und_type != 1)
+        return "und_type must be 0 (planar) or 1 (helical)";
+    if (d->n_periods < 1)
+        return "n_periods must be >= 1";
+    if (d->k_plane < 1 || d->k_plane > d->nz - 2)
+        return "k_plane must be in 1..nz-2";
+    for (int a = 0; a < 3; ++a)
+        if (d->tile[a] < 1 || d->tile[a] > 64)
+            return "tile dims must be in 1..64";
+    if (d->max_particles < 0 || d->max_particles > 0x7fffffffLL)
+        return "max_particles out of range";
+    const double v[] = {d->dx, d->dy, d->dz, d->x0, d->y0, d->z0, d->gamma, d->K, d->lambda_u, d->pol_angle_deg,
+                        d->z_entrance};
+    for (double x : v)
+        if (!std::isfinite(x))
+            return "non-finite descriptor value";
+    if (!(d->dx > 0 && d->dy > 0 && d->dz > 0))
+        return "mesh spacings must be positive";
+    const double q = (d->dz / d->dx) * (d->dz / d->dx) + (d->dz / d->dy) * (d->dz / d->dy);
+    if (!(q < 1.0))
+        return "NSFD stability needs (dz/dx)^2 + (dz/dy)^2 < 1";
+    if (!(d->gamma > 1.0 && d->K > 0.0 && d->lambda_u > 0.0))
+        return "gamma > 1, K > 0 and lambda_u > 0 are required";
+    if (!(gamma0_of(d) > 1.0))
+        return "frame Lorentz factor gamma0 must exceed 1";
+    if (d->record_power != 0 && d->record_power != 1)
+        return "record_power must be 0 or 1";
+    // key range: one past the largest tile-major key must fit in 32 bits
+    double tiles = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        const int cells = (a == 0 ? d->nx : (a == 1 ? d->ny : d->nz)) - 1;
+        tiles *= (double)((cells + d->tile[a] - 1) / d->tile[a]);
+    }
+    if (tiles * d->tile[0] * d->tile[1] * d->tile[2] >= 4294967295.0)
+        return "tile-major key range exceeds 32 bits";
+    return nullptr;
+}
+
+extern "C" size_t mithra_footprint_bytes(const mithra_grid_desc *d, int64_t n_particles)
+{
+    if (validate(d) || n_particles < 0)
+        return 0;
+    int64_t cap = n_particles > d->max_particles ? n_particles : d->max_particles;
+    return make_layout(d, cap).total;
+}
+
+extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size_t arena_bytes, void *hip_stream,
+                                mithra_handle *out)
+{
+    if (!out)
+        return MITHRA_EINVAL;
+    *out = nullptr;
+    static thread_local std::string init_err;
+    const char *why = validate(d);
+    mithra_handle h = new mithra_engine();
+    if (why) {
+        fail(h, MITHRA_EINVAL, "%s", why);
+        *out = h;  // the handle carries the message; destroy frees it
+        return MITHRA_EINVAL;
+    }
+    h->d = *d;
+    h->L = make_layout(d, d->max_particles);
+    if (!dev_arena || arena_bytes < h->L.total || ((uintptr_t)dev_arena & 255)) {
+        fail(h, MITHRA_ENOMEM, "arena of %zu bytes at %p; need %zu bytes aligned to 256", arena_bytes, dev_arena,
+             h->L.total);
+        *out = h;
+        return MITHRA_ENOMEM;
+    }
+    h->arena = (char *)dev_arena;
+    h->stream = (hipStream_t)hip_stream;
+    const char *env = getenv("MITHRA_NO_GRAPH");
+    h->use_graph = (env && env[0] == '1') ? 0 : 1;
+
+    RunDev &R = h->R;
+    memset(&R, 0, sizeof R);
+    R.nx = d->nx;
+    R.ny = d->ny;
+    R.nz = d->nz;
+    R.nn = (int64_t)d->nx * d->ny * d->nz;
+    R.dx = d->dx;
+    R.dy = d->dy;
+    R.dz = d->dz;
+    R.x0 = d->x0;
+    R.y0 = d->y0;
+    R.z0 = d->z0;
+    R.inv_dx = 1.0 / d->dx;
+    R.inv_dy = 1.0 / d->dy;
+    R.inv_dz = 1.0 / d->dz;
+    // Lorentz boost of mesh and time: dt = dz / c, dt_b = dt / N
+    R.dt = d->dz / kC;
+    R.dtb = R.dt / (double)d->n_sub;
+    R.n_sub = d->n_sub;
+    R.gamma0 = gamma0_of(d);
+    R.beta0 = std::sqrt(1.0 - 1.0 / (R.gamma0 * R.gamma0));
+    R.ku = 2.0 * kPi / d->lambda_u;
+    R.B0 = 2.0 * kPi * kMe * kC * d->K / (kQe * d->lambda_u);
+    R.Lu = d->n_periods * d->lambda_u;
+    R.z_ent = d->z_entrance;
+    R.theta = d->pol_angle_deg * kPi / 180.0;
+    R.und_type = d->und_type;
+    // NSFD: A = 0.25 (1 + 0.02 / ((dz/dx)^2 + (dz/dy)^2)); r_l = c dt / d_l
+    const double cdt = kC * R.dt;
+    const double rx2 = (cdt / d->dx) * (cdt / d->dx), ry2 = (cdt / d->dy) * (cdt / d->dy),
+                 rz2 = (cdt / d->dz) * (cdt / d->dz);
+    const double qq = (d->dz / d->dx) * (d->dz / d->dx) + (d->dz / d->dy) * (d->dz / d->dy);
+    R.A = 0.25 * (1.0 + 0.02 / qq);
+    R.a1 = 2.0 * (1.0 - (1.0 - 2.0 * R.A) * rx2 - (1.0 - 2.0 * R.A) * ry2 - rz2);
+    R.a2 = rx2;
+    R.a4 = ry2;
+    R.a6 = rz2 - 2.0 * R.A * (rx2 + ry2);
+    const double mu0 = 1.0 / (kEps0 * kC * kC);
+    R.sfac_A = cdt * cdt * mu0;
+    R.sfac_phi = cdt * cdt / kEps0;
+    R.space_charge = d->space_charge;
+    R.order = d->truncation_order;
+    R.cdt = cdt;
+    R.h[0] = d->dx;
+    R.h[1] = d->dy;
+    R.h[2] = d->dz;
+    for (int a = 0; a < 3; ++a) {
+        const double hn = R.h[a];
+        const double r1 = cdt / R.h[(a + 1) % 3], r2 = cdt / R.h[(a + 2) % 3];
+        R.mur_be0[a] = (cdt - hn) / (cdt + hn);
+        R.mur_be1[a] = 2.0 * hn / (cdt + hn);
+        R.mur_g1[a] = hn * (2.0 - r1 * r1 - r2 * r2) / (cdt + hn);
+        R.mur_ga[a] = r1 * r1 * hn / (2.0 * (cdt + hn));
+        R.mur_gb[a] = r2 * r2 * hn / (2.0 * (cdt + hn));
+    }
+    R.precision = d->field_precision;
+    R.compensated = d->compensated;
+    R.np = 0;
+    R.np_cap = d->max_particles;
+    for (int a = 0; a < 3; ++a) {
+        R.tile[a] = d->tile[a];
+        const int cells = (a == 0 ? d->nx : (a == 1 ? d->ny : d->nz)) - 1;
+        R.ntile[a] = (cells + d->tile[a] - 1) / d->tile[a];
+    }
+    R.key_inactive = (uint32_t)R.ntile[0] * R.ntile[1] * R.ntile[2] * (uint32_t)(d->tile[0] * d->tile[1] * d->tile[2]);
+
+    char *A = h->arena;
+    const Layout &L = h->L;
+    const size_t c = (size_t)(d->max_particles > 0 ? d->max_particles : 1);
+    R.ctl = (Ctl *)(A + L.ctl);
+    R.pot = A + L.pot;
+    R.src = A + L.src;
+    R.src_lo = L.src_lo == (size_t)-1 ? nullptr : A + L.src_lo;
+    R.eb = A + L.eb;
+    for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 6; ++a)
+            R.pr[b][a] = (double *)(A + L.pr) + (size_t)(b * 6 + a) * c;
+    R.pid[0] = (int32_t *)(A + L.pid);
+    R.pid[1] = R.pid[0] + c;
+    R.key_by_id = (uint32_t *)(A + L.key_by_id);
+    R.slot_of_id = (int32_t *)(A + L.slot_of_id);
+    h->cell_by_id = (int32_t *)(A + L.cell_by_id);
+    R.key_sorted = (uint32_t *)(A + L.key_sorted);
+    R.sk[0] = (uint32_t *)(A + L.sk);
+    R.sk[1] = R.sk[0] + c;
+    R.sv[0] = (int32_t *)(A + L.sv);
+    R.sv[1] = R.sv[0] + c;
+    R.hist = (uint32_t *)(A + L.hist);
+    R.sort_blocks = sort_blocks((int64_t)c);
+    R.power_hist = (double *)(A + L.power);
+    R.power_cap = kPowerCap;
+    R.k_plane = d->k_plane;
+    R.record_power = d->record_power;
+
+    // zero fields, sources, vertex fields and the power history; set the boxes empty
+    const size_t pf = d->field_precision == 32 ? 4 : 8;
+    const size_t nn = (size_t)R.nn;
+    HIPCHK(h, hipMemsetAsync(R.pot, 0, 12 * nn * pf, h->stream));
+    HIPCHK(h, hipMemsetAsync(R.src, 0, 8 * nn * pf, h->stream));
+    if (R.src_lo)
+        HIPCHK(h, hipMemsetAsync(R.src_lo, 0, 8 * nn * pf, h->stream));
+    HIPCHK(h, hipMemsetAsync(R.eb, 0, 6 * nn * pf, h->stream));
+    HIPCHK(h, hipMemsetAsync(R.power_hist, 0, (size_t)kPowerCap * 8, h->stream));
+    Ctl c0;
+    memset(&c0, 0, sizeof c0);
+    for (int s = 0; s < 2; ++s)
+        for (int a = 0; a < 3; ++a) {
+            c0.dep_lo[s][a] = 0x7fffffff;
+            c0.dep_hi[s][a] = -1;
+        }
+    for (int a = 0; a < 3; ++a) {
+        c0.cell_lo[a] = 0x7fffffff;
+        c0.cell_hi[a] = -1;
+    }
+    HIPCHK(h, hipMemcpyAsync(R.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    // default sweep tile: wide rows for large planes, narrower for small ones
+    h->sweep_shape = (d->nx - 2 <= 40) ? 2 : 0;
+    const char *sh = getenv("MITHRA_SWEEP_SHAPE");
+    if (sh)
+        h->sweep_shape = atoi(sh) % sweep_shape_count();
+    *out = h;
+    return MITHRA_OK;
+}
+
+static int enqueue_sort_with_cells(mithra_handle h);
+
+extern "C" int mithra_load_bunch(mithra_handle h, int64_t n, const double *xyz, const double *u, double q_macro)
+{
+    if (!h)
+        return MITHRA_EINVAL;
+    if (h->steps > 0 || h->loaded)
+        return fail(h, MITHRA_ESTATE, "load_bunch is allowed once, before the first step");
+    if (n <= 0 || n > h->d.max_particles)
+        return fail(h, MITHRA_EINVAL, "n = %lld outside 1..max_particles (%lld)", (long long)n,
+                    (long long)h->d.max_particles);
+    if (!xyz || !u || !std::isfinite(q_macro))
+        return fail(h, MITHRA_EINVAL, "null input or non-finite charge");
+    std::vector<double> col((size_t)n);
+    for (int64_t p = 0; p < 3 * n; ++p)
+        if (!std::isfinite(xyz[p]) || !std::isfinite(u[p]))
+            return fail(h, MITHRA_EINVAL, "non-finite particle value at index %lld", (long long)(p / 3));
+    RunDev &R = h->R;
+    for (int a = 0; a < 3; ++a) {
+        for (int64_t p = 0; p < n; ++p)
+            col[(size_t)p] = xyz[3 * p + a];
+        HIPCHK(h, hipMemcpy(R.pr[0][a], col.data(), (size_t)n * 8, hipMemcpyHostToDevice));
+        for (int64_t p = 0; p < n; ++p)
+            col[(size_t)p] = u[3 * p + a];
+        HIPCHK(h, hipMemcpy(R.pr[0][3 + a], col.data(), (size_t)n * 8, hipMemcpyHostToDevice));
+    }
+    std::vector<int32_t> ids((size_t)n);
+    for (int64_t p = 0; p < n; ++p)
+        ids[(size_t)p] = (int32_t)p;
+    HIPCHK(h, hipMemcpy(R.pid[0], ids.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+    R.np = n;
+    R.q = q_macro;
+    R.qV = q_macro / (h->d.dx * h->d.dy * h->d.dz);
+    HIPCHK(h, launch_load_deposit(R, h->stream));
+    hipLaunchKernelGGL(k_book_load, dim3(1), dim3(1), 0, h->stream, R.ctl);
+    int rc = enqueue_sort_with_cells(h);
+    if (rc)
+        return rc;
+    hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, h->stream, R.ctl, 0);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->loaded = true;
+    return MITHRA_OK;
+}
+
+// cell index per id, written beside the sort keys (read back on request)
+__global__ void k_cells_by_id(RunDev R, int32_t *cell_by_id)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= R.np)
+        return;
+    const int pb = R.ctl->pbuf;
+    const double g[3] = {(R.pr[pb][0][p] - R.x0) / R.dx, (R.pr[pb][1][p] - R.y0) / R.dy,
+                         (R.pr[pb][2][p] - R.z0) / R.dz};
+    const int n[3] = {R.nx, R.ny, R.nz};
+    int c[3];
+    bool act = true;
+    for (int a = 0; a < 3; ++a) {
+        const double f = floor(g[a]);
+        act = act && f >= 1.0 && f <= (double)(n[a] - 3);
+        c[a] = act ? (int)f : 0;
+    }
+    cell_by_id[R.pid[pb][p]] = act ? (int32_t)nid(R, c[0], c[1], c[2]) : -1;
+}
+
+static int enqueue_sort_with_cells(mithra_handle h)
+{
+    HIPCHK(h, launch_sort(h->R, h->stream));
+    return MITHRA_OK;
+}
+
+static int enqueue_step(mithra_handle h)
+{
+    RunDev &R = h->R;
+    hipStream_t st = h->stream;
+    HIPCHK(h, launch_sweep(R, h->sweep_shape, st));
+    HIPCHK(h, launch_mur(R, st));
+    HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
+    hipLaunchKernelGGL(k_book_mid, dim3(1), dim3(1), 0, st, R.ctl);
+    HIPCHK(h, launch_push_deposit(R, st));
+    HIPCHK(h, launch_sort(R, st));
+    if (R.record_power)
+        HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st));
+    hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);
+    HIPCHK(h, hipGetLastError());
+    return MITHRA_OK;
+}
+
+// Capture one step on a private stream (the caller's stream may be the
+// legacy default stream, which cannot be captured); the graph is then
+// launched on the caller's stream.
+static int build_graph(mithra_handle h)
+{
+    hipStream_t cap = nullptr;
+    HIPCHK(h, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t user = h->stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    int rc = MITHRA_OK;
+    if (e == hipSuccess) {
+        h->stream = cap;
+        rc = enqueue_step(h);
+        h->stream = user;
+        e = hipStreamEndCapture(cap, &g);
+    }
+    (void)hipStreamDestroy(cap);
+    if (rc) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess)
+        return fail(h, MITHRA_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess)
+        return fail(h, MITHRA_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_step(mithra_handle h, int64_t n_steps)
+{
+    if (!h)
+        return MITHRA_EINVAL;
+    if (!h->loaded)
+        return fail(h, MITHRA_ESTATE, "no bunch loaded");
+    if (n_steps < 0)
+        return fail(h, MITHRA_EINVAL, "negative step count");
+    for (int64_t i = 0; i < n_steps; ++i) {
+        if (h->use_graph) {
+            if (!h->graph) {
+                int rc = build_graph(h);
+                if (rc)
+                    return rc;
+            }
+            HIPCHK(h, hipGraphLaunch(h->graph, h->stream));
+        } else {
+            int rc = enqueue_step(h);
+            if (rc)
+                return rc;
+        }
+        h->steps += 1;
+    }
+    return MITHRA_OK;
+}
+
+static int check_nan(mithra_handle h)
+{
+    int32_t flag = 0;
+    HIPCHK(h, hipMemcpy(&flag, &h->R.ctl->nan_flag, 4, hipMemcpyDeviceToHost));
+    if (flag)
+        return fail(h, MITHRA_ENUMERIC, "non-finite value detected by the diagnostics");
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_read_fields(mithra_handle h, int field_id, int dtype, void *host_out, size_t bytes)
+{
+    if (!h)
+        return MITHRA_EINVAL;
+    const size_t nn = (size_t)h->R.nn;
+    const size_t esz = dtype == MITHRA_DTYPE_F32 ? 4 : 8;
+    if (field_id < 0 || field_id > MITHRA_FIELD_RHO || (dtype != 0 && dtype != 1) || !host_out || bytes != nn * esz)
+        return fail(h, MITHRA_EINVAL, "bad field id, dtype, buffer or size");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    int rc = check_nan(h);
+    if (rc)
+        return rc;
+    RunDev &R = h->R;
+    const size_t pf = R.precision == 32 ? 4 : 8;
+    const int64_t S = h->steps;
+    const char *src = nullptr, *lo = nullptr;
+    if (field_id <= MITHRA_FIELD_BZ) {
+        if (S == 0) {
+            memset(host_out, 0, bytes);
+            return MITHRA_OK;
+        }
+        HIPCHK(h, launch_vertex_fields(R, -1, 1, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        src = (const char *)R.eb + (size_t)field_id * nn * pf;
+    } else if (field_id <= MITHRA_FIELD_AZ || field_id == MITHRA_FIELD_PHI) {
+        const int comp = field_id == MITHRA_FIELD_PHI ? 3 : field_id - MITHRA_FIELD_AX;
+        src = (const char *)R.pot + ((size_t)slot_cur(S) * 4 + comp) * nn * pf;
+    } else {
+        const int comp = field_id == MITHRA_FIELD_RHO ? 3 : field_id - MITHRA_FIELD_JX;
+        const size_t o = ((size_t)(S & 1) * 4 + comp) * nn * pf;
+        src = (const char *)R.src + o;
+        if (R.src_lo)
+            lo = (const char *)R.src_lo + o;
+    }
+    std::vector<char> raw(nn * pf), rawlo;
+    HIPCHK(h, hipMemcpy(raw.data(), src, nn * pf, hipMemcpyDeviceToHost));
+    if (lo) {
+        rawlo.resize(nn * pf);
+        HIPCHK(h, hipMemcpy(rawlo.data(), lo, nn * pf, hipMemcpyDeviceToHost));
+    }
+    for (size_t i = 0; i < nn; ++i) {
+        double v = pf == 4 ? (double)((const float *)raw.data())[i] : ((const double *)raw.data())[i];
+        if (lo)
+            v += (double)((const float *)rawlo.data())[i];
+        if (esz == 4)
+            ((float *)host_out)[i] = (float)v;
+        else
+            ((double *)host_out)[i] = v;
+    }
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_read_particles(mithra_handle h, double *xyz, double *u, int32_t *cell, int32_t *sort_perm)
+{
+    if (!h)
+        return MITHRA_EINVAL;
+    if (!h->loaded)
+        return fail(h, MITHRA_ESTATE, "no bunch loaded");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    int rc = check_nan(h);
+    if (rc)
+        return rc;
+    RunDev &R = h->R;
+    const int64_t n = R.np;
+    int32_t pb = 0;
+    HIPCHK(h, hipMemcpy(&pb, &R.ctl->pbuf, 4, hipMemcpyDeviceToHost));
+    std::vector<int32_t> ids((size_t)n);
+    HIPCHK(h, hipMemcpy(ids.data(), R.pid[pb], (size_t)n * 4, hipMemcpyDeviceToHost));
+    if (sort_perm)
+        memcpy(sort_perm, ids.data(), (size_t)n * 4);
+    std::vector<double> col((size_t)n);
+    for (int a = 0; a < 6; ++a) {
+        double *dst = a < 3 ? xyz : u;
+        if (!dst)
+            continue;
+        HIPCHK(h, hipMemcpy(col.data(), R.pr[pb][a], (size_t)n * 8, hipMemcpyDeviceToHost));
+        for (int64_t r = 0; r < n; ++r)
+            dst[3 * (int64_t)ids[(size_t)r] + (a % 3)] = col[(size_t)r];
+    }
+    if (cell) {
+        hipLaunchKernelGGL(k_cells_by_id, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream, R,
+                           h->cell_by_id);
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        HIPCHK(h, hipMemcpy(cell, h->cell_by_id, (size_t)n * 4, hipMemcpyDeviceToHost));
+    }
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_radiated_power(mithra_handle h, int32_t k_plane, double *p_lab_W)
+{
+    if (!h || !p_lab_W)
+        return MITHRA_EINVAL;
+    if (k_plane < 1 || k_plane > h->d.nz - 2)
+        return fail(h, MITHRA_EINVAL, "k_plane outside 1..nz-2");
+    if (!h->loaded)
+        return fail(h, MITHRA_ESTATE, "no bunch loaded");
+    if (h->steps == 0) {
+        *p_lab_W = 0.0;
+        return MITHRA_OK;
+    }
+    double *dev = (double *)(h->arena + h->L.scratch) + 3 * kBunchBlocks;
+    HIPCHK(h, launch_plane_power(h->R, -1, k_plane, dev, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(p_lab_W, dev, 8, hipMemcpyDeviceToHost));
+    return MITHRA_OK;
+}
+
+extern "C" int64_t mithra_power_history(mithra_handle h, double *out, int64_t n)
+{
+    if (!h || !out || n < 0)
+        return MITHRA_EINVAL;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    int64_t m = h->steps < n ? h->steps : n;
+    if (m > kPowerCap)
+        m = kPowerCap;
+    if (m > 0)
+        HIPCHK(h, hipMemcpy(out, h->R.power_hist, (size_t)m * 8, hipMemcpyDeviceToHost));
+    return m;
+}
+
+extern "C" int mithra_bunching(mithra_handle h, double *b)
+{
+    if (!h || !b)
+        return MITHRA_EINVAL;
+    if (!h->loaded)
+        return fail(h, MITHRA_ESTATE, "no bunch loaded");
+    double *part = (double *)(h->arena + h->L.scratch);
+    HIPCHK(h, launch_bunching(h->R, part, kBunchBlocks, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    std::vector<double> hp(3 * kBunchBlocks);
+    HIPCHK(h, hipMemcpy(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost));
+    double re = 0, im = 0, n = 0;
+    for (int i = 0; i < kBunchBlocks; ++i) {
+        re += hp[3 * i];
+        im += hp[3 * i + 1];
+        n += hp[3 * i + 2];
+    }
+    *b = n > 0 ? std::sqrt(re * re + im * im) / n : 0.0;
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_constants(mithra_handle h, double *o)
+{
+    if (!h || !o)
+        return MITHRA_EINVAL;
+    o[0] = h->R.gamma0;
+    o[1] = h->R.beta0;
+    o[2] = h->R.dt;
+    o[3] = h->R.dtb;
+    o[4] = h->R.A;
+    o[5] = h->R.q;
+    o[6] = (double)h->steps;
+    o[7] = (double)h->R.np;
+    return MITHRA_OK;
+}
+
+extern "C" const char *mithra_last_error(mithra_handle h)
+{
+    if (!h)
+        return "null handle";
+    return h->err.c_str();
+}
+
+extern "C" int mithra_destroy(mithra_handle h)
+{
+    if (!h)
+        return MITHRA_EINVAL;
+    if (h->graph)
+        (void)hipGraphExecDestroy(h->graph);
+    delete h;
+    return MITHRA_OK;
+}
+
+// ---- internal entry points used by the Python binding for timing/tuning --
+
+extern "C" int mithra_set_sweep_shape(mithra_handle h, int shape)
+{
+    if (!h || shape < 0 || shape >= sweep_shape_count())
+        return MITHRA_EINVAL;
+    h->sweep_shape = shape;
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_sweep_shape_count(void) { return sweep_shape_count(); }

@@ -1,0 +1,556 @@
+// k_fdtd.hip -- field kernels of the boosted-frame PIC step.
+//
+//  * k_sweep: NSFD update of A_x, A_y, A_z and phi at interior nodes
+//    (MITHRA 2.0 manual, sec. "FDTD for Wave Equation", eqs. NSFDtrick and
+//    updateEquation; sec. "FDTD for Scalar Potential").  HBM-bound 15-point
+//    stencil: each thread owns one (i,j) column of a TX x TY tile and marches
+//    along z with a register queue of psi^n(k-1..k+1); the z-averaged value
+//    psi-bar of every column (plus a one-column halo ring) goes through a
+//    double-buffered LDS plane, so psi^n is read from HBM about once.  The
+//    source of the step (node-averaged edge current, or rho) is read only
+//    inside the bounding box of the last deposit, and the other source set is
+//    cleared inside its own box in the same pass.
+//  * k_mur: Mur absorbing boundaries (sec. "Boundary Truncation"), one
+//    thread per boundary node.  Faces use the printed first/second-order
+//    updates with permuted axes; edges and corners solve the sum of the
+//    first-order conditions of their faces discretised at the centre of the
+//    2x2 (2x2x2) node stencil, recomputing the neighbouring face/edge values
+//    they need so that one launch suffices.  Three time levels make all
+//    reads race-free.
+//  * k_vertex_fields: E and B at vertices (sec. "Field Evaluation"):
+//    E = -(A^{n+1} - A^n)/dt - grad phi, B = mean of curl A^n and curl A^{n+1}.
+#include "mithra_dev.hpp"
+
+namespace mithra {
+
+// ---------------------------------------------------------------------------
+// K1: NSFD sweep
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ inline T src_value(const RunDev &R, int comp, int set, int64_t c, int64_t back)
+{
+    // node-averaged edge current along comp, or rho; scaled to the update
+    if (comp < 3) {
+        const T *J = src_ptr<T>(R, set, comp);
+        double s = (double)J[c] + (double)J[c - back];
+        if (R.compensated) {
+            const T *L = srclo_ptr<T>(R, set, comp);
+            s += (double)L[c] + (double)L[c - back];
+        }
+        return (T)(R.sfac_A * 0.5 * s);
+    }
+    const T *Q = src_ptr<T>(R, set, 3);
+    double s = (double)Q[c];
+    if (R.compensated)
+        s += (double)srclo_ptr<T>(R, set, 3)[c];
+    return (T)(R.sfac_phi * s);
+}
+
+template <typename T, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX *TY) void k_sweep(RunDev R)
+{
+    __shared__ T sb[2][TY + 2][TX + 2];
+
+    const int ntx = (R.nx - 2 + TX - 1) / TX;
+    const int nty = (R.ny - 2 + TY - 1) / TY;
+    const int nch = (R.nz - 2 + TZ - 1) / TZ;
+    int64_t lb = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int tile_x = (int)(lb % ntx);
+    lb /= ntx;
+    const int tile_y = (int)(lb % nty);
+    lb /= nty;
+    const int chunk = (int)(lb % nch);
+    const int comp = (int)(lb / nch);
+
+    const int64_t s = R.ctl->step;
+    const int set_r = (int)(s & 1), set_c = (int)((s + 1) & 1);
+    const bool update = (comp < 3) || R.space_charge;
+
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int i = 1 + tile_x * TX + lx;
+    const int j = 1 + tile_y * TY + ly;
+    const bool inb = (i < R.nx) && (j < R.ny);
+    const bool valid = (i <= R.nx - 2) && (j <= R.ny - 2);
+    const int ic = min(i, R.nx - 1), jc = min(j, R.ny - 1);
+    const int64_t plane = (int64_t)R.nx * R.ny;
+    const int64_t col = (int64_t)jc * R.nx + ic;
+
+    // halo ring: left/right columns (TY each), bottom/top rows (TX each)
+    const int H = 2 * (TX + TY);
+    const int h = threadIdx.x;
+    int hx = 0, hy = 0, hi_ = 0, hj_ = 0;
+    bool hval = false;
+    if (h < H) {
+        if (h < TY) {
+            hx = -1; hy = h;
+        } else if (h < 2 * TY) {
+            hx = TX; hy = h - TY;
+        } else if (h < 2 * TY + TX) {
+            hy = -1; hx = h - 2 * TY;
+        } else {
+            hy = TY; hx = h - 2 * TY - TX;
+        }
+        hi_ = 1 + tile_x * TX + hx;
+        hj_ = 1 + tile_y * TY + hy;
+        hval = (hi_ >= 0) && (hi_ < R.nx) && (hj_ >= 0) && (hj_ < R.ny);
+    }
+    const int64_t hcol = hval ? ((int64_t)hj_ * R.nx + hi_) : 0;
+
+    const int kb = 1 + chunk * TZ;
+    const int ke = min(kb + TZ, R.nz - 1);
+
+    const T *cur = pot_ptr<T>(R, slot_cur(s), comp);
+    const T *prev = pot_ptr<T>(R, slot_prev(s), comp);
+    T *next = pot_ptr<T>(R, slot_next(s), comp);
+
+    // source box of the set read now (expanded by one node on the high side:
+    // a node average reaches the edge below it), clear box of the other set
+    const int *rlo = R.ctl->dep_lo[set_r];
+    const int *rhi = R.ctl->dep_hi[set_r];
+    const int *clo = R.ctl->dep_lo[set_c];
+    const int *chi = R.ctl->dep_hi[set_c];
+    const bool src_col = valid && i >= rlo[0] && i <= rhi[0] + 1 && j >= rlo[1] && j <= rhi[1] + 1;
+    const bool clr_col = valid && i >= clo[0] && i <= chi[0] && j >= clo[1] && j <= chi[1];
+    const int64_t back = comp == 0 ? 1 : (comp == 1 ? R.nx : plane);
+    T *clr = src_ptr<T>(R, set_c, comp);
+    T *clr_lo = R.compensated ? srclo_ptr<T>(R, set_c, comp) : nullptr;
+
+    const T cA = (T)R.A, c1A = (T)(1.0 - 2.0 * R.A);
+    const T a1 = (T)R.a1, a2 = (T)R.a2, a4 = (T)R.a4, a6 = (T)R.a6;
+
+    T qm = 0, q0 = 0, qp = 0, hqm = 0, hq0 = 0, hqp = 0;
+    if (inb) {
+        qm = cur[(int64_t)(kb - 1) * plane + col];
+        q0 = cur[(int64_t)kb * plane + col];
+        qp = cur[(int64_t)(kb + 1) * plane + col];
+    }
+    if (hval) {
+        hqm = cur[(int64_t)(kb - 1) * plane + hcol];
+        hq0 = cur[(int64_t)kb * plane + hcol];
+        hqp = cur[(int64_t)(kb + 1) * plane + hcol];
+    }
+
+    for (int k = kb; k < ke; ++k) {
+        const int64_t c = (int64_t)k * plane + col;
+        // issue the loads of this iteration before the barrier
+        T pf = 0, hpf = 0;
+        if (k + 1 < ke) {
+            if (inb)
+                pf = cur[c + 2 * plane];
+            if (hval)
+                hpf = cur[(int64_t)(k + 2) * plane + hcol];
+        }
+        T pm = 0, sv = 0;
+        if (valid && update) {
+            pm = prev[c];
+            if (src_col && k >= rlo[2] && k <= rhi[2] + 1)
+                sv = src_value<T>(R, comp, set_r, c, back);
+        }
+        if (clr_col && k >= clo[2] && k <= chi[2]) {
+            clr[c] = (T)0;
+            if (clr_lo)
+                clr_lo[c] = (T)0;
+        }
+        T(*buf)[TX + 2] = sb[k & 1];
+        buf[ly + 1][lx + 1] = cA * (qm + qp) + c1A * q0;
+        if (h < H)
+            buf[hy + 1][hx + 1] = cA * (hqm + hqp) + c1A * hq0;
+        __syncthreads();
+        if (valid && update) {
+            T v = a1 * q0 + a2 * (buf[ly + 1][lx + 2] + buf[ly + 1][lx]) +
+                  a4 * (buf[ly + 2][lx + 1] + buf[ly][lx + 1]) + a6 * (qp + qm) - pm + sv;
+            next[c] = v;
+        }
+        qm = q0;
+        q0 = qp;
+        qp = pf;
+        hqm = hq0;
+        hq0 = hqp;
+        hqp = hpf;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K2: Mur boundaries
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct Lv {
+    const T *pm;  // n-1
+    const T *p0;  // n
+    const T *pp;  // n+1 (interior written by the sweep)
+};
+
+__device__ inline int bside(const RunDev &R, int a, int v)
+{
+    const int n = a == 0 ? R.nx : (a == 1 ? R.ny : R.nz);
+    return v == 0 ? -1 : (v == n - 1 ? 1 : 0);
+}
+
+template <typename T>
+__device__ inline double ld(const T *a, const RunDev &R, const int p[3])
+{
+    return (double)a[nid(R, p[0], p[1], p[2])];
+}
+
+// n+1 value of a face node p (normal axis ax, side -1/+1)
+template <typename T>
+__device__ double face_np1(const RunDev &R, const Lv<T> &L, const int p[3], int ax, int side)
+{
+    int q[3] = {p[0], p[1], p[2]};
+    q[ax] -= side;  // first node inside
+    const double be0 = R.mur_be0[ax];
+    double v = be0 * (ld(L.pm, R, p) + ld(L.pp, R, q)) - ld(L.pm, R, q);
+    if (R.order == 1)
+        return v + R.mur_be1[ax] * (ld(L.p0, R, p) + ld(L.p0, R, q));
+    v += R.mur_g1[ax] * (ld(L.p0, R, p) + ld(L.p0, R, q));
+    const int t1 = (ax + 1) % 3, t2 = (ax + 2) % 3;
+    double s1 = 0.0, s2 = 0.0;
+    for (int d = -1; d <= 1; d += 2) {
+        int a[3] = {p[0], p[1], p[2]}, b[3] = {q[0], q[1], q[2]};
+        a[t1] += d;
+        b[t1] += d;
+        s1 += ld(L.p0, R, a) + ld(L.p0, R, b);
+        int c2[3] = {p[0], p[1], p[2]}, d2[3] = {q[0], q[1], q[2]};
+        c2[t2] += d;
+        d2[t2] += d;
+        s2 += ld(L.p0, R, c2) + ld(L.p0, R, d2);
+    }
+    return v + R.mur_ga[ax] * s1 + R.mur_gb[ax] * s2;
+}
+
+// Summed first-order conditions over the 2^m stencil of node p whose
+// boundary axes are ax[0..m-1].  Per stencil node X, with sigma_b = +1 on
+// the boundary side of axis b and -1 on the inner side, the conditions
+// (scaled by 2^m dt) contribute
+//   (w1 + w2) X^{n+1} - 2 w2 X^n + (w2 - w1) X^{n-1},
+//   w1 = sum_b sigma_b / h_b,  w2 = m / (c dt).
+// np1[] holds the n+1 values of the stencil nodes except node 0 (p).
+template <typename T>
+__device__ double solve_summed(const RunDev &R, const Lv<T> &L, const int p[3], const int *ax,
+                               const int *sd, int m, const double *np1)
+{
+    const double w2 = (double)m / R.cdt;
+    double rest = 0.0, cu = 0.0;
+    for (int st = 0; st < (1 << m); ++st) {
+        int q[3] = {p[0], p[1], p[2]};
+        double w1 = 0.0;
+        for (int b = 0; b < m; ++b) {
+            const bool inner = (st >> b) & 1;
+            if (inner)
+                q[ax[b]] -= sd[b];
+            w1 += (inner ? -1.0 : 1.0) / R.h[ax[b]];
+        }
+        rest += -2.0 * w2 * ld(L.p0, R, q) + (w2 - w1) * ld(L.pm, R, q);
+        if (st == 0)
+            cu = w1 + w2;
+        else
+            rest += (w1 + w2) * np1[st];
+    }
+    return -rest / cu;
+}
+
+template <typename T>
+__device__ double np1_face_or_interior(const RunDev &R, const Lv<T> &L, const int q[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        const int sd = bside(R, a, q[a]);
+        if (sd != 0)
+            return face_np1(R, L, q, a, sd);
+    }
+    return ld(L.pp, R, q);
+}
+
+template <typename T>
+__device__ double edge_np1(const RunDev &R, const Lv<T> &L, const int p[3], const int *ax, const int *sd)
+{
+    double np1[4];
+    for (int st = 1; st < 4; ++st) {
+        int q[3] = {p[0], p[1], p[2]};
+        for (int b = 0; b < 2; ++b)
+            if ((st >> b) & 1)
+                q[ax[b]] -= sd[b];
+        np1[st] = np1_face_or_interior(R, L, q);
+    }
+    return solve_summed(R, L, p, ax, sd, 2, np1);
+}
+
+template <typename T>
+__device__ double corner_np1(const RunDev &R, const Lv<T> &L, const int p[3], const int *ax, const int *sd)
+{
+    double np1[8];
+    for (int st = 1; st < 8; ++st) {
+        int q[3] = {p[0], p[1], p[2]};
+        int eax[3], esd[3], me = 0;
+        for (int b = 0; b < 3; ++b) {
+            if ((st >> b) & 1)
+                q[ax[b]] -= sd[b];
+            else {
+                eax[me] = ax[b];
+                esd[me] = sd[b];
+                ++me;
+            }
+        }
+        if (me == 2)
+            np1[st] = edge_np1(R, L, q, eax, esd);
+        else
+            np1[st] = np1_face_or_interior(R, L, q);
+    }
+    return solve_summed(R, L, p, ax, sd, 3, np1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mur(RunDev R)
+{
+    const int64_t nzf = 2LL * R.nx * R.ny;
+    const int64_t nyf = 2LL * R.nx * (R.nz - 2);
+    const int64_t nxf = 2LL * (R.ny - 2) * (R.nz - 2);
+    const int64_t nb = nzf + nyf + nxf;
+    const int ncomp = R.space_charge ? 4 : 3;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb * ncomp)
+        return;
+    const int comp = (int)(t / nb);
+    int64_t r = t % nb;
+    int p[3];
+    if (r < nzf) {
+        const int64_t half = (int64_t)R.nx * R.ny;
+        p[2] = r < half ? 0 : R.nz - 1;
+        r %= half;
+        p[0] = (int)(r % R.nx);
+        p[1] = (int)(r / R.nx);
+    } else if (r < nzf + nyf) {
+        r -= nzf;
+        const int64_t half = (int64_t)R.nx * (R.nz - 2);
+        p[1] = r < half ? 0 : R.ny - 1;
+        r %= half;
+        p[0] = (int)(r % R.nx);
+        p[2] = 1 + (int)(r / R.nx);
+    } else {
+        r -= nzf + nyf;
+        const int64_t half = (int64_t)(R.ny - 2) * (R.nz - 2);
+        p[0] = r < half ? 0 : R.nx - 1;
+        r %= half;
+        p[1] = 1 + (int)(r % (R.ny - 2));
+        p[2] = 1 + (int)(r / (R.ny - 2));
+    }
+    const int64_t s = R.ctl->step;
+    Lv<T> L{pot_ptr<T>(R, slot_prev(s), comp), pot_ptr<T>(R, slot_cur(s), comp),
+            pot_ptr<T>(R, slot_next(s), comp)};
+    int ax[3], sd[3], m = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int v = bside(R, a, p[a]);
+        if (v != 0) {
+            ax[m] = a;
+            sd[m] = v;
+            ++m;
+        }
+    }
+    double v;
+    if (m == 1)
+        v = face_np1(R, L, p, ax[0], sd[0]);
+    else if (m == 2)
+        v = edge_np1(R, L, p, ax, sd);
+    else
+        v = corner_np1(R, L, p, ax, sd);
+    pot_ptr<T>(R, slot_next(s), comp)[nid(R, p[0], p[1], p[2])] = (T)v;
+}
+
+// ---------------------------------------------------------------------------
+// K3: E and B at vertices
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ inline void vertex_eb(const RunDev &R, int64_t s, int i, int j, int k, double E[3], double B[3])
+{
+    const T *An[3], *Ap[3];
+    for (int c = 0; c < 3; ++c) {
+        An[c] = pot_ptr<T>(R, slot_cur(s), c);
+        Ap[c] = pot_ptr<T>(R, slot_next(s), c);
+    }
+    const int64_t c0 = nid(R, i, j, k);
+    const int64_t sx = 1, sy = R.nx, sz = (int64_t)R.nx * R.ny;
+    const double i2x = 0.5 / R.dx, i2y = 0.5 / R.dy, i2z = 0.5 / R.dz;
+    auto dif = [&](const T *a, int64_t st) { return (double)a[c0 + st] - (double)a[c0 - st]; };
+    // curl of A at n and at n+1, averaged
+    B[0] = 0.5 * ((dif(An[2], sy) + dif(Ap[2], sy)) * i2y - (dif(An[1], sz) + dif(Ap[1], sz)) * i2z);
+    B[1] = 0.5 * ((dif(An[0], sz) + dif(Ap[0], sz)) * i2z - (dif(An[2], sx) + dif(Ap[2], sx)) * i2x);
+    B[2] = 0.5 * ((dif(An[1], sx) + dif(Ap[1], sx)) * i2x - (dif(An[0], sy) + dif(Ap[0], sy)) * i2y);
+    double g[3] = {0.0, 0.0, 0.0};
+    if (R.space_charge) {
+        const T *ph = pot_ptr<T>(R, slot_cur(s), 3);
+        g[0] = dif(ph, sx) * i2x;
+        g[1] = dif(ph, sy) * i2y;
+        g[2] = dif(ph, sz) * i2z;
+    }
+    for (int c = 0; c < 3; ++c)
+        E[c] = -((double)Ap[c][c0] - (double)An[c][c0]) / R.dt - g[c];
+}
+
+// E, B over the active-particle box of the last sort (full == 0) or over
+// all interior nodes (full == 1).  step_bias selects the step whose levels
+// are used (0 during a step, -1 after it for read-back).
+template <typename T>
+__global__ __launch_bounds__(256) void k_vertex_fields(RunDev R, int step_bias, int full)
+{
+    const int64_t s = R.ctl->step + step_bias;
+    int lo[3], hi[3];
+    const int n[3] = {R.nx, R.ny, R.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (full) {
+            lo[a] = 1;
+            hi[a] = n[a] - 2;
+        } else {
+            lo[a] = max(1, R.ctl->cell_lo[a]);
+            hi[a] = min(n[a] - 2, R.ctl->cell_hi[a] + 1);
+        }
+        if (hi[a] < lo[a])
+            return;
+    }
+    const int64_t ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    const int64_t tot = ex * ey * ez;
+    T *eb[6];
+    for (int c = 0; c < 6; ++c)
+        eb[c] = eb_ptr<T>(R, c);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = lo[0] + (int)(t % ex);
+        const int j = lo[1] + (int)((t / ex) % ey);
+        const int k = lo[2] + (int)(t / (ex * ey));
+        double E[3], B[3];
+        vertex_eb<T>(R, s, i, j, k, E, B);
+        const int64_t c = nid(R, i, j, k);
+        for (int a = 0; a < 3; ++a) {
+            eb[a][c] = (T)E[a];
+            eb[3 + a][c] = (T)B[a];
+        }
+    }
+}
+
+// Radiated power through node plane k_plane of the fields at t_{s+1/2}
+// (lab-frame Poynting flux), one block: deterministic reduction order.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_plane_power(RunDev R, int step_bias, int kp, double *out)
+{
+    __shared__ double red[1024];
+    const int64_t s = R.ctl->step + step_bias;
+    const double g0 = R.gamma0, b0 = R.beta0;
+    double acc = 0.0;
+    const int wx = R.nx - 2, wy = R.ny - 2;
+    for (int t = threadIdx.x; t < wx * wy; t += blockDim.x) {
+        const int i = 1 + t % wx, j = 1 + t / wx;
+        double E[3], B[3];
+        vertex_eb<T>(R, s, i, j, kp, E, B);
+        const double Exl = g0 * (E[0] + b0 * kC * B[1]);
+        const double Eyl = g0 * (E[1] - b0 * kC * B[0]);
+        const double Bxl = g0 * (B[0] - b0 * E[1] / kC);
+        const double Byl = g0 * (B[1] + b0 * E[0] / kC);
+        acc += Exl * Byl - Eyl * Bxl;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mu0 = 1.0 / (kEps0 * kC * kC);
+        const double P = red[0] * R.dx * R.dy / mu0;
+        if (out) {
+            *out = P;
+        } else if (s >= 0 && s < R.power_cap) {
+            R.power_hist[s] = P;
+        }
+        if (!isfinite(P))
+            R.ctl->nan_flag = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+struct SweepShape {
+    int tx, ty, tz;
+};
+
+template <typename T, int TX, int TY, int TZ>
+static hipError_t launch_sweep_t(const RunDev &R, hipStream_t st)
+{
+    const int64_t ntx = (R.nx - 2 + TX - 1) / TX, nty = (R.ny - 2 + TY - 1) / TY;
+    const int64_t nch = (R.nz - 2 + TZ - 1) / TZ;
+    const int64_t nb = ntx * nty * nch * 4;
+    hipLaunchKernelGGL((k_sweep<T, TX, TY, TZ>), dim3((unsigned)nb), dim3(TX * TY), 0, st, R);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_sweep_shape(const RunDev &R, int shape, hipStream_t st)
+{
+    switch (shape) {
+    case 0: return launch_sweep_t<T, 64, 8, 32>(R, st);
+    case 1: return launch_sweep_t<T, 64, 4, 32>(R, st);
+    case 2: return launch_sweep_t<T, 32, 8, 32>(R, st);
+    case 3: return launch_sweep_t<T, 64, 8, 64>(R, st);
+    case 4: return launch_sweep_t<T, 128, 4, 32>(R, st);
+    case 5: return launch_sweep_t<T, 64, 16, 32>(R, st);
+    case 6: return launch_sweep_t<T, 32, 4, 16>(R, st);
+    case 7: return launch_sweep_t<T, 64, 8, 16>(R, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int sweep_shape_count() { return 8; }
+
+void sweep_shape_dims(int shape, int *tx, int *ty, int *tz)
+{
+    static const int d[8][3] = {{64, 8, 32}, {64, 4, 32}, {32, 8, 32}, {64, 8, 64},
+                                {128, 4, 32}, {64, 16, 32}, {32, 4, 16}, {64, 8, 16}};
+    *tx = d[shape][0];
+    *ty = d[shape][1];
+    *tz = d[shape][2];
+}
+
+hipError_t launch_sweep(const RunDev &R, int shape, hipStream_t st)
+{
+    return R.precision == 32 ? launch_sweep_shape<float>(R, shape, st) : launch_sweep_shape<double>(R, shape, st);
+}
+
+hipError_t launch_mur(const RunDev &R, hipStream_t st)
+{
+    const int64_t nb = 2LL * R.nx * R.ny + 2LL * R.nx * (R.nz - 2) + 2LL * (R.ny - 2) * (R.nz - 2);
+    const int64_t tot = nb * (R.space_charge ? 4 : 3);
+    const unsigned blocks = (unsigned)((tot + 255) / 256);
+    if (R.precision == 32)
+        hipLaunchKernelGGL(k_mur<float>, dim3(blocks), dim3(256), 0, st, R);
+    else
+        hipLaunchKernelGGL(k_mur<double>, dim3(blocks), dim3(256), 0, st, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStream_t st)
+{
+    const int64_t inner = (int64_t)(R.nx - 2) * (R.ny - 2) * (R.nz - 2);
+    int64_t blocks = (inner + 255) / 256;
+    if (blocks > 8192)
+        blocks = 8192;
+    if (blocks < 1)
+        blocks = 1;
+    if (R.precision == 32)
+        hipLaunchKernelGGL(k_vertex_fields<float>, dim3((unsigned)blocks), dim3(256), 0, st, R, step_bias, full);
+    else
+        hipLaunchKernelGGL(k_vertex_fields<double>, dim3((unsigned)blocks), dim3(256), 0, st, R, step_bias, full);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st)
+{
+    if (R.precision == 32)
+        hipLaunchKernelGGL(k_plane_power<float>, dim3(1), dim3(1024), 0, st, R, step_bias, kp, out);
+    else
+        hipLaunchKernelGGL(k_plane_power<double>, dim3(1), dim3(1024), 0, st, R, step_bias, kp, out);
+    return hipGetLastError();
+}
+
+}  // namespace mithra

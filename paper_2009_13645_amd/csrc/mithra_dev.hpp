@@ -1,0 +1,142 @@
+// mithra_dev.hpp -- device-side run description and helpers shared by the
+// HIP kernels of the boosted-frame PIC step (NSFD sweep, Mur, vertex fields,
+// push/deposit, sort, diagnostics).  Host code fills `RunDev` once per run;
+// kernels receive it by value and read the step counter from `Ctl`, so a
+// captured step can be replayed without changing any launch argument.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mithra {
+
+// CODATA 2018
+constexpr double kC = 299792458.0;
+constexpr double kQe = 1.602176634e-19;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kPi = 3.14159265358979323846;
+
+// Device-resident step bookkeeping.  Written only by the kernels of the
+// step pipeline (and zeroed at init).
+struct Ctl {
+    int64_t step;          // completed field steps
+    int32_t pbuf;          // particle buffer holding the current sorted state
+    int32_t nsort;         // sorts done
+    int32_t dep_lo[2][3];  // node bounding box of the nonzero entries of source set s
+    int32_t dep_hi[2][3];
+    int32_t cell_lo[3];    // bounding box of active particle cells at the last sort
+    int32_t cell_hi[3];
+    int32_t nan_flag;      // set when a diagnostic sees a non-finite value
+    int32_t n_active;      // particles in active cells at the last sort
+};
+
+constexpr int kMaxBatch = 1;  // one run per RunDev
+
+struct RunDev {
+    // mesh
+    int nx, ny, nz;
+    int64_t nn;
+    double dx, dy, dz, x0, y0, z0;
+    double inv_dx, inv_dy, inv_dz;  // only used where a product is not compared bitwise
+    // time
+    double dt, dtb;
+    int n_sub;
+    // frame and undulator
+    double gamma0, beta0;
+    double ku, B0, Lu, z_ent, theta;
+    int und_type;
+    // NSFD interior update: next = a1 cur + a2 (bar_x+ + bar_x-) + a4 (bar_y+ + bar_y-)
+    //                              + a6 (cur_k+ + cur_k-) - prev + S
+    double A, a1, a2, a4, a6;
+    double sfac_A;    // (c dt)^2 mu0, multiplies the node-averaged J
+    double sfac_phi;  // (c dt)^2 / eps0, multiplies rho
+    int space_charge;
+    int order;        // Mur order
+    // Mur coefficients per normal axis a (faces of axis a), transverse axes
+    // t1 = (a+1)%3 and t2 = (a+2)%3:
+    //   first order:  be0 (xi0^{n-1} + xi1^{n+1}) + be1 (xi0^n + xi1^n) - xi1^{n-1}
+    //   second order: be0 (...) + g1 (xi0^n + xi1^n) - xi1^{n-1}
+    //                 + ga (t1 neighbours on planes 0 and 1) + gb (t2 neighbours)
+    double mur_be0[3], mur_be1[3], mur_g1[3], mur_ga[3], mur_gb[3];
+    double h[3];      // dx dy dz
+    double cdt;       // c dt
+    int precision;    // 32 or 64
+    int compensated;
+    // particles
+    double q, qV;     // macro charge and q / (dx dy dz)
+    int64_t np;
+    int64_t np_cap;
+    int tile[3];
+    int ntile[3];
+    uint32_t key_inactive;  // sort key of particles outside the active region
+    // storage (element type T = float or double for the field arrays)
+    void *pot;        // [3 slots][4 comps][nn]
+    void *src;        // [2 sets][4: Jx Jy Jz rho][nn]
+    void *src_lo;     // compensation terms (same layout) or null
+    void *eb;         // [6: Ex Ey Ez Bx By Bz][nn]
+    double *pr[2][6]; // particle buffers: x y z ux uy uz
+    int32_t *pid[2];
+    uint32_t *key_by_id;
+    int32_t *slot_of_id;
+    uint32_t *key_sorted;
+    uint32_t *sk[2];
+    int32_t *sv[2];
+    uint32_t *hist;
+    int64_t sort_blocks;
+    double *power_hist;
+    int64_t power_cap;
+    int k_plane;
+    int record_power;
+    Ctl *ctl;
+};
+
+__host__ __device__ inline int64_t nid(const RunDev &R, int i, int j, int k)
+{
+    return ((int64_t)k * R.ny + j) * R.nx + i;
+}
+
+template <typename T>
+__device__ inline T *pot_ptr(const RunDev &R, int slot, int comp)
+{
+    return reinterpret_cast<T *>(R.pot) + ((int64_t)slot * 4 + comp) * R.nn;
+}
+
+template <typename T>
+__device__ inline T *src_ptr(const RunDev &R, int set, int comp)
+{
+    return reinterpret_cast<T *>(R.src) + ((int64_t)set * 4 + comp) * R.nn;
+}
+
+template <typename T>
+__device__ inline T *srclo_ptr(const RunDev &R, int set, int comp)
+{
+    return reinterpret_cast<T *>(R.src_lo) + ((int64_t)set * 4 + comp) * R.nn;
+}
+
+template <typename T>
+__device__ inline T *eb_ptr(const RunDev &R, int comp)
+{
+    return reinterpret_cast<T *>(R.eb) + (int64_t)comp * R.nn;
+}
+
+// Time-level slots of the three rotating potential arrays during step s:
+// prev (n-1), cur (n), next (n+1).
+__host__ __device__ inline int slot_prev(int64_t s) { return (int)(s % 3); }
+__host__ __device__ inline int slot_cur(int64_t s) { return (int)((s + 1) % 3); }
+__host__ __device__ inline int slot_next(int64_t s) { return (int)((s + 2) % 3); }
+
+// XCD-aware block order: the hardware deals consecutive workgroups round-
+// robin over the 8 XCDs; remap so that each XCD receives a contiguous range
+// of logical tiles (which share halos through that XCD's L2).
+__device__ inline int64_t xcd_swizzle(int64_t bid, int64_t nblocks)
+{
+    const int64_t nx = 8;
+    int64_t full = (nblocks / nx) * nx;
+    if (bid >= full)
+        return bid;
+    int64_t per = full / nx;
+    return (bid % nx) * per + bid / nx;
+}
+
+}  // namespace mithra

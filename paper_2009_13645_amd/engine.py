@@ -1,0 +1,218 @@
+"""Thin Python binding of the C ABI in include/mithra.h.
+
+Argument marshalling only: every step of the PIC path runs in the HIP
+library `libmithra.so`.  PyTorch provides the device arena (a uint8 tensor)
+and the stream; nothing here computes physics.  If the library is missing
+the import fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmithra.so")
+
+FIELD_IDS = {"Ex": 0, "Ey": 1, "Ez": 2, "Bx": 3, "By": 4, "Bz": 5, "Ax": 6, "Ay": 7,
+             "Az": 8, "Jx": 9, "Jy": 10, "Jz": 11, "F": 12, "Q": 13}
+ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "ENUMERIC"}
+
+
+class MithraError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GridDesc(C.Structure):
+    """ctypes mirror of `mithra_grid_desc`."""
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("truncation_order", C.c_int32), ("space_charge", C.c_int32),
+                ("solver", C.c_int32), ("n_sub", C.c_int32), ("field_precision", C.c_int32),
+                ("compensated", C.c_int32), ("und_type", C.c_int32), ("n_periods", C.c_int32),
+                ("k_plane", C.c_int32), ("tile", C.c_int32 * 3), ("record_power", C.c_int32),
+                ("max_particles", C.c_int64),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
+                ("gamma", C.c_double), ("K", C.c_double), ("lambda_u", C.c_double),
+                ("pol_angle_deg", C.c_double), ("z_entrance", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmithra.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2009_13645_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        H = C.c_void_p
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        L.mithra_footprint_bytes.argtypes = [C.POINTER(GridDesc), C.c_int64]
+        L.mithra_footprint_bytes.restype = C.c_size_t
+        L.mithra_init_grid.argtypes = [C.POINTER(GridDesc), C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(H)]
+        L.mithra_init_grid.restype = C.c_int
+        L.mithra_load_bunch.argtypes = [H, C.c_int64, dp, dp, C.c_double]
+        L.mithra_load_bunch.restype = C.c_int
+        L.mithra_step.argtypes = [H, C.c_int64]
+        L.mithra_step.restype = C.c_int
+        L.mithra_read_fields.argtypes = [H, C.c_int, C.c_int, C.c_void_p, C.c_size_t]
+        L.mithra_read_fields.restype = C.c_int
+        L.mithra_read_particles.argtypes = [H, dp, dp, ip, ip]
+        L.mithra_read_particles.restype = C.c_int
+        L.mithra_radiated_power.argtypes = [H, C.c_int32, dp]
+        L.mithra_radiated_power.restype = C.c_int
+        L.mithra_power_history.argtypes = [H, dp, C.c_int64]
+        L.mithra_power_history.restype = C.c_int64
+        L.mithra_bunching.argtypes = [H, dp]
+        L.mithra_bunching.restype = C.c_int
+        L.mithra_constants.argtypes = [H, dp]
+        L.mithra_constants.restype = C.c_int
+        L.mithra_last_error.argtypes = [H]
+        L.mithra_last_error.restype = C.c_char_p
+        L.mithra_destroy.argtypes = [H]
+        L.mithra_destroy.restype = C.c_int
+        L.mithra_set_sweep_shape.argtypes = [H, C.c_int]
+        L.mithra_set_sweep_shape.restype = C.c_int
+        L.mithra_sweep_shape_count.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def make_desc(d: dict, max_particles: int, record_power: int = 1) -> GridDesc:
+    g = GridDesc()
+    for k in ("nx", "ny", "nz", "truncation_order", "space_charge", "solver", "n_sub",
+              "field_precision", "compensated", "und_type", "n_periods", "k_plane"):
+        setattr(g, k, int(d[k]))
+    for a in range(3):
+        g.tile[a] = int(d["tile"][a])
+    g.record_power = int(d.get("record_power", record_power))
+    g.max_particles = int(max_particles)
+    for k in ("dx", "dy", "dz", "x0", "y0", "z0", "gamma", "K", "lambda_u", "pol_angle_deg",
+              "z_entrance"):
+        setattr(g, k, float(d[k]))
+    return g
+
+
+def footprint_bytes(d: dict, n_particles: int) -> int:
+    g = make_desc(d, n_particles)
+    return int(lib().mithra_footprint_bytes(C.byref(g), int(n_particles)))
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Engine:
+    """One run on the current CUDA/HIP device (torch provides arena and stream)."""
+
+    def __init__(self, desc: dict, max_particles: int, device: str = "cuda:0",
+                 stream=None, arena=None):
+        import torch
+        self._L = lib()
+        self.desc = dict(desc)
+        self.shape = (int(desc["nz"]), int(desc["ny"]), int(desc["nx"]))
+        self._g = make_desc(desc, max_particles)
+        nbytes = int(self._L.mithra_footprint_bytes(C.byref(self._g), int(max_particles)))
+        if nbytes == 0:
+            raise MithraError(-1, "invalid descriptor (footprint 0)")
+        self.footprint = nbytes
+        self.device = torch.device(device)
+        if arena is None:
+            arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.arena = arena
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        rc = self._L.mithra_init_grid(C.byref(self._g), C.c_void_p(arena.data_ptr()),
+                                      C.c_size_t(arena.numel()), C.c_void_p(self.stream.cuda_stream),
+                                      C.byref(h))
+        self._h = h
+        if rc != 0:
+            msg = self.last_error()
+            self.close()
+            raise MithraError(rc, msg)
+
+    # -- lifecycle --
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._L.mithra_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return self._L.mithra_last_error(self._h).decode()
+
+    def _check(self, rc: int):
+        if rc != 0:
+            raise MithraError(rc, self.last_error())
+
+    # -- the six calls --
+    def load_bunch(self, xyz: np.ndarray, u: np.ndarray, q_macro: float):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        self._check(self._L.mithra_load_bunch(self._h, xyz.shape[0], _dp(xyz), _dp(u), float(q_macro)))
+        self.np = xyz.shape[0]
+
+    def step(self, n: int = 1):
+        self._check(self._L.mithra_step(self._h, int(n)))
+
+    def read_field(self, name: str, dtype=np.float64) -> np.ndarray:
+        dt = 1 if np.dtype(dtype) == np.float64 else 0
+        out = np.empty(self.shape, dtype=np.float64 if dt else np.float32)
+        self._check(self._L.mithra_read_fields(self._h, FIELD_IDS[name], dt,
+                                               out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+    def read_particles(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+        n = self.np
+        xyz = np.empty((n, 3))
+        u = np.empty((n, 3))
+        cell = np.empty(n, dtype=np.int32)
+        perm = np.empty(n, dtype=np.int32)
+        self._check(self._L.mithra_read_particles(self._h, _dp(xyz), _dp(u),
+                                                  cell.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                  perm.ctypes.data_as(C.POINTER(C.c_int32))))
+        return xyz, u, cell, perm
+
+    def radiated_power(self, k: Optional[int] = None) -> float:
+        k = int(self.desc["k_plane"]) if k is None else int(k)
+        out = C.c_double()
+        self._check(self._L.mithra_radiated_power(self._h, k, C.byref(out)))
+        return out.value
+
+    # -- extras --
+    def power_history(self, n: int) -> np.ndarray:
+        out = np.zeros(n)
+        m = self._L.mithra_power_history(self._h, _dp(out), n)
+        if m < 0:
+            self._check(int(m))
+        return out[:m]
+
+    def bunching(self) -> float:
+        out = C.c_double()
+        self._check(self._L.mithra_bunching(self._h, C.byref(out)))
+        return out.value
+
+    def constants(self) -> dict:
+        out = np.zeros(8)
+        self._check(self._L.mithra_constants(self._h, _dp(out)))
+        return dict(zip(["gamma0", "beta0", "dt", "dtb", "A", "q", "steps", "np"], out.tolist()))
+
+    def set_sweep_shape(self, shape: int):
+        self._check(self._L.mithra_set_sweep_shape(self._h, int(shape)))
+
+    @staticmethod
+    def sweep_shape_count() -> int:
+        return int(lib().mithra_sweep_shape_count())

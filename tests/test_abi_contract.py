@@ -1,0 +1,75 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol the header declares, sizes its arena exactly, and rejects bad
+descriptors before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2009_13645_amd import engine as E
+from paper_2009_13645_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    hdr = open(os.path.join(ROOT, "include", "mithra.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(mithra_[a-z_0-9]+)\s*\(", hdr)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = E.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 9
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def _desc(**kw):
+    d = W.config1().descriptor()
+    d.update(kw)
+    return d
+
+
+def test_footprint_is_exact_monotone_and_zero_for_invalid():
+    f1 = E.footprint_bytes(_desc(), 4096)
+    f2 = E.footprint_bytes(_desc(), 8192)
+    f3 = E.footprint_bytes(_desc(nx=40), 4096)
+    f32 = E.footprint_bytes(_desc(field_precision=32), 4096)
+    f32c = E.footprint_bytes(_desc(field_precision=32, compensated=1), 4096)
+    assert 0 < f1 < f2 and f1 < f3
+    assert f32 < f1 and f32 < f32c
+    nn = 32 * 32 * 64
+    # potentials (12 arrays), sources (8), vertex fields (6) at 8 bytes at least
+    assert f1 >= 26 * nn * 8
+    assert E.footprint_bytes(_desc(nx=3), 4096) == 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=5), dict(truncation_order=3), dict(space_charge=2), dict(solver=1), dict(n_sub=0),
+    dict(field_precision=16), dict(compensated=1, field_precision=64), dict(und_type=2),
+    dict(n_periods=0), dict(k_plane=0), dict(k_plane=63), dict(tile=(0, 8, 8)),
+    dict(tile=(8, 65, 8)), dict(dx=0.0), dict(gamma=1.0), dict(K=0.0), dict(lambda_u=-1.0),
+    dict(dz=1.0), dict(z_entrance=float("nan")),
+])
+def test_invalid_descriptors_are_rejected_without_device(bad):
+    g = E.make_desc(_desc(**bad), 4096)
+    h = C.c_void_p()
+    rc = E.lib().mithra_init_grid(C.byref(g), None, 0, None, C.byref(h))
+    assert rc == -1
+    msg = E.lib().mithra_last_error(h).decode()
+    assert len(msg) > 5
+    E.lib().mithra_destroy(h)
+
+
+def test_small_arena_is_enomem_and_null_handle_calls_fail():
+    g = E.make_desc(_desc(), 4096)
+    h = C.c_void_p()
+    rc = E.lib().mithra_init_grid(C.byref(g), None, 0, None, C.byref(h))
+    assert rc == -2
+    E.lib().mithra_destroy(h)
+    assert E.lib().mithra_step(None, 1) == -1
+    assert E.lib().mithra_destroy(None) == -1
+    assert E.lib().mithra_last_error(None) == b"null handle"
