@@ -158,6 +158,18 @@ int mithra_bunching(mithra_handle h, double *b);
  * q_macro, steps done, particles. */
 int mithra_constants(mithra_handle h, double *out8);
 
+/* Tuning calls.  The field sweep (NSFD update of A and phi) has several
+ * workgroup tile shapes (x columns, y rows, z planes per workgroup);
+ * `mithra_sweep_shape_count` gives their number, `mithra_set_sweep_shape`
+ * selects one for the handle (EINVAL out of range), and
+ * `mithra_time_sweep` times `iters` launches of the sweep for the current
+ * step with HIP events on the handle's stream (shape -1: the current one),
+ * writing the mean milliseconds to *ms.  Repeating the sweep leaves the
+ * run's state unchanged.  Errors: EINVAL, ESTATE, EDEVICE. */
+int mithra_sweep_shape_count(void);
+int mithra_set_sweep_shape(mithra_handle h, int shape);
+int mithra_time_sweep(mithra_handle h, int shape, int iters, double *ms);
+
 /* Message of the last error on this handle (never NULL). */
 const char *mithra_last_error(mithra_handle h);
 

@@ -31,7 +31,7 @@ hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *ou
 hipError_t launch_push_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_load_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st);
-hipError_t launch_sort(const RunDev &R, hipStream_t st);
+hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready);
 int sort_passes(uint32_t key_inactive);
 int64_t sort_blocks(int64_t n);
 
@@ -76,8 +76,8 @@ static const int64_t kPowerCap = 1 << 16;
 static const int kBunchBlocks = 256;
 
 struct Layout {
-    size_t ctl, pot, src, src_lo, eb, pr, pid, key_by_id, slot_of_id, cell_by_id, key_sorted, sk, sv, hist, power,
-        scratch, total;
+    size_t ctl, pot, src, src_lo, eb, pr, pid, key_by_id, slot_of_id, cell_by_id, key_sorted, sk, sv, hist, boxpart,
+        cellpart, ppart, power, scratch, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -107,7 +107,10 @@ static Layout make_layout(const mithra_grid_desc *d, int64_t cap)
     L.key_sorted = take(c * 4);
     L.sk = take(2 * c * 4);
     L.sv = take(2 * c * 4);
-    L.hist = take(256 * (size_t)sort_blocks((int64_t)c) * 4);
+    L.hist = take((256 * (size_t)sort_blocks((int64_t)c) + 256) * 4);
+    L.boxpart = take(8 * 4 * (size_t)((c + 255) / 256));
+    L.cellpart = take(8 * 4 * (size_t)((c + 255) / 256));
+    L.ppart = take(256 * 8);
     L.power = take((size_t)kPowerCap * 8);
     L.scratch = take((size_t)(3 * kBunchBlocks + 8) * 8);
     L.total = off;
@@ -337,6 +340,9 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.sv[0] = (int32_t *)(A + L.sv);
     R.sv[1] = R.sv[0] + c;
     R.hist = (uint32_t *)(A + L.hist);
+    R.boxpart = (int32_t *)(A + L.boxpart);
+    R.cellpart = (int32_t *)(A + L.cellpart);
+    R.ppart = (double *)(A + L.ppart);
     R.sort_blocks = sort_blocks((int64_t)c);
     R.power_hist = (double *)(A + L.power);
     R.power_cap = kPowerCap;
@@ -365,8 +371,13 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     }
     HIPCHK(h, hipMemcpyAsync(R.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    // default sweep tile: wide rows for large planes, narrower for small ones
-    h->sweep_shape = (d->nx - 2 <= 40) ? 2 : 0;
+    // default sweep tile: vector tiles about as wide as the rows when the
+    // row length allows 16-byte vectors, else the scalar tiles
+    const int vec = d->field_precision == 32 ? 4 : 2;
+    if (d->nx % vec == 0)
+        h->sweep_shape = d->nx <= 48 ? 13 : (d->nx <= 80 ? 10 : 8);
+    else
+        h->sweep_shape = (d->nx - 2 <= 40) ? 2 : 0;
     const char *sh = getenv("MITHRA_SWEEP_SHAPE");
     if (sh)
         h->sweep_shape = atoi(sh) % sweep_shape_count();
@@ -407,13 +418,14 @@ extern "C" int mithra_load_bunch(mithra_handle h, int64_t n, const double *xyz, 
     R.np = n;
     R.q = q_macro;
     R.qV = q_macro / (h->d.dx * h->d.dy * h->d.dz);
-    HIPCHK(h, launch_load_deposit(R, h->stream));
+    // sort first so that the first deposit runs in cell order
     hipLaunchKernelGGL(k_book_load, dim3(1), dim3(1), 0, h->stream, R.ctl);
     int rc = enqueue_sort_with_cells(h);
     if (rc)
         return rc;
     hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, h->stream, R.ctl, 0);
     HIPCHK(h, hipGetLastError());
+    HIPCHK(h, launch_load_deposit(R, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->loaded = true;
     return MITHRA_OK;
@@ -441,7 +453,7 @@ __global__ void k_cells_by_id(RunDev R, int32_t *cell_by_id)
 
 static int enqueue_sort_with_cells(mithra_handle h)
 {
-    HIPCHK(h, launch_sort(h->R, h->stream));
+    HIPCHK(h, launch_sort(h->R, h->stream, false));
     return MITHRA_OK;
 }
 
@@ -454,7 +466,7 @@ static int enqueue_step(mithra_handle h)
     HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
     hipLaunchKernelGGL(k_book_mid, dim3(1), dim3(1), 0, st, R.ctl);
     HIPCHK(h, launch_push_deposit(R, st));
-    HIPCHK(h, launch_sort(R, st));
+    HIPCHK(h, launch_sort(R, st, true));
     if (R.record_power)
         HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st));
     hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);
@@ -718,3 +730,30 @@ extern "C" int mithra_set_sweep_shape(mithra_handle h, int shape)
 }
 
 extern "C" int mithra_sweep_shape_count(void) { return sweep_shape_count(); }
+
+// Time the field sweep alone: `iters` launches for the current step (the
+// sweep only rewrites the next time level and re-clears the stale source
+// set, so repeating it leaves the run's state unchanged).
+extern "C" int mithra_time_sweep(mithra_handle h, int shape, int iters, double *ms)
+{
+    if (!h || !ms || iters < 1 || shape < -1 || shape >= sweep_shape_count())
+        return MITHRA_EINVAL;
+    if (!h->loaded)
+        return fail(h, MITHRA_ESTATE, "no bunch loaded");
+    const int sh = shape < 0 ? h->sweep_shape : shape;
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    HIPCHK(h, launch_sweep(h->R, sh, h->stream));  // warm
+    HIPCHK(h, hipEventRecord(e0, h->stream));
+    for (int i = 0; i < iters; ++i)
+        HIPCHK(h, launch_sweep(h->R, sh, h->stream));
+    HIPCHK(h, hipEventRecord(e1, h->stream));
+    HIPCHK(h, hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = (double)t / iters;
+    return MITHRA_OK;
+}

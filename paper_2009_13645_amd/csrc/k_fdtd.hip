@@ -52,8 +52,11 @@ __global__ __launch_bounds__(TX *TY) void k_sweep(RunDev R)
 {
     __shared__ T sb[2][TY + 2][TX + 2];
 
-    const int ntx = (R.nx - 2 + TX - 1) / TX;
-    const int nty = (R.ny - 2 + TY - 1) / TY;
+    // tiles start at node 0 so that every row load is 128-byte aligned; the
+    // boundary columns load (they are the neighbours of the first interior
+    // column) but are not updated
+    const int ntx = (R.nx + TX - 1) / TX;
+    const int nty = (R.ny + TY - 1) / TY;
     const int nch = (R.nz - 2 + TZ - 1) / TZ;
     int64_t lb = xcd_swizzle(blockIdx.x, gridDim.x);
     const int tile_x = (int)(lb % ntx);
@@ -68,10 +71,10 @@ __global__ __launch_bounds__(TX *TY) void k_sweep(RunDev R)
     const bool update = (comp < 3) || R.space_charge;
 
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int i = 1 + tile_x * TX + lx;
-    const int j = 1 + tile_y * TY + ly;
+    const int i = tile_x * TX + lx;
+    const int j = tile_y * TY + ly;
     const bool inb = (i < R.nx) && (j < R.ny);
-    const bool valid = (i <= R.nx - 2) && (j <= R.ny - 2);
+    const bool valid = (i >= 1) && (j >= 1) && (i <= R.nx - 2) && (j <= R.ny - 2);
     const int ic = min(i, R.nx - 1), jc = min(j, R.ny - 1);
     const int64_t plane = (int64_t)R.nx * R.ny;
     const int64_t col = (int64_t)jc * R.nx + ic;
@@ -91,8 +94,8 @@ __global__ __launch_bounds__(TX *TY) void k_sweep(RunDev R)
         } else {
             hy = TY; hx = h - 2 * TY - TX;
         }
-        hi_ = 1 + tile_x * TX + hx;
-        hj_ = 1 + tile_y * TY + hy;
+        hi_ = tile_x * TX + hx;
+        hj_ = tile_y * TY + hy;
         hval = (hi_ >= 0) && (hi_ < R.nx) && (hj_ >= 0) && (hj_ < R.ny);
     }
     const int64_t hcol = hval ? ((int64_t)hj_ * R.nx + hi_) : 0;
@@ -168,6 +171,229 @@ __global__ __launch_bounds__(TX *TY) void k_sweep(RunDev R)
         hqm = hq0;
         hq0 = hqp;
         hqp = hpf;
+    }
+}
+
+// Vectorised sweep: each thread owns V consecutive x-nodes (16-byte loads
+// and stores), a tile is TXV*V nodes wide and TY rows high.  psi-bar of the
+// tile plus a one-node halo ring goes through a double-buffered LDS plane
+// whose interior starts on a 16-byte boundary; a thread reads its two outer
+// x-neighbours and its y-neighbour vectors from LDS.  Needs nx % V == 0 so
+// that every row starts aligned.
+template <typename T, int V>
+struct Vec {
+    T v[V];
+};
+
+template <typename T, int V>
+__device__ inline Vec<T, V> vload(const T *p)
+{
+    Vec<T, V> r;
+    if constexpr (sizeof(T) * V == 16) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(p);
+        memcpy(&r, &x, 16);
+    } else {
+        for (int e = 0; e < V; ++e)
+            r.v[e] = p[e];
+    }
+    return r;
+}
+
+template <typename T, int V>
+__device__ inline void vstore(T *p, const Vec<T, V> &a)
+{
+    if constexpr (sizeof(T) * V == 16) {
+        uint4 x;
+        memcpy(&x, &a, 16);
+        *reinterpret_cast<uint4 *>(p) = x;
+    } else {
+        for (int e = 0; e < V; ++e)
+            p[e] = a.v[e];
+    }
+}
+
+template <typename T, int V, int TXV, int TY, int TZ>
+__global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
+{
+    constexpr int TW = TXV * V;                          // tile width in nodes
+    constexpr int ROW = ((V + TW + 1) + V - 1) / V * V;  // LDS row: pad(V-1), left halo, tile, right halo
+    __shared__ __attribute__((aligned(16))) T sb[2][TY + 2][ROW];
+
+    const int ntx = (R.nx + TW - 1) / TW;
+    const int nty = (R.ny + TY - 1) / TY;
+    const int nch = (R.nz - 2 + TZ - 1) / TZ;
+    int64_t lb = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int tile_x = (int)(lb % ntx);
+    lb /= ntx;
+    const int tile_y = (int)(lb % nty);
+    lb /= nty;
+    const int chunk = (int)(lb % nch);
+    const int comp = (int)(lb / nch);
+
+    const int64_t s = R.ctl->step;
+    const int set_r = (int)(s & 1), set_c = (int)((s + 1) & 1);
+    const bool update = (comp < 3) || R.space_charge;
+
+    const int lx = threadIdx.x % TXV, ly = threadIdx.x / TXV;
+    const int i0 = tile_x * TW + lx * V;  // first node of this thread
+    const int j = tile_y * TY + ly;
+    const bool inb = (i0 < R.nx) && (j < R.ny);
+    const bool rowvalid = inb && j >= 1 && j <= R.ny - 2;
+    const int64_t plane = (int64_t)R.nx * R.ny;
+    const int64_t col = inb ? ((int64_t)j * R.nx + i0) : 0;
+
+    // halo: bottom/top rows (vector, TXV threads each), left/right columns
+    // (scalar, TY threads each)
+    const int t = threadIdx.x;
+    int hrole = -1, hx = 0, hy = 0;
+    int64_t hcol = 0;
+    bool hval = false;
+    if (t < 2 * TXV) {
+        hrole = 0;
+        hx = (t % TXV) * V;
+        hy = t < TXV ? -1 : TY;
+        const int hi_ = tile_x * TW + hx, hj_ = tile_y * TY + hy;
+        hval = hj_ >= 0 && hj_ < R.ny && hi_ < R.nx;
+        hcol = hval ? (int64_t)hj_ * R.nx + hi_ : 0;
+    } else if (t < 2 * TXV + 2 * TY) {
+        hrole = 1;
+        const int u = t - 2 * TXV;
+        hy = u % TY;
+        hx = u < TY ? -1 : TW;
+        const int hi_ = tile_x * TW + hx, hj_ = tile_y * TY + hy;
+        hval = hi_ >= 0 && hi_ < R.nx && hj_ < R.ny;
+        hcol = hval ? (int64_t)hj_ * R.nx + hi_ : 0;
+    }
+
+    const int kb = 1 + chunk * TZ;
+    const int ke = min(kb + TZ, R.nz - 1);
+    const T *cur = pot_ptr<T>(R, slot_cur(s), comp);
+    const T *prev = pot_ptr<T>(R, slot_prev(s), comp);
+    T *next = pot_ptr<T>(R, slot_next(s), comp);
+
+    const int *rlo = R.ctl->dep_lo[set_r];
+    const int *rhi = R.ctl->dep_hi[set_r];
+    const int *clo = R.ctl->dep_lo[set_c];
+    const int *chi = R.ctl->dep_hi[set_c];
+    const bool src_col = rowvalid && i0 + V - 1 >= rlo[0] && i0 <= rhi[0] + 1 && j >= rlo[1] && j <= rhi[1] + 1;
+    const bool clr_col = rowvalid && i0 + V - 1 >= clo[0] && i0 <= chi[0] && j >= clo[1] && j <= chi[1];
+    const T *J = src_ptr<T>(R, set_r, comp);
+    const T *Jl = R.compensated ? srclo_ptr<T>(R, set_r, comp) : nullptr;
+    T *clr = src_ptr<T>(R, set_c, comp);
+    T *clr_lo = R.compensated ? srclo_ptr<T>(R, set_c, comp) : nullptr;
+    const double sfac = comp < 3 ? 0.5 * R.sfac_A : R.sfac_phi;
+
+    const T cA = (T)R.A, c1A = (T)(1.0 - 2.0 * R.A);
+    const T a1 = (T)R.a1, a2 = (T)R.a2, a4 = (T)R.a4, a6 = (T)R.a6;
+
+    Vec<T, V> qm{}, q0{}, qp{}, hm{}, h0{}, hp{};
+    if (inb) {
+        qm = vload<T, V>(cur + (int64_t)(kb - 1) * plane + col);
+        q0 = vload<T, V>(cur + (int64_t)kb * plane + col);
+        qp = vload<T, V>(cur + (int64_t)(kb + 1) * plane + col);
+    }
+    if (hval) {
+        if (hrole == 0) {
+            hm = vload<T, V>(cur + (int64_t)(kb - 1) * plane + hcol);
+            h0 = vload<T, V>(cur + (int64_t)kb * plane + hcol);
+            hp = vload<T, V>(cur + (int64_t)(kb + 1) * plane + hcol);
+        } else {
+            hm.v[0] = cur[(int64_t)(kb - 1) * plane + hcol];
+            h0.v[0] = cur[(int64_t)kb * plane + hcol];
+            hp.v[0] = cur[(int64_t)(kb + 1) * plane + hcol];
+        }
+    }
+
+    for (int k = kb; k < ke; ++k) {
+        const int64_t c = (int64_t)k * plane + col;
+        Vec<T, V> pf{}, hpf{};
+        if (k + 1 < ke) {
+            if (inb)
+                pf = vload<T, V>(cur + c + 2 * plane);
+            if (hval) {
+                if (hrole == 0)
+                    hpf = vload<T, V>(cur + (int64_t)(k + 2) * plane + hcol);
+                else
+                    hpf.v[0] = cur[(int64_t)(k + 2) * plane + hcol];
+            }
+        }
+        Vec<T, V> pm{};
+        double sv[V];
+        for (int e = 0; e < V; ++e)
+            sv[e] = 0.0;
+        if (rowvalid && update) {
+            pm = vload<T, V>(prev + c);
+            if (src_col && k >= rlo[2] && k <= rhi[2] + 1) {
+                const Vec<T, V> a = vload<T, V>(J + c);
+                Vec<T, V> al{};
+                if (Jl)
+                    al = vload<T, V>(Jl + c);
+                if (comp == 3) {
+                    for (int e = 0; e < V; ++e)
+                        sv[e] = (double)a.v[e] + (double)al.v[e];
+                } else if (comp == 0) {
+                    double left = (double)J[c - 1] + (Jl ? (double)Jl[c - 1] : 0.0);
+                    for (int e = 0; e < V; ++e) {
+                        const double own = (double)a.v[e] + (double)al.v[e];
+                        sv[e] = own + left;
+                        left = own;
+                    }
+                } else {
+                    const int64_t back = comp == 1 ? R.nx : plane;
+                    const Vec<T, V> b = vload<T, V>(J + c - back);
+                    Vec<T, V> bl{};
+                    if (Jl)
+                        bl = vload<T, V>(Jl + c - back);
+                    for (int e = 0; e < V; ++e)
+                        sv[e] = (double)a.v[e] + (double)al.v[e] + (double)b.v[e] + (double)bl.v[e];
+                }
+            }
+        }
+        if (clr_col && k >= clo[2] && k <= chi[2]) {
+            const Vec<T, V> z{};
+            vstore<T, V>(clr + c, z);
+            if (clr_lo)
+                vstore<T, V>(clr_lo + c, z);
+        }
+        T(*buf)[ROW] = sb[k & 1];
+        Vec<T, V> bar;
+        for (int e = 0; e < V; ++e)
+            bar.v[e] = cA * (qm.v[e] + qp.v[e]) + c1A * q0.v[e];
+        vstore<T, V>(&buf[ly + 1][V + lx * V], bar);
+        if (hrole == 0) {
+            Vec<T, V> hb;
+            for (int e = 0; e < V; ++e)
+                hb.v[e] = cA * (hm.v[e] + hp.v[e]) + c1A * h0.v[e];
+            vstore<T, V>(&buf[hy + 1][V + hx], hb);
+        } else if (hrole == 1) {
+            buf[hy + 1][V + hx] = cA * (hm.v[0] + hp.v[0]) + c1A * h0.v[0];
+        }
+        __syncthreads();
+        if (rowvalid && update) {
+            const T left = buf[ly + 1][V + lx * V - 1];
+            const T right = buf[ly + 1][V + lx * V + V];
+            const Vec<T, V> dn = vload<T, V>(&buf[ly][V + lx * V]);
+            const Vec<T, V> up = vload<T, V>(&buf[ly + 2][V + lx * V]);
+            Vec<T, V> out;
+            for (int e = 0; e < V; ++e) {
+                const T xl = e == 0 ? left : bar.v[e - 1];
+                const T xr = e == V - 1 ? right : bar.v[e + 1];
+                out.v[e] = a1 * q0.v[e] + a2 * (xl + xr) + a4 * (dn.v[e] + up.v[e]) + a6 * (qp.v[e] + qm.v[e]) -
+                           pm.v[e] + (T)(sfac * sv[e]);
+            }
+            // the boundary columns of the row keep their (Mur) values
+            if (i0 == 0)
+                out.v[0] = next[c];
+            if (i0 + V == R.nx)
+                out.v[V - 1] = next[c + V - 1];
+            vstore<T, V>(next + c, out);
+        }
+        qm = q0;
+        q0 = qp;
+        qp = pf;
+        hm = h0;
+        h0 = hp;
+        hp = hpf;
     }
 }
 
@@ -428,16 +654,20 @@ __global__ __launch_bounds__(256) void k_vertex_fields(RunDev R, int step_bias, 
 }
 
 // Radiated power through node plane k_plane of the fields at t_{s+1/2}
-// (lab-frame Poynting flux), one block: deterministic reduction order.
+// (lab-frame Poynting flux).  kPowerBlocks blocks write partial sums over
+// a fixed node partition; one block adds them in fixed order, so the
+// result does not depend on scheduling.
+constexpr int kPowerBlocks = 64;
+
 template <typename T>
-__global__ __launch_bounds__(1024) void k_plane_power(RunDev R, int step_bias, int kp, double *out)
+__global__ __launch_bounds__(256) void k_plane_power(RunDev R, int step_bias, int kp)
 {
-    __shared__ double red[1024];
+    __shared__ double red[256];
     const int64_t s = R.ctl->step + step_bias;
     const double g0 = R.gamma0, b0 = R.beta0;
     double acc = 0.0;
     const int wx = R.nx - 2, wy = R.ny - 2;
-    for (int t = threadIdx.x; t < wx * wy; t += blockDim.x) {
+    for (int t = blockIdx.x * 256 + threadIdx.x; t < wx * wy; t += kPowerBlocks * 256) {
         const int i = 1 + t % wx, j = 1 + t / wx;
         double E[3], B[3];
         vertex_eb<T>(R, s, i, j, kp, E, B);
@@ -449,22 +679,29 @@ __global__ __launch_bounds__(1024) void k_plane_power(RunDev R, int step_bias, i
     }
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
             red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double mu0 = 1.0 / (kEps0 * kC * kC);
-        const double P = red[0] * R.dx * R.dy / mu0;
-        if (out) {
-            *out = P;
-        } else if (s >= 0 && s < R.power_cap) {
-            R.power_hist[s] = P;
-        }
-        if (!isfinite(P))
-            R.ctl->nan_flag = 1;
-    }
+    if (threadIdx.x == 0)
+        R.ppart[blockIdx.x] = red[0];
+}
+
+__global__ void k_plane_power_final(RunDev R, int step_bias, double *out)
+{
+    const int64_t s = R.ctl->step + step_bias;
+    double sum = 0.0;
+    for (int b = 0; b < kPowerBlocks; ++b)
+        sum += R.ppart[b];
+    const double mu0 = 1.0 / (kEps0 * kC * kC);
+    const double P = sum * R.dx * R.dy / mu0;
+    if (out)
+        *out = P;
+    else if (s >= 0 && s < R.power_cap)
+        R.power_hist[s] = P;
+    if (!isfinite(P))
+        R.ctl->nan_flag = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -478,17 +715,37 @@ struct SweepShape {
 template <typename T, int TX, int TY, int TZ>
 static hipError_t launch_sweep_t(const RunDev &R, hipStream_t st)
 {
-    const int64_t ntx = (R.nx - 2 + TX - 1) / TX, nty = (R.ny - 2 + TY - 1) / TY;
+    const int64_t ntx = (R.nx + TX - 1) / TX, nty = (R.ny + TY - 1) / TY;
     const int64_t nch = (R.nz - 2 + TZ - 1) / TZ;
     const int64_t nb = ntx * nty * nch * 4;
     hipLaunchKernelGGL((k_sweep<T, TX, TY, TZ>), dim3((unsigned)nb), dim3(TX * TY), 0, st, R);
     return hipGetLastError();
 }
 
+template <typename T, int V, int TXV, int TY, int TZ>
+static hipError_t launch_sweep_vec_t(const RunDev &R, hipStream_t st)
+{
+    constexpr int TW = TXV * V;
+    const int64_t ntx = (R.nx + TW - 1) / TW, nty = (R.ny + TY - 1) / TY;
+    const int64_t nch = (R.nz - 2 + TZ - 1) / TZ;
+    const int64_t nb = ntx * nty * nch * 4;
+    hipLaunchKernelGGL((k_sweep_vec<T, V, TXV, TY, TZ>), dim3((unsigned)nb), dim3(TXV * TY), 0, st, R);
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t launch_sweep_shape(const RunDev &R, int shape, hipStream_t st)
 {
+    constexpr int V = 16 / sizeof(T);
+    if (shape >= 8 && R.nx % V != 0)
+        shape = 0;  // vector tiles need aligned rows
     switch (shape) {
+    case 8: return launch_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 32>(R, st);
+    case 9: return launch_sweep_vec_t<T, V, 128 / V, 256 * V / 128, 32>(R, st);
+    case 10: return launch_sweep_vec_t<T, V, 64 / V, 512 * V / 64, 32>(R, st);
+    case 11: return launch_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 16>(R, st);
+    case 12: return launch_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 64>(R, st);
+    case 13: return launch_sweep_vec_t<T, V, 32 / V, 256 * V / 32, 32>(R, st);
     case 0: return launch_sweep_t<T, 64, 8, 32>(R, st);
     case 1: return launch_sweep_t<T, 64, 4, 32>(R, st);
     case 2: return launch_sweep_t<T, 32, 8, 32>(R, st);
@@ -501,12 +758,15 @@ static hipError_t launch_sweep_shape(const RunDev &R, int shape, hipStream_t st)
     }
 }
 
-int sweep_shape_count() { return 8; }
+int sweep_shape_count() { return 14; }
 
+// Tile of each shape in nodes (x, y, z) for FP32; shapes 8..13 are the
+// vector kernels (4 FP32 or 2 FP64 nodes per thread; y rows halve in FP64).
 void sweep_shape_dims(int shape, int *tx, int *ty, int *tz)
 {
-    static const int d[8][3] = {{64, 8, 32}, {64, 4, 32}, {32, 8, 32}, {64, 8, 64},
-                                {128, 4, 32}, {64, 16, 32}, {32, 4, 16}, {64, 8, 16}};
+    static const int d[14][3] = {{64, 8, 32},  {64, 4, 32},  {32, 8, 32},  {64, 8, 64},  {128, 4, 32},
+                                 {64, 16, 32}, {32, 4, 16},  {64, 8, 16},  {128, 16, 32}, {128, 8, 32},
+                                 {64, 32, 32}, {128, 16, 16}, {128, 16, 64}, {32, 32, 32}};
     *tx = d[shape][0];
     *ty = d[shape][1];
     *tz = d[shape][2];
@@ -547,9 +807,10 @@ hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStr
 hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st)
 {
     if (R.precision == 32)
-        hipLaunchKernelGGL(k_plane_power<float>, dim3(1), dim3(1024), 0, st, R, step_bias, kp, out);
+        hipLaunchKernelGGL(k_plane_power<float>, dim3(kPowerBlocks), dim3(256), 0, st, R, step_bias, kp);
     else
-        hipLaunchKernelGGL(k_plane_power<double>, dim3(1), dim3(1024), 0, st, R, step_bias, kp, out);
+        hipLaunchKernelGGL(k_plane_power<double>, dim3(kPowerBlocks), dim3(256), 0, st, R, step_bias, kp);
+    hipLaunchKernelGGL(k_plane_power_final, dim3(1), dim3(1), 0, st, R, step_bias, out);
     return hipGetLastError();
 }
 

@@ -106,60 +106,123 @@ __device__ inline bool cell_of(const RunDev &R, const double r[3], double g[3], 
 
 // --- accumulation --------------------------------------------------------
 
-__device__ inline void acc_add(double *p, double *, double v) { atomicAdd(p, v); }
-
-template <bool COMP>
-__device__ inline void acc_add(float *p, float *lo, double v)
-{
-    const float vf = (float)v;
-    const float old = atomicAdd(p, vf);
-    if (COMP) {
-        // exact error of old + vf (two-sum) plus the rounding of v to float
-        const float sm = old + vf;
-        const float bv = sm - old;
-        const float err = (old - (sm - bv)) + (vf - bv);
-        atomicAdd(lo, err + (float)(v - (double)vf));
-    }
-}
-
+// Global accumulation into source set `set` (J_x J_y J_z rho).  FP64: plain
+// atomic add.  FP32: atomic add of the rounded value; with compensation the
+// exact error of that addition (two-sum on the returned old value) plus the
+// rounding of the FP64 value goes into the second array by another atomic.
 template <typename T, bool COMP>
-struct Acc {
-    T *J[3];
-    T *Jlo[3];
-    T *Q;
-    T *Qlo;
-    __device__ inline void add(int comp, int64_t idx, double v) const
+struct GlobalAcc {
+    T *A[4];
+    T *Lo[4];
+    int nx;
+    int64_t nxy;
+    // four independent adds (zeros skipped); in the compensated mode all the
+    // returning adds are issued before their errors are added
+    __device__ inline void add4(const double v[4], const int idx[4][4]) const
     {
+        int64_t at[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            at[q] = (int64_t)idx[q][3] * nxy + (int64_t)idx[q][2] * nx + idx[q][1];
         if constexpr (sizeof(T) == 8) {
-            (void)COMP;
-            atomicAdd(reinterpret_cast<double *>(comp < 3 ? J[comp] : Q) + idx, v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (v[q] != 0.0)
+                    atomicAdd(reinterpret_cast<double *>(A[idx[q][0]]) + at[q], v[q]);
+        } else if (!COMP) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (v[q] != 0.0)
+                    atomicAdd(reinterpret_cast<float *>(A[idx[q][0]]) + at[q], (float)v[q]);
         } else {
-            acc_add<COMP>(reinterpret_cast<float *>(comp < 3 ? J[comp] : Q) + idx,
-                          COMP ? reinterpret_cast<float *>(comp < 3 ? Jlo[comp] : Qlo) + idx : nullptr, v);
+            float vf[4], old[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                vf[q] = (float)v[q];
+                old[q] = 0.0f;
+                if (v[q] != 0.0)
+                    old[q] = atomicAdd(reinterpret_cast<float *>(A[idx[q][0]]) + at[q], vf[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (v[q] != 0.0) {
+                    const float sm = old[q] + vf[q];
+                    const float bv = sm - old[q];
+                    const float err = (old[q] - (sm - bv)) + (vf[q] - bv);
+                    atomicAdd(reinterpret_cast<float *>(Lo[idx[q][0]]) + at[q], err + (float)(v[q] - (double)vf[q]));
+                }
+            }
+        }
+    }
+    __device__ inline void add(int comp, int i, int j, int k, double v) const
+    {
+        const int64_t idx = (int64_t)k * nxy + (int64_t)j * nx + i;
+        if constexpr (sizeof(T) == 8) {
+            atomicAdd(reinterpret_cast<double *>(A[comp]) + idx, v);
+        } else {
+            const float vf = (float)v;
+            const float old = atomicAdd(reinterpret_cast<float *>(A[comp]) + idx, vf);
+            if (COMP) {
+                const float sm = old + vf;
+                const float bv = sm - old;
+                const float err = (old - (sm - bv)) + (vf - bv);
+                atomicAdd(reinterpret_cast<float *>(Lo[comp]) + idx, err + (float)(v - (double)vf));
+            }
         }
     }
 };
 
 template <typename T, bool COMP>
-__device__ inline Acc<T, COMP> make_acc(const RunDev &R, int set)
+__device__ inline GlobalAcc<T, COMP> make_gacc(const RunDev &R, int set)
 {
-    Acc<T, COMP> a;
-    for (int c = 0; c < 3; ++c) {
-        a.J[c] = src_ptr<T>(R, set, c);
-        a.Jlo[c] = COMP ? srclo_ptr<T>(R, set, c) : nullptr;
+    GlobalAcc<T, COMP> a;
+    for (int c = 0; c < 4; ++c) {
+        a.A[c] = src_ptr<T>(R, set, c);
+        a.Lo[c] = COMP ? srclo_ptr<T>(R, set, c) : nullptr;
     }
-    a.Q = src_ptr<T>(R, set, 3);
-    a.Qlo = COMP ? srclo_ptr<T>(R, set, 3) : nullptr;
+    a.nx = R.nx;
+    a.nxy = (int64_t)R.nx * R.ny;
     return a;
 }
 
-// current of the straight segment a -> b (grid units) inside cell c
-template <typename T, bool COMP>
-__device__ inline void segment_current(const RunDev &R, const Acc<T, COMP> &acc, const double a[3],
-                                       const double b[3], const int c[3])
+// Block-local accumulation in LDS (FP64) over the block's node box.
+struct LdsAcc {
+    double *s;
+    int lo0, lo1, lo2, ex, ey, vol;
+    __device__ inline void add(int comp, int i, int j, int k, double v) const
+    {
+        atomicAdd(&s[comp * vol + ((k - lo2) * ey + (j - lo1)) * ex + (i - lo0)], v);
+    }
+};
+
+// the 12 edge currents of the straight segment a -> b (grid units) inside
+// cell c, ordered per component l as (0,0), (+m1), (+m1+m2), (+m2)
+__device__ inline void segment_weights(const RunDev &R, const double a[3], const double b[3], const int c[3],
+                                       double w[12])
 {
-    const int64_t stride[3] = {1, R.nx, (int64_t)R.nx * R.ny};
-    const int64_t base = nid(R, c[0], c[1], c[2]);
+    double d[3], W[3];
+    for (int l = 0; l < 3; ++l) {
+        d[l] = b[l] - a[l];
+        W[l] = 0.5 * (a[l] + b[l]) - (double)c[l];
+    }
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
+        const double F = R.qV * d[l] * R.h[l] / R.dt;
+        const double x = d[m1] * d[m2] * (1.0 / 12.0);
+        const double u1 = W[m1], u2 = W[m2];
+        w[4 * l] = F * ((1.0 - u1) * (1.0 - u2) + x);
+        w[4 * l + 1] = F * (u1 * (1.0 - u2) - x);
+        w[4 * l + 2] = F * (u1 * u2 + x);
+        w[4 * l + 3] = F * ((1.0 - u1) * u2 - x);
+    }
+}
+
+// current of the straight segment a -> b (grid units) inside cell c
+template <class Acc>
+__device__ inline void segment_current(const RunDev &R, const Acc &acc, const double a[3], const double b[3],
+                                       const int c[3])
+{
     double d[3], W[3];
     for (int l = 0; l < 3; ++l) {
         d[l] = b[l] - a[l];
@@ -172,39 +235,57 @@ __device__ inline void segment_current(const RunDev &R, const Acc<T, COMP> &acc,
         const double F = R.qV * d[l] * R.h[l] / R.dt;
         const double x = d[m1] * d[m2] * (1.0 / 12.0);
         const double u1 = W[m1], u2 = W[m2];
-        acc.add(l, base, F * ((1.0 - u1) * (1.0 - u2) + x));
-        acc.add(l, base + stride[m1], F * (u1 * (1.0 - u2) - x));
-        acc.add(l, base + stride[m2], F * ((1.0 - u1) * u2 - x));
-        acc.add(l, base + stride[m1] + stride[m2], F * (u1 * u2 + x));
+        int q[3] = {c[0], c[1], c[2]};
+        acc.add(l, q[0], q[1], q[2], F * ((1.0 - u1) * (1.0 - u2) + x));
+        q[m1] += 1;
+        acc.add(l, q[0], q[1], q[2], F * (u1 * (1.0 - u2) - x));
+        q[m2] += 1;
+        acc.add(l, q[0], q[1], q[2], F * (u1 * u2 + x));
+        q[m1] -= 1;
+        acc.add(l, q[0], q[1], q[2], F * ((1.0 - u1) * u2 - x));
     }
 }
 
-struct Box {
-    int lo[3], hi[3];
-};
-
-template <typename T, bool COMP>
-__device__ inline void deposit_move(const RunDev &R, const Acc<T, COMP> &acc, const double g1[3], const int c1[3],
-                                    const double g2[3], const int c2[3], Box &bx)
+template <class Acc>
+__device__ inline void deposit_move(const RunDev &R, const Acc &acc, const double g1[3], const int c1[3],
+                                    const double g2[3], const int c2[3])
 {
+    // Same cell before and after: both zigzag halves (relay at the midpoint)
+    // deposit onto the same 12 edges; their values are formed exactly as for
+    // two segments and summed in registers, so one set of 12 adds is issued.
+    if (c1[0] == c2[0] && c1[1] == c2[1] && c1[2] == c2[2]) {
+        double gm[3], w1[12], w2[12];
+        for (int l = 0; l < 3; ++l)
+            gm[l] = fmin((double)c1[l] + 1.0, fmax((double)c1[l], 0.5 * (g1[l] + g2[l])));
+        segment_weights(R, g1, gm, c1, w1);
+        segment_weights(R, gm, g2, c1, w2);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
+            int q[3] = {c1[0], c1[1], c1[2]};
+            acc.add(l, q[0], q[1], q[2], w1[4 * l] + w2[4 * l]);
+            q[m1] += 1;
+            acc.add(l, q[0], q[1], q[2], w1[4 * l + 1] + w2[4 * l + 1]);
+            q[m2] += 1;
+            acc.add(l, q[0], q[1], q[2], w1[4 * l + 2] + w2[4 * l + 2]);
+            q[m1] -= 1;
+            acc.add(l, q[0], q[1], q[2], w1[4 * l + 3] + w2[4 * l + 3]);
+        }
+        return;
+    }
     double gr[3];
     for (int l = 0; l < 3; ++l) {
         const double lo = (double)min(c1[l], c2[l]) + 1.0;
         const double hi = (double)max(c1[l], c2[l]);
         gr[l] = fmin(lo, fmax(hi, 0.5 * (g1[l] + g2[l])));
-        bx.lo[l] = min(bx.lo[l], min(c1[l], c2[l]));
-        bx.hi[l] = max(bx.hi[l], max(c1[l], c2[l]) + 1);
     }
-    segment_current<T, COMP>(R, acc, g1, gr, c1);
-    segment_current<T, COMP>(R, acc, gr, g2, c2);
+    segment_current(R, acc, g1, gr, c1);
+    segment_current(R, acc, gr, g2, c2);
 }
 
-template <typename T, bool COMP>
-__device__ inline void deposit_charge(const RunDev &R, const Acc<T, COMP> &acc, const double g[3], const int c[3],
-                                      Box &bx)
+template <class Acc>
+__device__ inline void deposit_charge(const RunDev &R, const Acc &acc, const double g[3], const int c[3])
 {
-    const int64_t base = nid(R, c[0], c[1], c[2]);
-    const int64_t sy = R.nx, sz = (int64_t)R.nx * R.ny;
     const double dx = g[0] - c[0], dy = g[1] - c[1], dz = g[2] - c[2];
     const double wx[2] = {1.0 - dx, dx}, wy[2] = {1.0 - dy, dy}, wz[2] = {1.0 - dz, dz};
 #pragma unroll
@@ -213,135 +294,202 @@ __device__ inline void deposit_charge(const RunDev &R, const Acc<T, COMP> &acc, 
         for (int J = 0; J < 2; ++J)
 #pragma unroll
             for (int I = 0; I < 2; ++I)
-                acc.add(3, base + I + J * sy + K * sz, R.qV * wx[I] * wy[J] * wz[K]);
-    for (int l = 0; l < 3; ++l) {
-        bx.lo[l] = min(bx.lo[l], c[l]);
-        bx.hi[l] = max(bx.hi[l], c[l] + 1);
-    }
+                acc.add(3, c[0] + I, c[1] + J, c[2] + K, R.qV * wx[I] * wy[J] * wz[K]);
 }
 
-// reduce the per-thread boxes of a block into ctl->dep box `slot`
-__device__ inline void box_flush(const RunDev &R, Box &bx, int slot)
+__device__ inline int wave_min(int v)
 {
-    __shared__ int sh[6];
-    if (threadIdx.x < 3) {
-        sh[threadIdx.x] = 0x7fffffff;
-        sh[3 + threadIdx.x] = -1;
-    }
-    __syncthreads();
-    for (int l = 0; l < 3; ++l) {
-        if (bx.hi[l] >= 0) {
-            atomicMin(&sh[l], bx.lo[l]);
-            atomicMax(&sh[3 + l], bx.hi[l]);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < 3 && sh[3 + threadIdx.x] >= 0) {
-        atomicMin(&R.ctl->dep_lo[slot][threadIdx.x], sh[threadIdx.x]);
-        atomicMax(&R.ctl->dep_hi[slot][threadIdx.x], sh[3 + threadIdx.x]);
-    }
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, __shfl_xor(v, o));
+    return v;
 }
 
-// K4: gather + undulator + N_b Boris sub-steps + deposit of J^{n+1} and
-// rho^{n+3/2} into source set (n+1) & 1.
-template <typename T, bool COMP>
-__global__ __launch_bounds__(256) void k_push_deposit(RunDev R)
+__device__ inline int wave_max(int v)
 {
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+constexpr int kDepThreads = 256;
+constexpr int kLdsNodes = 1536;  // node box capacity of the LDS stage (4 arrays, FP64: 48 KiB)
+
+// Gather + undulator + N_b Boris sub-steps + deposit (MODE 0), or the load
+// deposit of the backward-drift move (MODE 1, sorted particles, set 0).
+// The block's deposits are summed in LDS over its node box when the box
+// fits, then added to HBM once per touched node; otherwise directly.
+template <typename T, bool COMP, int MODE>
+__global__ __launch_bounds__(kDepThreads) void k_push_deposit(RunDev R)
+{
+    __shared__ double lds[4 * kLdsNodes];
+    __shared__ int bb[6];
     const int64_t s = R.ctl->step;
     const int pb = R.ctl->pbuf;
-    const int set = (int)((s + 1) & 1);
+    const int set = MODE == 0 ? (int)((s + 1) & 1) : 0;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    Box bx;
-    for (int l = 0; l < 3; ++l) {
-        bx.lo[l] = 0x7fffffff;
-        bx.hi[l] = -1;
+    if (threadIdx.x < 3) {
+        bb[threadIdx.x] = 0x7fffffff;
+        bb[3 + threadIdx.x] = -1;
     }
+
+    double g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0};
+    int c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
+    bool dep_j = false, dep_q = false;
     if (p < R.np) {
         double r[3], u[3];
         for (int a = 0; a < 3; ++a) {
             r[a] = R.pr[pb][a][p];
             u[a] = R.pr[pb][3 + a][p];
         }
-        double g1[3];
-        int c1[3];
-        const bool act1 = cell_of(R, r, g1, c1);
-        double Eg[3] = {0, 0, 0}, Bg[3] = {0, 0, 0};
-        if (act1) {
-            const int64_t base = nid(R, c1[0], c1[1], c1[2]);
-            const int64_t sy = R.nx, sz = (int64_t)R.nx * R.ny;
-            const double dx = g1[0] - c1[0], dy = g1[1] - c1[1], dz = g1[2] - c1[2];
-            const double wx[2] = {1.0 - dx, dx}, wy[2] = {1.0 - dy, dy}, wz[2] = {1.0 - dz, dz};
-            for (int K = 0; K < 2; ++K)
-                for (int J = 0; J < 2; ++J)
-                    for (int I = 0; I < 2; ++I) {
-                        const double w = wx[I] * wy[J] * wz[K];
-                        const int64_t n = base + I + J * sy + K * sz;
-                        for (int a = 0; a < 3; ++a) {
-                            Eg[a] += w * (double)eb_ptr<T>(R, a)[n];
-                            Bg[a] += w * (double)eb_ptr<T>(R, 3 + a)[n];
-                        }
-                    }
-        }
-        const double t_half = ((double)s + 0.5) * R.dt;
-        for (int sub = 0; sub < R.n_sub; ++sub) {
-            double Ee[3], Be[3];
-            undulator_field(R, r[0], r[1], r[2], t_half + (double)sub * R.dtb, Ee, Be);
-            for (int a = 0; a < 3; ++a) {
-                Ee[a] += Eg[a];
-                Be[a] += Bg[a];
-            }
-            boris(u, Ee, Be, R.dtb);
+        if (MODE == 1) {
             const double ig = 1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            double r0[3];
             for (int a = 0; a < 3; ++a)
-                r[a] = r[a] + kC * R.dtb * u[a] * ig;
+                r0[a] = r[a] - kC * R.dt * u[a] * ig;
+            const bool a1 = cell_of(R, r0, g1, c1);
+            const bool a2 = cell_of(R, r, g2, c2);
+            dep_j = a1 && a2;
+            dep_q = a2;
+        } else {
+            const bool act1 = cell_of(R, r, g1, c1);
+            double Eg[3] = {0, 0, 0}, Bg[3] = {0, 0, 0};
+            if (act1) {
+                const int64_t base = nid(R, c1[0], c1[1], c1[2]);
+                const int64_t sy = R.nx, sz = (int64_t)R.nx * R.ny;
+                const double dx = g1[0] - c1[0], dy = g1[1] - c1[1], dz = g1[2] - c1[2];
+                const double wx[2] = {1.0 - dx, dx}, wy[2] = {1.0 - dy, dy}, wz[2] = {1.0 - dz, dz};
+                for (int K = 0; K < 2; ++K)
+                    for (int J = 0; J < 2; ++J)
+                        for (int I = 0; I < 2; ++I) {
+                            const double w = wx[I] * wy[J] * wz[K];
+                            const int64_t n = base + I + J * sy + K * sz;
+                            for (int a = 0; a < 3; ++a) {
+                                Eg[a] += w * (double)eb_ptr<T>(R, a)[n];
+                                Bg[a] += w * (double)eb_ptr<T>(R, 3 + a)[n];
+                            }
+                        }
+            }
+            const double t_half = ((double)s + 0.5) * R.dt;
+            for (int sub = 0; sub < R.n_sub; ++sub) {
+                double Ee[3], Be[3];
+                undulator_field(R, r[0], r[1], r[2], t_half + (double)sub * R.dtb, Ee, Be);
+                for (int a = 0; a < 3; ++a) {
+                    Ee[a] += Eg[a];
+                    Be[a] += Bg[a];
+                }
+                boris(u, Ee, Be, R.dtb);
+                const double ig = 1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                for (int a = 0; a < 3; ++a)
+                    r[a] = r[a] + kC * R.dtb * u[a] * ig;
+            }
+            for (int a = 0; a < 3; ++a) {
+                R.pr[pb][a][p] = r[a];
+                R.pr[pb][3 + a][p] = u[a];
+            }
+            const bool act2 = cell_of(R, r, g2, c2);
+            dep_j = act1 && act2;
+            dep_q = act2;
+            // sort key of the new position, in id order, for this step's sort
+            const int32_t id = R.pid[pb][p];
+            R.key_by_id[id] = act2 ? key_of_cell(R, c2) : R.key_inactive;
+            R.slot_of_id[id] = (int32_t)p;
         }
-        for (int a = 0; a < 3; ++a) {
-            R.pr[pb][a][p] = r[a];
-            R.pr[pb][3 + a][p] = u[a];
-        }
-        double g2[3];
-        int c2[3];
-        const bool act2 = cell_of(R, r, g2, c2);
-        const Acc<T, COMP> acc = make_acc<T, COMP>(R, set);
-        if (act1 && act2)
-            deposit_move<T, COMP>(R, acc, g1, c1, g2, c2, bx);
-        if (act2)
-            deposit_charge<T, COMP>(R, acc, g2, c2, bx);
     }
-    box_flush(R, bx, set);
-}
-
-// Load: first current from the backward drift r - c dt u/gamma -> r and
-// charge at r, into source set 0 (particles in buffer 0, id order).
-template <typename T, bool COMP>
-__global__ __launch_bounds__(256) void k_load_deposit(RunDev R)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    Box bx;
+    if (MODE == 0) {
+        // per-block box of the active cells after the push (sort statistics)
+        __shared__ int32_t cw[4][7];
+        int clo[3], chi[3];
+        for (int l = 0; l < 3; ++l) {
+            clo[l] = dep_q ? c2[l] : 0x7fffffff;
+            chi[l] = dep_q ? c2[l] : -1;
+            clo[l] = wave_min(clo[l]);
+            chi[l] = wave_max(chi[l]);
+        }
+        const int nact = __popcll(__ballot(dep_q));
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            for (int l = 0; l < 3; ++l) {
+                cw[wave][l] = clo[l];
+                cw[wave][3 + l] = chi[l];
+            }
+            cw[wave][6] = nact;
+        }
+        __syncthreads();
+        if (threadIdx.x < 7) {
+            int32_t v = cw[0][threadIdx.x];
+            for (int w = 1; w < kDepThreads / 64; ++w) {
+                const int32_t x = cw[w][threadIdx.x];
+                v = threadIdx.x < 3 ? min(v, x) : (threadIdx.x < 6 ? max(v, x) : v + x);
+            }
+            R.cellpart[8 * (int64_t)blockIdx.x + threadIdx.x] = v;
+        }
+    }
+    // node box of this thread's deposits
+    int lo[3], hi[3];
     for (int l = 0; l < 3; ++l) {
-        bx.lo[l] = 0x7fffffff;
-        bx.hi[l] = -1;
-    }
-    if (p < R.np) {
-        double r[3], u[3], r0[3];
-        for (int a = 0; a < 3; ++a) {
-            r[a] = R.pr[0][a][p];
-            u[a] = R.pr[0][3 + a][p];
+        lo[l] = 0x7fffffff;
+        hi[l] = -1;
+        if (dep_j) {
+            lo[l] = min(c1[l], c2[l]);
+            hi[l] = max(c1[l], c2[l]) + 1;
+        } else if (dep_q) {
+            lo[l] = c2[l];
+            hi[l] = c2[l] + 1;
         }
-        const double ig = 1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-        for (int a = 0; a < 3; ++a)
-            r0[a] = r[a] - kC * R.dt * u[a] * ig;
-        double g1[3], g2[3];
-        int c1[3], c2[3];
-        const bool act1 = cell_of(R, r0, g1, c1);
-        const bool act2 = cell_of(R, r, g2, c2);
-        const Acc<T, COMP> acc = make_acc<T, COMP>(R, 0);
-        if (act1 && act2)
-            deposit_move<T, COMP>(R, acc, g1, c1, g2, c2, bx);
-        if (act2)
-            deposit_charge<T, COMP>(R, acc, g2, c2, bx);
+        lo[l] = wave_min(lo[l]);
+        hi[l] = wave_max(hi[l]);
     }
-    box_flush(R, bx, 0);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0 && hi[0] >= 0)
+        for (int l = 0; l < 3; ++l) {
+            atomicMin(&bb[l], lo[l]);
+            atomicMax(&bb[3 + l], hi[l]);
+        }
+    __syncthreads();
+    // this block's box goes to its partial slot (reduced by k_box_reduce)
+    if (threadIdx.x < 7)
+        R.boxpart[8 * (int64_t)blockIdx.x + threadIdx.x] = threadIdx.x < 6 ? bb[threadIdx.x] : 0;
+    const int L0 = bb[0], L1 = bb[1], L2 = bb[2];
+    if (bb[3] < 0)
+        return;  // nothing deposited by this block (uniform)
+    const int ex = bb[3] - L0 + 1, ey = bb[4] - L1 + 1, ez = bb[5] - L2 + 1;
+    const int vol = ex * ey * ez;
+    if (vol <= kLdsNodes) {
+        for (int e = threadIdx.x; e < 4 * vol; e += kDepThreads)
+            lds[e] = 0.0;
+        __syncthreads();
+        const LdsAcc acc{lds, L0, L1, L2, ex, ey, vol};
+        if (dep_j)
+            deposit_move(R, acc, g1, c1, g2, c2);
+        if (dep_q)
+            deposit_charge(R, acc, g2, c2);
+        __syncthreads();
+        const GlobalAcc<T, COMP> gacc = make_gacc<T, COMP>(R, set);
+        // four entries per thread per round, so that the returning atomics of
+        // the compensated mode are in flight together
+        for (int e0 = threadIdx.x; e0 < 4 * vol; e0 += 4 * kDepThreads) {
+            double v[4];
+            int idx[4][4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = e0 + q * kDepThreads;
+                v[q] = e < 4 * vol ? lds[e] : 0.0;
+                const int comp = e / vol;
+                const int r = e - comp * vol;
+                idx[q][0] = comp;
+                idx[q][1] = L0 + r % ex;
+                idx[q][2] = L1 + (r / ex) % ey;
+                idx[q][3] = L2 + r / (ex * ey);
+            }
+            gacc.add4(v, idx);
+        }
+    } else {
+        const GlobalAcc<T, COMP> gacc = make_gacc<T, COMP>(R, set);
+        if (dep_j)
+            deposit_move(R, gacc, g1, c1, g2, c2);
+        if (dep_q)
+            deposit_charge(R, gacc, g2, c2);
+    }
 }
 
 // |sum exp(i k_r z)| over active particles, in two partial sums per block
@@ -383,30 +531,120 @@ __global__ __launch_bounds__(256) void k_bunching(RunDev R, double *part)
 
 // ---------------------------------------------------------------------------
 
-hipError_t launch_push_deposit(const RunDev &R, hipStream_t st)
+template <int MODE>
+static hipError_t launch_dep(const RunDev &R, hipStream_t st)
 {
     if (R.np <= 0)
         return hipSuccess;
-    const unsigned blocks = (unsigned)((R.np + 255) / 256);
+    const unsigned blocks = (unsigned)((R.np + kDepThreads - 1) / kDepThreads);
     if (R.precision == 64)
-        hipLaunchKernelGGL((k_push_deposit<double, false>), dim3(blocks), dim3(256), 0, st, R);
+        hipLaunchKernelGGL((k_push_deposit<double, false, MODE>), dim3(blocks), dim3(kDepThreads), 0, st, R);
     else if (R.compensated)
-        hipLaunchKernelGGL((k_push_deposit<float, true>), dim3(blocks), dim3(256), 0, st, R);
+        hipLaunchKernelGGL((k_push_deposit<float, true, MODE>), dim3(blocks), dim3(kDepThreads), 0, st, R);
     else
-        hipLaunchKernelGGL((k_push_deposit<float, false>), dim3(blocks), dim3(256), 0, st, R);
+        hipLaunchKernelGGL((k_push_deposit<float, false, MODE>), dim3(blocks), dim3(kDepThreads), 0, st, R);
     return hipGetLastError();
+}
+
+// Reduce the per-block partial boxes (and counts) of `nblocks` blocks into
+// lo/hi (and *count if non-null): one block, fixed order.
+__global__ __launch_bounds__(1024) void k_box_reduce(const int32_t *part, int64_t nblocks, int32_t *lo, int32_t *hi,
+                                                    int32_t *count)
+{
+    __shared__ int32_t sh[7][1024];
+    int32_t v[7] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1, 0};
+    for (int64_t b = threadIdx.x; b < nblocks; b += 1024) {
+        const int32_t *q = part + 8 * b;
+        for (int a = 0; a < 3; ++a) {
+            v[a] = min(v[a], q[a]);
+            v[3 + a] = max(v[3 + a], q[3 + a]);
+        }
+        v[6] += q[6];
+    }
+    for (int a = 0; a < 7; ++a)
+        sh[a][threadIdx.x] = v[a];
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int a = 0; a < 3; ++a) {
+                sh[a][threadIdx.x] = min(sh[a][threadIdx.x], sh[a][threadIdx.x + w]);
+                sh[3 + a][threadIdx.x] = max(sh[3 + a][threadIdx.x], sh[3 + a][threadIdx.x + w]);
+            }
+            sh[6][threadIdx.x] += sh[6][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = sh[a][0];
+            hi[a] = sh[3 + a][0];
+        }
+        if (count)
+            *count = sh[6][0];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_box_reduce_set(RunDev R, int64_t nblocks)
+{
+    const int set = (int)((R.ctl->step + 1) & 1);
+    __shared__ int32_t sh[6][1024];
+    int32_t v[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
+    for (int64_t b = threadIdx.x; b < nblocks; b += 1024) {
+        const int32_t *q = R.boxpart + 8 * b;
+        for (int a = 0; a < 3; ++a) {
+            v[a] = min(v[a], q[a]);
+            v[3 + a] = max(v[3 + a], q[3 + a]);
+        }
+    }
+    for (int a = 0; a < 6; ++a)
+        sh[a][threadIdx.x] = v[a];
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int a = 0; a < 3; ++a) {
+                sh[a][threadIdx.x] = min(sh[a][threadIdx.x], sh[a][threadIdx.x + w]);
+                sh[3 + a][threadIdx.x] = max(sh[3 + a][threadIdx.x], sh[3 + a][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        R.ctl->dep_lo[set][threadIdx.x] = sh[threadIdx.x][0];
+        R.ctl->dep_hi[set][threadIdx.x] = sh[3 + threadIdx.x][0];
+    }
+}
+
+hipError_t launch_box_reduce_set(const RunDev &R, int64_t nblocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_box_reduce_set, dim3(1), dim3(1024), 0, st, R, nblocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
+                             int32_t *count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_box_reduce, dim3(1), dim3(1024), 0, st, part, nblocks, lo, hi, count);
+    return hipGetLastError();
+}
+
+int64_t dep_blocks(int64_t np) { return (np + kDepThreads - 1) / kDepThreads; }
+
+hipError_t launch_push_deposit(const RunDev &R, hipStream_t st)
+{
+    hipError_t e = launch_dep<0>(R, st);
+    if (e != hipSuccess || R.np <= 0)
+        return e;
+    // the box of set (s+1)&1 is written by a kernel that reads the step
+    // number on the device, like every other stage
+    return launch_box_reduce_set(R, dep_blocks(R.np), st);
 }
 
 hipError_t launch_load_deposit(const RunDev &R, hipStream_t st)
 {
-    const unsigned blocks = (unsigned)((R.np + 255) / 256);
-    if (R.precision == 64)
-        hipLaunchKernelGGL((k_load_deposit<double, false>), dim3(blocks), dim3(256), 0, st, R);
-    else if (R.compensated)
-        hipLaunchKernelGGL((k_load_deposit<float, true>), dim3(blocks), dim3(256), 0, st, R);
-    else
-        hipLaunchKernelGGL((k_load_deposit<float, false>), dim3(blocks), dim3(256), 0, st, R);
-    return hipGetLastError();
+    hipError_t e = launch_dep<1>(R, st);
+    if (e != hipSuccess)
+        return e;
+    return launch_box_reduce(R, dep_blocks(R.np), R.boxpart, CTL_ADDR(R.ctl, dep_lo), CTL_ADDR(R.ctl, dep_hi), nullptr,
+                             st);
 }
 
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st)

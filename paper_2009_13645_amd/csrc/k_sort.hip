@@ -13,11 +13,11 @@
 // Method: keys are scattered to id order, then an LSD radix sort with
 // 8-bit digits and stable passes runs on (key, id) pairs starting from the
 // identity order, which makes ties come out in id order.  Each pass is a
-// per-block digit histogram, one exclusive scan over (digit, block), and a
-// stable scatter that ranks equal digits within a wavefront with ballots.
-// Finally the particle state is gathered into the other buffer in sorted
-// order.  No library sort and no memset: every pass is a plain kernel, so
-// the pipeline can be captured in a graph.
+// per-block digit histogram, 256 independent per-digit scans over the
+// blocks, and a stable scatter that ranks equal digits within a wavefront
+// with ballots.  Finally the particle state is gathered into the other
+// buffer in sorted order.  No library sort and no memset: every pass is a
+// plain kernel, so the pipeline can be captured in a graph.
 #include "mithra_dev.hpp"
 
 namespace mithra {
@@ -38,48 +38,64 @@ __device__ inline uint32_t particle_key(const RunDev &R, double x, double y, dou
     }
     if (!act)
         return R.key_inactive;
-    const int Tx = R.tile[0], Ty = R.tile[1], Tz = R.tile[2];
-    const uint32_t tl = ((uint32_t)(c[2] / Tz) * (uint32_t)R.ntile[1] + (uint32_t)(c[1] / Ty)) * (uint32_t)R.ntile[0] +
-                        (uint32_t)(c[0] / Tx);
-    const uint32_t loc = ((uint32_t)(c[2] % Tz) * Ty + (uint32_t)(c[1] % Ty)) * Tx + (uint32_t)(c[0] % Tx);
-    return tl * (uint32_t)(Tx * Ty * Tz) + loc;
+    return key_of_cell(R, c);
+}
+
+__device__ inline int wmin(int v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ inline int wmax(int v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, __shfl_xor(v, o));
+    return v;
 }
 
 // keys to id order, slot of every id, box of active cells, active count
 __global__ __launch_bounds__(256) void k_sort_keys(RunDev R)
 {
-    __shared__ int sh[7];
-    if (threadIdx.x < 3) {
-        sh[threadIdx.x] = 0x7fffffff;
-        sh[3 + threadIdx.x] = -1;
-    }
-    if (threadIdx.x == 0)
-        sh[6] = 0;
-    __syncthreads();
     const int pb = R.ctl->pbuf;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-1, -1, -1};
+    bool act = false;
     if (p < R.np) {
         int c[3];
-        bool act;
         const uint32_t key = particle_key(R, R.pr[pb][0][p], R.pr[pb][1][p], R.pr[pb][2][p], c, act);
         const int32_t id = R.pid[pb][p];
         R.key_by_id[id] = key;
         R.slot_of_id[id] = (int32_t)p;
-        if (act) {
-            for (int a = 0; a < 3; ++a) {
-                atomicMin(&sh[a], c[a]);
-                atomicMax(&sh[3 + a], c[a]);
-            }
-            atomicAdd(&sh[6], 1);
+        if (act)
+            for (int a = 0; a < 3; ++a)
+                lo[a] = hi[a] = c[a];
+    }
+    __shared__ int32_t wv[4][7];
+    const int nact = __popcll(__ballot(act));
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = wmin(lo[a]);
+        hi[a] = wmax(hi[a]);
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        for (int a = 0; a < 3; ++a) {
+            wv[wave][a] = lo[a];
+            wv[wave][3 + a] = hi[a];
         }
+        wv[wave][6] = nact;
     }
     __syncthreads();
-    if (threadIdx.x < 3 && sh[3 + threadIdx.x] >= 0) {
-        atomicMin(&R.ctl->cell_lo[threadIdx.x], sh[threadIdx.x]);
-        atomicMax(&R.ctl->cell_hi[threadIdx.x], sh[3 + threadIdx.x]);
+    // block partial (reduced over blocks by k_box_reduce)
+    if (threadIdx.x < 7) {
+        int32_t v = wv[0][threadIdx.x];
+        for (int w = 1; w < 4; ++w) {
+            const int32_t x = wv[w][threadIdx.x];
+            v = threadIdx.x < 3 ? min(v, x) : (threadIdx.x < 6 ? max(v, x) : v + x);
+        }
+        R.boxpart[8 * (int64_t)blockIdx.x + threadIdx.x] = v;
     }
-    if (threadIdx.x == 0 && sh[6] > 0)
-        atomicAdd(&R.ctl->n_active, sh[6]);
 }
 
 // per-block digit histogram, stored digit-major: hist[d * nblocks + b]
@@ -99,43 +115,76 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *key
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan in place over `total` counters, one block of 1024 threads
-__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t *a, int64_t total)
+// Per digit d (one block each): exclusive scan of hist[d][0..nblocks) in
+// place, and the digit total into tot[d].
+__global__ __launch_bounds__(256) void k_digit_scan(uint32_t *hist, int64_t nblocks, uint32_t *tot)
 {
-    __shared__ uint32_t part[1024];
-    const int64_t per = (total + 1023) / 1024;
-    const int64_t b = (int64_t)threadIdx.x * per;
-    const int64_t e = min(b + per, total);
-    uint32_t s = 0;
-    for (int64_t x = b; x < e; ++x)
-        s += a[x];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 partial sums
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __shared__ uint32_t ws[4];
+    uint32_t *a = hist + (int64_t)blockIdx.x * nblocks;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nblocks; base += 4 * 256) {
+        const int64_t e0 = base + 4 * (int64_t)threadIdx.x;
+        uint32_t v[4];
+        for (int q = 0; q < 4; ++q)
+            v[q] = (e0 + q < nblocks) ? a[e0 + q] : 0u;
+        const uint32_t ts = v[0] + v[1] + v[2] + v[3];
+        uint32_t inc = ts;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o);
+            if (lane >= o)
+                inc += t;
+        }
+        if (lane == 63)
+            ws[wave] = inc;
         __syncthreads();
-        part[threadIdx.x] += v;
+        uint32_t wbase = 0, btot = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < wave)
+                wbase += ws[w];
+            btot += ws[w];
+        }
+        uint32_t run = carry + wbase + inc - ts;
+        for (int q = 0; q < 4; ++q) {
+            if (e0 + q < nblocks)
+                a[e0 + q] = run;
+            run += v[q];
+        }
+        carry += btot;
         __syncthreads();
     }
-    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    for (int64_t x = b; x < e; ++x) {
-        const uint32_t v = a[x];
-        a[x] = run;
-        run += v;
-    }
+    if (threadIdx.x == 0)
+        tot[blockIdx.x] = carry;
 }
 
 // stable scatter of one pass.  vals_in == nullptr means identity values.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *keys_in, const int32_t *vals_in,
                                                              uint32_t *keys_out, int32_t *vals_out, int64_t n,
-                                                             int shift, const uint32_t *offs, int64_t nblocks)
+                                                             int shift, const uint32_t *offs, int64_t nblocks,
+                                                             const uint32_t *tot)
 {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[kSortThreads / 64][256];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    run[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    // digit base = sum of the totals of smaller digits (inclusive wave scan)
+    {
+        const uint32_t t = tot[threadIdx.x];
+        uint32_t inc = t;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(inc, o);
+            if (lane >= o)
+                inc += u;
+        }
+        if (lane == 63)
+            wcnt[0][wave] = inc;
+        __syncthreads();
+        uint32_t wb = 0;
+        for (int w = 0; w < wave; ++w)
+            wb += wcnt[0][w];
+        run[threadIdx.x] = wb + inc - t + offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+        __syncthreads();
+    }
     const int64_t base = (int64_t)blockIdx.x * kSortChunk;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     for (int it = 0; it < kSortItems; ++it) {
@@ -196,6 +245,9 @@ __global__ __launch_bounds__(256) void k_sort_gather(RunDev R, const uint32_t *k
 
 // ---------------------------------------------------------------------------
 
+hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
+                             int32_t *count, hipStream_t st);
+
 int sort_passes(uint32_t key_inactive)
 {
     int bits = 0;
@@ -206,12 +258,19 @@ int sort_passes(uint32_t key_inactive)
 
 int64_t sort_blocks(int64_t n) { return (n + kSortChunk - 1) / kSortChunk; }
 
-hipError_t launch_sort(const RunDev &R, hipStream_t st)
+// keys_ready: the push kernel has already written the keys, the slots and
+// its per-block active-cell boxes (R.cellpart, one per 256 particles)
+hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready)
 {
     if (R.np <= 0)
         return hipSuccess;
     const unsigned pblocks = (unsigned)((R.np + 255) / 256);
-    hipLaunchKernelGGL(k_sort_keys, dim3(pblocks), dim3(256), 0, st, R);
+    if (!keys_ready)
+        hipLaunchKernelGGL(k_sort_keys, dim3(pblocks), dim3(256), 0, st, R);
+    hipError_t e = launch_box_reduce(R, pblocks, keys_ready ? R.cellpart : R.boxpart, CTL_ADDR(R.ctl, cell_lo),
+                                     CTL_ADDR(R.ctl, cell_hi), CTL_ADDR(R.ctl, n_active), st);
+    if (e != hipSuccess)
+        return e;
     const int passes = sort_passes(R.key_inactive);
     const int64_t nb = R.sort_blocks;
     const uint32_t *kin = R.key_by_id;
@@ -220,9 +279,9 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st)
         uint32_t *kout = R.sk[ps & 1];
         int32_t *vout = R.sv[ps & 1];
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, R.np, 8 * ps, R.hist, nb);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, R.hist, 256 * nb);
+        hipLaunchKernelGGL(k_digit_scan, dim3(256), dim3(256), 0, st, R.hist, nb, R.hist + 256 * nb);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, R.np,
-                           8 * ps, R.hist, nb);
+                           8 * ps, R.hist, nb, R.hist + 256 * nb);
         kin = kout;
         vin = vout;
     }

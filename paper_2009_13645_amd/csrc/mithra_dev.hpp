@@ -6,6 +6,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace mithra {
@@ -84,12 +85,18 @@ struct RunDev {
     int32_t *sv[2];
     uint32_t *hist;
     int64_t sort_blocks;
+    int32_t *boxpart;  // per-block partial boxes: [block][8] = lo[3], hi[3], count, pad
+    int32_t *cellpart; // per-block partial active-cell boxes of the push kernel, same layout
+    double *ppart;     // partial sums of the plane-power kernel
     double *power_hist;
     int64_t power_cap;
     int k_plane;
     int record_power;
     Ctl *ctl;
 };
+
+// Device address of a Ctl member, formed on the host without dereferencing.
+#define CTL_ADDR(ctl, member) ((int32_t *)((char *)(ctl) + offsetof(::mithra::Ctl, member)))
 
 __host__ __device__ inline int64_t nid(const RunDev &R, int i, int j, int k)
 {
@@ -137,6 +144,16 @@ __device__ inline int64_t xcd_swizzle(int64_t bid, int64_t nblocks)
         return bid;
     int64_t per = full / nx;
     return (bid % nx) * per + bid / nx;
+}
+
+// Tile-major sort key of an active cell c (see k_sort.hip for the order).
+__device__ inline uint32_t key_of_cell(const RunDev &R, const int c[3])
+{
+    const int Tx = R.tile[0], Ty = R.tile[1], Tz = R.tile[2];
+    const uint32_t tl = ((uint32_t)(c[2] / Tz) * (uint32_t)R.ntile[1] + (uint32_t)(c[1] / Ty)) * (uint32_t)R.ntile[0] +
+                        (uint32_t)(c[0] / Tx);
+    const uint32_t loc = ((uint32_t)(c[2] % Tz) * Ty + (uint32_t)(c[1] % Ty)) * Tx + (uint32_t)(c[0] % Tx);
+    return tl * (uint32_t)(Tx * Ty * Tz) + loc;
 }
 
 }  // namespace mithra

@@ -82,6 +82,8 @@ def lib():
         L.mithra_set_sweep_shape.argtypes = [H, C.c_int]
         L.mithra_set_sweep_shape.restype = C.c_int
         L.mithra_sweep_shape_count.restype = C.c_int
+        L.mithra_time_sweep.argtypes = [H, C.c_int, C.c_int, dp]
+        L.mithra_time_sweep.restype = C.c_int
         _lib = L
     return _lib
 
@@ -212,6 +214,12 @@ class Engine:
 
     def set_sweep_shape(self, shape: int):
         self._check(self._L.mithra_set_sweep_shape(self._h, int(shape)))
+
+    def time_sweep(self, shape: int = -1, iters: int = 20) -> float:
+        """Average ms of one field-sweep launch (tile shape `shape`, -1: current)."""
+        out = C.c_double()
+        self._check(self._L.mithra_time_sweep(self._h, int(shape), int(iters), C.byref(out)))
+        return out.value
 
     @staticmethod
     def sweep_shape_count() -> int:
