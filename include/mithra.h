@@ -170,6 +170,13 @@ int mithra_sweep_shape_count(void);
 int mithra_set_sweep_shape(mithra_handle h, int shape);
 int mithra_time_sweep(mithra_handle h, int shape, int iters, double *ms);
 
+/* Measurement call: run n_steps exactly as mithra_step would, by direct
+ * launches with HIP events on the handle's stream around every sweep
+ * launch and around every whole step; synchronises, then adds the summed
+ * milliseconds to *sweep_ms and *step_ms.  Errors: EINVAL, ESTATE,
+ * EDEVICE. */
+int mithra_step_timed(mithra_handle h, int64_t n_steps, double *sweep_ms, double *step_ms);
+
 /* Message of the last error on this handle (never NULL). */
 const char *mithra_last_error(mithra_handle h);
 

@@ -1,0 +1,115 @@
+"""HBM traffic of the field sweep from hardware counters (rocprofv3 --pmc).
+
+Two steps, each under its own profiler run:
+
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_f> -- python3 -m paper_2009_13645_amd.counters run
+  rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_w> -- python3 -m paper_2009_13645_amd.counters run
+  python3 -m paper_2009_13645_amd.counters summarize <dir_f> <dir_w>
+
+`run` executes the benchmark workload (FEL amplifier, FP32) for a few
+steps, then 10 launches of the sweep alone, then a plain device-to-device
+copy of a known size (torch's copy kernel) used to calibrate what the
+counters read per byte.  `summarize` writes profiles/sweep_traffic.json
+(bytes per sweep launch, tagged with the hash of the sweep's source file)
+and profiles/sweep_traffic.md.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 256 * 1024 * 1024
+
+
+def run():
+    sys.path.insert(0, ROOT)
+    import torch
+    from paper_2009_13645_amd import workloads as W
+    from paper_2009_13645_amd.engine import Engine
+    w = W.config2(field_precision=32, compensated=0)
+    d = w.descriptor()
+    xyz, u, q = W.make_bunch(w)
+    e = Engine(d, max_particles=len(xyz))
+    e.load_bunch(xyz, u, q)
+    e.step(20)
+    torch.cuda.synchronize()
+    e.time_sweep(-1, 10)
+    torch.cuda.synchronize()
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("counters: run done", flush=True)
+
+
+def _rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _per_dispatch(rows, name_part, counter):
+    vals = {}
+    for r in rows:
+        if name_part not in r.get("Kernel_Name", "") or r.get("Counter_Name") != counter:
+            continue
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+    return list(vals.values())
+
+
+def summarize(dir_f, dir_w):
+    rf, rw = _rows(dir_f), _rows(dir_w)
+    sweep_f = _per_dispatch(rf, "k_sweep", "FETCH_SIZE")
+    sweep_w = _per_dispatch(rw, "k_sweep", "WRITE_SIZE")
+    # torch's device-to-device copy_ runs as the runtime's copyBuffer kernel
+    copy_f = _per_dispatch(rf, "copyBuffer", "FETCH_SIZE")
+    copy_w = _per_dispatch(rw, "copyBuffer", "WRITE_SIZE")
+    # counters are in KiB per dispatch; calibrate on the copy (reads and
+    # writes COPY_BYTES each); skip the first (cold) launches
+    cf = COPY_BYTES / (1024.0 * max(copy_f[-3:]))
+    cw = COPY_BYTES / (1024.0 * max(copy_w[-3:]))
+    sf = sorted(sweep_f[-10:])[len(sweep_f[-10:]) // 2] * 1024.0 * cf
+    sw = sorted(sweep_w[-10:])[len(sweep_w[-10:]) // 2] * 1024.0 * cw
+    src = os.path.join(ROOT, "paper_2009_13645_amd", "csrc", "k_fdtd.hip")
+    rec = {
+        "kernel": "k_sweep_vec (NSFD sweep, FP32, 128x128x1024 nodes, 4 potentials)",
+        "fetch_bytes_per_launch": sf, "write_bytes_per_launch": sw, "bytes_per_launch": sf + sw,
+        "copy_calibration": {"fetch_factor": cf, "write_factor": cw, "copy_bytes": COPY_BYTES},
+        "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_f> -- python3 -m paper_2009_13645_amd.counters run",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_w> -- python3 -m paper_2009_13645_amd.counters run",
+            "python3 -m paper_2009_13645_amd.counters summarize <dir_f> <dir_w>",
+        ],
+    }
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "sweep_traffic.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    with open(os.path.join(ROOT, "profiles", "sweep_traffic.md"), "w") as f:
+        f.write("# HBM traffic of the NSFD sweep (FEL amplifier, FP32, 128x128x1024)\n\n")
+        for c in rec["commands"]:
+            f.write(f"    {c}\n")
+        f.write(f"\nFETCH_SIZE per launch: {sf/1e6:.1f} MB (copy calibration x{cf:.3f})\n")
+        f.write(f"WRITE_SIZE per launch: {sw/1e6:.1f} MB (copy calibration x{cw:.3f})\n")
+        f.write(f"Total: {(sf+sw)/1e6:.1f} MB per launch\n")
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 2 and sys.argv[1] == "run":
+        run()
+    elif len(sys.argv) >= 4 and sys.argv[1] == "summarize":
+        summarize(sys.argv[2], sys.argv[3])
+    else:
+        print(__doc__)
+        sys.exit(1)

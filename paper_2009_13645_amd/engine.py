@@ -84,6 +84,8 @@ def lib():
         L.mithra_sweep_shape_count.restype = C.c_int
         L.mithra_time_sweep.argtypes = [H, C.c_int, C.c_int, dp]
         L.mithra_time_sweep.restype = C.c_int
+        L.mithra_step_timed.argtypes = [H, C.c_int64, dp, dp]
+        L.mithra_step_timed.restype = C.c_int
         _lib = L
     return _lib
 
@@ -220,6 +222,13 @@ class Engine:
         out = C.c_double()
         self._check(self._L.mithra_time_sweep(self._h, int(shape), int(iters), C.byref(out)))
         return out.value
+
+    def step_timed(self, n: int) -> Tuple[float, float]:
+        """n steps with HIP events around each sweep and each step:
+        returns (summed sweep ms, summed step ms)."""
+        a, b = C.c_double(0.0), C.c_double(0.0)
+        self._check(self._L.mithra_step_timed(self._h, int(n), C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     @staticmethod
     def sweep_shape_count() -> int:
