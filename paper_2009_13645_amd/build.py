@@ -13,9 +13,10 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmithra.so")
-SOURCES = ["engine.hip", "k_fdtd.hip", "k_particles.hip", "k_sort.hip"]
+SOURCES = ["engine.hip", "k_fdtd.hip", "k_particles.hip", "k_sort.hip", "k_tiles.hip"]
 
 HIPCC_FLAGS = [
+    "-I" + os.path.join(os.path.dirname(HERE), "include"),
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-munsafe-fp-atomics",
     # no packed-FP32 instructions anywhere in the device code

@@ -11,6 +11,7 @@
 // captured once into a HIP graph and replayed for the following steps.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -18,7 +19,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mithra.h"
+#include "mithra.h"
 #include "mithra_dev.hpp"
 
 namespace mithra {
@@ -26,12 +27,23 @@ hipError_t launch_sweep(const RunDev &R, int shape, hipStream_t st);
 int sweep_shape_count();
 void sweep_shape_dims(int shape, int *tx, int *ty, int *tz);
 hipError_t launch_mur(const RunDev &R, hipStream_t st);
+int sweep_fuses_xfaces(const RunDev &R, int shape);
 hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStream_t st);
 hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st);
 hipError_t launch_push_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_load_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st);
-hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready);
+hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts);
+hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
+                             int32_t *count, hipStream_t st, int32_t *zero);
+hipError_t launch_box_reduce_set(const RunDev &R, int64_t nblocks, hipStream_t st);
+bool tile_kernel_fits(const int tile[3]);
+int tile_partials(const RunDev &R);
+hipError_t launch_tile_items(const RunDev &R, hipStream_t st);
+hipError_t launch_tile_step(const RunDev &R, hipStream_t st);
+hipError_t launch_tile_load(const RunDev &R, hipStream_t st);
+int tile_blocks_per_cu(int precision, int compensated);
+int64_t dep_blocks(int64_t np);
 int sort_passes(uint32_t key_inactive);
 int64_t sort_blocks(int64_t n);
 
@@ -42,6 +54,8 @@ int64_t sort_blocks(int64_t n);
 __global__ void k_book_mid(Ctl *ctl)
 {
     const int set = (int)((ctl->step + 1) & 1);
+    ctl->sorted_active = ctl->n_active;
+    ctl->item_next = 0;
     for (int a = 0; a < 3; ++a) {
         ctl->dep_lo[set][a] = 0x7fffffff;
         ctl->dep_hi[set][a] = -1;
@@ -59,6 +73,12 @@ __global__ void k_book_end(Ctl *ctl, int advance)
         ctl->step += 1;
 }
 
+__global__ void k_book_mid_load(Ctl *ctl)
+{
+    ctl->sorted_active = ctl->n_active;
+    ctl->item_next = 0;
+}
+
 __global__ void k_book_load(Ctl *ctl)
 {
     for (int a = 0; a < 3; ++a) {
@@ -73,11 +93,12 @@ __global__ void k_book_load(Ctl *ctl)
 using namespace mithra;
 
 static const int64_t kPowerCap = 1 << 16;
+static const int kPartials = 8192;  // per-block partial slots (>= persistent blocks + inactive blocks)
 static const int kBunchBlocks = 256;
 
 struct Layout {
     size_t ctl, pot, src, src_lo, eb, pr, pid, key_by_id, slot_of_id, cell_by_id, key_sorted, sk, sv, hist, boxpart,
-        cellpart, ppart, power, scratch, total;
+        cellpart, items, items_n, ppart, power, scratch, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -108,8 +129,16 @@ static Layout make_layout(const mithra_grid_desc *d, int64_t cap)
     L.sk = take(2 * c * 4);
     L.sv = take(2 * c * 4);
     L.hist = take((256 * (size_t)sort_blocks((int64_t)c) + 256) * 4);
-    L.boxpart = take(8 * 4 * (size_t)((c + 255) / 256));
-    L.cellpart = take(8 * 4 * (size_t)((c + 255) / 256));
+    const size_t nparts = std::max((size_t)((c + 255) / 256), (size_t)kPartials);
+    L.boxpart = take(8 * 4 * nparts);
+    L.cellpart = take(8 * 4 * nparts);
+    size_t ntiles = 1;
+    for (int a = 0; a < 3; ++a) {
+        const size_t cells = (size_t)((a == 0 ? d->nx : (a == 1 ? d->ny : d->nz)) - 1);
+        ntiles *= (cells + d->tile[a] - 1) / d->tile[a];
+    }
+    L.items_n = c / 512 + std::min(c, ntiles) + 16;
+    L.items = take(16 * L.items_n);
     L.ppart = take(256 * 8);
     L.power = take((size_t)kPowerCap * 8);
     L.scratch = take((size_t)(3 * kBunchBlocks + 8) * 8);
@@ -126,6 +155,7 @@ struct mithra_engine {
     int64_t steps = 0;
     bool loaded = false;
     int sweep_shape = 0;
+    bool tiled = false;
     int32_t *cell_by_id = nullptr;
     hipGraphExec_t graph = nullptr;
     int use_graph = 1;
@@ -342,6 +372,8 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.hist = (uint32_t *)(A + L.hist);
     R.boxpart = (int32_t *)(A + L.boxpart);
     R.cellpart = (int32_t *)(A + L.cellpart);
+    R.items = (int32_t *)(A + L.items);
+    R.item_cap = (int64_t)L.items_n;
     R.ppart = (double *)(A + L.ppart);
     R.sort_blocks = sort_blocks((int64_t)c);
     R.power_hist = (double *)(A + L.power);
@@ -371,6 +403,17 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     }
     HIPCHK(h, hipMemcpyAsync(R.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    // persistent grid of the tile-owned particle kernel
+    // particle kernel: per-block LDS-staged deposit (default; measured faster
+    // on the benchmark run) or the tile-owned kernel ("tile")
+    const char *pp = getenv("MITHRA_PARTICLE_PATH");
+    h->tiled = pp && strcmp(pp, "tile") == 0 && tile_kernel_fits(d->tile);
+    if (h->tiled) {
+        int dev = 0, cus = 0;
+        HIPCHK(h, hipGetDevice(&dev));
+        HIPCHK(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        R.tile_grid = std::min(cus * tile_blocks_per_cu(d->field_precision, d->compensated), kPartials - 128);
+    }
     // default sweep tile: vector tiles about as wide as the rows when the
     // row length allows 16-byte vectors, else the scalar tiles
     const int vec = d->field_precision == 32 ? 4 : 2;
@@ -381,6 +424,7 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     const char *sh = getenv("MITHRA_SWEEP_SHAPE");
     if (sh)
         h->sweep_shape = atoi(sh) % sweep_shape_count();
+    R.xface_fused = sweep_fuses_xfaces(R, h->sweep_shape);
     *out = h;
     return MITHRA_OK;
 }
@@ -425,7 +469,15 @@ extern "C" int mithra_load_bunch(mithra_handle h, int64_t n, const double *xyz, 
         return rc;
     hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, h->stream, R.ctl, 0);
     HIPCHK(h, hipGetLastError());
-    HIPCHK(h, launch_load_deposit(R, h->stream));
+    if (h->tiled) {
+        HIPCHK(h, launch_tile_items(R, h->stream));
+        hipLaunchKernelGGL(k_book_mid_load, dim3(1), dim3(1), 0, h->stream, R.ctl);
+        HIPCHK(h, launch_tile_load(R, h->stream));
+        HIPCHK(h, launch_box_reduce(R, R.tile_grid, R.boxpart, CTL_ADDR(R.ctl, dep_lo), CTL_ADDR(R.ctl, dep_hi),
+                                    nullptr, h->stream, nullptr));
+    } else {
+        HIPCHK(h, launch_load_deposit(R, h->stream));
+    }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->loaded = true;
     return MITHRA_OK;
@@ -453,7 +505,26 @@ __global__ void k_cells_by_id(RunDev R, int32_t *cell_by_id)
 
 static int enqueue_sort_with_cells(mithra_handle h)
 {
-    HIPCHK(h, launch_sort(h->R, h->stream, false));
+    HIPCHK(h, launch_sort(h->R, h->stream, false, 0));
+    return MITHRA_OK;
+}
+
+// the particle part of a step: push + deposit, bin + sort, next work items
+static int enqueue_particles(mithra_handle h, hipStream_t st)
+{
+    RunDev &R = h->R;
+    if (h->tiled) {
+        hipLaunchKernelGGL(k_book_mid, dim3(1), dim3(1), 0, st, R.ctl);
+        HIPCHK(h, launch_tile_step(R, st));
+        HIPCHK(h, launch_box_reduce_set(R, tile_partials(R), st));
+        HIPCHK(h, launch_sort(R, st, true, tile_partials(R)));
+        HIPCHK(h, launch_tile_items(R, st));
+    } else {
+        HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
+        hipLaunchKernelGGL(k_book_mid, dim3(1), dim3(1), 0, st, R.ctl);
+        HIPCHK(h, launch_push_deposit(R, st));
+        HIPCHK(h, launch_sort(R, st, true, dep_blocks(R.np)));
+    }
     return MITHRA_OK;
 }
 
@@ -463,10 +534,9 @@ static int enqueue_step(mithra_handle h)
     hipStream_t st = h->stream;
     HIPCHK(h, launch_sweep(R, h->sweep_shape, st));
     HIPCHK(h, launch_mur(R, st));
-    HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
-    hipLaunchKernelGGL(k_book_mid, dim3(1), dim3(1), 0, st, R.ctl);
-    HIPCHK(h, launch_push_deposit(R, st));
-    HIPCHK(h, launch_sort(R, st, true));
+    int rc = enqueue_particles(h, st);
+    if (rc)
+        return rc;
     if (R.record_power)
         HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st));
     hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);
@@ -722,6 +792,7 @@ extern "C" int mithra_set_sweep_shape(mithra_handle h, int shape)
     if (!h || shape < 0 || shape >= sweep_shape_count())
         return MITHRA_EINVAL;
     h->sweep_shape = shape;
+    h->R.xface_fused = sweep_fuses_xfaces(h->R, shape);
     if (h->graph) {
         (void)hipGraphExecDestroy(h->graph);
         h->graph = nullptr;
@@ -751,10 +822,9 @@ extern "C" int mithra_step_timed(mithra_handle h, int64_t n, double *sweep_ms, d
         HIPCHK(h, launch_sweep(R, h->sweep_shape, st));
         HIPCHK(h, hipEventRecord(ev[(size_t)(3 * i + 1)], st));
         HIPCHK(h, launch_mur(R, st));
-        HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
-        hipLaunchKernelGGL(k_book_mid, dim3(1), dim3(1), 0, st, R.ctl);
-        HIPCHK(h, launch_push_deposit(R, st));
-        HIPCHK(h, launch_sort(R, st, true));
+        int rc = enqueue_particles(h, st);
+        if (rc)
+            return rc;
         if (R.record_power)
             HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st));
         hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);

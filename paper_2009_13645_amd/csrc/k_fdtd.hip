@@ -218,6 +218,8 @@ __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
     constexpr int TW = TXV * V;                          // tile width in nodes
     constexpr int ROW = ((V + TW + 1) + V - 1) / V * V;  // LDS row: pad(V-1), left halo, tile, right halo
     __shared__ __attribute__((aligned(16))) T sb[2][TY + 2][ROW];
+    // psi^n at the two outermost nodes of each row end (x-face update)
+    __shared__ T rawe[2][TY + 2][4];
 
     const int ntx = (R.nx + TW - 1) / TW;
     const int nty = (R.ny + TY - 1) / TY;
@@ -368,6 +370,28 @@ __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
         } else if (hrole == 1) {
             buf[hy + 1][V + hx] = cA * (hm.v[0] + hp.v[0]) + c1A * h0.v[0];
         }
+        if (R.xface_fused) {
+            T(*raw)[4] = rawe[k & 1];
+            if (inb && i0 == 0) {
+                raw[ly + 1][0] = q0.v[0];
+                raw[ly + 1][1] = q0.v[1];
+            }
+            if (inb && i0 + V == R.nx) {
+                raw[ly + 1][2] = q0.v[V - 2];
+                raw[ly + 1][3] = q0.v[V - 1];
+            }
+            if (hrole == 0 && hval) {
+                const int hi_ = tile_x * TW + hx;
+                if (hi_ == 0) {
+                    raw[hy + 1][0] = h0.v[0];
+                    raw[hy + 1][1] = h0.v[1];
+                }
+                if (hi_ + V == R.nx) {
+                    raw[hy + 1][2] = h0.v[V - 2];
+                    raw[hy + 1][3] = h0.v[V - 1];
+                }
+            }
+        }
         __syncthreads();
         if (rowvalid && update) {
             const T left = buf[ly + 1][V + lx * V - 1];
@@ -381,11 +405,36 @@ __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
                 out.v[e] = a1 * q0.v[e] + a2 * (xl + xr) + a4 * (dn.v[e] + up.v[e]) + a6 * (qp.v[e] + qm.v[e]) -
                            pm.v[e] + (T)(sfac * sv[e]);
             }
-            // the boundary columns of the row keep their (Mur) values
-            if (i0 == 0)
-                out.v[0] = next[c];
-            if (i0 + V == R.nx)
-                out.v[V - 1] = next[c + V - 1];
+            // the x-face nodes of the row: Mur update (faces of the x axis,
+            // transverse y and z), from this thread's own columns, the
+            // neighbouring rows' values in LDS and the new inner value; or
+            // left to the Mur kernel
+            if (i0 == 0 || i0 + V == R.nx) {
+                const T(*raw)[4] = rawe[k & 1];
+                for (int side = 0; side < 2; ++side) {
+                    if ((side == 0 && i0 != 0) || (side == 1 && i0 + V != R.nx))
+                        continue;
+                    const int eb = side == 0 ? 0 : V - 1, ei = side == 0 ? 1 : V - 2;
+                    if (!R.xface_fused) {
+                        out.v[eb] = next[c + eb];
+                        continue;
+                    }
+                    const int ro = side == 0 ? 0 : 2;
+                    const int rb = side == 0 ? ro : ro + 1, ri = side == 0 ? ro + 1 : ro;
+                    double v = R.mur_be0[0] * ((double)pm.v[eb] + (double)out.v[ei]) - (double)pm.v[ei];
+                    if (R.order == 1) {
+                        v += R.mur_be1[0] * ((double)q0.v[eb] + (double)q0.v[ei]);
+                    } else {
+                        v += R.mur_g1[0] * ((double)q0.v[eb] + (double)q0.v[ei]);
+                        const double s1 = ((double)raw[ly][rb] + (double)raw[ly][ri]) +
+                                          ((double)raw[ly + 2][rb] + (double)raw[ly + 2][ri]);
+                        const double s2 = ((double)qm.v[eb] + (double)qm.v[ei]) + ((double)qp.v[eb] + (double)qp.v[ei]);
+                        v += R.mur_ga[0] * s1;
+                        v += R.mur_gb[0] * s2;
+                    }
+                    out.v[eb] = (T)v;
+                }
+            }
             vstore<T, V>(next + c, out);
         }
         qm = q0;
@@ -531,7 +580,7 @@ __global__ __launch_bounds__(256) void k_mur(RunDev R)
 {
     const int64_t nzf = 2LL * R.nx * R.ny;
     const int64_t nyf = 2LL * R.nx * (R.nz - 2);
-    const int64_t nxf = 2LL * (R.ny - 2) * (R.nz - 2);
+    const int64_t nxf = R.xface_fused ? 0 : 2LL * (R.ny - 2) * (R.nz - 2);
     const int64_t nb = nzf + nyf + nxf;
     const int ncomp = R.space_charge ? 4 : 3;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -733,6 +782,12 @@ static hipError_t launch_sweep_vec_t(const RunDev &R, hipStream_t st)
     return hipGetLastError();
 }
 
+int sweep_fuses_xfaces(const RunDev &R, int shape)
+{
+    const int V = R.precision == 32 ? 4 : 2;
+    return (shape >= 8 && R.nx % V == 0) ? 1 : 0;
+}
+
 template <typename T>
 static hipError_t launch_sweep_shape(const RunDev &R, int shape, hipStream_t st)
 {
@@ -779,7 +834,7 @@ hipError_t launch_sweep(const RunDev &R, int shape, hipStream_t st)
 
 hipError_t launch_mur(const RunDev &R, hipStream_t st)
 {
-    const int64_t nb = 2LL * R.nx * R.ny + 2LL * R.nx * (R.nz - 2) + 2LL * (R.ny - 2) * (R.nz - 2);
+    const int64_t nb = 2LL * R.nx * R.ny + 2LL * R.nx * (R.nz - 2) + (R.xface_fused ? 0 : 2LL * (R.ny - 2) * (R.nz - 2));
     const int64_t tot = nb * (R.space_charge ? 4 : 3);
     const unsigned blocks = (unsigned)((tot + 255) / 256);
     if (R.precision == 32)

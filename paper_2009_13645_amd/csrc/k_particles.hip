@@ -1,316 +1,14 @@
-// k_particles.hip -- particle phase of the boosted-frame PIC step.
-//
-//  * gather of the vertex E and B (trilinear, eq. fieldInterpolation with
-//    the linear weights 1 - d, d);
-//  * external static undulator field: lab-frame field at the position
-//    z' = gamma0 (z - z_entrance + beta0 c t) with entrance and exit fringes,
-//    boosted with E' = 0 (eqs. undulatorField, fringingField,
-//    LorentzTransformR2L, LorentzTransformElectric/Magnetic); helical = the
-//    planar pattern plus its 90-degree rotation a quarter period upstream;
-//  * N_b Boris sub-steps (eq. BorisScheme) with the grid field held at
-//    t_{n+1/2} and the undulator field re-evaluated per sub-step;
-//  * charge-conserving deposit: zigzag split at the printed relay point,
-//    each segment carrying the exact current of a straight move inside one
-//    cell under linear weights; cloud-in-cell charge.  Accumulation is by
-//    device-scope atomics into the source set of the next step; in the
-//    compensated FP32 mode every atomic add is followed by an atomic add of
-//    its exact rounding error (two-sum) into a second array.
-// Particles are processed in the order of the last sort (by cell tile).
-#include "mithra_dev.hpp"
+// k_particles.hip -- per-block particle step (used where a sort tile is too
+// large for the tile-owned kernel of k_tiles.hip), box reductions and the
+// bunching diagnostic.  Particles are processed in the order of the last
+// sort; each block sums its deposits in LDS over the node box its particles
+// touch and adds that box to HBM once, or adds directly when the box does
+// not fit.
+#include "particle_dev.hpp"
 
 namespace mithra {
 
-__device__ inline void lab_planar(const RunDev &R, double x, double y, double zl, double cth, double sth,
-                                  double Bl[3])
-{
-    const double eta = x * sth + y * cth;
-    double g, hh;
-    if (zl < 0.0) {
-        const double a = R.ku * zl;
-        const double e = exp(-0.5 * a * a);
-        g = a * e;
-        hh = e;
-    } else if (zl > R.Lu) {
-        const double a = R.ku * (zl - R.Lu);
-        const double e = exp(-0.5 * a * a);
-        g = a * e;
-        hh = e;
-    } else {
-        sincos(R.ku * zl, &g, &hh);
-    }
-    const double ke = R.ku * eta;
-    const double bp = R.B0 * cosh(ke) * g;
-    Bl[0] = bp * sth;
-    Bl[1] = bp * cth;
-    Bl[2] = R.B0 * sinh(ke) * hh;
-}
-
-__device__ inline void undulator_field(const RunDev &R, double x, double y, double z, double t, double E[3],
-                                       double B[3])
-{
-    const double zl = R.gamma0 * (z - R.z_ent + R.beta0 * kC * t);
-    double Bl[3];
-    if (R.und_type == 1) {
-        double b2[3];
-        lab_planar(R, x, y, zl, 1.0, 0.0, Bl);
-        lab_planar(R, x, y, zl + 0.25 * (2.0 * kPi / R.ku), 0.0, 1.0, b2);
-        for (int a = 0; a < 3; ++a)
-            Bl[a] += b2[a];
-    } else {
-        double sth, cth;
-        sincos(R.theta, &sth, &cth);
-        lab_planar(R, x, y, zl, cth, sth, Bl);
-    }
-    const double gbc = R.gamma0 * R.beta0 * kC;
-    E[0] = -gbc * Bl[1];
-    E[1] = gbc * Bl[0];
-    E[2] = 0.0;
-    B[0] = R.gamma0 * Bl[0];
-    B[1] = R.gamma0 * Bl[1];
-    B[2] = Bl[2];
-}
-
-__device__ inline void boris(double u[3], const double E[3], const double B[3], double dtb)
-{
-    const double ek = kQe * dtb / (2.0 * kMe * kC);
-    double t1[3];
-    for (int a = 0; a < 3; ++a)
-        t1[a] = u[a] - ek * E[a];
-    const double alpha = -kQe * dtb / (2.0 * kMe * sqrt(1.0 + t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]));
-    double t2[3];
-    t2[0] = t1[0] + alpha * (t1[1] * B[2] - t1[2] * B[1]);
-    t2[1] = t1[1] + alpha * (t1[2] * B[0] - t1[0] * B[2]);
-    t2[2] = t1[2] + alpha * (t1[0] * B[1] - t1[1] * B[0]);
-    const double f = 2.0 * alpha / (1.0 + alpha * alpha * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]));
-    const double s[3] = {f * B[0], f * B[1], f * B[2]};
-    u[0] = t1[0] + (t2[1] * s[2] - t2[2] * s[1]) - ek * E[0];
-    u[1] = t1[1] + (t2[2] * s[0] - t2[0] * s[2]) - ek * E[1];
-    u[2] = t1[2] + (t2[0] * s[1] - t2[1] * s[0]) - ek * E[2];
-}
-
-// grid coordinates and active cell (1 <= cell <= n-3 on every axis)
-__device__ inline bool cell_of(const RunDev &R, const double r[3], double g[3], int c[3])
-{
-    g[0] = (r[0] - R.x0) / R.dx;
-    g[1] = (r[1] - R.y0) / R.dy;
-    g[2] = (r[2] - R.z0) / R.dz;
-    const int n[3] = {R.nx, R.ny, R.nz};
-    bool ok = true;
-    for (int a = 0; a < 3; ++a) {
-        const double f = floor(g[a]);
-        ok = ok && (f >= 1.0) && (f <= (double)(n[a] - 3));
-        c[a] = ok ? (int)f : 0;
-    }
-    return ok;
-}
-
-// --- accumulation --------------------------------------------------------
-
-// Global accumulation into source set `set` (J_x J_y J_z rho).  FP64: plain
-// atomic add.  FP32: atomic add of the rounded value; with compensation the
-// exact error of that addition (two-sum on the returned old value) plus the
-// rounding of the FP64 value goes into the second array by another atomic.
-template <typename T, bool COMP>
-struct GlobalAcc {
-    T *A[4];
-    T *Lo[4];
-    int nx;
-    int64_t nxy;
-    // four independent adds (zeros skipped); in the compensated mode all the
-    // returning adds are issued before their errors are added
-    __device__ inline void add4(const double v[4], const int idx[4][4]) const
-    {
-        int64_t at[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            at[q] = (int64_t)idx[q][3] * nxy + (int64_t)idx[q][2] * nx + idx[q][1];
-        if constexpr (sizeof(T) == 8) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (v[q] != 0.0)
-                    atomicAdd(reinterpret_cast<double *>(A[idx[q][0]]) + at[q], v[q]);
-        } else if (!COMP) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (v[q] != 0.0)
-                    atomicAdd(reinterpret_cast<float *>(A[idx[q][0]]) + at[q], (float)v[q]);
-        } else {
-            float vf[4], old[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                vf[q] = (float)v[q];
-                old[q] = 0.0f;
-                if (v[q] != 0.0)
-                    old[q] = atomicAdd(reinterpret_cast<float *>(A[idx[q][0]]) + at[q], vf[q]);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (v[q] != 0.0) {
-                    const float sm = old[q] + vf[q];
-                    const float bv = sm - old[q];
-                    const float err = (old[q] - (sm - bv)) + (vf[q] - bv);
-                    atomicAdd(reinterpret_cast<float *>(Lo[idx[q][0]]) + at[q], err + (float)(v[q] - (double)vf[q]));
-                }
-            }
-        }
-    }
-    __device__ inline void add(int comp, int i, int j, int k, double v) const
-    {
-        const int64_t idx = (int64_t)k * nxy + (int64_t)j * nx + i;
-        if constexpr (sizeof(T) == 8) {
-            atomicAdd(reinterpret_cast<double *>(A[comp]) + idx, v);
-        } else {
-            const float vf = (float)v;
-            const float old = atomicAdd(reinterpret_cast<float *>(A[comp]) + idx, vf);
-            if (COMP) {
-                const float sm = old + vf;
-                const float bv = sm - old;
-                const float err = (old - (sm - bv)) + (vf - bv);
-                atomicAdd(reinterpret_cast<float *>(Lo[comp]) + idx, err + (float)(v - (double)vf));
-            }
-        }
-    }
-};
-
-template <typename T, bool COMP>
-__device__ inline GlobalAcc<T, COMP> make_gacc(const RunDev &R, int set)
-{
-    GlobalAcc<T, COMP> a;
-    for (int c = 0; c < 4; ++c) {
-        a.A[c] = src_ptr<T>(R, set, c);
-        a.Lo[c] = COMP ? srclo_ptr<T>(R, set, c) : nullptr;
-    }
-    a.nx = R.nx;
-    a.nxy = (int64_t)R.nx * R.ny;
-    return a;
-}
-
-// Block-local accumulation in LDS (FP64) over the block's node box.
-struct LdsAcc {
-    double *s;
-    int lo0, lo1, lo2, ex, ey, vol;
-    __device__ inline void add(int comp, int i, int j, int k, double v) const
-    {
-        atomicAdd(&s[comp * vol + ((k - lo2) * ey + (j - lo1)) * ex + (i - lo0)], v);
-    }
-};
-
-// the 12 edge currents of the straight segment a -> b (grid units) inside
-// cell c, ordered per component l as (0,0), (+m1), (+m1+m2), (+m2)
-__device__ inline void segment_weights(const RunDev &R, const double a[3], const double b[3], const int c[3],
-                                       double w[12])
-{
-    double d[3], W[3];
-    for (int l = 0; l < 3; ++l) {
-        d[l] = b[l] - a[l];
-        W[l] = 0.5 * (a[l] + b[l]) - (double)c[l];
-    }
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
-        const double F = R.qV * d[l] * R.h[l] / R.dt;
-        const double x = d[m1] * d[m2] * (1.0 / 12.0);
-        const double u1 = W[m1], u2 = W[m2];
-        w[4 * l] = F * ((1.0 - u1) * (1.0 - u2) + x);
-        w[4 * l + 1] = F * (u1 * (1.0 - u2) - x);
-        w[4 * l + 2] = F * (u1 * u2 + x);
-        w[4 * l + 3] = F * ((1.0 - u1) * u2 - x);
-    }
-}
-
-// current of the straight segment a -> b (grid units) inside cell c
-template <class Acc>
-__device__ inline void segment_current(const RunDev &R, const Acc &acc, const double a[3], const double b[3],
-                                       const int c[3])
-{
-    double d[3], W[3];
-    for (int l = 0; l < 3; ++l) {
-        d[l] = b[l] - a[l];
-        W[l] = 0.5 * (a[l] + b[l]) - (double)c[l];
-    }
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
-        // J_l = q (displacement in metres) / (dt V) times the edge weights
-        const double F = R.qV * d[l] * R.h[l] / R.dt;
-        const double x = d[m1] * d[m2] * (1.0 / 12.0);
-        const double u1 = W[m1], u2 = W[m2];
-        int q[3] = {c[0], c[1], c[2]};
-        acc.add(l, q[0], q[1], q[2], F * ((1.0 - u1) * (1.0 - u2) + x));
-        q[m1] += 1;
-        acc.add(l, q[0], q[1], q[2], F * (u1 * (1.0 - u2) - x));
-        q[m2] += 1;
-        acc.add(l, q[0], q[1], q[2], F * (u1 * u2 + x));
-        q[m1] -= 1;
-        acc.add(l, q[0], q[1], q[2], F * ((1.0 - u1) * u2 - x));
-    }
-}
-
-template <class Acc>
-__device__ inline void deposit_move(const RunDev &R, const Acc &acc, const double g1[3], const int c1[3],
-                                    const double g2[3], const int c2[3])
-{
-    // Same cell before and after: both zigzag halves (relay at the midpoint)
-    // deposit onto the same 12 edges; their values are formed exactly as for
-    // two segments and summed in registers, so one set of 12 adds is issued.
-    if (c1[0] == c2[0] && c1[1] == c2[1] && c1[2] == c2[2]) {
-        double gm[3], w1[12], w2[12];
-        for (int l = 0; l < 3; ++l)
-            gm[l] = fmin((double)c1[l] + 1.0, fmax((double)c1[l], 0.5 * (g1[l] + g2[l])));
-        segment_weights(R, g1, gm, c1, w1);
-        segment_weights(R, gm, g2, c1, w2);
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
-            int q[3] = {c1[0], c1[1], c1[2]};
-            acc.add(l, q[0], q[1], q[2], w1[4 * l] + w2[4 * l]);
-            q[m1] += 1;
-            acc.add(l, q[0], q[1], q[2], w1[4 * l + 1] + w2[4 * l + 1]);
-            q[m2] += 1;
-            acc.add(l, q[0], q[1], q[2], w1[4 * l + 2] + w2[4 * l + 2]);
-            q[m1] -= 1;
-            acc.add(l, q[0], q[1], q[2], w1[4 * l + 3] + w2[4 * l + 3]);
-        }
-        return;
-    }
-    double gr[3];
-    for (int l = 0; l < 3; ++l) {
-        const double lo = (double)min(c1[l], c2[l]) + 1.0;
-        const double hi = (double)max(c1[l], c2[l]);
-        gr[l] = fmin(lo, fmax(hi, 0.5 * (g1[l] + g2[l])));
-    }
-    segment_current(R, acc, g1, gr, c1);
-    segment_current(R, acc, gr, g2, c2);
-}
-
-template <class Acc>
-__device__ inline void deposit_charge(const RunDev &R, const Acc &acc, const double g[3], const int c[3])
-{
-    const double dx = g[0] - c[0], dy = g[1] - c[1], dz = g[2] - c[2];
-    const double wx[2] = {1.0 - dx, dx}, wy[2] = {1.0 - dy, dy}, wz[2] = {1.0 - dz, dz};
-#pragma unroll
-    for (int K = 0; K < 2; ++K)
-#pragma unroll
-        for (int J = 0; J < 2; ++J)
-#pragma unroll
-            for (int I = 0; I < 2; ++I)
-                acc.add(3, c[0] + I, c[1] + J, c[2] + K, R.qV * wx[I] * wy[J] * wz[K]);
-}
-
-__device__ inline int wave_min(int v)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        v = min(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ inline int wave_max(int v)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        v = max(v, __shfl_xor(v, o));
-    return v;
-}
-
+// cosh and sinh of x from one expm1 (no cancellation near x = 0)
 constexpr int kDepThreads = 256;
 constexpr int kLdsNodes = 1536;  // node box capacity of the LDS stage (4 arrays, FP64: 48 KiB)
 
@@ -358,11 +56,15 @@ __global__ __launch_bounds__(kDepThreads) void k_push_deposit(RunDev R)
                 const int64_t sy = R.nx, sz = (int64_t)R.nx * R.ny;
                 const double dx = g1[0] - c1[0], dy = g1[1] - c1[1], dz = g1[2] - c1[2];
                 const double wx[2] = {1.0 - dx, dx}, wy[2] = {1.0 - dy, dy}, wz[2] = {1.0 - dz, dz};
+#pragma unroll
                 for (int K = 0; K < 2; ++K)
+#pragma unroll
                     for (int J = 0; J < 2; ++J)
+#pragma unroll
                         for (int I = 0; I < 2; ++I) {
                             const double w = wx[I] * wy[J] * wz[K];
                             const int64_t n = base + I + J * sy + K * sz;
+#pragma unroll
                             for (int a = 0; a < 3; ++a) {
                                 Eg[a] += w * (double)eb_ptr<T>(R, a)[n];
                                 Bg[a] += w * (double)eb_ptr<T>(R, 3 + a)[n];
@@ -458,7 +160,7 @@ __global__ __launch_bounds__(kDepThreads) void k_push_deposit(RunDev R)
         for (int e = threadIdx.x; e < 4 * vol; e += kDepThreads)
             lds[e] = 0.0;
         __syncthreads();
-        const LdsAcc acc{lds, L0, L1, L2, ex, ey, vol};
+        const LdsAcc<double> acc{lds, L0, L1, L2, ex, ey, vol};
         if (dep_j)
             deposit_move(R, acc, g1, c1, g2, c2);
         if (dep_q)
@@ -549,8 +251,10 @@ static hipError_t launch_dep(const RunDev &R, hipStream_t st)
 // Reduce the per-block partial boxes (and counts) of `nblocks` blocks into
 // lo/hi (and *count if non-null): one block, fixed order.
 __global__ __launch_bounds__(1024) void k_box_reduce(const int32_t *part, int64_t nblocks, int32_t *lo, int32_t *hi,
-                                                    int32_t *count)
+                                                    int32_t *count, int32_t *zero)
 {
+    if (zero && threadIdx.x == 0)
+        *zero = 0;
     __shared__ int32_t sh[7][1024];
     int32_t v[7] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1, 0};
     for (int64_t b = threadIdx.x; b < nblocks; b += 1024) {
@@ -620,9 +324,9 @@ hipError_t launch_box_reduce_set(const RunDev &R, int64_t nblocks, hipStream_t s
 }
 
 hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
-                             int32_t *count, hipStream_t st)
+                             int32_t *count, hipStream_t st, int32_t *zero)
 {
-    hipLaunchKernelGGL(k_box_reduce, dim3(1), dim3(1024), 0, st, part, nblocks, lo, hi, count);
+    hipLaunchKernelGGL(k_box_reduce, dim3(1), dim3(1024), 0, st, part, nblocks, lo, hi, count, zero);
     return hipGetLastError();
 }
 
@@ -644,7 +348,7 @@ hipError_t launch_load_deposit(const RunDev &R, hipStream_t st)
     if (e != hipSuccess)
         return e;
     return launch_box_reduce(R, dep_blocks(R.np), R.boxpart, CTL_ADDR(R.ctl, dep_lo), CTL_ADDR(R.ctl, dep_hi), nullptr,
-                             st);
+                             st, nullptr);
 }
 
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st)

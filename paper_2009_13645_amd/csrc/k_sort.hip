@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_sort_gather(RunDev R, const uint32_t *k
 // ---------------------------------------------------------------------------
 
 hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
-                             int32_t *count, hipStream_t st);
+                             int32_t *count, hipStream_t st, int32_t *zero);
 
 int sort_passes(uint32_t key_inactive)
 {
@@ -258,17 +258,19 @@ int sort_passes(uint32_t key_inactive)
 
 int64_t sort_blocks(int64_t n) { return (n + kSortChunk - 1) / kSortChunk; }
 
-// keys_ready: the push kernel has already written the keys, the slots and
-// its per-block active-cell boxes (R.cellpart, one per 256 particles)
-hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready)
+// keys_ready: the push kernels have already written the keys, the slots
+// and `nparts` per-block active-cell boxes in R.cellpart.  The tile work
+// item counter is reset here, before the items of the new order are built.
+hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts)
 {
     if (R.np <= 0)
         return hipSuccess;
     const unsigned pblocks = (unsigned)((R.np + 255) / 256);
     if (!keys_ready)
         hipLaunchKernelGGL(k_sort_keys, dim3(pblocks), dim3(256), 0, st, R);
-    hipError_t e = launch_box_reduce(R, pblocks, keys_ready ? R.cellpart : R.boxpart, CTL_ADDR(R.ctl, cell_lo),
-                                     CTL_ADDR(R.ctl, cell_hi), CTL_ADDR(R.ctl, n_active), st);
+    hipError_t e = launch_box_reduce(R, keys_ready ? nparts : pblocks, keys_ready ? R.cellpart : R.boxpart,
+                                     CTL_ADDR(R.ctl, cell_lo), CTL_ADDR(R.ctl, cell_hi), CTL_ADDR(R.ctl, n_active),
+                                     st, CTL_ADDR(R.ctl, n_items));
     if (e != hipSuccess)
         return e;
     const int passes = sort_passes(R.key_inactive);

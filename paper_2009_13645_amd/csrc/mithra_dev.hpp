@@ -30,6 +30,10 @@ struct Ctl {
     int32_t cell_hi[3];
     int32_t nan_flag;      // set when a diagnostic sees a non-finite value
     int32_t n_active;      // particles in active cells at the last sort
+    int32_t sorted_active; // n_active of the sort the current push works on
+    int32_t n_items;       // tile work items built after the last sort
+    int32_t item_next;     // next work item to take (persistent push)
+    int32_t pad_;
 };
 
 constexpr int kMaxBatch = 1;  // one run per RunDev
@@ -62,6 +66,7 @@ struct RunDev {
     double mur_be0[3], mur_be1[3], mur_g1[3], mur_ga[3], mur_gb[3];
     double h[3];      // dx dy dz
     double cdt;       // c dt
+    int xface_fused;  // 1: the (vector) sweep also updates the x-face nodes
     int precision;    // 32 or 64
     int compensated;
     // particles
@@ -87,6 +92,9 @@ struct RunDev {
     int64_t sort_blocks;
     int32_t *boxpart;  // per-block partial boxes: [block][8] = lo[3], hi[3], count, pad
     int32_t *cellpart; // per-block partial active-cell boxes of the push kernel, same layout
+    int32_t *items;    // tile work items [n][4] = tile, begin, end, pad
+    int64_t item_cap;
+    int tile_grid;     // persistent blocks of the tile push kernel (0: tile kernel not used)
     double *ppart;     // partial sums of the plane-power kernel
     double *power_hist;
     int64_t power_cap;

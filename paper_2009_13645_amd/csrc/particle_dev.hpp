@@ -1,0 +1,316 @@
+// particle_dev.hpp -- device functions of the particle phase shared by the
+// per-block and the tile-owned push/deposit kernels:
+//  * external static undulator field: lab-frame field at the position
+//    z' = gamma0 (z - z_entrance + beta0 c t) with entrance and exit fringes,
+//    boosted with E' = 0 (MITHRA 2.0 manual, eqs. undulatorField,
+//    fringingField, LorentzTransformR2L, LorentzTransformElectric/Magnetic);
+//    helical = the planar pattern plus its 90-degree rotation a quarter
+//    period upstream;
+//  * Boris momentum update (eq. BorisScheme);
+//  * charge-conserving deposit: zigzag split at the printed relay point,
+//    each segment carrying the exact current of a straight move inside one
+//    cell under linear weights; cloud-in-cell charge.
+#pragma once
+
+#include "mithra_dev.hpp"
+
+namespace mithra {
+
+__device__ inline void cosh_sinh(double x, double &ch, double &sh)
+{
+    const double em = expm1(x);
+    const double inv = 1.0 / (1.0 + em);
+    sh = 0.5 * em * (2.0 + em) * inv;
+    ch = 1.0 + 0.5 * em * em * inv;
+}
+
+// longitudinal profile of the planar pattern at lab z': (g, h) multiply
+// cosh / sinh of the transverse argument for the transverse / longitudinal
+// field: periodic body, fringe before the entrance and (mirrored) after
+// the exit
+__device__ inline void profile(const RunDev &R, double zl, double &g, double &h)
+{
+    if (zl < 0.0 || zl > R.Lu) {
+        const double a = R.ku * (zl < 0.0 ? zl : zl - R.Lu);
+        const double e = exp(-0.5 * a * a);
+        g = a * e;
+        h = e;
+    } else {
+        sincos(R.ku * zl, &g, &h);
+    }
+}
+
+__device__ inline void undulator_field(const RunDev &R, double x, double y, double z, double t, double E[3],
+                                       double B[3])
+{
+    const double zl = R.gamma0 * (z - R.z_ent + R.beta0 * kC * t);
+    double Bl[3];
+    if (R.und_type == 1) {
+        // planar pattern along y at z' plus planar pattern along x at
+        // z' + lambda_u/4; inside the magnet the second profile is the
+        // first shifted by a quarter period: (g, h) -> (h, -g)
+        const double zq = zl + 0.25 * (2.0 * kPi / R.ku);
+        double g1, h1, g2, h2;
+        profile(R, zl, g1, h1);
+        if (zq >= 0.0 && zq <= R.Lu && zl >= 0.0) {
+            g2 = h1;
+            h2 = -g1;
+        } else {
+            profile(R, zq, g2, h2);
+        }
+        double chy, shy, chx, shx;
+        cosh_sinh(R.ku * y, chy, shy);
+        cosh_sinh(R.ku * x, chx, shx);
+        Bl[0] = R.B0 * chx * g2;
+        Bl[1] = R.B0 * chy * g1;
+        Bl[2] = R.B0 * (shy * h1 + shx * h2);
+    } else {
+        double sth, cth, g, h, ch, sh;
+        sincos(R.theta, &sth, &cth);
+        profile(R, zl, g, h);
+        cosh_sinh(R.ku * (x * sth + y * cth), ch, sh);
+        const double bp = R.B0 * ch * g;
+        Bl[0] = bp * sth;
+        Bl[1] = bp * cth;
+        Bl[2] = R.B0 * sh * h;
+    }
+    const double gbc = R.gamma0 * R.beta0 * kC;
+    E[0] = -gbc * Bl[1];
+    E[1] = gbc * Bl[0];
+    E[2] = 0.0;
+    B[0] = R.gamma0 * Bl[0];
+    B[1] = R.gamma0 * Bl[1];
+    B[2] = Bl[2];
+}
+
+__device__ inline void boris(double u[3], const double E[3], const double B[3], double dtb)
+{
+    const double ek = kQe * dtb / (2.0 * kMe * kC);
+    double t1[3];
+    for (int a = 0; a < 3; ++a)
+        t1[a] = u[a] - ek * E[a];
+    const double alpha = -kQe * dtb / (2.0 * kMe * sqrt(1.0 + t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]));
+    double t2[3];
+    t2[0] = t1[0] + alpha * (t1[1] * B[2] - t1[2] * B[1]);
+    t2[1] = t1[1] + alpha * (t1[2] * B[0] - t1[0] * B[2]);
+    t2[2] = t1[2] + alpha * (t1[0] * B[1] - t1[1] * B[0]);
+    const double f = 2.0 * alpha / (1.0 + alpha * alpha * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]));
+    const double s[3] = {f * B[0], f * B[1], f * B[2]};
+    u[0] = t1[0] + (t2[1] * s[2] - t2[2] * s[1]) - ek * E[0];
+    u[1] = t1[1] + (t2[2] * s[0] - t2[0] * s[2]) - ek * E[1];
+    u[2] = t1[2] + (t2[0] * s[1] - t2[1] * s[0]) - ek * E[2];
+}
+
+// grid coordinates and active cell (1 <= cell <= n-3 on every axis)
+__device__ inline bool cell_of(const RunDev &R, const double r[3], double g[3], int c[3])
+{
+    g[0] = (r[0] - R.x0) / R.dx;
+    g[1] = (r[1] - R.y0) / R.dy;
+    g[2] = (r[2] - R.z0) / R.dz;
+    const int n[3] = {R.nx, R.ny, R.nz};
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double f = floor(g[a]);
+        ok = ok && (f >= 1.0) && (f <= (double)(n[a] - 3));
+        c[a] = ok ? (int)f : 0;
+    }
+    return ok;
+}
+
+// --- accumulation --------------------------------------------------------
+
+// Global accumulation into source set `set` (J_x J_y J_z rho).  FP64: plain
+// atomic add.  FP32: atomic add of the rounded value; with compensation the
+// exact error of that addition (two-sum on the returned old value) plus the
+// rounding of the FP64 value goes into the second array by another atomic.
+template <typename T, bool COMP>
+struct GlobalAcc {
+    // the four arrays of a source set are contiguous: array c starts at c * nn
+    T *A0;
+    T *Lo0;
+    int64_t nn;
+    int nx;
+    int64_t nxy;
+    // four independent adds (zeros skipped); in the compensated mode all the
+    // returning adds are issued before their errors are added
+    __device__ inline void add4(const double v[4], const int idx[4][4]) const
+    {
+        int64_t at[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            at[q] = (int64_t)idx[q][3] * nxy + (int64_t)idx[q][2] * nx + idx[q][1];
+        if constexpr (sizeof(T) == 8) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (v[q] != 0.0)
+                    atomicAdd(reinterpret_cast<double *>(A0) + idx[q][0] * nn + at[q], v[q]);
+        } else if (!COMP) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (v[q] != 0.0)
+                    atomicAdd(reinterpret_cast<float *>(A0) + idx[q][0] * nn + at[q], (float)v[q]);
+        } else {
+            float vf[4], old[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                vf[q] = (float)v[q];
+                old[q] = 0.0f;
+                if (v[q] != 0.0)
+                    old[q] = atomicAdd(reinterpret_cast<float *>(A0) + idx[q][0] * nn + at[q], vf[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (v[q] != 0.0) {
+                    const float sm = old[q] + vf[q];
+                    const float bv = sm - old[q];
+                    const float err = (old[q] - (sm - bv)) + (vf[q] - bv);
+                    atomicAdd(reinterpret_cast<float *>(Lo0) + idx[q][0] * nn + at[q], err + (float)(v[q] - (double)vf[q]));
+                }
+            }
+        }
+    }
+    __device__ inline void add(int comp, int i, int j, int k, double v) const
+    {
+        const int64_t idx = (int64_t)k * nxy + (int64_t)j * nx + i;
+        if constexpr (sizeof(T) == 8) {
+            atomicAdd(reinterpret_cast<double *>(A0) + comp * nn + idx, v);
+        } else {
+            const float vf = (float)v;
+            const float old = atomicAdd(reinterpret_cast<float *>(A0) + comp * nn + idx, vf);
+            if (COMP) {
+                const float sm = old + vf;
+                const float bv = sm - old;
+                const float err = (old - (sm - bv)) + (vf - bv);
+                atomicAdd(reinterpret_cast<float *>(Lo0) + comp * nn + idx, err + (float)(v - (double)vf));
+            }
+        }
+    }
+};
+
+template <typename T, bool COMP>
+__device__ inline GlobalAcc<T, COMP> make_gacc(const RunDev &R, int set)
+{
+    GlobalAcc<T, COMP> a;
+    a.A0 = src_ptr<T>(R, set, 0);
+    a.Lo0 = COMP ? srclo_ptr<T>(R, set, 0) : nullptr;
+    a.nn = R.nn;
+    a.nx = R.nx;
+    a.nxy = (int64_t)R.nx * R.ny;
+    return a;
+}
+
+// Block-local accumulation in LDS over a node box (FP64, or FP32 where the
+// run accumulates in FP32 without compensation).
+template <typename AccT = double>
+struct LdsAcc {
+    AccT *s;
+    int lo0, lo1, lo2, ex, ey, vol;
+    __device__ inline void add(int comp, int i, int j, int k, double v) const
+    {
+        atomicAdd(&s[comp * vol + ((k - lo2) * ey + (j - lo1)) * ex + (i - lo0)], (AccT)v);
+    }
+};
+
+// current of the straight segment a -> b (grid units) inside cell c
+template <class Acc>
+__device__ inline void segment_current(const RunDev &R, const Acc &acc, const double a[3], const double b[3],
+                                       const int c[3])
+{
+    double d[3], W[3];
+    for (int l = 0; l < 3; ++l) {
+        d[l] = b[l] - a[l];
+        W[l] = 0.5 * (a[l] + b[l]) - (double)c[l];
+    }
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
+        // J_l = q (displacement in metres) / (dt V) times the edge weights
+        const double F = R.qV * d[l] * R.h[l] / R.dt;
+        const double x = d[m1] * d[m2] * (1.0 / 12.0);
+        const double u1 = W[m1], u2 = W[m2];
+        int q[3] = {c[0], c[1], c[2]};
+        acc.add(l, q[0], q[1], q[2], F * ((1.0 - u1) * (1.0 - u2) + x));
+        q[m1] += 1;
+        acc.add(l, q[0], q[1], q[2], F * (u1 * (1.0 - u2) - x));
+        q[m2] += 1;
+        acc.add(l, q[0], q[1], q[2], F * (u1 * u2 + x));
+        q[m1] -= 1;
+        acc.add(l, q[0], q[1], q[2], F * ((1.0 - u1) * u2 - x));
+    }
+}
+
+template <class Acc>
+__device__ inline void deposit_move(const RunDev &R, const Acc &acc, const double g1[3], const int c1[3],
+                                    const double g2[3], const int c2[3])
+{
+    // Same cell before and after: both zigzag halves (relay at the midpoint)
+    // deposit onto the same 12 edges; their values are formed exactly as for
+    // two segments and summed in registers, so one set of 12 adds is issued.
+    if (c1[0] == c2[0] && c1[1] == c2[1] && c1[2] == c2[2]) {
+        double d1[3], d2[3], W1[3], W2[3];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const double gm = fmin((double)c1[l] + 1.0, fmax((double)c1[l], 0.5 * (g1[l] + g2[l])));
+            d1[l] = gm - g1[l];
+            d2[l] = g2[l] - gm;
+            W1[l] = 0.5 * (g1[l] + gm) - (double)c1[l];
+            W2[l] = 0.5 * (gm + g2[l]) - (double)c1[l];
+        }
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
+            const double F1 = R.qV * d1[l] * R.h[l] / R.dt, F2 = R.qV * d2[l] * R.h[l] / R.dt;
+            const double x1 = d1[m1] * d1[m2] * (1.0 / 12.0), x2 = d2[m1] * d2[m2] * (1.0 / 12.0);
+            const double a1 = W1[m1], b1 = W1[m2], a2 = W2[m1], b2 = W2[m2];
+            int q[3] = {c1[0], c1[1], c1[2]};
+            acc.add(l, q[0], q[1], q[2],
+                    F1 * ((1.0 - a1) * (1.0 - b1) + x1) + F2 * ((1.0 - a2) * (1.0 - b2) + x2));
+            q[m1] += 1;
+            acc.add(l, q[0], q[1], q[2], F1 * (a1 * (1.0 - b1) - x1) + F2 * (a2 * (1.0 - b2) - x2));
+            q[m2] += 1;
+            acc.add(l, q[0], q[1], q[2], F1 * (a1 * b1 + x1) + F2 * (a2 * b2 + x2));
+            q[m1] -= 1;
+            acc.add(l, q[0], q[1], q[2], F1 * ((1.0 - a1) * b1 - x1) + F2 * ((1.0 - a2) * b2 - x2));
+        }
+        return;
+    }
+    double gr[3];
+    for (int l = 0; l < 3; ++l) {
+        const double lo = (double)min(c1[l], c2[l]) + 1.0;
+        const double hi = (double)max(c1[l], c2[l]);
+        gr[l] = fmin(lo, fmax(hi, 0.5 * (g1[l] + g2[l])));
+    }
+    segment_current(R, acc, g1, gr, c1);
+    segment_current(R, acc, gr, g2, c2);
+}
+
+template <class Acc>
+__device__ inline void deposit_charge(const RunDev &R, const Acc &acc, const double g[3], const int c[3])
+{
+    const double dx = g[0] - c[0], dy = g[1] - c[1], dz = g[2] - c[2];
+    const double wx[2] = {1.0 - dx, dx}, wy[2] = {1.0 - dy, dy}, wz[2] = {1.0 - dz, dz};
+#pragma unroll
+    for (int K = 0; K < 2; ++K)
+#pragma unroll
+        for (int J = 0; J < 2; ++J)
+#pragma unroll
+            for (int I = 0; I < 2; ++I)
+                acc.add(3, c[0] + I, c[1] + J, c[2] + K, R.qV * wx[I] * wy[J] * wz[K]);
+}
+
+__device__ inline int wave_min(int v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ inline int wave_max(int v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+}  // namespace mithra
