@@ -418,7 +418,7 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     // row length allows 16-byte vectors, else the scalar tiles
     const int vec = d->field_precision == 32 ? 4 : 2;
     if (d->nx % vec == 0)
-        h->sweep_shape = d->nx <= 48 ? 13 : (d->nx <= 80 ? 10 : 8);
+        h->sweep_shape = d->nx <= 48 ? 13 : (d->nx <= 80 ? 17 : 14);
     else
         h->sweep_shape = (d->nx - 2 <= 40) ? 2 : 0;
     const char *sh = getenv("MITHRA_SWEEP_SHAPE");

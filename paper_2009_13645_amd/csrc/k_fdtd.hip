@@ -20,6 +20,7 @@
 //  * k_vertex_fields: E and B at vertices (sec. "Field Evaluation"):
 //    E = -(A^{n+1} - A^n)/dt - grad phi, B = mean of curl A^n and curl A^{n+1}.
 #include "mithra_dev.hpp"
+#include <type_traits>
 
 namespace mithra {
 
@@ -212,11 +213,47 @@ __device__ inline void vstore(T *p, const Vec<T, V> &a)
     }
 }
 
-template <typename T, int V, int TXV, int TY, int TZ>
+// Streaming (non-temporal) 16-byte accesses: data touched once per sweep
+// (psi^{n-1}, psi^{n+1}, the cleared source set) bypass cache retention so
+// that the psi^n stencil planes stay in L2.
+typedef unsigned int nt_u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int V>
+__device__ inline void vstore_nt(T *p, const Vec<T, V> &a)
+{
+    static_assert(sizeof(T) * V == 16, "16-byte vectors only");
+    nt_u32x4 w;
+    memcpy(&w, &a, 16);
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_u32x4 *>(p));
+}
+
+template <typename T, int V>
+__device__ inline Vec<T, V> vload_nt(const T *p)
+{
+    static_assert(sizeof(T) * V == 16, "16-byte vectors only");
+    const nt_u32x4 w = __builtin_nontemporal_load(reinterpret_cast<const nt_u32x4 *>(p));
+    Vec<T, V> r;
+    memcpy(&r, &w, 16);
+    return r;
+}
+
+// Sources of one thread's V nodes on one plane: own edge/node values (a),
+// the edge one step back along the component's axis (b, vector) or the
+// left neighbour of the first node (lf, x component), with the two-sum low
+// parts when compensated.
+template <typename T, int V, bool LO>
+struct PlaneSrc {
+    Vec<T, V> pm, a, al, b, bl;
+    T lf, lfl;
+};
+
+template <typename T, int V, int TXV, int TY, int TZ, bool LO>
 __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
 {
     constexpr int TW = TXV * V;                          // tile width in nodes
     constexpr int ROW = ((V + TW + 1) + V - 1) / V * V;  // LDS row: pad(V-1), left halo, tile, right halo
+    // source sums: FP64 for FP64 fields and for compensated FP32 (hi + lo)
+    using ST = typename std::conditional<LO || sizeof(T) == 8, double, T>::type;
     __shared__ __attribute__((aligned(16))) T sb[2][TY + 2][ROW];
     // psi^n at the two outermost nodes of each row end (x-face update)
     __shared__ T rawe[2][TY + 2][4];
@@ -241,6 +278,7 @@ __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
     const int j = tile_y * TY + ly;
     const bool inb = (i0 < R.nx) && (j < R.ny);
     const bool rowvalid = inb && j >= 1 && j <= R.ny - 2;
+    const bool work = rowvalid && update;
     const int64_t plane = (int64_t)R.nx * R.ny;
     const int64_t col = inb ? ((int64_t)j * R.nx + i0) : 0;
 
@@ -279,14 +317,50 @@ __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
     const int *chi = R.ctl->dep_hi[set_c];
     const bool src_col = rowvalid && i0 + V - 1 >= rlo[0] && i0 <= rhi[0] + 1 && j >= rlo[1] && j <= rhi[1] + 1;
     const bool clr_col = rowvalid && i0 + V - 1 >= clo[0] && i0 <= chi[0] && j >= clo[1] && j <= chi[1];
+    const int sk_lo = rlo[2], sk_hi = rhi[2] + 1;
     const T *J = src_ptr<T>(R, set_r, comp);
-    const T *Jl = R.compensated ? srclo_ptr<T>(R, set_r, comp) : nullptr;
+    const T *Jl = LO ? srclo_ptr<T>(R, set_r, comp) : nullptr;
     T *clr = src_ptr<T>(R, set_c, comp);
-    T *clr_lo = R.compensated ? srclo_ptr<T>(R, set_c, comp) : nullptr;
-    const double sfac = comp < 3 ? 0.5 * R.sfac_A : R.sfac_phi;
+    T *clr_lo = LO ? srclo_ptr<T>(R, set_c, comp) : nullptr;
+    const ST sfac = (ST)(comp < 3 ? 0.5 * R.sfac_A : R.sfac_phi);
 
     const T cA = (T)R.A, c1A = (T)(1.0 - 2.0 * R.A);
     const T a1 = (T)R.a1, a2 = (T)R.a2, a4 = (T)R.a4, a6 = (T)R.a6;
+
+    // psi^{n-1} and the sources of plane kk; the z component's back edge is
+    // the previous plane's own edge, carried in registers (zero below the
+    // source box, where the source is zero)
+    auto fetch = [&](int kk, const PlaneSrc<T, V, LO> &prv) {
+        PlaneSrc<T, V, LO> r{};
+        if (!work)
+            return r;
+        const int64_t c = (int64_t)kk * plane + col;
+        r.pm = vload_nt<T, V>(prev + c);
+        if (src_col && kk >= sk_lo && kk <= sk_hi) {
+            r.a = vload<T, V>(J + c);
+            if constexpr (LO)
+                r.al = vload<T, V>(Jl + c);
+            if (comp == 0) {
+                r.lf = J[c - 1];
+                if constexpr (LO)
+                    r.lfl = Jl[c - 1];
+            } else if (comp == 1) {
+                r.b = vload<T, V>(J + c - R.nx);
+                if constexpr (LO)
+                    r.bl = vload<T, V>(Jl + c - R.nx);
+            } else if (comp == 2) {
+                if (kk > kb && kk - 1 >= sk_lo) {
+                    r.b = prv.a;
+                    r.bl = prv.al;
+                } else {
+                    r.b = vload<T, V>(J + c - plane);
+                    if constexpr (LO)
+                        r.bl = vload<T, V>(Jl + c - plane);
+                }
+            }
+        }
+        return r;
+    };
 
     Vec<T, V> qm{}, q0{}, qp{}, hm{}, h0{}, hp{};
     if (inb) {
@@ -305,10 +379,13 @@ __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
             hp.v[0] = cur[(int64_t)(kb + 1) * plane + hcol];
         }
     }
+    PlaneSrc<T, V, LO> ps = fetch(kb, PlaneSrc<T, V, LO>{});
 
     for (int k = kb; k < ke; ++k) {
         const int64_t c = (int64_t)k * plane + col;
+        // prefetch: psi^n two planes up, psi^{n-1} and sources one plane up
         Vec<T, V> pf{}, hpf{};
+        PlaneSrc<T, V, LO> pn{};
         if (k + 1 < ke) {
             if (inb)
                 pf = vload<T, V>(cur + c + 2 * plane);
@@ -318,44 +395,29 @@ __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
                 else
                     hpf.v[0] = cur[(int64_t)(k + 2) * plane + hcol];
             }
+            pn = fetch(k + 1, ps);
         }
-        Vec<T, V> pm{};
-        double sv[V];
-        for (int e = 0; e < V; ++e)
-            sv[e] = 0.0;
-        if (rowvalid && update) {
-            pm = vload<T, V>(prev + c);
-            if (src_col && k >= rlo[2] && k <= rhi[2] + 1) {
-                const Vec<T, V> a = vload<T, V>(J + c);
-                Vec<T, V> al{};
-                if (Jl)
-                    al = vload<T, V>(Jl + c);
-                if (comp == 3) {
-                    for (int e = 0; e < V; ++e)
-                        sv[e] = (double)a.v[e] + (double)al.v[e];
-                } else if (comp == 0) {
-                    double left = (double)J[c - 1] + (Jl ? (double)Jl[c - 1] : 0.0);
-                    for (int e = 0; e < V; ++e) {
-                        const double own = (double)a.v[e] + (double)al.v[e];
-                        sv[e] = own + left;
-                        left = own;
-                    }
-                } else {
-                    const int64_t back = comp == 1 ? R.nx : plane;
-                    const Vec<T, V> b = vload<T, V>(J + c - back);
-                    Vec<T, V> bl{};
-                    if (Jl)
-                        bl = vload<T, V>(Jl + c - back);
-                    for (int e = 0; e < V; ++e)
-                        sv[e] = (double)a.v[e] + (double)al.v[e] + (double)b.v[e] + (double)bl.v[e];
-                }
+        ST sv[V];
+        if (comp == 3) {
+            for (int e = 0; e < V; ++e)
+                sv[e] = (ST)ps.a.v[e] + (LO ? (ST)ps.al.v[e] : (ST)0);
+        } else if (comp == 0) {
+            ST left = (ST)ps.lf + (LO ? (ST)ps.lfl : (ST)0);
+            for (int e = 0; e < V; ++e) {
+                const ST own = (ST)ps.a.v[e] + (LO ? (ST)ps.al.v[e] : (ST)0);
+                sv[e] = own + left;
+                left = own;
             }
+        } else {
+            for (int e = 0; e < V; ++e)
+                sv[e] = LO ? ((ST)ps.a.v[e] + (ST)ps.al.v[e]) + ((ST)ps.b.v[e] + (ST)ps.bl.v[e])
+                           : (ST)ps.a.v[e] + (ST)ps.b.v[e];
         }
         if (clr_col && k >= clo[2] && k <= chi[2]) {
             const Vec<T, V> z{};
-            vstore<T, V>(clr + c, z);
-            if (clr_lo)
-                vstore<T, V>(clr_lo + c, z);
+            vstore_nt<T, V>(clr + c, z);
+            if constexpr (LO)
+                vstore_nt<T, V>(clr_lo + c, z);
         }
         T(*buf)[ROW] = sb[k & 1];
         Vec<T, V> bar;
@@ -393,7 +455,7 @@ __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
             }
         }
         __syncthreads();
-        if (rowvalid && update) {
+        if (work) {
             const T left = buf[ly + 1][V + lx * V - 1];
             const T right = buf[ly + 1][V + lx * V + V];
             const Vec<T, V> dn = vload<T, V>(&buf[ly][V + lx * V]);
@@ -403,7 +465,7 @@ __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
                 const T xl = e == 0 ? left : bar.v[e - 1];
                 const T xr = e == V - 1 ? right : bar.v[e + 1];
                 out.v[e] = a1 * q0.v[e] + a2 * (xl + xr) + a4 * (dn.v[e] + up.v[e]) + a6 * (qp.v[e] + qm.v[e]) -
-                           pm.v[e] + (T)(sfac * sv[e]);
+                           ps.pm.v[e] + (T)(sfac * sv[e]);
             }
             // the x-face nodes of the row: Mur update (faces of the x axis,
             // transverse y and z), from this thread's own columns, the
@@ -421,6 +483,7 @@ __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
                     }
                     const int ro = side == 0 ? 0 : 2;
                     const int rb = side == 0 ? ro : ro + 1, ri = side == 0 ? ro + 1 : ro;
+                    const Vec<T, V> &pm = ps.pm;
                     double v = R.mur_be0[0] * ((double)pm.v[eb] + (double)out.v[ei]) - (double)pm.v[ei];
                     if (R.order == 1) {
                         v += R.mur_be1[0] * ((double)q0.v[eb] + (double)q0.v[ei]);
@@ -435,7 +498,7 @@ __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
                     out.v[eb] = (T)v;
                 }
             }
-            vstore<T, V>(next + c, out);
+            vstore_nt<T, V>(next + c, out);
         }
         qm = q0;
         q0 = qp;
@@ -443,6 +506,7 @@ __global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
         hm = h0;
         h0 = hp;
         hp = hpf;
+        ps = pn;
     }
 }
 
@@ -778,7 +842,13 @@ static hipError_t launch_sweep_vec_t(const RunDev &R, hipStream_t st)
     const int64_t ntx = (R.nx + TW - 1) / TW, nty = (R.ny + TY - 1) / TY;
     const int64_t nch = (R.nz - 2 + TZ - 1) / TZ;
     const int64_t nb = ntx * nty * nch * 4;
-    hipLaunchKernelGGL((k_sweep_vec<T, V, TXV, TY, TZ>), dim3((unsigned)nb), dim3(TXV * TY), 0, st, R);
+    if constexpr (sizeof(T) == 4) {
+        if (R.compensated) {
+            hipLaunchKernelGGL((k_sweep_vec<T, V, TXV, TY, TZ, true>), dim3((unsigned)nb), dim3(TXV * TY), 0, st, R);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_sweep_vec<T, V, TXV, TY, TZ, false>), dim3((unsigned)nb), dim3(TXV * TY), 0, st, R);
     return hipGetLastError();
 }
 
@@ -801,6 +871,10 @@ static hipError_t launch_sweep_shape(const RunDev &R, int shape, hipStream_t st)
     case 11: return launch_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 16>(R, st);
     case 12: return launch_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 64>(R, st);
     case 13: return launch_sweep_vec_t<T, V, 32 / V, 256 * V / 32, 32>(R, st);
+    case 14: return launch_sweep_vec_t<T, V, 128 / V, 256 * V / 128, 16>(R, st);
+    case 15: return launch_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 8>(R, st);
+    case 16: return launch_sweep_vec_t<T, V, 128 / V, 1024 * V / 128, 16>(R, st);
+    case 17: return launch_sweep_vec_t<T, V, 64 / V, 512 * V / 64, 16>(R, st);
     case 0: return launch_sweep_t<T, 64, 8, 32>(R, st);
     case 1: return launch_sweep_t<T, 64, 4, 32>(R, st);
     case 2: return launch_sweep_t<T, 32, 8, 32>(R, st);
@@ -813,15 +887,16 @@ static hipError_t launch_sweep_shape(const RunDev &R, int shape, hipStream_t st)
     }
 }
 
-int sweep_shape_count() { return 14; }
+int sweep_shape_count() { return 18; }
 
 // Tile of each shape in nodes (x, y, z) for FP32; shapes 8..13 are the
 // vector kernels (4 FP32 or 2 FP64 nodes per thread; y rows halve in FP64).
 void sweep_shape_dims(int shape, int *tx, int *ty, int *tz)
 {
-    static const int d[14][3] = {{64, 8, 32},  {64, 4, 32},  {32, 8, 32},  {64, 8, 64},  {128, 4, 32},
+    static const int d[18][3] = {{64, 8, 32},  {64, 4, 32},  {32, 8, 32},  {64, 8, 64},  {128, 4, 32},
                                  {64, 16, 32}, {32, 4, 16},  {64, 8, 16},  {128, 16, 32}, {128, 8, 32},
-                                 {64, 32, 32}, {128, 16, 16}, {128, 16, 64}, {32, 32, 32}};
+                                 {64, 32, 32}, {128, 16, 16}, {128, 16, 64}, {32, 32, 32}, {128, 8, 16},
+                                 {128, 16, 8}, {128, 32, 16}, {64, 32, 16}};
     *tx = d[shape][0];
     *ty = d[shape][1];
     *tz = d[shape][2];
