@@ -177,6 +177,59 @@ int mithra_time_sweep(mithra_handle h, int shape, int iters, double *ms);
  * EDEVICE. */
 int mithra_step_timed(mithra_handle h, int64_t n_steps, double *sweep_ms, double *step_ms);
 
+/* Sweep-shape autotuner: times every distinct sweep tile shape on this
+ * run's grid, each with the boundary kernel it implies, over `iters`
+ * launches, selects the fastest for the handle and writes it to
+ * *best_shape (nullable).  Results are cached per (precision,
+ * compensation, space charge, grid size) for the process.  The run's state
+ * is unchanged.  Errors: EINVAL, ESTATE (no bunch loaded), EDEVICE. */
+int mithra_autotune_sweep(mithra_handle h, int iters, int *best_shape);
+
+/* ---- Batches: many independent runs stepped together -------------------
+ *
+ * Runs of different grid sizes, particle counts, precisions and sweep
+ * shapes, each created and loaded as usual, are stepped by grouped
+ * launches: every stage of the PIC step is one launch per kernel variant
+ * for all member runs that use it, the members' workgroups laid end to
+ * end.  One batched step is captured into a HIP graph at creation and
+ * replayed.  Each member stops at its own step count.  Results are those
+ * of the same runs stepped alone (the step arithmetic of a run does not
+ * depend on the other members; only the order of floating-point atomic
+ * additions in the deposit may differ, as between two solo runs).
+ *
+ * While a handle belongs to a batch, mithra_step and mithra_step_timed on
+ * it fail with ESTATE; the read calls synchronise the batch stream as well
+ * as the handle's own.  Destroy the batch before destroying its members. */
+typedef struct mithra_batch_s *mithra_batch;
+
+/* Device workspace needed by a batch of n runs (group tables), or 0 for
+ * n <= 0.  Pure function. */
+size_t mithra_batch_workspace_bytes(int32_t n_runs);
+
+/* Create a batch of n distinct loaded handles (not using the tile-owned
+ * particle kernel, not in another batch) on `hip_stream`, borrowing
+ * `dev_workspace` (256-byte aligned, at least the size above) for the
+ * batch's lifetime.  Synchronises the members' streams.  Errors: EINVAL,
+ * ENOMEM (workspace), ESTATE (a member not loaded or already batched),
+ * EDEVICE. */
+int mithra_batch_create(const mithra_handle *runs, int32_t n_runs, void *dev_workspace, size_t workspace_bytes,
+                        void *hip_stream, mithra_batch *out);
+
+/* Advance member i by n_steps[i] >= 0 steps (array of n_runs).  Waits for
+ * the batch's previous work, then enqueues max_i n_steps[i] replays of the
+ * batched step and returns without waiting.  Errors: EINVAL, EDEVICE. */
+int mithra_batch_run(mithra_batch b, const int64_t *n_steps);
+
+/* Wait for the batch's enqueued work. */
+int mithra_batch_sync(mithra_batch b);
+
+/* Message of the last error on the batch (never NULL). */
+const char *mithra_batch_last_error(mithra_batch b);
+
+/* Wait for the batch's work and release it; the members become ordinary
+ * handles again (their step counts include the batched steps). */
+int mithra_batch_destroy(mithra_batch b);
+
 /* Message of the last error on this handle (never NULL). */
 const char *mithra_last_error(mithra_handle h);
 

@@ -16,7 +16,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "mithra.h"
@@ -38,6 +41,20 @@ hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *pa
                              int32_t *count, hipStream_t st, int32_t *zero);
 hipError_t launch_box_reduce_set(const RunDev &R, int64_t nblocks, hipStream_t st);
 bool tile_kernel_fits(const int tile[3]);
+int64_t sweep_blocks(const RunDev &R, int shape);
+hipError_t launch_sweep_group(const Group &g, int64_t total, int precision, int compensated, int shape,
+                              hipStream_t st);
+int64_t mur_blocks(const RunDev &R);
+hipError_t launch_mur_group(const Group &g, int64_t total, int precision, hipStream_t st);
+int64_t vertex_blocks(const RunDev &R);
+hipError_t launch_vertex_group(const Group &g, int64_t total, int precision, hipStream_t st);
+int64_t power_blocks();
+hipError_t launch_power_group(const Group &g, int64_t total, const Group &gf, int64_t total_f, int precision,
+                              hipStream_t st);
+hipError_t launch_push_group(const Group &g, int64_t total, int precision, int compensated, hipStream_t st);
+hipError_t launch_box_group(const Group &g, int64_t total, hipStream_t st);
+hipError_t launch_sort_group(const Group &gs, int64_t total_s, const Group &gd, int64_t total_d, const Group &gp,
+                             int64_t total_p, int max_passes, hipStream_t st);
 int tile_partials(const RunDev &R);
 hipError_t launch_tile_items(const RunDev &R, hipStream_t st);
 hipError_t launch_tile_step(const RunDev &R, hipStream_t st);
@@ -51,7 +68,7 @@ int64_t sort_blocks(int64_t n);
 
 // after the vertex fields of step s: empty the deposit box of set (s+1)&1
 // (its stale entries were cleared by the sweep) and the active-cell box
-__global__ void k_book_mid(Ctl *ctl)
+__device__ inline void book_mid(Ctl *ctl)
 {
     const int set = (int)((ctl->step + 1) & 1);
     ctl->sorted_active = ctl->n_active;
@@ -65,13 +82,26 @@ __global__ void k_book_mid(Ctl *ctl)
     ctl->n_active = 0;
 }
 
-__global__ void k_book_end(Ctl *ctl, int advance)
+__device__ inline void book_end(Ctl *ctl, int advance)
 {
     ctl->pbuf ^= 1;
     ctl->nsort += 1;
     if (advance)
         ctl->step += 1;
 }
+
+__global__ void k_book_mid(Ctl *ctl) { book_mid(ctl); }
+__global__ void k_book_end(Ctl *ctl, int advance) { book_end(ctl, advance); }
+
+struct BookMid {
+    static constexpr int kThreads = 1;
+    static __device__ void run(const RunDev &R, Blk) { book_mid(R.ctl); }
+};
+
+struct BookEnd {
+    static constexpr int kThreads = 1;
+    static __device__ void run(const RunDev &R, Blk) { book_end(R.ctl, 1); }
+};
 
 __global__ void k_book_mid_load(Ctl *ctl)
 {
@@ -159,8 +189,21 @@ struct mithra_engine {
     int32_t *cell_by_id = nullptr;
     hipGraphExec_t graph = nullptr;
     int use_graph = 1;
+    bool batched = false;              // the run belongs to a batch
+    hipStream_t ext_stream = nullptr;  // that batch's stream
     std::string err;
 };
+
+// the run's own stream and, while it belongs to a batch, the batch's stream
+static hipError_t sync_run(mithra_handle h)
+{
+    if (h->batched) {
+        hipError_t e = hipStreamSynchronize(h->ext_stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipStreamSynchronize(h->stream);
+}
 
 static int fail(mithra_handle h, int code, const char *fmt, ...)
 {
@@ -402,7 +445,7 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
         c0.cell_hi[a] = -1;
     }
     HIPCHK(h, hipMemcpyAsync(R.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, sync_run(h));
     // persistent grid of the tile-owned particle kernel
     // particle kernel: per-block LDS-staged deposit (default; measured faster
     // on the benchmark run) or the tile-owned kernel ("tile")
@@ -478,7 +521,7 @@ extern "C" int mithra_load_bunch(mithra_handle h, int64_t n, const double *xyz, 
     } else {
         HIPCHK(h, launch_load_deposit(R, h->stream));
     }
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, sync_run(h));
     h->loaded = true;
     return MITHRA_OK;
 }
@@ -584,6 +627,8 @@ extern "C" int mithra_step(mithra_handle h, int64_t n_steps)
         return fail(h, MITHRA_ESTATE, "no bunch loaded");
     if (n_steps < 0)
         return fail(h, MITHRA_EINVAL, "negative step count");
+    if (h->batched)
+        return fail(h, MITHRA_ESTATE, "the run belongs to a batch: step it with mithra_batch_run");
     for (int64_t i = 0; i < n_steps; ++i) {
         if (h->use_graph) {
             if (!h->graph) {
@@ -619,7 +664,7 @@ extern "C" int mithra_read_fields(mithra_handle h, int field_id, int dtype, void
     const size_t esz = dtype == MITHRA_DTYPE_F32 ? 4 : 8;
     if (field_id < 0 || field_id > MITHRA_FIELD_RHO || (dtype != 0 && dtype != 1) || !host_out || bytes != nn * esz)
         return fail(h, MITHRA_EINVAL, "bad field id, dtype, buffer or size");
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, sync_run(h));
     int rc = check_nan(h);
     if (rc)
         return rc;
@@ -633,7 +678,7 @@ extern "C" int mithra_read_fields(mithra_handle h, int field_id, int dtype, void
             return MITHRA_OK;
         }
         HIPCHK(h, launch_vertex_fields(R, -1, 1, h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
+        HIPCHK(h, sync_run(h));
         src = (const char *)R.eb + (size_t)field_id * nn * pf;
     } else if (field_id <= MITHRA_FIELD_AZ || field_id == MITHRA_FIELD_PHI) {
         const int comp = field_id == MITHRA_FIELD_PHI ? 3 : field_id - MITHRA_FIELD_AX;
@@ -669,7 +714,7 @@ extern "C" int mithra_read_particles(mithra_handle h, double *xyz, double *u, in
         return MITHRA_EINVAL;
     if (!h->loaded)
         return fail(h, MITHRA_ESTATE, "no bunch loaded");
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, sync_run(h));
     int rc = check_nan(h);
     if (rc)
         return rc;
@@ -694,7 +739,7 @@ extern "C" int mithra_read_particles(mithra_handle h, double *xyz, double *u, in
         hipLaunchKernelGGL(k_cells_by_id, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream, R,
                            h->cell_by_id);
         HIPCHK(h, hipGetLastError());
-        HIPCHK(h, hipStreamSynchronize(h->stream));
+        HIPCHK(h, sync_run(h));
         HIPCHK(h, hipMemcpy(cell, h->cell_by_id, (size_t)n * 4, hipMemcpyDeviceToHost));
     }
     return MITHRA_OK;
@@ -714,7 +759,7 @@ extern "C" int mithra_radiated_power(mithra_handle h, int32_t k_plane, double *p
     }
     double *dev = (double *)(h->arena + h->L.scratch) + 3 * kBunchBlocks;
     HIPCHK(h, launch_plane_power(h->R, -1, k_plane, dev, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, sync_run(h));
     HIPCHK(h, hipMemcpy(p_lab_W, dev, 8, hipMemcpyDeviceToHost));
     return MITHRA_OK;
 }
@@ -723,7 +768,7 @@ extern "C" int64_t mithra_power_history(mithra_handle h, double *out, int64_t n)
 {
     if (!h || !out || n < 0)
         return MITHRA_EINVAL;
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, sync_run(h));
     int64_t m = h->steps < n ? h->steps : n;
     if (m > kPowerCap)
         m = kPowerCap;
@@ -740,7 +785,7 @@ extern "C" int mithra_bunching(mithra_handle h, double *b)
         return fail(h, MITHRA_ESTATE, "no bunch loaded");
     double *part = (double *)(h->arena + h->L.scratch);
     HIPCHK(h, launch_bunching(h->R, part, kBunchBlocks, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, sync_run(h));
     std::vector<double> hp(3 * kBunchBlocks);
     HIPCHK(h, hipMemcpy(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost));
     double re = 0, im = 0, n = 0;
@@ -791,6 +836,8 @@ extern "C" int mithra_set_sweep_shape(mithra_handle h, int shape)
 {
     if (!h || shape < 0 || shape >= sweep_shape_count())
         return MITHRA_EINVAL;
+    if (h->batched)
+        return fail(h, MITHRA_ESTATE, "the run belongs to a batch: its sweep shape is fixed");
     h->sweep_shape = shape;
     h->R.xface_fused = sweep_fuses_xfaces(h->R, shape);
     if (h->graph) {
@@ -812,6 +859,8 @@ extern "C" int mithra_step_timed(mithra_handle h, int64_t n, double *sweep_ms, d
         return MITHRA_EINVAL;
     if (!h->loaded)
         return fail(h, MITHRA_ESTATE, "no bunch loaded");
+    if (h->batched)
+        return fail(h, MITHRA_ESTATE, "the run belongs to a batch: step it with mithra_batch_run");
     std::vector<hipEvent_t> ev((size_t)(3 * n + 1));
     for (auto &e : ev)
         HIPCHK(h, hipEventCreate(&e));
@@ -858,6 +907,7 @@ extern "C" int mithra_time_sweep(mithra_handle h, int shape, int iters, double *
     if (!h->loaded)
         return fail(h, MITHRA_ESTATE, "no bunch loaded");
     const int sh = shape < 0 ? h->sweep_shape : shape;
+    HIPCHK(h, sync_run(h));
     hipEvent_t e0, e1;
     HIPCHK(h, hipEventCreate(&e0));
     HIPCHK(h, hipEventCreate(&e1));
@@ -872,5 +922,407 @@ extern "C" int mithra_time_sweep(mithra_handle h, int shape, int iters, double *
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *ms = (double)t / iters;
+    return MITHRA_OK;
+}
+
+// ===========================================================================
+// Sweep-shape autotuner
+// ===========================================================================
+
+namespace {
+struct TuneKey {
+    int32_t prec, comp, sc, nx, ny, nz;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(prec, comp, sc, nx, ny, nz) < std::tie(o.prec, o.comp, o.sc, o.nx, o.ny, o.nz);
+    }
+};
+std::map<TuneKey, int> g_tuned;
+std::mutex g_tune_mu;
+}  // namespace
+
+// Time every distinct effective sweep shape, each together with the Mur
+// kernel it implies (the vector shapes update the x faces themselves), and
+// keep the fastest.  Results are cached per (precision, compensation, space
+// charge, grid) for the process.  Repeating sweep and Mur leaves the run's
+// state unchanged.
+extern "C" int mithra_autotune_sweep(mithra_handle h, int iters, int *best_shape)
+{
+    if (!h || iters < 1)
+        return MITHRA_EINVAL;
+    if (!h->loaded)
+        return fail(h, MITHRA_ESTATE, "no bunch loaded");
+    const TuneKey key{h->d.field_precision, h->d.compensated, h->d.space_charge, h->d.nx, h->d.ny, h->d.nz};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            if (best_shape)
+                *best_shape = it->second;
+            return mithra_set_sweep_shape(h, it->second);
+        }
+    }
+    HIPCHK(h, sync_run(h));
+    const int V = h->R.precision == 32 ? 4 : 2;
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    const int saved_fuse = h->R.xface_fused;
+    int best = h->sweep_shape;
+    float best_t = 1e30f;
+    for (int sh = 0; sh < sweep_shape_count(); ++sh) {
+        if (sh >= 8 && h->R.nx % V != 0)
+            continue;  // falls back to shape 0, timed already
+        RunDev R = h->R;
+        R.xface_fused = sweep_fuses_xfaces(R, sh);
+        HIPCHK(h, launch_sweep(R, sh, h->stream));
+        HIPCHK(h, launch_mur(R, h->stream));
+        HIPCHK(h, hipEventRecord(e0, h->stream));
+        for (int i = 0; i < iters; ++i) {
+            HIPCHK(h, launch_sweep(R, sh, h->stream));
+            HIPCHK(h, launch_mur(R, h->stream));
+        }
+        HIPCHK(h, hipEventRecord(e1, h->stream));
+        HIPCHK(h, hipEventSynchronize(e1));
+        float t = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&t, e0, e1));
+        if (t < best_t) {
+            best_t = t;
+            best = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->R.xface_fused = saved_fuse;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[key] = best;
+    }
+    if (best_shape)
+        *best_shape = best;
+    return mithra_set_sweep_shape(h, best);
+}
+
+// ===========================================================================
+// Batches: several runs stepped together by grouped launches
+// ===========================================================================
+//
+// Every stage of the step is one launch per kernel variant for all member
+// runs that use it (precision, compensation, sweep shape); the workgroups
+// of a launch are the members' grids laid end to end (k_group).  One
+// batched step is captured into a graph.  Each member stops at its own
+// target step: its kernels return at once after that, so runs of different
+// lengths share the replays.
+
+struct GroupTab {
+    Group g{};
+    int64_t total = 0;
+};
+
+struct mithra_batch_s {
+    std::vector<mithra_handle> runs;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0, ws_used = 0;
+    struct SweepCls {
+        int precision, comp, shape;
+        GroupTab t;
+    };
+    std::vector<SweepCls> sweep;
+    GroupTab mur[2], vertex[2], power[2], power_final[2], push[3], one, sort_s, sort_d, sort_p;
+    int max_passes = 0;
+    hipGraphExec_t graph = nullptr;
+    std::vector<int64_t> host_targets;
+    std::string err;
+};
+
+static int bfail(mithra_batch b, int code, const char *fmt, ...)
+{
+    if (b) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        b->err = buf;
+    }
+    return code;
+}
+
+#define BHIPCHK(b, call)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return bfail(b, MITHRA_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+static size_t tab_bytes(size_t n)
+{
+    return align256(n * sizeof(RunDev)) + align256((n + 1) * sizeof(int64_t)) + align256(n * sizeof(int64_t));
+}
+
+extern "C" size_t mithra_batch_workspace_bytes(int32_t n_runs)
+{
+    if (n_runs <= 0)
+        return 0;
+    const size_t n = (size_t)n_runs;
+    // every stage kind holds each member at most once; sweep classes add at
+    // most one table per member
+    return 10 * tab_bytes(n) + (n + 16) * 3 * 256 + 256;
+}
+
+// table of members `mem` (indices into b->runs), nb(member) workgroups each
+template <class NB>
+static int make_tab(mithra_batch b, const std::vector<int> &mem, NB nb, GroupTab *out)
+{
+    *out = GroupTab{};
+    const size_t n = mem.size();
+    if (n == 0)
+        return MITHRA_OK;
+    std::vector<RunDev> rd(n);
+    std::vector<int64_t> boff(n + 1), nblk(n);
+    boff[0] = 0;
+    for (size_t m = 0; m < n; ++m) {
+        rd[m] = b->runs[mem[m]]->R;
+        nblk[m] = nb(rd[m]);
+        boff[m + 1] = boff[m] + (nblk[m] + 7) / 8 * 8;
+    }
+    if (boff[n] > 0x7fffffffLL)
+        return bfail(b, MITHRA_EINVAL, "grouped launch too large");
+    const size_t need = tab_bytes(n);
+    if (b->ws_used + need > b->ws_bytes)
+        return bfail(b, MITHRA_ENOMEM, "batch workspace too small");
+    char *base = b->ws + b->ws_used;
+    b->ws_used += need;
+    RunDev *d_runs = (RunDev *)base;
+    int64_t *d_boff = (int64_t *)(base + align256(n * sizeof(RunDev)));
+    int64_t *d_nblk = (int64_t *)((char *)d_boff + align256((n + 1) * sizeof(int64_t)));
+    BHIPCHK(b, hipMemcpy(d_runs, rd.data(), n * sizeof(RunDev), hipMemcpyHostToDevice));
+    BHIPCHK(b, hipMemcpy(d_boff, boff.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    BHIPCHK(b, hipMemcpy(d_nblk, nblk.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
+    out->g.runs = d_runs;
+    out->g.boff = d_boff;
+    out->g.nblk = d_nblk;
+    out->g.nmem = (int)n;
+    out->total = boff[n];
+    return MITHRA_OK;
+}
+
+static int effective_shape(const mithra_handle h)
+{
+    const int V = h->R.precision == 32 ? 4 : 2;
+    return (h->sweep_shape >= 8 && h->R.nx % V != 0) ? 0 : h->sweep_shape;
+}
+
+static int build_tables(mithra_batch b)
+{
+    const int n = (int)b->runs.size();
+    std::vector<int> all(n);
+    for (int i = 0; i < n; ++i)
+        all[i] = i;
+    // sweep classes
+    std::map<std::tuple<int, int, int>, std::vector<int>> cls;
+    for (int i = 0; i < n; ++i) {
+        const mithra_handle h = b->runs[i];
+        cls[{h->R.precision, h->R.compensated, effective_shape(h)}].push_back(i);
+    }
+    for (auto &kv : cls) {
+        mithra_batch_s::SweepCls c{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), {}};
+        const int shape = c.shape;
+        int rc = make_tab(b, kv.second, [shape](const RunDev &R) { return sweep_blocks(R, shape); }, &c.t);
+        if (rc)
+            return rc;
+        b->sweep.push_back(c);
+    }
+    for (int pi = 0; pi < 2; ++pi) {
+        const int prec = pi == 0 ? 32 : 64;
+        std::vector<int> mem, memp;
+        for (int i = 0; i < n; ++i)
+            if (b->runs[i]->R.precision == prec) {
+                mem.push_back(i);
+                if (b->runs[i]->R.record_power)
+                    memp.push_back(i);
+            }
+        int rc = make_tab(b, mem, [](const RunDev &R) { return mur_blocks(R); }, &b->mur[pi]);
+        if (!rc)
+            rc = make_tab(b, mem, [](const RunDev &R) { return vertex_blocks(R); }, &b->vertex[pi]);
+        if (!rc)
+            rc = make_tab(b, memp, [](const RunDev &) { return power_blocks(); }, &b->power[pi]);
+        if (!rc)
+            rc = make_tab(b, memp, [](const RunDev &) { return (int64_t)1; }, &b->power_final[pi]);
+        if (rc)
+            return rc;
+    }
+    for (int ci = 0; ci < 3; ++ci) {  // FP64, FP32, FP32 compensated
+        std::vector<int> mem;
+        for (int i = 0; i < n; ++i) {
+            const RunDev &R = b->runs[i]->R;
+            const int c = R.precision == 64 ? 0 : (R.compensated ? 2 : 1);
+            if (c == ci)
+                mem.push_back(i);
+        }
+        int rc = make_tab(b, mem, [](const RunDev &R) { return dep_blocks(R.np); }, &b->push[ci]);
+        if (rc)
+            return rc;
+    }
+    int rc = make_tab(b, all, [](const RunDev &) { return (int64_t)1; }, &b->one);
+    if (!rc)
+        rc = make_tab(b, all, [](const RunDev &R) { return R.sort_blocks; }, &b->sort_s);
+    if (!rc)
+        rc = make_tab(b, all, [](const RunDev &) { return (int64_t)256; }, &b->sort_d);
+    if (!rc)
+        rc = make_tab(b, all, [](const RunDev &R) { return (R.np + 255) / 256; }, &b->sort_p);
+    if (rc)
+        return rc;
+    b->max_passes = 0;
+    for (int i = 0; i < n; ++i)
+        b->max_passes = std::max(b->max_passes, sort_passes(b->runs[i]->R.key_inactive));
+    return MITHRA_OK;
+}
+
+static int enqueue_batch_step(mithra_batch b, hipStream_t st)
+{
+    for (auto &c : b->sweep)
+        BHIPCHK(b, launch_sweep_group(c.t.g, c.t.total, c.precision, c.comp, c.shape, st));
+    for (int pi = 0; pi < 2; ++pi)
+        BHIPCHK(b, launch_mur_group(b->mur[pi].g, b->mur[pi].total, pi == 0 ? 32 : 64, st));
+    for (int pi = 0; pi < 2; ++pi)
+        BHIPCHK(b, launch_vertex_group(b->vertex[pi].g, b->vertex[pi].total, pi == 0 ? 32 : 64, st));
+    hipLaunchKernelGGL((k_group<BookMid>), dim3((unsigned)b->one.total), dim3(1), 0, st, b->one.g);
+    for (int ci = 0; ci < 3; ++ci)
+        BHIPCHK(b, launch_push_group(b->push[ci].g, b->push[ci].total, ci == 0 ? 64 : 32, ci == 2, st));
+    BHIPCHK(b, launch_box_group(b->one.g, b->one.total, st));
+    BHIPCHK(b, launch_sort_group(b->sort_s.g, b->sort_s.total, b->sort_d.g, b->sort_d.total, b->sort_p.g,
+                                 b->sort_p.total, b->max_passes, st));
+    for (int pi = 0; pi < 2; ++pi)
+        BHIPCHK(b, launch_power_group(b->power[pi].g, b->power[pi].total, b->power_final[pi].g,
+                                      b->power_final[pi].total, pi == 0 ? 32 : 64, st));
+    hipLaunchKernelGGL((k_group<BookEnd>), dim3((unsigned)b->one.total), dim3(1), 0, st, b->one.g);
+    BHIPCHK(b, hipGetLastError());
+    return MITHRA_OK;
+}
+
+static int build_batch_graph(mithra_batch b)
+{
+    hipStream_t cap = nullptr;
+    BHIPCHK(b, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    int rc = MITHRA_OK;
+    if (e == hipSuccess) {
+        rc = enqueue_batch_step(b, cap);
+        e = hipStreamEndCapture(cap, &g);
+    }
+    (void)hipStreamDestroy(cap);
+    if (rc) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess)
+        return bfail(b, MITHRA_EDEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess)
+        return bfail(b, MITHRA_EDEVICE, "batch graph instantiate failed: %s", hipGetErrorString(e));
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_batch_create(const mithra_handle *runs, int32_t n_runs, void *dev_workspace,
+                                   size_t workspace_bytes, void *hip_stream, mithra_batch *out)
+{
+    if (!out)
+        return MITHRA_EINVAL;
+    *out = nullptr;
+    if (!runs || n_runs <= 0 || !dev_workspace || ((uintptr_t)dev_workspace & 255))
+        return MITHRA_EINVAL;
+    if (workspace_bytes < mithra_batch_workspace_bytes(n_runs))
+        return MITHRA_ENOMEM;
+    for (int i = 0; i < n_runs; ++i) {
+        if (!runs[i] || !runs[i]->loaded || runs[i]->batched || runs[i]->tiled)
+            return MITHRA_ESTATE;
+        for (int j = 0; j < i; ++j)
+            if (runs[j] == runs[i])
+                return MITHRA_EINVAL;
+    }
+    mithra_batch b = new mithra_batch_s;
+    b->runs.assign(runs, runs + n_runs);
+    b->stream = (hipStream_t)hip_stream;
+    b->ws = (char *)dev_workspace;
+    b->ws_bytes = workspace_bytes;
+    for (auto h : b->runs) {
+        if (hipStreamSynchronize(h->stream) != hipSuccess) {
+            delete b;
+            return MITHRA_EDEVICE;
+        }
+    }
+    int rc = build_tables(b);
+    if (!rc)
+        rc = build_batch_graph(b);
+    if (rc) {
+        if (b->graph)
+            (void)hipGraphExecDestroy(b->graph);
+        delete b;
+        return rc;
+    }
+    for (auto h : b->runs) {
+        h->batched = true;
+        h->ext_stream = b->stream;
+    }
+    *out = b;
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_batch_run(mithra_batch b, const int64_t *n_steps)
+{
+    if (!b || !n_steps)
+        return MITHRA_EINVAL;
+    const size_t n = b->runs.size();
+    int64_t most = 0;
+    for (size_t i = 0; i < n; ++i) {
+        if (n_steps[i] < 0)
+            return bfail(b, MITHRA_EINVAL, "negative step count for member %zu", i);
+        most = std::max(most, n_steps[i]);
+    }
+    // the previous call's replays read the old targets until they finish
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->host_targets.resize(n);
+    for (size_t i = 0; i < n; ++i) {
+        mithra_handle h = b->runs[i];
+        b->host_targets[i] = h->steps + n_steps[i];
+        BHIPCHK(b, hipMemcpy(&h->R.ctl->target, &b->host_targets[i], sizeof(int64_t), hipMemcpyHostToDevice));
+    }
+    for (int64_t k = 0; k < most; ++k)
+        BHIPCHK(b, hipGraphLaunch(b->graph, b->stream));
+    for (size_t i = 0; i < n; ++i)
+        b->runs[i]->steps += n_steps[i];
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_batch_sync(mithra_batch b)
+{
+    if (!b)
+        return MITHRA_EINVAL;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    return MITHRA_OK;
+}
+
+extern "C" const char *mithra_batch_last_error(mithra_batch b)
+{
+    return b ? b->err.c_str() : "null batch";
+}
+
+extern "C" int mithra_batch_destroy(mithra_batch b)
+{
+    if (!b)
+        return MITHRA_EINVAL;
+    (void)hipStreamSynchronize(b->stream);
+    for (auto h : b->runs) {
+        h->batched = false;
+        h->ext_stream = nullptr;
+    }
+    if (b->graph)
+        (void)hipGraphExecDestroy(b->graph);
+    delete b;
     return MITHRA_OK;
 }

@@ -20,6 +20,7 @@
 //  * k_vertex_fields: E and B at vertices (sec. "Field Evaluation"):
 //    E = -(A^{n+1} - A^n)/dt - grad phi, B = mean of curl A^n and curl A^{n+1}.
 #include "mithra_dev.hpp"
+#include <algorithm>
 #include <type_traits>
 
 namespace mithra {
@@ -49,131 +50,136 @@ __device__ inline T src_value(const RunDev &R, int comp, int set, int64_t c, int
 }
 
 template <typename T, int TX, int TY, int TZ>
-__global__ __launch_bounds__(TX *TY) void k_sweep(RunDev R)
-{
-    __shared__ T sb[2][TY + 2][TX + 2];
+struct Sweep {
+    static constexpr int kThreads = TX * TY;
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        __shared__ T sb[2][TY + 2][TX + 2];
 
-    // tiles start at node 0 so that every row load is 128-byte aligned; the
-    // boundary columns load (they are the neighbours of the first interior
-    // column) but are not updated
-    const int ntx = (R.nx + TX - 1) / TX;
-    const int nty = (R.ny + TY - 1) / TY;
-    const int nch = (R.nz - 2 + TZ - 1) / TZ;
-    int64_t lb = xcd_swizzle(blockIdx.x, gridDim.x);
-    const int tile_x = (int)(lb % ntx);
-    lb /= ntx;
-    const int tile_y = (int)(lb % nty);
-    lb /= nty;
-    const int chunk = (int)(lb % nch);
-    const int comp = (int)(lb / nch);
+        // tiles start at node 0 so that every row load is 128-byte aligned; the
+        // boundary columns load (they are the neighbours of the first interior
+        // column) but are not updated
+        const int ntx = (R.nx + TX - 1) / TX;
+        const int nty = (R.ny + TY - 1) / TY;
+        const int nch = (R.nz - 2 + TZ - 1) / TZ;
+        int64_t lb = xcd_swizzle(blk.id, blk.n);
+        const int tile_x = (int)(lb % ntx);
+        lb /= ntx;
+        const int tile_y = (int)(lb % nty);
+        lb /= nty;
+        const int chunk = (int)(lb % nch);
+        const int comp = (int)(lb / nch);
+        if (comp >= 4)
+            return;  // grid larger than the tiling (never for the launchers here)
 
-    const int64_t s = R.ctl->step;
-    const int set_r = (int)(s & 1), set_c = (int)((s + 1) & 1);
-    const bool update = (comp < 3) || R.space_charge;
+        const int64_t s = R.ctl->step;
+        const int set_r = (int)(s & 1), set_c = (int)((s + 1) & 1);
+        const bool update = (comp < 3) || R.space_charge;
 
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int i = tile_x * TX + lx;
-    const int j = tile_y * TY + ly;
-    const bool inb = (i < R.nx) && (j < R.ny);
-    const bool valid = (i >= 1) && (j >= 1) && (i <= R.nx - 2) && (j <= R.ny - 2);
-    const int ic = min(i, R.nx - 1), jc = min(j, R.ny - 1);
-    const int64_t plane = (int64_t)R.nx * R.ny;
-    const int64_t col = (int64_t)jc * R.nx + ic;
+        const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+        const int i = tile_x * TX + lx;
+        const int j = tile_y * TY + ly;
+        const bool inb = (i < R.nx) && (j < R.ny);
+        const bool valid = (i >= 1) && (j >= 1) && (i <= R.nx - 2) && (j <= R.ny - 2);
+        const int ic = min(i, R.nx - 1), jc = min(j, R.ny - 1);
+        const int64_t plane = (int64_t)R.nx * R.ny;
+        const int64_t col = (int64_t)jc * R.nx + ic;
 
-    // halo ring: left/right columns (TY each), bottom/top rows (TX each)
-    const int H = 2 * (TX + TY);
-    const int h = threadIdx.x;
-    int hx = 0, hy = 0, hi_ = 0, hj_ = 0;
-    bool hval = false;
-    if (h < H) {
-        if (h < TY) {
-            hx = -1; hy = h;
-        } else if (h < 2 * TY) {
-            hx = TX; hy = h - TY;
-        } else if (h < 2 * TY + TX) {
-            hy = -1; hx = h - 2 * TY;
-        } else {
-            hy = TY; hx = h - 2 * TY - TX;
+        // halo ring: left/right columns (TY each), bottom/top rows (TX each)
+        const int H = 2 * (TX + TY);
+        const int h = threadIdx.x;
+        int hx = 0, hy = 0, hi_ = 0, hj_ = 0;
+        bool hval = false;
+        if (h < H) {
+            if (h < TY) {
+                hx = -1; hy = h;
+            } else if (h < 2 * TY) {
+                hx = TX; hy = h - TY;
+            } else if (h < 2 * TY + TX) {
+                hy = -1; hx = h - 2 * TY;
+            } else {
+                hy = TY; hx = h - 2 * TY - TX;
+            }
+            hi_ = tile_x * TX + hx;
+            hj_ = tile_y * TY + hy;
+            hval = (hi_ >= 0) && (hi_ < R.nx) && (hj_ >= 0) && (hj_ < R.ny);
         }
-        hi_ = tile_x * TX + hx;
-        hj_ = tile_y * TY + hy;
-        hval = (hi_ >= 0) && (hi_ < R.nx) && (hj_ >= 0) && (hj_ < R.ny);
+        const int64_t hcol = hval ? ((int64_t)hj_ * R.nx + hi_) : 0;
+
+        const int kb = 1 + chunk * TZ;
+        const int ke = min(kb + TZ, R.nz - 1);
+
+        const T *cur = pot_ptr<T>(R, slot_cur(s), comp);
+        const T *prev = pot_ptr<T>(R, slot_prev(s), comp);
+        T *next = pot_ptr<T>(R, slot_next(s), comp);
+
+        // source box of the set read now (expanded by one node on the high side:
+        // a node average reaches the edge below it), clear box of the other set
+        const int *rlo = R.ctl->dep_lo[set_r];
+        const int *rhi = R.ctl->dep_hi[set_r];
+        const int *clo = R.ctl->dep_lo[set_c];
+        const int *chi = R.ctl->dep_hi[set_c];
+        const bool src_col = valid && i >= rlo[0] && i <= rhi[0] + 1 && j >= rlo[1] && j <= rhi[1] + 1;
+        const bool clr_col = valid && i >= clo[0] && i <= chi[0] && j >= clo[1] && j <= chi[1];
+        const int64_t back = comp == 0 ? 1 : (comp == 1 ? R.nx : plane);
+        T *clr = src_ptr<T>(R, set_c, comp);
+        T *clr_lo = R.compensated ? srclo_ptr<T>(R, set_c, comp) : nullptr;
+
+        const T cA = (T)R.A, c1A = (T)(1.0 - 2.0 * R.A);
+        const T a1 = (T)R.a1, a2 = (T)R.a2, a4 = (T)R.a4, a6 = (T)R.a6;
+
+        T qm = 0, q0 = 0, qp = 0, hqm = 0, hq0 = 0, hqp = 0;
+        if (inb) {
+            qm = cur[(int64_t)(kb - 1) * plane + col];
+            q0 = cur[(int64_t)kb * plane + col];
+            qp = cur[(int64_t)(kb + 1) * plane + col];
+        }
+        if (hval) {
+            hqm = cur[(int64_t)(kb - 1) * plane + hcol];
+            hq0 = cur[(int64_t)kb * plane + hcol];
+            hqp = cur[(int64_t)(kb + 1) * plane + hcol];
+        }
+
+        for (int k = kb; k < ke; ++k) {
+            const int64_t c = (int64_t)k * plane + col;
+            // issue the loads of this iteration before the barrier
+            T pf = 0, hpf = 0;
+            if (k + 1 < ke) {
+                if (inb)
+                    pf = cur[c + 2 * plane];
+                if (hval)
+                    hpf = cur[(int64_t)(k + 2) * plane + hcol];
+            }
+            T pm = 0, sv = 0;
+            if (valid && update) {
+                pm = prev[c];
+                if (src_col && k >= rlo[2] && k <= rhi[2] + 1)
+                    sv = src_value<T>(R, comp, set_r, c, back);
+            }
+            if (clr_col && k >= clo[2] && k <= chi[2]) {
+                clr[c] = (T)0;
+                if (clr_lo)
+                    clr_lo[c] = (T)0;
+            }
+            T(*buf)[TX + 2] = sb[k & 1];
+            buf[ly + 1][lx + 1] = cA * (qm + qp) + c1A * q0;
+            if (h < H)
+                buf[hy + 1][hx + 1] = cA * (hqm + hqp) + c1A * hq0;
+            __syncthreads();
+            if (valid && update) {
+                T v = a1 * q0 + a2 * (buf[ly + 1][lx + 2] + buf[ly + 1][lx]) +
+                      a4 * (buf[ly + 2][lx + 1] + buf[ly][lx + 1]) + a6 * (qp + qm) - pm + sv;
+                next[c] = v;
+            }
+            qm = q0;
+            q0 = qp;
+            qp = pf;
+            hqm = hq0;
+            hq0 = hqp;
+            hqp = hpf;
+        }
     }
-    const int64_t hcol = hval ? ((int64_t)hj_ * R.nx + hi_) : 0;
-
-    const int kb = 1 + chunk * TZ;
-    const int ke = min(kb + TZ, R.nz - 1);
-
-    const T *cur = pot_ptr<T>(R, slot_cur(s), comp);
-    const T *prev = pot_ptr<T>(R, slot_prev(s), comp);
-    T *next = pot_ptr<T>(R, slot_next(s), comp);
-
-    // source box of the set read now (expanded by one node on the high side:
-    // a node average reaches the edge below it), clear box of the other set
-    const int *rlo = R.ctl->dep_lo[set_r];
-    const int *rhi = R.ctl->dep_hi[set_r];
-    const int *clo = R.ctl->dep_lo[set_c];
-    const int *chi = R.ctl->dep_hi[set_c];
-    const bool src_col = valid && i >= rlo[0] && i <= rhi[0] + 1 && j >= rlo[1] && j <= rhi[1] + 1;
-    const bool clr_col = valid && i >= clo[0] && i <= chi[0] && j >= clo[1] && j <= chi[1];
-    const int64_t back = comp == 0 ? 1 : (comp == 1 ? R.nx : plane);
-    T *clr = src_ptr<T>(R, set_c, comp);
-    T *clr_lo = R.compensated ? srclo_ptr<T>(R, set_c, comp) : nullptr;
-
-    const T cA = (T)R.A, c1A = (T)(1.0 - 2.0 * R.A);
-    const T a1 = (T)R.a1, a2 = (T)R.a2, a4 = (T)R.a4, a6 = (T)R.a6;
-
-    T qm = 0, q0 = 0, qp = 0, hqm = 0, hq0 = 0, hqp = 0;
-    if (inb) {
-        qm = cur[(int64_t)(kb - 1) * plane + col];
-        q0 = cur[(int64_t)kb * plane + col];
-        qp = cur[(int64_t)(kb + 1) * plane + col];
-    }
-    if (hval) {
-        hqm = cur[(int64_t)(kb - 1) * plane + hcol];
-        hq0 = cur[(int64_t)kb * plane + hcol];
-        hqp = cur[(int64_t)(kb + 1) * plane + hcol];
-    }
-
-    for (int k = kb; k < ke; ++k) {
-        const int64_t c = (int64_t)k * plane + col;
-        // issue the loads of this iteration before the barrier
-        T pf = 0, hpf = 0;
-        if (k + 1 < ke) {
-            if (inb)
-                pf = cur[c + 2 * plane];
-            if (hval)
-                hpf = cur[(int64_t)(k + 2) * plane + hcol];
-        }
-        T pm = 0, sv = 0;
-        if (valid && update) {
-            pm = prev[c];
-            if (src_col && k >= rlo[2] && k <= rhi[2] + 1)
-                sv = src_value<T>(R, comp, set_r, c, back);
-        }
-        if (clr_col && k >= clo[2] && k <= chi[2]) {
-            clr[c] = (T)0;
-            if (clr_lo)
-                clr_lo[c] = (T)0;
-        }
-        T(*buf)[TX + 2] = sb[k & 1];
-        buf[ly + 1][lx + 1] = cA * (qm + qp) + c1A * q0;
-        if (h < H)
-            buf[hy + 1][hx + 1] = cA * (hqm + hqp) + c1A * hq0;
-        __syncthreads();
-        if (valid && update) {
-            T v = a1 * q0 + a2 * (buf[ly + 1][lx + 2] + buf[ly + 1][lx]) +
-                  a4 * (buf[ly + 2][lx + 1] + buf[ly][lx + 1]) + a6 * (qp + qm) - pm + sv;
-            next[c] = v;
-        }
-        qm = q0;
-        q0 = qp;
-        qp = pf;
-        hqm = hq0;
-        hq0 = hqp;
-        hqp = hpf;
-    }
-}
+};
 
 // Vectorised sweep: each thread owns V consecutive x-nodes (16-byte loads
 // and stores), a tile is TXV*V nodes wide and TY rows high.  psi-bar of the
@@ -248,267 +254,272 @@ struct PlaneSrc {
 };
 
 template <typename T, int V, int TXV, int TY, int TZ, bool LO>
-__global__ __launch_bounds__(TXV *TY) void k_sweep_vec(RunDev R)
-{
-    constexpr int TW = TXV * V;                          // tile width in nodes
-    constexpr int ROW = ((V + TW + 1) + V - 1) / V * V;  // LDS row: pad(V-1), left halo, tile, right halo
-    // source sums: FP64 for FP64 fields and for compensated FP32 (hi + lo)
-    using ST = typename std::conditional<LO || sizeof(T) == 8, double, T>::type;
-    __shared__ __attribute__((aligned(16))) T sb[2][TY + 2][ROW];
-    // psi^n at the two outermost nodes of each row end (x-face update)
-    __shared__ T rawe[2][TY + 2][4];
+struct SweepVec {
+    static constexpr int kThreads = TXV * TY;
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        constexpr int TW = TXV * V;                          // tile width in nodes
+        constexpr int ROW = ((V + TW + 1) + V - 1) / V * V;  // LDS row: pad(V-1), left halo, tile, right halo
+        // source sums: FP64 for FP64 fields and for compensated FP32 (hi + lo)
+        using ST = typename std::conditional<LO || sizeof(T) == 8, double, T>::type;
+        __shared__ __attribute__((aligned(16))) T sb[2][TY + 2][ROW];
+        // psi^n at the two outermost nodes of each row end (x-face update)
+        __shared__ T rawe[2][TY + 2][4];
 
-    const int ntx = (R.nx + TW - 1) / TW;
-    const int nty = (R.ny + TY - 1) / TY;
-    const int nch = (R.nz - 2 + TZ - 1) / TZ;
-    int64_t lb = xcd_swizzle(blockIdx.x, gridDim.x);
-    const int tile_x = (int)(lb % ntx);
-    lb /= ntx;
-    const int tile_y = (int)(lb % nty);
-    lb /= nty;
-    const int chunk = (int)(lb % nch);
-    const int comp = (int)(lb / nch);
+        const int ntx = (R.nx + TW - 1) / TW;
+        const int nty = (R.ny + TY - 1) / TY;
+        const int nch = (R.nz - 2 + TZ - 1) / TZ;
+        int64_t lb = xcd_swizzle(blk.id, blk.n);
+        const int tile_x = (int)(lb % ntx);
+        lb /= ntx;
+        const int tile_y = (int)(lb % nty);
+        lb /= nty;
+        const int chunk = (int)(lb % nch);
+        const int comp = (int)(lb / nch);
+        if (comp >= 4)
+            return;  // grid larger than the tiling (never for the launchers here)
 
-    const int64_t s = R.ctl->step;
-    const int set_r = (int)(s & 1), set_c = (int)((s + 1) & 1);
-    const bool update = (comp < 3) || R.space_charge;
+        const int64_t s = R.ctl->step;
+        const int set_r = (int)(s & 1), set_c = (int)((s + 1) & 1);
+        const bool update = (comp < 3) || R.space_charge;
 
-    const int lx = threadIdx.x % TXV, ly = threadIdx.x / TXV;
-    const int i0 = tile_x * TW + lx * V;  // first node of this thread
-    const int j = tile_y * TY + ly;
-    const bool inb = (i0 < R.nx) && (j < R.ny);
-    const bool rowvalid = inb && j >= 1 && j <= R.ny - 2;
-    const bool work = rowvalid && update;
-    const int64_t plane = (int64_t)R.nx * R.ny;
-    const int64_t col = inb ? ((int64_t)j * R.nx + i0) : 0;
+        const int lx = threadIdx.x % TXV, ly = threadIdx.x / TXV;
+        const int i0 = tile_x * TW + lx * V;  // first node of this thread
+        const int j = tile_y * TY + ly;
+        const bool inb = (i0 < R.nx) && (j < R.ny);
+        const bool rowvalid = inb && j >= 1 && j <= R.ny - 2;
+        const bool work = rowvalid && update;
+        const int64_t plane = (int64_t)R.nx * R.ny;
+        const int64_t col = inb ? ((int64_t)j * R.nx + i0) : 0;
 
-    // halo: bottom/top rows (vector, TXV threads each), left/right columns
-    // (scalar, TY threads each)
-    const int t = threadIdx.x;
-    int hrole = -1, hx = 0, hy = 0;
-    int64_t hcol = 0;
-    bool hval = false;
-    if (t < 2 * TXV) {
-        hrole = 0;
-        hx = (t % TXV) * V;
-        hy = t < TXV ? -1 : TY;
-        const int hi_ = tile_x * TW + hx, hj_ = tile_y * TY + hy;
-        hval = hj_ >= 0 && hj_ < R.ny && hi_ < R.nx;
-        hcol = hval ? (int64_t)hj_ * R.nx + hi_ : 0;
-    } else if (t < 2 * TXV + 2 * TY) {
-        hrole = 1;
-        const int u = t - 2 * TXV;
-        hy = u % TY;
-        hx = u < TY ? -1 : TW;
-        const int hi_ = tile_x * TW + hx, hj_ = tile_y * TY + hy;
-        hval = hi_ >= 0 && hi_ < R.nx && hj_ < R.ny;
-        hcol = hval ? (int64_t)hj_ * R.nx + hi_ : 0;
-    }
+        // halo: bottom/top rows (vector, TXV threads each), left/right columns
+        // (scalar, TY threads each)
+        const int t = threadIdx.x;
+        int hrole = -1, hx = 0, hy = 0;
+        int64_t hcol = 0;
+        bool hval = false;
+        if (t < 2 * TXV) {
+            hrole = 0;
+            hx = (t % TXV) * V;
+            hy = t < TXV ? -1 : TY;
+            const int hi_ = tile_x * TW + hx, hj_ = tile_y * TY + hy;
+            hval = hj_ >= 0 && hj_ < R.ny && hi_ < R.nx;
+            hcol = hval ? (int64_t)hj_ * R.nx + hi_ : 0;
+        } else if (t < 2 * TXV + 2 * TY) {
+            hrole = 1;
+            const int u = t - 2 * TXV;
+            hy = u % TY;
+            hx = u < TY ? -1 : TW;
+            const int hi_ = tile_x * TW + hx, hj_ = tile_y * TY + hy;
+            hval = hi_ >= 0 && hi_ < R.nx && hj_ < R.ny;
+            hcol = hval ? (int64_t)hj_ * R.nx + hi_ : 0;
+        }
 
-    const int kb = 1 + chunk * TZ;
-    const int ke = min(kb + TZ, R.nz - 1);
-    const T *cur = pot_ptr<T>(R, slot_cur(s), comp);
-    const T *prev = pot_ptr<T>(R, slot_prev(s), comp);
-    T *next = pot_ptr<T>(R, slot_next(s), comp);
+        const int kb = 1 + chunk * TZ;
+        const int ke = min(kb + TZ, R.nz - 1);
+        const T *cur = pot_ptr<T>(R, slot_cur(s), comp);
+        const T *prev = pot_ptr<T>(R, slot_prev(s), comp);
+        T *next = pot_ptr<T>(R, slot_next(s), comp);
 
-    const int *rlo = R.ctl->dep_lo[set_r];
-    const int *rhi = R.ctl->dep_hi[set_r];
-    const int *clo = R.ctl->dep_lo[set_c];
-    const int *chi = R.ctl->dep_hi[set_c];
-    const bool src_col = rowvalid && i0 + V - 1 >= rlo[0] && i0 <= rhi[0] + 1 && j >= rlo[1] && j <= rhi[1] + 1;
-    const bool clr_col = rowvalid && i0 + V - 1 >= clo[0] && i0 <= chi[0] && j >= clo[1] && j <= chi[1];
-    const int sk_lo = rlo[2], sk_hi = rhi[2] + 1;
-    const T *J = src_ptr<T>(R, set_r, comp);
-    const T *Jl = LO ? srclo_ptr<T>(R, set_r, comp) : nullptr;
-    T *clr = src_ptr<T>(R, set_c, comp);
-    T *clr_lo = LO ? srclo_ptr<T>(R, set_c, comp) : nullptr;
-    const ST sfac = (ST)(comp < 3 ? 0.5 * R.sfac_A : R.sfac_phi);
+        const int *rlo = R.ctl->dep_lo[set_r];
+        const int *rhi = R.ctl->dep_hi[set_r];
+        const int *clo = R.ctl->dep_lo[set_c];
+        const int *chi = R.ctl->dep_hi[set_c];
+        const bool src_col = rowvalid && i0 + V - 1 >= rlo[0] && i0 <= rhi[0] + 1 && j >= rlo[1] && j <= rhi[1] + 1;
+        const bool clr_col = rowvalid && i0 + V - 1 >= clo[0] && i0 <= chi[0] && j >= clo[1] && j <= chi[1];
+        const int sk_lo = rlo[2], sk_hi = rhi[2] + 1;
+        const T *J = src_ptr<T>(R, set_r, comp);
+        const T *Jl = LO ? srclo_ptr<T>(R, set_r, comp) : nullptr;
+        T *clr = src_ptr<T>(R, set_c, comp);
+        T *clr_lo = LO ? srclo_ptr<T>(R, set_c, comp) : nullptr;
+        const ST sfac = (ST)(comp < 3 ? 0.5 * R.sfac_A : R.sfac_phi);
 
-    const T cA = (T)R.A, c1A = (T)(1.0 - 2.0 * R.A);
-    const T a1 = (T)R.a1, a2 = (T)R.a2, a4 = (T)R.a4, a6 = (T)R.a6;
+        const T cA = (T)R.A, c1A = (T)(1.0 - 2.0 * R.A);
+        const T a1 = (T)R.a1, a2 = (T)R.a2, a4 = (T)R.a4, a6 = (T)R.a6;
 
-    // psi^{n-1} and the sources of plane kk; the z component's back edge is
-    // the previous plane's own edge, carried in registers (zero below the
-    // source box, where the source is zero)
-    auto fetch = [&](int kk, const PlaneSrc<T, V, LO> &prv) {
-        PlaneSrc<T, V, LO> r{};
-        if (!work)
-            return r;
-        const int64_t c = (int64_t)kk * plane + col;
-        r.pm = vload_nt<T, V>(prev + c);
-        if (src_col && kk >= sk_lo && kk <= sk_hi) {
-            r.a = vload<T, V>(J + c);
-            if constexpr (LO)
-                r.al = vload<T, V>(Jl + c);
-            if (comp == 0) {
-                r.lf = J[c - 1];
+        // psi^{n-1} and the sources of plane kk; the z component's back edge is
+        // the previous plane's own edge, carried in registers (zero below the
+        // source box, where the source is zero)
+        auto fetch = [&](int kk, const PlaneSrc<T, V, LO> &prv) {
+            PlaneSrc<T, V, LO> r{};
+            if (!work)
+                return r;
+            const int64_t c = (int64_t)kk * plane + col;
+            r.pm = vload_nt<T, V>(prev + c);
+            if (src_col && kk >= sk_lo && kk <= sk_hi) {
+                r.a = vload<T, V>(J + c);
                 if constexpr (LO)
-                    r.lfl = Jl[c - 1];
-            } else if (comp == 1) {
-                r.b = vload<T, V>(J + c - R.nx);
-                if constexpr (LO)
-                    r.bl = vload<T, V>(Jl + c - R.nx);
-            } else if (comp == 2) {
-                if (kk > kb && kk - 1 >= sk_lo) {
-                    r.b = prv.a;
-                    r.bl = prv.al;
-                } else {
-                    r.b = vload<T, V>(J + c - plane);
+                    r.al = vload<T, V>(Jl + c);
+                if (comp == 0) {
+                    r.lf = J[c - 1];
                     if constexpr (LO)
-                        r.bl = vload<T, V>(Jl + c - plane);
-                }
-            }
-        }
-        return r;
-    };
-
-    Vec<T, V> qm{}, q0{}, qp{}, hm{}, h0{}, hp{};
-    if (inb) {
-        qm = vload<T, V>(cur + (int64_t)(kb - 1) * plane + col);
-        q0 = vload<T, V>(cur + (int64_t)kb * plane + col);
-        qp = vload<T, V>(cur + (int64_t)(kb + 1) * plane + col);
-    }
-    if (hval) {
-        if (hrole == 0) {
-            hm = vload<T, V>(cur + (int64_t)(kb - 1) * plane + hcol);
-            h0 = vload<T, V>(cur + (int64_t)kb * plane + hcol);
-            hp = vload<T, V>(cur + (int64_t)(kb + 1) * plane + hcol);
-        } else {
-            hm.v[0] = cur[(int64_t)(kb - 1) * plane + hcol];
-            h0.v[0] = cur[(int64_t)kb * plane + hcol];
-            hp.v[0] = cur[(int64_t)(kb + 1) * plane + hcol];
-        }
-    }
-    PlaneSrc<T, V, LO> ps = fetch(kb, PlaneSrc<T, V, LO>{});
-
-    for (int k = kb; k < ke; ++k) {
-        const int64_t c = (int64_t)k * plane + col;
-        // prefetch: psi^n two planes up, psi^{n-1} and sources one plane up
-        Vec<T, V> pf{}, hpf{};
-        PlaneSrc<T, V, LO> pn{};
-        if (k + 1 < ke) {
-            if (inb)
-                pf = vload<T, V>(cur + c + 2 * plane);
-            if (hval) {
-                if (hrole == 0)
-                    hpf = vload<T, V>(cur + (int64_t)(k + 2) * plane + hcol);
-                else
-                    hpf.v[0] = cur[(int64_t)(k + 2) * plane + hcol];
-            }
-            pn = fetch(k + 1, ps);
-        }
-        ST sv[V];
-        if (comp == 3) {
-            for (int e = 0; e < V; ++e)
-                sv[e] = (ST)ps.a.v[e] + (LO ? (ST)ps.al.v[e] : (ST)0);
-        } else if (comp == 0) {
-            ST left = (ST)ps.lf + (LO ? (ST)ps.lfl : (ST)0);
-            for (int e = 0; e < V; ++e) {
-                const ST own = (ST)ps.a.v[e] + (LO ? (ST)ps.al.v[e] : (ST)0);
-                sv[e] = own + left;
-                left = own;
-            }
-        } else {
-            for (int e = 0; e < V; ++e)
-                sv[e] = LO ? ((ST)ps.a.v[e] + (ST)ps.al.v[e]) + ((ST)ps.b.v[e] + (ST)ps.bl.v[e])
-                           : (ST)ps.a.v[e] + (ST)ps.b.v[e];
-        }
-        if (clr_col && k >= clo[2] && k <= chi[2]) {
-            const Vec<T, V> z{};
-            vstore_nt<T, V>(clr + c, z);
-            if constexpr (LO)
-                vstore_nt<T, V>(clr_lo + c, z);
-        }
-        T(*buf)[ROW] = sb[k & 1];
-        Vec<T, V> bar;
-        for (int e = 0; e < V; ++e)
-            bar.v[e] = cA * (qm.v[e] + qp.v[e]) + c1A * q0.v[e];
-        vstore<T, V>(&buf[ly + 1][V + lx * V], bar);
-        if (hrole == 0) {
-            Vec<T, V> hb;
-            for (int e = 0; e < V; ++e)
-                hb.v[e] = cA * (hm.v[e] + hp.v[e]) + c1A * h0.v[e];
-            vstore<T, V>(&buf[hy + 1][V + hx], hb);
-        } else if (hrole == 1) {
-            buf[hy + 1][V + hx] = cA * (hm.v[0] + hp.v[0]) + c1A * h0.v[0];
-        }
-        if (R.xface_fused) {
-            T(*raw)[4] = rawe[k & 1];
-            if (inb && i0 == 0) {
-                raw[ly + 1][0] = q0.v[0];
-                raw[ly + 1][1] = q0.v[1];
-            }
-            if (inb && i0 + V == R.nx) {
-                raw[ly + 1][2] = q0.v[V - 2];
-                raw[ly + 1][3] = q0.v[V - 1];
-            }
-            if (hrole == 0 && hval) {
-                const int hi_ = tile_x * TW + hx;
-                if (hi_ == 0) {
-                    raw[hy + 1][0] = h0.v[0];
-                    raw[hy + 1][1] = h0.v[1];
-                }
-                if (hi_ + V == R.nx) {
-                    raw[hy + 1][2] = h0.v[V - 2];
-                    raw[hy + 1][3] = h0.v[V - 1];
-                }
-            }
-        }
-        __syncthreads();
-        if (work) {
-            const T left = buf[ly + 1][V + lx * V - 1];
-            const T right = buf[ly + 1][V + lx * V + V];
-            const Vec<T, V> dn = vload<T, V>(&buf[ly][V + lx * V]);
-            const Vec<T, V> up = vload<T, V>(&buf[ly + 2][V + lx * V]);
-            Vec<T, V> out;
-            for (int e = 0; e < V; ++e) {
-                const T xl = e == 0 ? left : bar.v[e - 1];
-                const T xr = e == V - 1 ? right : bar.v[e + 1];
-                out.v[e] = a1 * q0.v[e] + a2 * (xl + xr) + a4 * (dn.v[e] + up.v[e]) + a6 * (qp.v[e] + qm.v[e]) -
-                           ps.pm.v[e] + (T)(sfac * sv[e]);
-            }
-            // the x-face nodes of the row: Mur update (faces of the x axis,
-            // transverse y and z), from this thread's own columns, the
-            // neighbouring rows' values in LDS and the new inner value; or
-            // left to the Mur kernel
-            if (i0 == 0 || i0 + V == R.nx) {
-                const T(*raw)[4] = rawe[k & 1];
-                for (int side = 0; side < 2; ++side) {
-                    if ((side == 0 && i0 != 0) || (side == 1 && i0 + V != R.nx))
-                        continue;
-                    const int eb = side == 0 ? 0 : V - 1, ei = side == 0 ? 1 : V - 2;
-                    if (!R.xface_fused) {
-                        out.v[eb] = next[c + eb];
-                        continue;
-                    }
-                    const int ro = side == 0 ? 0 : 2;
-                    const int rb = side == 0 ? ro : ro + 1, ri = side == 0 ? ro + 1 : ro;
-                    const Vec<T, V> &pm = ps.pm;
-                    double v = R.mur_be0[0] * ((double)pm.v[eb] + (double)out.v[ei]) - (double)pm.v[ei];
-                    if (R.order == 1) {
-                        v += R.mur_be1[0] * ((double)q0.v[eb] + (double)q0.v[ei]);
+                        r.lfl = Jl[c - 1];
+                } else if (comp == 1) {
+                    r.b = vload<T, V>(J + c - R.nx);
+                    if constexpr (LO)
+                        r.bl = vload<T, V>(Jl + c - R.nx);
+                } else if (comp == 2) {
+                    if (kk > kb && kk - 1 >= sk_lo) {
+                        r.b = prv.a;
+                        r.bl = prv.al;
                     } else {
-                        v += R.mur_g1[0] * ((double)q0.v[eb] + (double)q0.v[ei]);
-                        const double s1 = ((double)raw[ly][rb] + (double)raw[ly][ri]) +
-                                          ((double)raw[ly + 2][rb] + (double)raw[ly + 2][ri]);
-                        const double s2 = ((double)qm.v[eb] + (double)qm.v[ei]) + ((double)qp.v[eb] + (double)qp.v[ei]);
-                        v += R.mur_ga[0] * s1;
-                        v += R.mur_gb[0] * s2;
+                        r.b = vload<T, V>(J + c - plane);
+                        if constexpr (LO)
+                            r.bl = vload<T, V>(Jl + c - plane);
                     }
-                    out.v[eb] = (T)v;
                 }
             }
-            vstore_nt<T, V>(next + c, out);
+            return r;
+        };
+
+        Vec<T, V> qm{}, q0{}, qp{}, hm{}, h0{}, hp{};
+        if (inb) {
+            qm = vload<T, V>(cur + (int64_t)(kb - 1) * plane + col);
+            q0 = vload<T, V>(cur + (int64_t)kb * plane + col);
+            qp = vload<T, V>(cur + (int64_t)(kb + 1) * plane + col);
         }
-        qm = q0;
-        q0 = qp;
-        qp = pf;
-        hm = h0;
-        h0 = hp;
-        hp = hpf;
-        ps = pn;
+        if (hval) {
+            if (hrole == 0) {
+                hm = vload<T, V>(cur + (int64_t)(kb - 1) * plane + hcol);
+                h0 = vload<T, V>(cur + (int64_t)kb * plane + hcol);
+                hp = vload<T, V>(cur + (int64_t)(kb + 1) * plane + hcol);
+            } else {
+                hm.v[0] = cur[(int64_t)(kb - 1) * plane + hcol];
+                h0.v[0] = cur[(int64_t)kb * plane + hcol];
+                hp.v[0] = cur[(int64_t)(kb + 1) * plane + hcol];
+            }
+        }
+        PlaneSrc<T, V, LO> ps = fetch(kb, PlaneSrc<T, V, LO>{});
+
+        for (int k = kb; k < ke; ++k) {
+            const int64_t c = (int64_t)k * plane + col;
+            // prefetch: psi^n two planes up, psi^{n-1} and sources one plane up
+            Vec<T, V> pf{}, hpf{};
+            PlaneSrc<T, V, LO> pn{};
+            if (k + 1 < ke) {
+                if (inb)
+                    pf = vload<T, V>(cur + c + 2 * plane);
+                if (hval) {
+                    if (hrole == 0)
+                        hpf = vload<T, V>(cur + (int64_t)(k + 2) * plane + hcol);
+                    else
+                        hpf.v[0] = cur[(int64_t)(k + 2) * plane + hcol];
+                }
+                pn = fetch(k + 1, ps);
+            }
+            ST sv[V];
+            if (comp == 3) {
+                for (int e = 0; e < V; ++e)
+                    sv[e] = (ST)ps.a.v[e] + (LO ? (ST)ps.al.v[e] : (ST)0);
+            } else if (comp == 0) {
+                ST left = (ST)ps.lf + (LO ? (ST)ps.lfl : (ST)0);
+                for (int e = 0; e < V; ++e) {
+                    const ST own = (ST)ps.a.v[e] + (LO ? (ST)ps.al.v[e] : (ST)0);
+                    sv[e] = own + left;
+                    left = own;
+                }
+            } else {
+                for (int e = 0; e < V; ++e)
+                    sv[e] = LO ? ((ST)ps.a.v[e] + (ST)ps.al.v[e]) + ((ST)ps.b.v[e] + (ST)ps.bl.v[e])
+                               : (ST)ps.a.v[e] + (ST)ps.b.v[e];
+            }
+            if (clr_col && k >= clo[2] && k <= chi[2]) {
+                const Vec<T, V> z{};
+                vstore_nt<T, V>(clr + c, z);
+                if constexpr (LO)
+                    vstore_nt<T, V>(clr_lo + c, z);
+            }
+            T(*buf)[ROW] = sb[k & 1];
+            Vec<T, V> bar;
+            for (int e = 0; e < V; ++e)
+                bar.v[e] = cA * (qm.v[e] + qp.v[e]) + c1A * q0.v[e];
+            vstore<T, V>(&buf[ly + 1][V + lx * V], bar);
+            if (hrole == 0) {
+                Vec<T, V> hb;
+                for (int e = 0; e < V; ++e)
+                    hb.v[e] = cA * (hm.v[e] + hp.v[e]) + c1A * h0.v[e];
+                vstore<T, V>(&buf[hy + 1][V + hx], hb);
+            } else if (hrole == 1) {
+                buf[hy + 1][V + hx] = cA * (hm.v[0] + hp.v[0]) + c1A * h0.v[0];
+            }
+            if (R.xface_fused) {
+                T(*raw)[4] = rawe[k & 1];
+                if (inb && i0 == 0) {
+                    raw[ly + 1][0] = q0.v[0];
+                    raw[ly + 1][1] = q0.v[1];
+                }
+                if (inb && i0 + V == R.nx) {
+                    raw[ly + 1][2] = q0.v[V - 2];
+                    raw[ly + 1][3] = q0.v[V - 1];
+                }
+                if (hrole == 0 && hval) {
+                    const int hi_ = tile_x * TW + hx;
+                    if (hi_ == 0) {
+                        raw[hy + 1][0] = h0.v[0];
+                        raw[hy + 1][1] = h0.v[1];
+                    }
+                    if (hi_ + V == R.nx) {
+                        raw[hy + 1][2] = h0.v[V - 2];
+                        raw[hy + 1][3] = h0.v[V - 1];
+                    }
+                }
+            }
+            __syncthreads();
+            if (work) {
+                const T left = buf[ly + 1][V + lx * V - 1];
+                const T right = buf[ly + 1][V + lx * V + V];
+                const Vec<T, V> dn = vload<T, V>(&buf[ly][V + lx * V]);
+                const Vec<T, V> up = vload<T, V>(&buf[ly + 2][V + lx * V]);
+                Vec<T, V> out;
+                for (int e = 0; e < V; ++e) {
+                    const T xl = e == 0 ? left : bar.v[e - 1];
+                    const T xr = e == V - 1 ? right : bar.v[e + 1];
+                    out.v[e] = a1 * q0.v[e] + a2 * (xl + xr) + a4 * (dn.v[e] + up.v[e]) + a6 * (qp.v[e] + qm.v[e]) -
+                               ps.pm.v[e] + (T)(sfac * sv[e]);
+                }
+                // the x-face nodes of the row: Mur update (faces of the x axis,
+                // transverse y and z), from this thread's own columns, the
+                // neighbouring rows' values in LDS and the new inner value; or
+                // left to the Mur kernel
+                if (i0 == 0 || i0 + V == R.nx) {
+                    const T(*raw)[4] = rawe[k & 1];
+                    for (int side = 0; side < 2; ++side) {
+                        if ((side == 0 && i0 != 0) || (side == 1 && i0 + V != R.nx))
+                            continue;
+                        const int eb = side == 0 ? 0 : V - 1, ei = side == 0 ? 1 : V - 2;
+                        if (!R.xface_fused) {
+                            out.v[eb] = next[c + eb];
+                            continue;
+                        }
+                        const int ro = side == 0 ? 0 : 2;
+                        const int rb = side == 0 ? ro : ro + 1, ri = side == 0 ? ro + 1 : ro;
+                        const Vec<T, V> &pm = ps.pm;
+                        double v = R.mur_be0[0] * ((double)pm.v[eb] + (double)out.v[ei]) - (double)pm.v[ei];
+                        if (R.order == 1) {
+                            v += R.mur_be1[0] * ((double)q0.v[eb] + (double)q0.v[ei]);
+                        } else {
+                            v += R.mur_g1[0] * ((double)q0.v[eb] + (double)q0.v[ei]);
+                            const double s1 = ((double)raw[ly][rb] + (double)raw[ly][ri]) +
+                                              ((double)raw[ly + 2][rb] + (double)raw[ly + 2][ri]);
+                            const double s2 = ((double)qm.v[eb] + (double)qm.v[ei]) + ((double)qp.v[eb] + (double)qp.v[ei]);
+                            v += R.mur_ga[0] * s1;
+                            v += R.mur_gb[0] * s2;
+                        }
+                        out.v[eb] = (T)v;
+                    }
+                }
+                vstore_nt<T, V>(next + c, out);
+            }
+            qm = q0;
+            q0 = qp;
+            qp = pf;
+            hm = h0;
+            h0 = hp;
+            hp = hpf;
+            ps = pn;
+        }
     }
-}
+};
 
 // ---------------------------------------------------------------------------
 // K2: Mur boundaries
@@ -640,61 +651,64 @@ __device__ double corner_np1(const RunDev &R, const Lv<T> &L, const int p[3], co
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_mur(RunDev R)
-{
-    const int64_t nzf = 2LL * R.nx * R.ny;
-    const int64_t nyf = 2LL * R.nx * (R.nz - 2);
-    const int64_t nxf = R.xface_fused ? 0 : 2LL * (R.ny - 2) * (R.nz - 2);
-    const int64_t nb = nzf + nyf + nxf;
-    const int ncomp = R.space_charge ? 4 : 3;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nb * ncomp)
-        return;
-    const int comp = (int)(t / nb);
-    int64_t r = t % nb;
-    int p[3];
-    if (r < nzf) {
-        const int64_t half = (int64_t)R.nx * R.ny;
-        p[2] = r < half ? 0 : R.nz - 1;
-        r %= half;
-        p[0] = (int)(r % R.nx);
-        p[1] = (int)(r / R.nx);
-    } else if (r < nzf + nyf) {
-        r -= nzf;
-        const int64_t half = (int64_t)R.nx * (R.nz - 2);
-        p[1] = r < half ? 0 : R.ny - 1;
-        r %= half;
-        p[0] = (int)(r % R.nx);
-        p[2] = 1 + (int)(r / R.nx);
-    } else {
-        r -= nzf + nyf;
-        const int64_t half = (int64_t)(R.ny - 2) * (R.nz - 2);
-        p[0] = r < half ? 0 : R.nx - 1;
-        r %= half;
-        p[1] = 1 + (int)(r % (R.ny - 2));
-        p[2] = 1 + (int)(r / (R.ny - 2));
-    }
-    const int64_t s = R.ctl->step;
-    Lv<T> L{pot_ptr<T>(R, slot_prev(s), comp), pot_ptr<T>(R, slot_cur(s), comp),
-            pot_ptr<T>(R, slot_next(s), comp)};
-    int ax[3], sd[3], m = 0;
-    for (int a = 0; a < 3; ++a) {
-        const int v = bside(R, a, p[a]);
-        if (v != 0) {
-            ax[m] = a;
-            sd[m] = v;
-            ++m;
+struct Mur {
+    static constexpr int kThreads = 256;
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        const int64_t nzf = 2LL * R.nx * R.ny;
+        const int64_t nyf = 2LL * R.nx * (R.nz - 2);
+        const int64_t nxf = R.xface_fused ? 0 : 2LL * (R.ny - 2) * (R.nz - 2);
+        const int64_t nb = nzf + nyf + nxf;
+        const int ncomp = R.space_charge ? 4 : 3;
+        const int64_t t = (int64_t)blk.id * blockDim.x + threadIdx.x;
+        if (t >= nb * ncomp)
+            return;
+        const int comp = (int)(t / nb);
+        int64_t r = t % nb;
+        int p[3];
+        if (r < nzf) {
+            const int64_t half = (int64_t)R.nx * R.ny;
+            p[2] = r < half ? 0 : R.nz - 1;
+            r %= half;
+            p[0] = (int)(r % R.nx);
+            p[1] = (int)(r / R.nx);
+        } else if (r < nzf + nyf) {
+            r -= nzf;
+            const int64_t half = (int64_t)R.nx * (R.nz - 2);
+            p[1] = r < half ? 0 : R.ny - 1;
+            r %= half;
+            p[0] = (int)(r % R.nx);
+            p[2] = 1 + (int)(r / R.nx);
+        } else {
+            r -= nzf + nyf;
+            const int64_t half = (int64_t)(R.ny - 2) * (R.nz - 2);
+            p[0] = r < half ? 0 : R.nx - 1;
+            r %= half;
+            p[1] = 1 + (int)(r % (R.ny - 2));
+            p[2] = 1 + (int)(r / (R.ny - 2));
         }
+        const int64_t s = R.ctl->step;
+        Lv<T> L{pot_ptr<T>(R, slot_prev(s), comp), pot_ptr<T>(R, slot_cur(s), comp),
+                pot_ptr<T>(R, slot_next(s), comp)};
+        int ax[3], sd[3], m = 0;
+        for (int a = 0; a < 3; ++a) {
+            const int v = bside(R, a, p[a]);
+            if (v != 0) {
+                ax[m] = a;
+                sd[m] = v;
+                ++m;
+            }
+        }
+        double v;
+        if (m == 1)
+            v = face_np1(R, L, p, ax[0], sd[0]);
+        else if (m == 2)
+            v = edge_np1(R, L, p, ax, sd);
+        else
+            v = corner_np1(R, L, p, ax, sd);
+        pot_ptr<T>(R, slot_next(s), comp)[nid(R, p[0], p[1], p[2])] = (T)v;
     }
-    double v;
-    if (m == 1)
-        v = face_np1(R, L, p, ax[0], sd[0]);
-    else if (m == 2)
-        v = edge_np1(R, L, p, ax, sd);
-    else
-        v = corner_np1(R, L, p, ax, sd);
-    pot_ptr<T>(R, slot_next(s), comp)[nid(R, p[0], p[1], p[2])] = (T)v;
-}
+};
 
 // ---------------------------------------------------------------------------
 // K3: E and B at vertices
@@ -731,40 +745,43 @@ __device__ inline void vertex_eb(const RunDev &R, int64_t s, int i, int j, int k
 // all interior nodes (full == 1).  step_bias selects the step whose levels
 // are used (0 during a step, -1 after it for read-back).
 template <typename T>
-__global__ __launch_bounds__(256) void k_vertex_fields(RunDev R, int step_bias, int full)
-{
-    const int64_t s = R.ctl->step + step_bias;
-    int lo[3], hi[3];
-    const int n[3] = {R.nx, R.ny, R.nz};
-    for (int a = 0; a < 3; ++a) {
-        if (full) {
-            lo[a] = 1;
-            hi[a] = n[a] - 2;
-        } else {
-            lo[a] = max(1, R.ctl->cell_lo[a]);
-            hi[a] = min(n[a] - 2, R.ctl->cell_hi[a] + 1);
-        }
-        if (hi[a] < lo[a])
-            return;
-    }
-    const int64_t ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
-    const int64_t tot = ex * ey * ez;
-    T *eb[6];
-    for (int c = 0; c < 6; ++c)
-        eb[c] = eb_ptr<T>(R, c);
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
-        const int i = lo[0] + (int)(t % ex);
-        const int j = lo[1] + (int)((t / ex) % ey);
-        const int k = lo[2] + (int)(t / (ex * ey));
-        double E[3], B[3];
-        vertex_eb<T>(R, s, i, j, k, E, B);
-        const int64_t c = nid(R, i, j, k);
+struct VertexFields {
+    static constexpr int kThreads = 256;
+    static __device__ void run(const RunDev &R, Blk blk, int step_bias, int full)
+    {
+        const int64_t s = R.ctl->step + step_bias;
+        int lo[3], hi[3];
+        const int n[3] = {R.nx, R.ny, R.nz};
         for (int a = 0; a < 3; ++a) {
-            eb[a][c] = (T)E[a];
-            eb[3 + a][c] = (T)B[a];
+            if (full) {
+                lo[a] = 1;
+                hi[a] = n[a] - 2;
+            } else {
+                lo[a] = max(1, R.ctl->cell_lo[a]);
+                hi[a] = min(n[a] - 2, R.ctl->cell_hi[a] + 1);
+            }
+            if (hi[a] < lo[a])
+                return;
+        }
+        const int64_t ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+        const int64_t tot = ex * ey * ez;
+        T *eb[6];
+        for (int c = 0; c < 6; ++c)
+            eb[c] = eb_ptr<T>(R, c);
+        for (int64_t t = (int64_t)blk.id * blockDim.x + threadIdx.x; t < tot; t += (int64_t)blk.n * blockDim.x) {
+            const int i = lo[0] + (int)(t % ex);
+            const int j = lo[1] + (int)((t / ex) % ey);
+            const int k = lo[2] + (int)(t / (ex * ey));
+            double E[3], B[3];
+            vertex_eb<T>(R, s, i, j, k, E, B);
+            const int64_t c = nid(R, i, j, k);
+            for (int a = 0; a < 3; ++a) {
+                eb[a][c] = (T)E[a];
+                eb[3 + a][c] = (T)B[a];
+            }
         }
     }
-}
+};
 
 // Radiated power through node plane k_plane of the fields at t_{s+1/2}
 // (lab-frame Poynting flux).  kPowerBlocks blocks write partial sums over
@@ -773,49 +790,56 @@ __global__ __launch_bounds__(256) void k_vertex_fields(RunDev R, int step_bias, 
 constexpr int kPowerBlocks = 64;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_plane_power(RunDev R, int step_bias, int kp)
-{
-    __shared__ double red[256];
-    const int64_t s = R.ctl->step + step_bias;
-    const double g0 = R.gamma0, b0 = R.beta0;
-    double acc = 0.0;
-    const int wx = R.nx - 2, wy = R.ny - 2;
-    for (int t = blockIdx.x * 256 + threadIdx.x; t < wx * wy; t += kPowerBlocks * 256) {
-        const int i = 1 + t % wx, j = 1 + t / wx;
-        double E[3], B[3];
-        vertex_eb<T>(R, s, i, j, kp, E, B);
-        const double Exl = g0 * (E[0] + b0 * kC * B[1]);
-        const double Eyl = g0 * (E[1] - b0 * kC * B[0]);
-        const double Bxl = g0 * (B[0] - b0 * E[1] / kC);
-        const double Byl = g0 * (B[1] + b0 * E[0] / kC);
-        acc += Exl * Byl - Eyl * Bxl;
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            red[threadIdx.x] += red[threadIdx.x + w];
+struct PlanePower {
+    static constexpr int kThreads = 256;
+    static __device__ void run(const RunDev &R, Blk blk, int step_bias, int kp_arg)
+    {
+        __shared__ double red[256];
+        const int kp = kp_arg < 0 ? R.k_plane : kp_arg;  // < 0: the run's diagnostic plane
+        const int64_t s = R.ctl->step + step_bias;
+        const double g0 = R.gamma0, b0 = R.beta0;
+        double acc = 0.0;
+        const int wx = R.nx - 2, wy = R.ny - 2;
+        for (int t = blk.id * 256 + threadIdx.x; t < wx * wy; t += kPowerBlocks * 256) {
+            const int i = 1 + t % wx, j = 1 + t / wx;
+            double E[3], B[3];
+            vertex_eb<T>(R, s, i, j, kp, E, B);
+            const double Exl = g0 * (E[0] + b0 * kC * B[1]);
+            const double Eyl = g0 * (E[1] - b0 * kC * B[0]);
+            const double Bxl = g0 * (B[0] - b0 * E[1] / kC);
+            const double Byl = g0 * (B[1] + b0 * E[0] / kC);
+            acc += Exl * Byl - Eyl * Bxl;
+        }
+        red[threadIdx.x] = acc;
         __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w)
+                red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            R.ppart[blk.id] = red[0];
     }
-    if (threadIdx.x == 0)
-        R.ppart[blockIdx.x] = red[0];
-}
+};
 
-__global__ void k_plane_power_final(RunDev R, int step_bias, double *out)
-{
-    const int64_t s = R.ctl->step + step_bias;
-    double sum = 0.0;
-    for (int b = 0; b < kPowerBlocks; ++b)
-        sum += R.ppart[b];
-    const double mu0 = 1.0 / (kEps0 * kC * kC);
-    const double P = sum * R.dx * R.dy / mu0;
-    if (out)
-        *out = P;
-    else if (s >= 0 && s < R.power_cap)
-        R.power_hist[s] = P;
-    if (!isfinite(P))
-        R.ctl->nan_flag = 1;
-}
+struct PlanePowerFinal {
+    static constexpr int kThreads = 1;
+    static __device__ void run(const RunDev &R, Blk blk, int step_bias, double *out)
+    {
+        const int64_t s = R.ctl->step + step_bias;
+        double sum = 0.0;
+        for (int b = 0; b < kPowerBlocks; ++b)
+            sum += R.ppart[b];
+        const double mu0 = 1.0 / (kEps0 * kC * kC);
+        const double P = sum * R.dx * R.dy / mu0;
+        if (out)
+            *out = P;
+        else if (s >= 0 && s < R.power_cap)
+            R.power_hist[s] = P;
+        if (!isfinite(P))
+            R.ctl->nan_flag = 1;
+    }
+};
 
 // ---------------------------------------------------------------------------
 // host launchers
@@ -831,7 +855,7 @@ static hipError_t launch_sweep_t(const RunDev &R, hipStream_t st)
     const int64_t ntx = (R.nx + TX - 1) / TX, nty = (R.ny + TY - 1) / TY;
     const int64_t nch = (R.nz - 2 + TZ - 1) / TZ;
     const int64_t nb = ntx * nty * nch * 4;
-    hipLaunchKernelGGL((k_sweep<T, TX, TY, TZ>), dim3((unsigned)nb), dim3(TX * TY), 0, st, R);
+    hipLaunchKernelGGL((k_run<Sweep<T, TX, TY, TZ>>), dim3((unsigned)nb), dim3(TX * TY), 0, st, R);
     return hipGetLastError();
 }
 
@@ -844,11 +868,11 @@ static hipError_t launch_sweep_vec_t(const RunDev &R, hipStream_t st)
     const int64_t nb = ntx * nty * nch * 4;
     if constexpr (sizeof(T) == 4) {
         if (R.compensated) {
-            hipLaunchKernelGGL((k_sweep_vec<T, V, TXV, TY, TZ, true>), dim3((unsigned)nb), dim3(TXV * TY), 0, st, R);
+            hipLaunchKernelGGL((k_run<SweepVec<T, V, TXV, TY, TZ, true>>), dim3((unsigned)nb), dim3(TXV * TY), 0, st, R);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_sweep_vec<T, V, TXV, TY, TZ, false>), dim3((unsigned)nb), dim3(TXV * TY), 0, st, R);
+    hipLaunchKernelGGL((k_run<SweepVec<T, V, TXV, TY, TZ, false>>), dim3((unsigned)nb), dim3(TXV * TY), 0, st, R);
     return hipGetLastError();
 }
 
@@ -913,9 +937,9 @@ hipError_t launch_mur(const RunDev &R, hipStream_t st)
     const int64_t tot = nb * (R.space_charge ? 4 : 3);
     const unsigned blocks = (unsigned)((tot + 255) / 256);
     if (R.precision == 32)
-        hipLaunchKernelGGL(k_mur<float>, dim3(blocks), dim3(256), 0, st, R);
+        hipLaunchKernelGGL((k_run<Mur<float>>), dim3(blocks), dim3(256), 0, st, R);
     else
-        hipLaunchKernelGGL(k_mur<double>, dim3(blocks), dim3(256), 0, st, R);
+        hipLaunchKernelGGL((k_run<Mur<double>>), dim3(blocks), dim3(256), 0, st, R);
     return hipGetLastError();
 }
 
@@ -928,19 +952,147 @@ hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStr
     if (blocks < 1)
         blocks = 1;
     if (R.precision == 32)
-        hipLaunchKernelGGL(k_vertex_fields<float>, dim3((unsigned)blocks), dim3(256), 0, st, R, step_bias, full);
+        hipLaunchKernelGGL((k_run<VertexFields<float>, int, int>), dim3((unsigned)blocks), dim3(256), 0, st, R, step_bias, full);
     else
-        hipLaunchKernelGGL(k_vertex_fields<double>, dim3((unsigned)blocks), dim3(256), 0, st, R, step_bias, full);
+        hipLaunchKernelGGL((k_run<VertexFields<double>, int, int>), dim3((unsigned)blocks), dim3(256), 0, st, R, step_bias, full);
     return hipGetLastError();
 }
 
 hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st)
 {
     if (R.precision == 32)
-        hipLaunchKernelGGL(k_plane_power<float>, dim3(kPowerBlocks), dim3(256), 0, st, R, step_bias, kp);
+        hipLaunchKernelGGL((k_run<PlanePower<float>, int, int>), dim3(kPowerBlocks), dim3(256), 0, st, R, step_bias, kp);
     else
-        hipLaunchKernelGGL(k_plane_power<double>, dim3(kPowerBlocks), dim3(256), 0, st, R, step_bias, kp);
-    hipLaunchKernelGGL(k_plane_power_final, dim3(1), dim3(1), 0, st, R, step_bias, out);
+        hipLaunchKernelGGL((k_run<PlanePower<double>, int, int>), dim3(kPowerBlocks), dim3(256), 0, st, R, step_bias, kp);
+    hipLaunchKernelGGL((k_run<PlanePowerFinal, int, double *>), dim3(1), dim3(1), 0, st, R, step_bias, out);
+    return hipGetLastError();
+}
+
+}  // namespace mithra
+
+// ---------------------------------------------------------------------------
+// grouped launches (several runs per launch; see k_group)
+// ---------------------------------------------------------------------------
+namespace mithra {
+
+int64_t sweep_blocks(const RunDev &R, int shape)
+{
+    const int V = R.precision == 32 ? 4 : 2;
+    if (shape >= 8 && R.nx % V != 0)
+        shape = 0;
+    int tx, ty, tz;
+    sweep_shape_dims(shape, &tx, &ty, &tz);
+    if (shape >= 8 && V == 2)
+        ty /= 2;  // FP64 vector tiles: same thread count, half the rows
+    const int64_t ntx = (R.nx + tx - 1) / tx, nty = (R.ny + ty - 1) / ty;
+    const int64_t nch = (R.nz - 2 + tz - 1) / tz;
+    return ntx * nty * nch * 4;
+}
+
+template <typename T, int TX, int TY, int TZ>
+static void grp_sweep_t(const Group &g, int64_t total, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_group<Sweep<T, TX, TY, TZ>>), dim3((unsigned)total), dim3(TX * TY), 0, st, g);
+}
+
+template <typename T, int V, int TXV, int TY, int TZ>
+static void grp_sweep_vec_t(const Group &g, int64_t total, bool lo, hipStream_t st)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (lo) {
+            hipLaunchKernelGGL((k_group<SweepVec<T, V, TXV, TY, TZ, true>>), dim3((unsigned)total), dim3(TXV * TY), 0,
+                               st, g);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_group<SweepVec<T, V, TXV, TY, TZ, false>>), dim3((unsigned)total), dim3(TXV * TY), 0, st, g);
+}
+
+template <typename T>
+static hipError_t grp_sweep(const Group &g, int64_t total, int shape, bool lo, hipStream_t st)
+{
+    constexpr int V = 16 / sizeof(T);
+    switch (shape) {
+    case 8: grp_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 32>(g, total, lo, st); break;
+    case 9: grp_sweep_vec_t<T, V, 128 / V, 256 * V / 128, 32>(g, total, lo, st); break;
+    case 10: grp_sweep_vec_t<T, V, 64 / V, 512 * V / 64, 32>(g, total, lo, st); break;
+    case 11: grp_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 16>(g, total, lo, st); break;
+    case 12: grp_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 64>(g, total, lo, st); break;
+    case 13: grp_sweep_vec_t<T, V, 32 / V, 256 * V / 32, 32>(g, total, lo, st); break;
+    case 14: grp_sweep_vec_t<T, V, 128 / V, 256 * V / 128, 16>(g, total, lo, st); break;
+    case 15: grp_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 8>(g, total, lo, st); break;
+    case 16: grp_sweep_vec_t<T, V, 128 / V, 1024 * V / 128, 16>(g, total, lo, st); break;
+    case 17: grp_sweep_vec_t<T, V, 64 / V, 512 * V / 64, 16>(g, total, lo, st); break;
+    case 0: grp_sweep_t<T, 64, 8, 32>(g, total, st); break;
+    case 1: grp_sweep_t<T, 64, 4, 32>(g, total, st); break;
+    case 2: grp_sweep_t<T, 32, 8, 32>(g, total, st); break;
+    case 3: grp_sweep_t<T, 64, 8, 64>(g, total, st); break;
+    case 4: grp_sweep_t<T, 128, 4, 32>(g, total, st); break;
+    case 5: grp_sweep_t<T, 64, 16, 32>(g, total, st); break;
+    case 6: grp_sweep_t<T, 32, 4, 16>(g, total, st); break;
+    case 7: grp_sweep_t<T, 64, 8, 16>(g, total, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// all members share precision, compensation and the (effective) shape
+hipError_t launch_sweep_group(const Group &g, int64_t total, int precision, int compensated, int shape,
+                              hipStream_t st)
+{
+    if (total <= 0)
+        return hipSuccess;
+    return precision == 32 ? grp_sweep<float>(g, total, shape, compensated != 0, st)
+                           : grp_sweep<double>(g, total, shape, false, st);
+}
+
+int64_t mur_blocks(const RunDev &R)
+{
+    const int64_t nb = 2LL * R.nx * R.ny + 2LL * R.nx * (R.nz - 2) + (R.xface_fused ? 0 : 2LL * (R.ny - 2) * (R.nz - 2));
+    return (nb * (R.space_charge ? 4 : 3) + 255) / 256;
+}
+
+hipError_t launch_mur_group(const Group &g, int64_t total, int precision, hipStream_t st)
+{
+    if (total <= 0)
+        return hipSuccess;
+    if (precision == 32)
+        hipLaunchKernelGGL((k_group<Mur<float>>), dim3((unsigned)total), dim3(256), 0, st, g);
+    else
+        hipLaunchKernelGGL((k_group<Mur<double>>), dim3((unsigned)total), dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+int64_t vertex_blocks(const RunDev &R)
+{
+    const int64_t inner = (int64_t)(R.nx - 2) * (R.ny - 2) * (R.nz - 2);
+    return std::min<int64_t>(8192, std::max<int64_t>(1, (inner + 255) / 256));
+}
+
+hipError_t launch_vertex_group(const Group &g, int64_t total, int precision, hipStream_t st)
+{
+    if (total <= 0)
+        return hipSuccess;
+    if (precision == 32)
+        hipLaunchKernelGGL((k_group<VertexFields<float>, int, int>), dim3((unsigned)total), dim3(256), 0, st, g, 0, 0);
+    else
+        hipLaunchKernelGGL((k_group<VertexFields<double>, int, int>), dim3((unsigned)total), dim3(256), 0, st, g, 0, 0);
+    return hipGetLastError();
+}
+
+int64_t power_blocks() { return kPowerBlocks; }
+
+hipError_t launch_power_group(const Group &g, int64_t total, const Group &gf, int64_t total_f, int precision,
+                              hipStream_t st)
+{
+    if (total <= 0)
+        return hipSuccess;
+    if (precision == 32)
+        hipLaunchKernelGGL((k_group<PlanePower<float>, int, int>), dim3((unsigned)total), dim3(256), 0, st, g, 0, -1);
+    else
+        hipLaunchKernelGGL((k_group<PlanePower<double>, int, int>), dim3((unsigned)total), dim3(256), 0, st, g, 0, -1);
+    hipLaunchKernelGGL((k_group<PlanePowerFinal, int, double *>), dim3((unsigned)total_f), dim3(1), 0, st, gf, 0,
+                       (double *)nullptr);
     return hipGetLastError();
 }
 

@@ -10,189 +10,193 @@ namespace mithra {
 
 // cosh and sinh of x from one expm1 (no cancellation near x = 0)
 constexpr int kDepThreads = 256;
-constexpr int kLdsNodes = 1536;  // node box capacity of the LDS stage (4 arrays, FP64: 48 KiB)
+constexpr int kLdsNodes = 1536;
+__host__ __device__ inline int64_t dep_blocks_dev(int64_t np) { return (np + kDepThreads - 1) / kDepThreads; }  // node box capacity of the LDS stage (4 arrays, FP64: 48 KiB)
 
 // Gather + undulator + N_b Boris sub-steps + deposit (MODE 0), or the load
 // deposit of the backward-drift move (MODE 1, sorted particles, set 0).
 // The block's deposits are summed in LDS over its node box when the box
 // fits, then added to HBM once per touched node; otherwise directly.
 template <typename T, bool COMP, int MODE>
-__global__ __launch_bounds__(kDepThreads) void k_push_deposit(RunDev R)
-{
-    __shared__ double lds[4 * kLdsNodes];
-    __shared__ int bb[6];
-    const int64_t s = R.ctl->step;
-    const int pb = R.ctl->pbuf;
-    const int set = MODE == 0 ? (int)((s + 1) & 1) : 0;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (threadIdx.x < 3) {
-        bb[threadIdx.x] = 0x7fffffff;
-        bb[3 + threadIdx.x] = -1;
-    }
+struct PushDeposit {
+    static constexpr int kThreads = kDepThreads;
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        __shared__ double lds[4 * kLdsNodes];
+        __shared__ int bb[6];
+        const int64_t s = R.ctl->step;
+        const int pb = R.ctl->pbuf;
+        const int set = MODE == 0 ? (int)((s + 1) & 1) : 0;
+        const int64_t p = (int64_t)blk.id * blockDim.x + threadIdx.x;
+        if (threadIdx.x < 3) {
+            bb[threadIdx.x] = 0x7fffffff;
+            bb[3 + threadIdx.x] = -1;
+        }
 
-    double g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0};
-    int c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
-    bool dep_j = false, dep_q = false;
-    if (p < R.np) {
-        double r[3], u[3];
-        for (int a = 0; a < 3; ++a) {
-            r[a] = R.pr[pb][a][p];
-            u[a] = R.pr[pb][3 + a][p];
-        }
-        if (MODE == 1) {
-            const double ig = 1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            double r0[3];
-            for (int a = 0; a < 3; ++a)
-                r0[a] = r[a] - kC * R.dt * u[a] * ig;
-            const bool a1 = cell_of(R, r0, g1, c1);
-            const bool a2 = cell_of(R, r, g2, c2);
-            dep_j = a1 && a2;
-            dep_q = a2;
-        } else {
-            const bool act1 = cell_of(R, r, g1, c1);
-            double Eg[3] = {0, 0, 0}, Bg[3] = {0, 0, 0};
-            if (act1) {
-                const int64_t base = nid(R, c1[0], c1[1], c1[2]);
-                const int64_t sy = R.nx, sz = (int64_t)R.nx * R.ny;
-                const double dx = g1[0] - c1[0], dy = g1[1] - c1[1], dz = g1[2] - c1[2];
-                const double wx[2] = {1.0 - dx, dx}, wy[2] = {1.0 - dy, dy}, wz[2] = {1.0 - dz, dz};
-#pragma unroll
-                for (int K = 0; K < 2; ++K)
-#pragma unroll
-                    for (int J = 0; J < 2; ++J)
-#pragma unroll
-                        for (int I = 0; I < 2; ++I) {
-                            const double w = wx[I] * wy[J] * wz[K];
-                            const int64_t n = base + I + J * sy + K * sz;
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                Eg[a] += w * (double)eb_ptr<T>(R, a)[n];
-                                Bg[a] += w * (double)eb_ptr<T>(R, 3 + a)[n];
-                            }
-                        }
-            }
-            const double t_half = ((double)s + 0.5) * R.dt;
-            for (int sub = 0; sub < R.n_sub; ++sub) {
-                double Ee[3], Be[3];
-                undulator_field(R, r[0], r[1], r[2], t_half + (double)sub * R.dtb, Ee, Be);
-                for (int a = 0; a < 3; ++a) {
-                    Ee[a] += Eg[a];
-                    Be[a] += Bg[a];
-                }
-                boris(u, Ee, Be, R.dtb);
-                const double ig = 1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-                for (int a = 0; a < 3; ++a)
-                    r[a] = r[a] + kC * R.dtb * u[a] * ig;
-            }
+        double g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0};
+        int c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
+        bool dep_j = false, dep_q = false;
+        if (p < R.np) {
+            double r[3], u[3];
             for (int a = 0; a < 3; ++a) {
-                R.pr[pb][a][p] = r[a];
-                R.pr[pb][3 + a][p] = u[a];
+                r[a] = R.pr[pb][a][p];
+                u[a] = R.pr[pb][3 + a][p];
             }
-            const bool act2 = cell_of(R, r, g2, c2);
-            dep_j = act1 && act2;
-            dep_q = act2;
-            // sort key of the new position, in id order, for this step's sort
-            const int32_t id = R.pid[pb][p];
-            R.key_by_id[id] = act2 ? key_of_cell(R, c2) : R.key_inactive;
-            R.slot_of_id[id] = (int32_t)p;
+            if (MODE == 1) {
+                const double ig = 1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                double r0[3];
+                for (int a = 0; a < 3; ++a)
+                    r0[a] = r[a] - kC * R.dt * u[a] * ig;
+                const bool a1 = cell_of(R, r0, g1, c1);
+                const bool a2 = cell_of(R, r, g2, c2);
+                dep_j = a1 && a2;
+                dep_q = a2;
+            } else {
+                const bool act1 = cell_of(R, r, g1, c1);
+                double Eg[3] = {0, 0, 0}, Bg[3] = {0, 0, 0};
+                if (act1) {
+                    const int64_t base = nid(R, c1[0], c1[1], c1[2]);
+                    const int64_t sy = R.nx, sz = (int64_t)R.nx * R.ny;
+                    const double dx = g1[0] - c1[0], dy = g1[1] - c1[1], dz = g1[2] - c1[2];
+                    const double wx[2] = {1.0 - dx, dx}, wy[2] = {1.0 - dy, dy}, wz[2] = {1.0 - dz, dz};
+    #pragma unroll
+                    for (int K = 0; K < 2; ++K)
+    #pragma unroll
+                        for (int J = 0; J < 2; ++J)
+    #pragma unroll
+                            for (int I = 0; I < 2; ++I) {
+                                const double w = wx[I] * wy[J] * wz[K];
+                                const int64_t n = base + I + J * sy + K * sz;
+    #pragma unroll
+                                for (int a = 0; a < 3; ++a) {
+                                    Eg[a] += w * (double)eb_ptr<T>(R, a)[n];
+                                    Bg[a] += w * (double)eb_ptr<T>(R, 3 + a)[n];
+                                }
+                            }
+                }
+                const double t_half = ((double)s + 0.5) * R.dt;
+                for (int sub = 0; sub < R.n_sub; ++sub) {
+                    double Ee[3], Be[3];
+                    undulator_field(R, r[0], r[1], r[2], t_half + (double)sub * R.dtb, Ee, Be);
+                    for (int a = 0; a < 3; ++a) {
+                        Ee[a] += Eg[a];
+                        Be[a] += Bg[a];
+                    }
+                    boris(u, Ee, Be, R.dtb);
+                    const double ig = 1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                    for (int a = 0; a < 3; ++a)
+                        r[a] = r[a] + kC * R.dtb * u[a] * ig;
+                }
+                for (int a = 0; a < 3; ++a) {
+                    R.pr[pb][a][p] = r[a];
+                    R.pr[pb][3 + a][p] = u[a];
+                }
+                const bool act2 = cell_of(R, r, g2, c2);
+                dep_j = act1 && act2;
+                dep_q = act2;
+                // sort key of the new position, in id order, for this step's sort
+                const int32_t id = R.pid[pb][p];
+                R.key_by_id[id] = act2 ? key_of_cell(R, c2) : R.key_inactive;
+                R.slot_of_id[id] = (int32_t)p;
+            }
         }
-    }
-    if (MODE == 0) {
-        // per-block box of the active cells after the push (sort statistics)
-        __shared__ int32_t cw[4][7];
-        int clo[3], chi[3];
-        for (int l = 0; l < 3; ++l) {
-            clo[l] = dep_q ? c2[l] : 0x7fffffff;
-            chi[l] = dep_q ? c2[l] : -1;
-            clo[l] = wave_min(clo[l]);
-            chi[l] = wave_max(chi[l]);
-        }
-        const int nact = __popcll(__ballot(dep_q));
-        const int wave = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0) {
+        if (MODE == 0) {
+            // per-block box of the active cells after the push (sort statistics)
+            __shared__ int32_t cw[4][7];
+            int clo[3], chi[3];
             for (int l = 0; l < 3; ++l) {
-                cw[wave][l] = clo[l];
-                cw[wave][3 + l] = chi[l];
+                clo[l] = dep_q ? c2[l] : 0x7fffffff;
+                chi[l] = dep_q ? c2[l] : -1;
+                clo[l] = wave_min(clo[l]);
+                chi[l] = wave_max(chi[l]);
             }
-            cw[wave][6] = nact;
-        }
-        __syncthreads();
-        if (threadIdx.x < 7) {
-            int32_t v = cw[0][threadIdx.x];
-            for (int w = 1; w < kDepThreads / 64; ++w) {
-                const int32_t x = cw[w][threadIdx.x];
-                v = threadIdx.x < 3 ? min(v, x) : (threadIdx.x < 6 ? max(v, x) : v + x);
+            const int nact = __popcll(__ballot(dep_q));
+            const int wave = threadIdx.x >> 6;
+            if ((threadIdx.x & 63) == 0) {
+                for (int l = 0; l < 3; ++l) {
+                    cw[wave][l] = clo[l];
+                    cw[wave][3 + l] = chi[l];
+                }
+                cw[wave][6] = nact;
             }
-            R.cellpart[8 * (int64_t)blockIdx.x + threadIdx.x] = v;
+            __syncthreads();
+            if (threadIdx.x < 7) {
+                int32_t v = cw[0][threadIdx.x];
+                for (int w = 1; w < kDepThreads / 64; ++w) {
+                    const int32_t x = cw[w][threadIdx.x];
+                    v = threadIdx.x < 3 ? min(v, x) : (threadIdx.x < 6 ? max(v, x) : v + x);
+                }
+                R.cellpart[8 * (int64_t)blk.id + threadIdx.x] = v;
+            }
         }
-    }
-    // node box of this thread's deposits
-    int lo[3], hi[3];
-    for (int l = 0; l < 3; ++l) {
-        lo[l] = 0x7fffffff;
-        hi[l] = -1;
-        if (dep_j) {
-            lo[l] = min(c1[l], c2[l]);
-            hi[l] = max(c1[l], c2[l]) + 1;
-        } else if (dep_q) {
-            lo[l] = c2[l];
-            hi[l] = c2[l] + 1;
-        }
-        lo[l] = wave_min(lo[l]);
-        hi[l] = wave_max(hi[l]);
-    }
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0 && hi[0] >= 0)
+        // node box of this thread's deposits
+        int lo[3], hi[3];
         for (int l = 0; l < 3; ++l) {
-            atomicMin(&bb[l], lo[l]);
-            atomicMax(&bb[3 + l], hi[l]);
-        }
-    __syncthreads();
-    // this block's box goes to its partial slot (reduced by k_box_reduce)
-    if (threadIdx.x < 7)
-        R.boxpart[8 * (int64_t)blockIdx.x + threadIdx.x] = threadIdx.x < 6 ? bb[threadIdx.x] : 0;
-    const int L0 = bb[0], L1 = bb[1], L2 = bb[2];
-    if (bb[3] < 0)
-        return;  // nothing deposited by this block (uniform)
-    const int ex = bb[3] - L0 + 1, ey = bb[4] - L1 + 1, ez = bb[5] - L2 + 1;
-    const int vol = ex * ey * ez;
-    if (vol <= kLdsNodes) {
-        for (int e = threadIdx.x; e < 4 * vol; e += kDepThreads)
-            lds[e] = 0.0;
-        __syncthreads();
-        const LdsAcc<double> acc{lds, L0, L1, L2, ex, ey, vol};
-        if (dep_j)
-            deposit_move(R, acc, g1, c1, g2, c2);
-        if (dep_q)
-            deposit_charge(R, acc, g2, c2);
-        __syncthreads();
-        const GlobalAcc<T, COMP> gacc = make_gacc<T, COMP>(R, set);
-        // four entries per thread per round, so that the returning atomics of
-        // the compensated mode are in flight together
-        for (int e0 = threadIdx.x; e0 < 4 * vol; e0 += 4 * kDepThreads) {
-            double v[4];
-            int idx[4][4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int e = e0 + q * kDepThreads;
-                v[q] = e < 4 * vol ? lds[e] : 0.0;
-                const int comp = e / vol;
-                const int r = e - comp * vol;
-                idx[q][0] = comp;
-                idx[q][1] = L0 + r % ex;
-                idx[q][2] = L1 + (r / ex) % ey;
-                idx[q][3] = L2 + r / (ex * ey);
+            lo[l] = 0x7fffffff;
+            hi[l] = -1;
+            if (dep_j) {
+                lo[l] = min(c1[l], c2[l]);
+                hi[l] = max(c1[l], c2[l]) + 1;
+            } else if (dep_q) {
+                lo[l] = c2[l];
+                hi[l] = c2[l] + 1;
             }
-            gacc.add4(v, idx);
+            lo[l] = wave_min(lo[l]);
+            hi[l] = wave_max(hi[l]);
         }
-    } else {
-        const GlobalAcc<T, COMP> gacc = make_gacc<T, COMP>(R, set);
-        if (dep_j)
-            deposit_move(R, gacc, g1, c1, g2, c2);
-        if (dep_q)
-            deposit_charge(R, gacc, g2, c2);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0 && hi[0] >= 0)
+            for (int l = 0; l < 3; ++l) {
+                atomicMin(&bb[l], lo[l]);
+                atomicMax(&bb[3 + l], hi[l]);
+            }
+        __syncthreads();
+        // this block's box goes to its partial slot (reduced by k_box_reduce)
+        if (threadIdx.x < 7)
+            R.boxpart[8 * (int64_t)blk.id + threadIdx.x] = threadIdx.x < 6 ? bb[threadIdx.x] : 0;
+        const int L0 = bb[0], L1 = bb[1], L2 = bb[2];
+        if (bb[3] < 0)
+            return;  // nothing deposited by this block (uniform)
+        const int ex = bb[3] - L0 + 1, ey = bb[4] - L1 + 1, ez = bb[5] - L2 + 1;
+        const int vol = ex * ey * ez;
+        if (vol <= kLdsNodes) {
+            for (int e = threadIdx.x; e < 4 * vol; e += kDepThreads)
+                lds[e] = 0.0;
+            __syncthreads();
+            const LdsAcc<double> acc{lds, L0, L1, L2, ex, ey, vol};
+            if (dep_j)
+                deposit_move(R, acc, g1, c1, g2, c2);
+            if (dep_q)
+                deposit_charge(R, acc, g2, c2);
+            __syncthreads();
+            const GlobalAcc<T, COMP> gacc = make_gacc<T, COMP>(R, set);
+            // four entries per thread per round, so that the returning atomics of
+            // the compensated mode are in flight together
+            for (int e0 = threadIdx.x; e0 < 4 * vol; e0 += 4 * kDepThreads) {
+                double v[4];
+                int idx[4][4];
+    #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = e0 + q * kDepThreads;
+                    v[q] = e < 4 * vol ? lds[e] : 0.0;
+                    const int comp = e / vol;
+                    const int r = e - comp * vol;
+                    idx[q][0] = comp;
+                    idx[q][1] = L0 + r % ex;
+                    idx[q][2] = L1 + (r / ex) % ey;
+                    idx[q][3] = L2 + r / (ex * ey);
+                }
+                gacc.add4(v, idx);
+            }
+        } else {
+            const GlobalAcc<T, COMP> gacc = make_gacc<T, COMP>(R, set);
+            if (dep_j)
+                deposit_move(R, gacc, g1, c1, g2, c2);
+            if (dep_q)
+                deposit_charge(R, gacc, g2, c2);
+        }
     }
-}
+};
 
 // |sum exp(i k_r z)| over active particles, in two partial sums per block
 __global__ __launch_bounds__(256) void k_bunching(RunDev R, double *part)
@@ -240,18 +244,18 @@ static hipError_t launch_dep(const RunDev &R, hipStream_t st)
         return hipSuccess;
     const unsigned blocks = (unsigned)((R.np + kDepThreads - 1) / kDepThreads);
     if (R.precision == 64)
-        hipLaunchKernelGGL((k_push_deposit<double, false, MODE>), dim3(blocks), dim3(kDepThreads), 0, st, R);
+        hipLaunchKernelGGL((k_run<PushDeposit<double, false, MODE>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
     else if (R.compensated)
-        hipLaunchKernelGGL((k_push_deposit<float, true, MODE>), dim3(blocks), dim3(kDepThreads), 0, st, R);
+        hipLaunchKernelGGL((k_run<PushDeposit<float, true, MODE>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
     else
-        hipLaunchKernelGGL((k_push_deposit<float, false, MODE>), dim3(blocks), dim3(kDepThreads), 0, st, R);
+        hipLaunchKernelGGL((k_run<PushDeposit<float, false, MODE>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
     return hipGetLastError();
 }
 
 // Reduce the per-block partial boxes (and counts) of `nblocks` blocks into
 // lo/hi (and *count if non-null): one block, fixed order.
-__global__ __launch_bounds__(1024) void k_box_reduce(const int32_t *part, int64_t nblocks, int32_t *lo, int32_t *hi,
-                                                    int32_t *count, int32_t *zero)
+__device__ inline void box_reduce_blk(const int32_t *part, int64_t nblocks, int32_t *lo, int32_t *hi, int32_t *count,
+                                      int32_t *zero)
 {
     if (zero && threadIdx.x == 0)
         *zero = 0;
@@ -288,38 +292,60 @@ __global__ __launch_bounds__(1024) void k_box_reduce(const int32_t *part, int64_
     }
 }
 
-__global__ __launch_bounds__(1024) void k_box_reduce_set(RunDev R, int64_t nblocks)
+__global__ __launch_bounds__(1024) void k_box_reduce(const int32_t *part, int64_t nblocks, int32_t *lo, int32_t *hi,
+                                                    int32_t *count, int32_t *zero)
 {
-    const int set = (int)((R.ctl->step + 1) & 1);
-    __shared__ int32_t sh[6][1024];
-    int32_t v[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
-    for (int64_t b = threadIdx.x; b < nblocks; b += 1024) {
-        const int32_t *q = R.boxpart + 8 * b;
-        for (int a = 0; a < 3; ++a) {
-            v[a] = min(v[a], q[a]);
-            v[3 + a] = max(v[3 + a], q[3 + a]);
+    box_reduce_blk(part, nblocks, lo, hi, count, zero);
+}
+
+// after the push of a step: the box of the active cells of the new
+// positions and their count, from the per-block partials; the tile work
+// item counter is reset (the sort that follows builds the new order)
+struct BoxReduceCells {
+    static constexpr int kThreads = 1024;
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        box_reduce_blk(R.cellpart, dep_blocks_dev(R.np), R.ctl->cell_lo, R.ctl->cell_hi, &R.ctl->n_active,
+                       &R.ctl->n_items);
+    }
+};
+
+struct BoxReduceSet {
+    static constexpr int kThreads = 1024;
+    static __device__ void run(const RunDev &R, Blk blk, int64_t nblocks_arg)
+    {
+        const int64_t nblocks = nblocks_arg < 0 ? dep_blocks_dev(R.np) : nblocks_arg;
+        const int set = (int)((R.ctl->step + 1) & 1);
+        __shared__ int32_t sh[6][1024];
+        int32_t v[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
+        for (int64_t b = threadIdx.x; b < nblocks; b += 1024) {
+            const int32_t *q = R.boxpart + 8 * b;
+            for (int a = 0; a < 3; ++a) {
+                v[a] = min(v[a], q[a]);
+                v[3 + a] = max(v[3 + a], q[3 + a]);
+            }
+        }
+        for (int a = 0; a < 6; ++a)
+            sh[a][threadIdx.x] = v[a];
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w)
+                for (int a = 0; a < 3; ++a) {
+                    sh[a][threadIdx.x] = min(sh[a][threadIdx.x], sh[a][threadIdx.x + w]);
+                    sh[3 + a][threadIdx.x] = max(sh[3 + a][threadIdx.x], sh[3 + a][threadIdx.x + w]);
+                }
+            __syncthreads();
+        }
+        if (threadIdx.x < 3) {
+            R.ctl->dep_lo[set][threadIdx.x] = sh[threadIdx.x][0];
+            R.ctl->dep_hi[set][threadIdx.x] = sh[3 + threadIdx.x][0];
         }
     }
-    for (int a = 0; a < 6; ++a)
-        sh[a][threadIdx.x] = v[a];
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int a = 0; a < 3; ++a) {
-                sh[a][threadIdx.x] = min(sh[a][threadIdx.x], sh[a][threadIdx.x + w]);
-                sh[3 + a][threadIdx.x] = max(sh[3 + a][threadIdx.x], sh[3 + a][threadIdx.x + w]);
-            }
-        __syncthreads();
-    }
-    if (threadIdx.x < 3) {
-        R.ctl->dep_lo[set][threadIdx.x] = sh[threadIdx.x][0];
-        R.ctl->dep_hi[set][threadIdx.x] = sh[3 + threadIdx.x][0];
-    }
-}
+};
 
 hipError_t launch_box_reduce_set(const RunDev &R, int64_t nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_box_reduce_set, dim3(1), dim3(1024), 0, st, R, nblocks);
+    hipLaunchKernelGGL((k_run<BoxReduceSet, int64_t>), dim3(1), dim3(1024), 0, st, R, nblocks);
     return hipGetLastError();
 }
 
@@ -354,6 +380,36 @@ hipError_t launch_load_deposit(const RunDev &R, hipStream_t st)
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bunching, dim3(blocks), dim3(256), 0, st, R, part);
+    return hipGetLastError();
+}
+
+}  // namespace mithra
+
+// ---------------------------------------------------------------------------
+// grouped launches (several runs per launch; see k_group)
+// ---------------------------------------------------------------------------
+namespace mithra {
+
+hipError_t launch_push_group(const Group &g, int64_t total, int precision, int compensated, hipStream_t st)
+{
+    if (total <= 0)
+        return hipSuccess;
+    if (precision == 64)
+        hipLaunchKernelGGL((k_group<PushDeposit<double, false, 0>>), dim3((unsigned)total), dim3(kDepThreads), 0, st, g);
+    else if (compensated)
+        hipLaunchKernelGGL((k_group<PushDeposit<float, true, 0>>), dim3((unsigned)total), dim3(kDepThreads), 0, st, g);
+    else
+        hipLaunchKernelGGL((k_group<PushDeposit<float, false, 0>>), dim3((unsigned)total), dim3(kDepThreads), 0, st, g);
+    return hipGetLastError();
+}
+
+// one workgroup per member each
+hipError_t launch_box_group(const Group &g, int64_t total, hipStream_t st)
+{
+    if (total <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((k_group<BoxReduceSet, int64_t>), dim3((unsigned)total), dim3(1024), 0, st, g, (int64_t)-1);
+    hipLaunchKernelGGL((k_group<BoxReduceCells>), dim3((unsigned)total), dim3(1024), 0, st, g);
     return hipGetLastError();
 }
 

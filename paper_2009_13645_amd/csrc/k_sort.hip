@@ -99,28 +99,34 @@ __global__ __launch_bounds__(256) void k_sort_keys(RunDev R)
 }
 
 // per-block digit histogram, stored digit-major: hist[d * nblocks + b]
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *keys, int64_t n, int shift, uint32_t *hist,
-                                                          int64_t nblocks)
+__device__ inline void radix_hist_blk(const uint32_t *keys, int64_t n, int shift, uint32_t *hist, int64_t nblocks,
+                                      int64_t bid)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+    const int64_t base = (int64_t)bid * kSortChunk;
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t e = base + (int64_t)it * kSortThreads + threadIdx.x;
         if (e < n)
             atomicAdd(&h[(keys[e] >> shift) & 0xFF], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    hist[(int64_t)threadIdx.x * nblocks + bid] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *keys, int64_t n, int shift, uint32_t *hist,
+                                                          int64_t nblocks)
+{
+    radix_hist_blk(keys, n, shift, hist, nblocks, blockIdx.x);
 }
 
 // Per digit d (one block each): exclusive scan of hist[d][0..nblocks) in
 // place, and the digit total into tot[d].
-__global__ __launch_bounds__(256) void k_digit_scan(uint32_t *hist, int64_t nblocks, uint32_t *tot)
+__device__ inline void digit_scan_blk(uint32_t *hist, int64_t nblocks, uint32_t *tot, int64_t bid)
 {
     __shared__ uint32_t ws[4];
-    uint32_t *a = hist + (int64_t)blockIdx.x * nblocks;
+    uint32_t *a = hist + (int64_t)bid * nblocks;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t carry = 0;
     for (int64_t base = 0; base < nblocks; base += 4 * 256) {
@@ -154,14 +160,18 @@ __global__ __launch_bounds__(256) void k_digit_scan(uint32_t *hist, int64_t nblo
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        tot[blockIdx.x] = carry;
+        tot[bid] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_digit_scan(uint32_t *hist, int64_t nblocks, uint32_t *tot)
+{
+    digit_scan_blk(hist, nblocks, tot, blockIdx.x);
 }
 
 // stable scatter of one pass.  vals_in == nullptr means identity values.
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *keys_in, const int32_t *vals_in,
-                                                             uint32_t *keys_out, int32_t *vals_out, int64_t n,
-                                                             int shift, const uint32_t *offs, int64_t nblocks,
-                                                             const uint32_t *tot)
+__device__ inline void radix_scatter_blk(const uint32_t *keys_in, const int32_t *vals_in, uint32_t *keys_out,
+                                         int32_t *vals_out, int64_t n, int shift, const uint32_t *offs, int64_t nblocks,
+                                         const uint32_t *tot, int64_t bid)
 {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[kSortThreads / 64][256];
@@ -182,10 +192,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
         uint32_t wb = 0;
         for (int w = 0; w < wave; ++w)
             wb += wcnt[0][w];
-        run[threadIdx.x] = wb + inc - t + offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+        run[threadIdx.x] = wb + inc - t + offs[(int64_t)threadIdx.x * nblocks + bid];
         __syncthreads();
     }
-    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+    const int64_t base = (int64_t)bid * kSortChunk;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     for (int it = 0; it < kSortItems; ++it) {
         for (int w = 0; w < kSortThreads / 64; ++w)
@@ -227,12 +237,20 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     }
 }
 
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *keys_in, const int32_t *vals_in,
+                                                             uint32_t *keys_out, int32_t *vals_out, int64_t n,
+                                                             int shift, const uint32_t *offs, int64_t nblocks,
+                                                             const uint32_t *tot)
+{
+    radix_scatter_blk(keys_in, vals_in, keys_out, vals_out, n, shift, offs, nblocks, tot, blockIdx.x);
+}
+
 // gather particle state into the other buffer in sorted order
-__global__ __launch_bounds__(256) void k_sort_gather(RunDev R, const uint32_t *keys, const int32_t *ids)
+__device__ inline void sort_gather_blk(const RunDev &R, const uint32_t *keys, const int32_t *ids, int64_t bid)
 {
     const int pb = R.ctl->pbuf;
     const int nb = pb ^ 1;
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = (int64_t)bid * blockDim.x + threadIdx.x;
     if (r >= R.np)
         return;
     const int32_t id = ids[r];
@@ -243,18 +261,72 @@ __global__ __launch_bounds__(256) void k_sort_gather(RunDev R, const uint32_t *k
     R.key_sorted[r] = keys[r];
 }
 
-// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sort_gather(RunDev R, const uint32_t *keys, const int32_t *ids)
+{
+    sort_gather_blk(R, keys, ids, blockIdx.x);
+}
 
-hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
-                             int32_t *count, hipStream_t st, int32_t *zero);
-
-int sort_passes(uint32_t key_inactive)
+// The same passes with every pointer derived from the run, for grouped
+// launches over runs of different sizes and key ranges: pass ps of a run
+// that needs fewer passes does nothing, and the gather reads the output of
+// the run's own last pass.
+__host__ __device__ inline int sort_passes_of(uint32_t key_inactive)
 {
     int bits = 0;
     while (bits < 32 && (key_inactive >> bits) != 0)
         ++bits;
     return bits <= 8 ? 1 : (bits + 7) / 8;
 }
+
+struct RadixHistRun {
+    static constexpr int kThreads = kSortThreads;
+    static __device__ void run(const RunDev &R, Blk blk, int ps)
+    {
+        if (ps >= sort_passes_of(R.key_inactive) || R.np <= 0)
+            return;
+        const uint32_t *kin = ps == 0 ? R.key_by_id : R.sk[(ps - 1) & 1];
+        radix_hist_blk(kin, R.np, 8 * ps, R.hist, R.sort_blocks, blk.id);
+    }
+};
+
+struct DigitScanRun {
+    static constexpr int kThreads = 256;
+    static __device__ void run(const RunDev &R, Blk blk, int ps)
+    {
+        if (ps >= sort_passes_of(R.key_inactive) || R.np <= 0)
+            return;
+        digit_scan_blk(R.hist, R.sort_blocks, R.hist + 256 * R.sort_blocks, blk.id);
+    }
+};
+
+struct RadixScatterRun {
+    static constexpr int kThreads = kSortThreads;
+    static __device__ void run(const RunDev &R, Blk blk, int ps)
+    {
+        if (ps >= sort_passes_of(R.key_inactive) || R.np <= 0)
+            return;
+        const uint32_t *kin = ps == 0 ? R.key_by_id : R.sk[(ps - 1) & 1];
+        const int32_t *vin = ps == 0 ? nullptr : R.sv[(ps - 1) & 1];
+        radix_scatter_blk(kin, vin, R.sk[ps & 1], R.sv[ps & 1], R.np, 8 * ps, R.hist, R.sort_blocks,
+                          R.hist + 256 * R.sort_blocks, blk.id);
+    }
+};
+
+struct SortGatherRun {
+    static constexpr int kThreads = 256;
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        const int last = sort_passes_of(R.key_inactive) - 1;
+        sort_gather_blk(R, R.sk[last & 1], R.sv[last & 1], blk.id);
+    }
+};
+
+// ---------------------------------------------------------------------------
+
+hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
+                             int32_t *count, hipStream_t st, int32_t *zero);
+
+int sort_passes(uint32_t key_inactive) { return sort_passes_of(key_inactive); }
 
 int64_t sort_blocks(int64_t n) { return (n + kSortChunk - 1) / kSortChunk; }
 
@@ -288,6 +360,29 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
         vin = vout;
     }
     hipLaunchKernelGGL(k_sort_gather, dim3(pblocks), dim3(256), 0, st, R, kin, vin);
+    return hipGetLastError();
+}
+
+}  // namespace mithra
+
+// ---------------------------------------------------------------------------
+// grouped launches (several runs per launch; see k_group)
+// ---------------------------------------------------------------------------
+namespace mithra {
+
+// gs: members with sort_blocks workgroups; gd: 256 workgroups each (one
+// per digit); gp: one workgroup per 256 particles
+hipError_t launch_sort_group(const Group &gs, int64_t total_s, const Group &gd, int64_t total_d, const Group &gp,
+                             int64_t total_p, int max_passes, hipStream_t st)
+{
+    if (total_p <= 0)
+        return hipSuccess;
+    for (int ps = 0; ps < max_passes; ++ps) {
+        hipLaunchKernelGGL((k_group<RadixHistRun, int>), dim3((unsigned)total_s), dim3(kSortThreads), 0, st, gs, ps);
+        hipLaunchKernelGGL((k_group<DigitScanRun, int>), dim3((unsigned)total_d), dim3(256), 0, st, gd, ps);
+        hipLaunchKernelGGL((k_group<RadixScatterRun, int>), dim3((unsigned)total_s), dim3(kSortThreads), 0, st, gs, ps);
+    }
+    hipLaunchKernelGGL((k_group<SortGatherRun>), dim3((unsigned)total_p), dim3(256), 0, st, gp);
     return hipGetLastError();
 }
 

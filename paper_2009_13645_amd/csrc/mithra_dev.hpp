@@ -34,6 +34,7 @@ struct Ctl {
     int32_t n_items;       // tile work items built after the last sort
     int32_t item_next;     // next work item to take (persistent push)
     int32_t pad_;
+    int64_t target;        // step count at which a batched run stops (grouped launches only)
 };
 
 constexpr int kMaxBatch = 1;  // one run per RunDev
@@ -152,6 +153,59 @@ __device__ inline int64_t xcd_swizzle(int64_t bid, int64_t nblocks)
         return bid;
     int64_t per = full / nx;
     return (bid % nx) * per + bid / nx;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel bodies and their two entries.  A body is a struct F with
+//   static constexpr int kThreads;
+//   static __device__ void run(const RunDev &R, Blk b, args...);
+// where Blk replaces blockIdx.x / gridDim.x.  k_run launches it for one run
+// (R passed by value); k_group launches it for several runs at once: the
+// grid is the concatenation of the members' grids, each member's part
+// starting on a multiple of 8 workgroups so that the XCD-aware block order
+// holds inside it.  A member whose step counter has reached its target
+// does no work (a batch of runs with different lengths replays one graph).
+struct Blk {
+    int64_t id, n;
+};
+
+struct Group {
+    const RunDev *runs;    // member descriptors (device memory)
+    const int64_t *boff;   // nmem+1 workgroup offsets, multiples of 8
+    const int64_t *nblk;   // workgroups each member needs (<= its slice)
+    int nmem;
+};
+
+__device__ inline int group_find(const Group &G, int64_t b)
+{
+    int lo = 0, hi = G.nmem - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (G.boff[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class F, class... A>
+__global__ __launch_bounds__(F::kThreads) void k_run(RunDev R, A... a)
+{
+    F::run(R, Blk{(int64_t)blockIdx.x, (int64_t)gridDim.x}, a...);
+}
+
+template <class F, class... A>
+__global__ __launch_bounds__(F::kThreads) void k_group(Group G, A... a)
+{
+    const int m = group_find(G, (int64_t)blockIdx.x);
+    const int64_t id = (int64_t)blockIdx.x - G.boff[m];
+    if (id >= G.nblk[m])
+        return;
+    const RunDev &R = G.runs[m];
+    if (R.ctl->step >= R.ctl->target)
+        return;
+    F::run(R, Blk{id, G.nblk[m]}, a...);
 }
 
 // Tile-major sort key of an active cell c (see k_sort.hip for the order).

@@ -86,6 +86,21 @@ def lib():
         L.mithra_time_sweep.restype = C.c_int
         L.mithra_step_timed.argtypes = [H, C.c_int64, dp, dp]
         L.mithra_step_timed.restype = C.c_int
+        L.mithra_autotune_sweep.argtypes = [H, C.c_int, C.POINTER(C.c_int)]
+        L.mithra_autotune_sweep.restype = C.c_int
+        L.mithra_batch_workspace_bytes.argtypes = [C.c_int32]
+        L.mithra_batch_workspace_bytes.restype = C.c_size_t
+        L.mithra_batch_create.argtypes = [C.POINTER(H), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                          C.POINTER(H)]
+        L.mithra_batch_create.restype = C.c_int
+        L.mithra_batch_run.argtypes = [H, C.POINTER(C.c_int64)]
+        L.mithra_batch_run.restype = C.c_int
+        L.mithra_batch_sync.argtypes = [H]
+        L.mithra_batch_sync.restype = C.c_int
+        L.mithra_batch_last_error.argtypes = [H]
+        L.mithra_batch_last_error.restype = C.c_char_p
+        L.mithra_batch_destroy.argtypes = [H]
+        L.mithra_batch_destroy.restype = C.c_int
         _lib = L
     return _lib
 
@@ -230,6 +245,66 @@ class Engine:
         self._check(self._L.mithra_step_timed(self._h, int(n), C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    def autotune_sweep(self, iters: int = 10) -> int:
+        """Time every sweep tile shape on this run's grid, keep the fastest."""
+        out = C.c_int(-1)
+        self._check(self._L.mithra_autotune_sweep(self._h, int(iters), C.byref(out)))
+        return out.value
+
     @staticmethod
     def sweep_shape_count() -> int:
         return int(lib().mithra_sweep_shape_count())
+
+
+class Batch:
+    """Several loaded runs stepped together by grouped launches (one graph
+    per batched step).  Members keep their own read calls; they cannot be
+    stepped alone while the batch exists."""
+
+    def __init__(self, engines, stream=None):
+        import torch
+        self._L = lib()
+        self.engines = list(engines)
+        n = len(self.engines)
+        if n == 0:
+            raise ValueError("empty batch")
+        dev = self.engines[0].device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        nbytes = int(self._L.mithra_batch_workspace_bytes(n))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        hs = (C.c_void_p * n)(*[e._h.value for e in self.engines])
+        b = C.c_void_p()
+        rc = self._L.mithra_batch_create(hs, n, C.c_void_p(self.workspace.data_ptr()), C.c_size_t(nbytes),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(b))
+        if rc != 0:
+            raise MithraError(rc, "batch creation failed")
+        self._b = b
+
+    def last_error(self) -> str:
+        return self._L.mithra_batch_last_error(self._b).decode()
+
+    def _check(self, rc: int):
+        if rc != 0:
+            raise MithraError(rc, self.last_error())
+
+    def run(self, steps):
+        """Advance member i by steps[i] (an int applies to every member)."""
+        n = len(self.engines)
+        if isinstance(steps, (int, np.integer)):
+            steps = [int(steps)] * n
+        arr = (C.c_int64 * n)(*[int(x) for x in steps])
+        self._check(self._L.mithra_batch_run(self._b, arr))
+
+    def sync(self):
+        self._check(self._L.mithra_batch_sync(self._b))
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            self._L.mithra_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

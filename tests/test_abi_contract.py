@@ -73,3 +73,17 @@ def test_small_arena_is_enomem_and_null_handle_calls_fail():
     assert E.lib().mithra_step(None, 1) == -1
     assert E.lib().mithra_destroy(None) == -1
     assert E.lib().mithra_last_error(None) == b"null handle"
+
+
+def test_batch_workspace_and_argument_checks_without_device():
+    L = E.lib()
+    assert L.mithra_batch_workspace_bytes(0) == 0
+    w1 = L.mithra_batch_workspace_bytes(1)
+    w64 = L.mithra_batch_workspace_bytes(64)
+    assert 0 < w1 < w64
+    out = C.c_void_p()
+    # no members, null workspace: rejected before any device call
+    assert L.mithra_batch_create(None, 0, None, 0, None, C.byref(out)) == -1
+    assert out.value is None
+    assert L.mithra_batch_run(None, None) == -1
+    assert L.mithra_batch_destroy(None) == -1
