@@ -36,6 +36,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--latency-runs", type=int, default=12)
+    ap.add_argument("--workload", choices=["fel-amplifier", "batched-scan", "served-stream"],
+                    default="fel-amplifier")
+    ap.add_argument("--requests", type=int, default=1000, help="served stream: number of requests")
+    ap.add_argument("--rate", type=float, default=20.0, help="served stream: Poisson arrival rate (1/s)")
+    ap.add_argument("--tick", type=int, default=50, help="batched scan / served stream: steps per tick")
     return ap.parse_args()
 
 
@@ -119,6 +124,125 @@ def run_latency(runs: int) -> dict:
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
 
 
+def bench_batched_scan(args) -> dict:
+    """64 independent undulator runs of uneven size (grids 32..96 x 32..96 x
+    32..256, 1e4..5e5 e-, FP32 or FP64, 500..3000 steps) stepped as one
+    batch: grouped launches, one captured graph per batched step, each run
+    stopping at its own step count; sweep tiles from the autotuner.  Also
+    times the same runs stepped one after another alone (100 steps each)."""
+    import numpy as np
+    import torch
+    from paper_2009_13645_amd import workloads as W
+    from paper_2009_13645_amd.engine import Batch, Engine
+    runs = W.config4_runs(64)
+    t_tune = 0.0
+    engs = []
+    for w in runs:
+        d = w.descriptor()
+        xyz, u, q = W.make_bunch(w)
+        e = Engine(d, max_particles=len(xyz))
+        e.load_bunch(xyz, u, q)
+        t0 = time.perf_counter()
+        e.autotune_sweep(3)
+        t_tune += time.perf_counter() - t0
+        engs.append(e)
+    torch.cuda.synchronize()
+    # the same runs alone, one after another, 100 steps each (graph replay)
+    solo = []
+    for w in runs:
+        d = w.descriptor()
+        xyz, u, q = W.make_bunch(w)
+        e = Engine(d, max_particles=len(xyz))
+        e.load_bunch(xyz, u, q)
+        e.autotune_sweep(3)
+        e.step(5)
+        torch.cuda.synchronize()
+        solo.append(e)
+    t0 = time.perf_counter()
+    for e in solo:
+        e.step(100)
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    solo_cells = sum(w.n_nodes * 100 for w in runs)
+    solo_p = sum(w.n_particles * 100 for w in runs)
+    for e in solo:
+        e.close()
+    del solo
+    torch.cuda.empty_cache()
+
+    b = Batch(engs)
+    remaining = [w.steps for w in runs]
+    done_t = [None] * len(runs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ticks = 0
+    while any(r > 0 for r in remaining):
+        n = [min(args.tick, r) for r in remaining]
+        b.run(n)
+        b.sync()
+        ticks += 1
+        t = time.perf_counter() - t0
+        for i, k in enumerate(n):
+            remaining[i] -= k
+            if remaining[i] == 0 and done_t[i] is None:
+                done_t[i] = t
+    wall = time.perf_counter() - t0
+    b.close()
+    cells = sum(w.n_nodes * w.steps for w in runs)
+    psteps = sum(w.n_particles * w.steps for w in runs)
+    lat = np.array(done_t) * 1e3
+    return {
+        "metric": "cell-updates/s + particle-steps/s per GPU; p50/p99 run completion latency",
+        "value": cells / wall, "unit": "cell-updates/s", "particle_steps_per_s": psteps / wall,
+        "n_gpus": 1, "steps": int(max(w.steps for w in runs)), "warmup": 0,
+        "ms_per_step": wall * 1e3 / max(w.steps for w in runs), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "mixed f32/f64", "data": "synthetic",
+        "config": {"workload": "batched scan: 64 undulator runs, grids 32..96 x 32..96 x 32..256, "
+                               "1e4..5e5 e-, gamma 50..300, K 0.5..2, FP32/FP64 mixed, 500..3000 steps",
+                   "runs": len(runs), "total_cell_updates": cells, "total_particle_steps": psteps,
+                   "ticks": ticks, "tick_steps": args.tick, "parallelism": "single GPU"},
+        "latency": {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                    "max_ms": float(lat.max()), "what": "completion time of each run from the batch start"},
+        "solo_sequential": {"cell_updates_per_s": solo_cells / t_solo, "particle_steps_per_s": solo_p / t_solo,
+                            "what": "the same 64 runs stepped alone one after another, 100 steps each"},
+        "autotune_s": t_tune,
+    }
+
+
+def bench_served_stream(args) -> dict:
+    """Poisson arrivals of batched-scan-like runs (500..3000 steps), admitted
+    by HBM footprint under a 250 GB cap, continuously batched; the first
+    5 % of requests are warm-up (excluded from the latency percentiles)."""
+    import torch
+    from paper_2009_13645_amd import workloads as W
+    from paper_2009_13645_amd.serve import Server, request_from_workload, summarize
+    reqs = [request_from_workload(i, t, w) for i, (t, w) in
+            enumerate(W.config5_requests(n_req=args.requests, rate_hz=args.rate))]
+    srv = Server(cap_bytes=250e9, max_active=64, tick_steps=args.tick)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = srv.run(reqs, realtime=True)
+    wall = time.perf_counter() - t0
+    warm = max(1, len(reqs) // 20)
+    s = summarize(res, wall, warmup=warm)
+    offered_cells = sum(r.desc["nx"] * r.desc["ny"] * r.desc["nz"] * r.steps for r in reqs) / reqs[-1].arrival
+    return {
+        "metric": "cell-updates/s + particle-steps/s per GPU; p50/p99 request completion latency",
+        "value": s["cell_updates_per_s"], "unit": "cell-updates/s",
+        "particle_steps_per_s": s["particle_steps_per_s"], "n_gpus": 1, "steps": None, "warmup": warm,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "mixed f32/f64", "data": "synthetic",
+        "config": {"workload": f"served stream: {len(reqs)} requests, Poisson {args.rate}/s, batched-scan "
+                               "run mix, 500..3000 steps, footprint admission under 250 GB",
+                   "offered_cell_updates_per_s": offered_cells, "tick_steps": args.tick,
+                   "parallelism": "single GPU"},
+        "latency": {"p50_s": s["p50_latency_s"], "p99_s": s["p99_latency_s"], "mean_s": s["mean_latency_s"],
+                    "what": "finish - arrival, warm-up requests excluded"},
+        "server": srv.stats,
+        "wall_s": wall,
+    }
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -126,6 +250,13 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(multi-GPU sharding is a design note, not a benchmark here)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched-scan":
+        print(json.dumps(bench_batched_scan(args)))
+        return
+    if args.workload == "served-stream":
+        print(json.dumps(bench_served_stream(args)))
+        return
 
     import numpy as np
     import torch
