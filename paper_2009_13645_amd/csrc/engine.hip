@@ -36,7 +36,7 @@ hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *ou
 hipError_t launch_push_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_load_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st);
-hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts);
+hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts, bool gather);
 hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
                              int32_t *count, hipStream_t st, int32_t *zero);
 hipError_t launch_box_reduce_set(const RunDev &R, int64_t nblocks, hipStream_t st);
@@ -149,7 +149,7 @@ static Layout make_layout(const mithra_grid_desc *d, int64_t cap)
     L.pot = take(12 * nn * pf);
     L.src = take(8 * nn * pf);
     L.src_lo = (d->compensated && d->field_precision == 32) ? take(8 * nn * pf) : (size_t)-1;
-    L.eb = take(6 * nn * pf);
+    L.eb = take(8 * nn * pf);
     L.pr = take(12 * c * 8);
     L.pid = take(2 * c * 4);
     L.key_by_id = take(c * 4);
@@ -419,6 +419,7 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.item_cap = (int64_t)L.items_n;
     R.ppart = (double *)(A + L.ppart);
     R.sort_blocks = sort_blocks((int64_t)c);
+    R.sorted_ids = R.sv[(sort_passes(R.key_inactive) - 1) & 1];
     R.power_hist = (double *)(A + L.power);
     R.power_cap = kPowerCap;
     R.k_plane = d->k_plane;
@@ -431,7 +432,7 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     HIPCHK(h, hipMemsetAsync(R.src, 0, 8 * nn * pf, h->stream));
     if (R.src_lo)
         HIPCHK(h, hipMemsetAsync(R.src_lo, 0, 8 * nn * pf, h->stream));
-    HIPCHK(h, hipMemsetAsync(R.eb, 0, 6 * nn * pf, h->stream));
+    HIPCHK(h, hipMemsetAsync(R.eb, 0, 8 * nn * pf, h->stream));
     HIPCHK(h, hipMemsetAsync(R.power_hist, 0, (size_t)kPowerCap * 8, h->stream));
     Ctl c0;
     memset(&c0, 0, sizeof c0);
@@ -510,7 +511,8 @@ extern "C" int mithra_load_bunch(mithra_handle h, int64_t n, const double *xyz, 
     int rc = enqueue_sort_with_cells(h);
     if (rc)
         return rc;
-    hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, h->stream, R.ctl, 0);
+    if (h->tiled)  // the gathered state is in the other buffer
+        hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, h->stream, R.ctl, 0);
     HIPCHK(h, hipGetLastError());
     if (h->tiled) {
         HIPCHK(h, launch_tile_items(R, h->stream));
@@ -548,7 +550,7 @@ __global__ void k_cells_by_id(RunDev R, int32_t *cell_by_id)
 
 static int enqueue_sort_with_cells(mithra_handle h)
 {
-    HIPCHK(h, launch_sort(h->R, h->stream, false, 0));
+    HIPCHK(h, launch_sort(h->R, h->stream, false, 0, h->tiled));
     return MITHRA_OK;
 }
 
@@ -560,13 +562,13 @@ static int enqueue_particles(mithra_handle h, hipStream_t st)
         hipLaunchKernelGGL(k_book_mid, dim3(1), dim3(1), 0, st, R.ctl);
         HIPCHK(h, launch_tile_step(R, st));
         HIPCHK(h, launch_box_reduce_set(R, tile_partials(R), st));
-        HIPCHK(h, launch_sort(R, st, true, tile_partials(R)));
+        HIPCHK(h, launch_sort(R, st, true, tile_partials(R), true));
         HIPCHK(h, launch_tile_items(R, st));
     } else {
         HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
         hipLaunchKernelGGL(k_book_mid, dim3(1), dim3(1), 0, st, R.ctl);
         HIPCHK(h, launch_push_deposit(R, st));
-        HIPCHK(h, launch_sort(R, st, true, dep_blocks(R.np)));
+        HIPCHK(h, launch_sort(R, st, true, dep_blocks(R.np), false));
     }
     return MITHRA_OK;
 }
@@ -679,7 +681,18 @@ extern "C" int mithra_read_fields(mithra_handle h, int field_id, int dtype, void
         }
         HIPCHK(h, launch_vertex_fields(R, -1, 1, h->stream));
         HIPCHK(h, sync_run(h));
-        src = (const char *)R.eb + (size_t)field_id * nn * pf;
+        // node-interleaved: 8 words per node, component field_id
+        std::vector<char> all(8 * nn * pf);
+        HIPCHK(h, hipMemcpy(all.data(), R.eb, all.size(), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < nn; ++i) {
+            const double v = pf == 4 ? (double)((const float *)all.data())[8 * i + field_id]
+                                     : ((const double *)all.data())[8 * i + field_id];
+            if (esz == 4)
+                ((float *)host_out)[i] = (float)v;
+            else
+                ((double *)host_out)[i] = v;
+        }
+        return MITHRA_OK;
     } else if (field_id <= MITHRA_FIELD_AZ || field_id == MITHRA_FIELD_PHI) {
         const int comp = field_id == MITHRA_FIELD_PHI ? 3 : field_id - MITHRA_FIELD_AX;
         src = (const char *)R.pot + ((size_t)slot_cur(S) * 4 + comp) * nn * pf;
@@ -722,10 +735,13 @@ extern "C" int mithra_read_particles(mithra_handle h, double *xyz, double *u, in
     const int64_t n = R.np;
     int32_t pb = 0;
     HIPCHK(h, hipMemcpy(&pb, &R.ctl->pbuf, 4, hipMemcpyDeviceToHost));
+    // the state sits in buffer pb in the slots pid[pb]; the order of the
+    // last sort is R.sorted_ids (the per-block path does not move the state
+    // after sorting) or the gathered pid[pb] (tile-owned path)
     std::vector<int32_t> ids((size_t)n);
     HIPCHK(h, hipMemcpy(ids.data(), R.pid[pb], (size_t)n * 4, hipMemcpyDeviceToHost));
     if (sort_perm)
-        memcpy(sort_perm, ids.data(), (size_t)n * 4);
+        HIPCHK(h, hipMemcpy(sort_perm, h->tiled ? R.pid[pb] : R.sorted_ids, (size_t)n * 4, hipMemcpyDeviceToHost));
     std::vector<double> col((size_t)n);
     for (int a = 0; a < 6; ++a) {
         double *dst = a < 3 ? xyz : u;

@@ -187,38 +187,6 @@ struct Sweep {
 // whose interior starts on a 16-byte boundary; a thread reads its two outer
 // x-neighbours and its y-neighbour vectors from LDS.  Needs nx % V == 0 so
 // that every row starts aligned.
-template <typename T, int V>
-struct Vec {
-    T v[V];
-};
-
-template <typename T, int V>
-__device__ inline Vec<T, V> vload(const T *p)
-{
-    Vec<T, V> r;
-    if constexpr (sizeof(T) * V == 16) {
-        const uint4 x = *reinterpret_cast<const uint4 *>(p);
-        memcpy(&r, &x, 16);
-    } else {
-        for (int e = 0; e < V; ++e)
-            r.v[e] = p[e];
-    }
-    return r;
-}
-
-template <typename T, int V>
-__device__ inline void vstore(T *p, const Vec<T, V> &a)
-{
-    if constexpr (sizeof(T) * V == 16) {
-        uint4 x;
-        memcpy(&x, &a, 16);
-        *reinterpret_cast<uint4 *>(p) = x;
-    } else {
-        for (int e = 0; e < V; ++e)
-            p[e] = a.v[e];
-    }
-}
-
 // Streaming (non-temporal) 16-byte accesses: data touched once per sweep
 // (psi^{n-1}, psi^{n+1}, the cleared source set) bypass cache retention so
 // that the psi^n stencil planes stay in L2.
@@ -765,20 +733,20 @@ struct VertexFields {
         }
         const int64_t ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
         const int64_t tot = ex * ey * ez;
-        T *eb[6];
-        for (int c = 0; c < 6; ++c)
-            eb[c] = eb_ptr<T>(R, c);
         for (int64_t t = (int64_t)blk.id * blockDim.x + threadIdx.x; t < tot; t += (int64_t)blk.n * blockDim.x) {
             const int i = lo[0] + (int)(t % ex);
             const int j = lo[1] + (int)((t / ex) % ey);
             const int k = lo[2] + (int)(t / (ex * ey));
             double E[3], B[3];
             vertex_eb<T>(R, s, i, j, k, E, B);
-            const int64_t c = nid(R, i, j, k);
-            for (int a = 0; a < 3; ++a) {
-                eb[a][c] = (T)E[a];
-                eb[3 + a][c] = (T)B[a];
-            }
+            constexpr int V = 16 / sizeof(T);
+            Vec<T, V> w[8 / V];
+            const T all[8] = {(T)E[0], (T)E[1], (T)E[2], (T)B[0], (T)B[1], (T)B[2], (T)0, (T)0};
+            for (int q = 0; q < 8; ++q)
+                w[q / V].v[q % V] = all[q];
+            T *dst = eb_node<T>(R, nid(R, i, j, k));
+            for (int q = 0; q < 8 / V; ++q)
+                vstore<T, V>(dst + q * V, w[q]);
         }
     }
 };

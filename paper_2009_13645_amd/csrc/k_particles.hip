@@ -14,12 +14,16 @@ constexpr int kLdsNodes = 1536;
 __host__ __device__ inline int64_t dep_blocks_dev(int64_t np) { return (np + kDepThreads - 1) / kDepThreads; }  // node box capacity of the LDS stage (4 arrays, FP64: 48 KiB)
 
 // Gather + undulator + N_b Boris sub-steps + deposit (MODE 0), or the load
-// deposit of the backward-drift move (MODE 1, sorted particles, set 0).
+// deposit of the backward-drift move (MODE 1, set 0).  Rank p handles the
+// particle R.sorted_ids[p] of the last sort, read from its slot in buffer pbuf;
+// MODE 0 writes the pushed state to rank p of the other buffer (the step's
+// last bookkeeping kernel flips pbuf), so the sort never moves the state.
 // The block's deposits are summed in LDS over its node box when the box
 // fits, then added to HBM once per touched node; otherwise directly.
 template <typename T, bool COMP, int MODE>
 struct PushDeposit {
     static constexpr int kThreads = kDepThreads;
+    static constexpr int kWaves = 3;  // the LDS box allows 3 blocks per CU
     static __device__ void run(const RunDev &R, Blk blk)
     {
         __shared__ double lds[4 * kLdsNodes];
@@ -37,10 +41,14 @@ struct PushDeposit {
         int c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
         bool dep_j = false, dep_q = false;
         if (p < R.np) {
+            // rank p of the last sort: particle id, read where the previous
+            // push (or the load) left it
+            const int32_t id = R.sorted_ids[p];
+            const int32_t src = R.slot_of_id[id];
             double r[3], u[3];
             for (int a = 0; a < 3; ++a) {
-                r[a] = R.pr[pb][a][p];
-                u[a] = R.pr[pb][3 + a][p];
+                r[a] = R.pr[pb][a][src];
+                u[a] = R.pr[pb][3 + a][src];
             }
             if (MODE == 1) {
                 const double ig = 1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
@@ -67,10 +75,21 @@ struct PushDeposit {
                             for (int I = 0; I < 2; ++I) {
                                 const double w = wx[I] * wy[J] * wz[K];
                                 const int64_t n = base + I + J * sy + K * sz;
+                                // the corner's six words: 2 (FP32) or 3 (FP64) 16-byte loads
+                                constexpr int V = 16 / sizeof(T);
+                                const T *q = eb_node<T>(R, n);
+                                T f[6 + (V == 4 ? 2 : 0)];
+    #pragma unroll
+                                for (int h = 0; h < (6 + V - 1) / V; ++h) {
+                                    const Vec<T, V> x = vload<T, V>(q + h * V);
+    #pragma unroll
+                                    for (int e = 0; e < V; ++e)
+                                        f[h * V + e] = x.v[e];
+                                }
     #pragma unroll
                                 for (int a = 0; a < 3; ++a) {
-                                    Eg[a] += w * (double)eb_ptr<T>(R, a)[n];
-                                    Bg[a] += w * (double)eb_ptr<T>(R, 3 + a)[n];
+                                    Eg[a] += w * (double)f[a];
+                                    Bg[a] += w * (double)f[3 + a];
                                 }
                             }
                 }
@@ -87,15 +106,17 @@ struct PushDeposit {
                     for (int a = 0; a < 3; ++a)
                         r[a] = r[a] + kC * R.dtb * u[a] * ig;
                 }
+                // the pushed state goes to the other buffer in sort order
+                const int nb = pb ^ 1;
                 for (int a = 0; a < 3; ++a) {
-                    R.pr[pb][a][p] = r[a];
-                    R.pr[pb][3 + a][p] = u[a];
+                    R.pr[nb][a][p] = r[a];
+                    R.pr[nb][3 + a][p] = u[a];
                 }
+                R.pid[nb][p] = id;
                 const bool act2 = cell_of(R, r, g2, c2);
                 dep_j = act1 && act2;
                 dep_q = act2;
                 // sort key of the new position, in id order, for this step's sort
-                const int32_t id = R.pid[pb][p];
                 R.key_by_id[id] = act2 ? key_of_cell(R, c2) : R.key_inactive;
                 R.slot_of_id[id] = (int32_t)p;
             }

@@ -333,7 +333,7 @@ int64_t sort_blocks(int64_t n) { return (n + kSortChunk - 1) / kSortChunk; }
 // keys_ready: the push kernels have already written the keys, the slots
 // and `nparts` per-block active-cell boxes in R.cellpart.  The tile work
 // item counter is reset here, before the items of the new order are built.
-hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts)
+hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts, bool gather)
 {
     if (R.np <= 0)
         return hipSuccess;
@@ -359,7 +359,10 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
         kin = kout;
         vin = vout;
     }
-    hipLaunchKernelGGL(k_sort_gather, dim3(pblocks), dim3(256), 0, st, R, kin, vin);
+    // the tile-owned kernel reads the state in sorted slots; the per-block
+    // kernel reads it through R.sorted_ids
+    if (gather)
+        hipLaunchKernelGGL(k_sort_gather, dim3(pblocks), dim3(256), 0, st, R, kin, vin);
     return hipGetLastError();
 }
 
@@ -382,7 +385,7 @@ hipError_t launch_sort_group(const Group &gs, int64_t total_s, const Group &gd, 
         hipLaunchKernelGGL((k_group<DigitScanRun, int>), dim3((unsigned)total_d), dim3(256), 0, st, gd, ps);
         hipLaunchKernelGGL((k_group<RadixScatterRun, int>), dim3((unsigned)total_s), dim3(kSortThreads), 0, st, gs, ps);
     }
-    hipLaunchKernelGGL((k_group<SortGatherRun>), dim3((unsigned)total_p), dim3(256), 0, st, gp);
+    (void)gp;
     return hipGetLastError();
 }
 

@@ -8,6 +8,9 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+#include <string.h>
+
+#include <type_traits>
 
 namespace mithra {
 
@@ -68,6 +71,7 @@ struct RunDev {
     double h[3];      // dx dy dz
     double cdt;       // c dt
     int xface_fused;  // 1: the (vector) sweep also updates the x-face nodes
+    const int32_t *sorted_ids;  // particle ids in the order of the last sort (output of its last pass)
     int precision;    // 32 or 64
     int compensated;
     // particles
@@ -130,10 +134,46 @@ __device__ inline T *srclo_ptr(const RunDev &R, int set, int comp)
     return reinterpret_cast<T *>(R.src_lo) + ((int64_t)set * 4 + comp) * R.nn;
 }
 
-template <typename T>
-__device__ inline T *eb_ptr(const RunDev &R, int comp)
+// V consecutive values moved as one 16-byte access when sizeof(T) V == 16.
+template <typename T, int V>
+struct Vec {
+    T v[V];
+};
+
+template <typename T, int V>
+__device__ inline Vec<T, V> vload(const T *p)
 {
-    return reinterpret_cast<T *>(R.eb) + (int64_t)comp * R.nn;
+    Vec<T, V> r;
+    if constexpr (sizeof(T) * V == 16) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(p);
+        memcpy(&r, &x, 16);
+    } else {
+        for (int e = 0; e < V; ++e)
+            r.v[e] = p[e];
+    }
+    return r;
+}
+
+template <typename T, int V>
+__device__ inline void vstore(T *p, const Vec<T, V> &a)
+{
+    if constexpr (sizeof(T) * V == 16) {
+        uint4 x;
+        memcpy(&x, &a, 16);
+        *reinterpret_cast<uint4 *>(p) = x;
+    } else {
+        for (int e = 0; e < V; ++e)
+            p[e] = a.v[e];
+    }
+}
+
+// E and B at the vertices are stored node-interleaved: node n holds
+// Ex Ey Ez Bx By Bz and two pad words at eb[8 n .. 8 n + 7] (32 bytes in FP32,
+// 64 in FP64), so that a corner of the gather is two or four 16-byte loads.
+template <typename T>
+__device__ inline T *eb_node(const RunDev &R, int64_t n)
+{
+    return reinterpret_cast<T *>(R.eb) + 8 * n;
 }
 
 // Time-level slots of the three rotating potential arrays during step s:
@@ -189,14 +229,28 @@ __device__ inline int group_find(const Group &G, int64_t b)
     return lo;
 }
 
+// Minimum waves per SIMD a body asks the register allocator for
+// (F::kWaves when present): a body limited by latency rather than issue
+// rate trades a few registers for occupancy.
+template <class F, class = void>
+struct WavesOf {
+    static constexpr int value = 1;
+};
+template <class F>
+struct WavesOf<F, std::void_t<decltype(F::kWaves)>> {
+    static constexpr int value = F::kWaves;
+};
+
 template <class F, class... A>
-__global__ __launch_bounds__(F::kThreads) void k_run(RunDev R, A... a)
+__global__ __launch_bounds__(F::kThreads) __attribute__((amdgpu_waves_per_eu(WavesOf<F>::value))) void k_run(RunDev R,
+                                                                                                          A... a)
 {
     F::run(R, Blk{(int64_t)blockIdx.x, (int64_t)gridDim.x}, a...);
 }
 
 template <class F, class... A>
-__global__ __launch_bounds__(F::kThreads) void k_group(Group G, A... a)
+__global__ __launch_bounds__(F::kThreads) __attribute__((amdgpu_waves_per_eu(WavesOf<F>::value))) void k_group(
+    Group G, A... a)
 {
     const int m = group_find(G, (int64_t)blockIdx.x);
     const int64_t id = (int64_t)blockIdx.x - G.boff[m];
