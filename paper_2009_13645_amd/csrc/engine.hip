@@ -362,6 +362,9 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.a2 = rx2;
     R.a4 = ry2;
     R.a6 = rz2 - 2.0 * R.A * (rx2 + ry2);
+    R.rx2 = rx2;
+    R.ry2 = ry2;
+    R.rz2 = rz2;
     const double mu0 = 1.0 / (kEps0 * kC * kC);
     R.sfac_A = cdt * cdt * mu0;
     R.sfac_phi = cdt * cdt / kEps0;

@@ -49,12 +49,26 @@ __device__ inline T src_value(const RunDev &R, int comp, int set, int64_t c, int
     return (T)(R.sfac_phi * s);
 }
 
+// FP32 sweeps use the difference form of the update,
+//   psi^{n+1} = psi + [(psi - psi^{n-1}) + rx2 (d_xx psi + d_xx c)
+//               + ry2 (d_yy psi + d_yy c) + rz2 d_zz psi + S],
+//   c = psi-bar - psi = A ((psi_{k-1} - psi) + (psi_{k+1} - psi)),
+// with every second difference formed from neighbour differences: for a
+// smooth field those are exact in FP32, and psi enters once per step, so the
+// rounding the leapfrog integrates is relative to the increment instead of
+// to psi.  It is the same update as eq. updateEquation (its coefficients
+// summed); FP64 sweeps keep the coefficient form.
+template <typename T>
+constexpr bool kDiffForm = sizeof(T) == 4;
+
 template <typename T, int TX, int TY, int TZ>
 struct Sweep {
     static constexpr int kThreads = TX * TY;
     static __device__ void run(const RunDev &R, Blk blk)
     {
         __shared__ T sb[2][TY + 2][TX + 2];
+        // difference form: psi-bar - psi of the same node
+        __shared__ T sbc[kDiffForm<T> ? 2 : 1][kDiffForm<T> ? TY + 2 : 1][TX + 2];
 
         // tiles start at node 0 so that every row load is 128-byte aligned; the
         // boundary columns load (they are the neighbours of the first interior
@@ -127,6 +141,7 @@ struct Sweep {
 
         const T cA = (T)R.A, c1A = (T)(1.0 - 2.0 * R.A);
         const T a1 = (T)R.a1, a2 = (T)R.a2, a4 = (T)R.a4, a6 = (T)R.a6;
+        const T rx2 = (T)R.rx2, ry2 = (T)R.ry2, rz2 = (T)R.rz2;
 
         T qm = 0, q0 = 0, qp = 0, hqm = 0, hq0 = 0, hqp = 0;
         if (inb) {
@@ -162,14 +177,35 @@ struct Sweep {
                     clr_lo[c] = (T)0;
             }
             T(*buf)[TX + 2] = sb[k & 1];
-            buf[ly + 1][lx + 1] = cA * (qm + qp) + c1A * q0;
-            if (h < H)
-                buf[hy + 1][hx + 1] = cA * (hqm + hqp) + c1A * hq0;
+            if constexpr (kDiffForm<T>) {
+                T(*cbuf)[TX + 2] = sbc[k & 1];
+                buf[ly + 1][lx + 1] = q0;
+                cbuf[ly + 1][lx + 1] = cA * ((qm - q0) + (qp - q0));
+                if (h < H) {
+                    buf[hy + 1][hx + 1] = hq0;
+                    cbuf[hy + 1][hx + 1] = cA * ((hqm - hq0) + (hqp - hq0));
+                }
+            } else {
+                buf[ly + 1][lx + 1] = cA * (qm + qp) + c1A * q0;
+                if (h < H)
+                    buf[hy + 1][hx + 1] = cA * (hqm + hqp) + c1A * hq0;
+            }
             __syncthreads();
             if (valid && update) {
-                T v = a1 * q0 + a2 * (buf[ly + 1][lx + 2] + buf[ly + 1][lx]) +
-                      a4 * (buf[ly + 2][lx + 1] + buf[ly][lx + 1]) + a6 * (qp + qm) - pm + sv;
-                next[c] = v;
+                if constexpr (kDiffForm<T>) {
+                    T(*cbuf)[TX + 2] = sbc[k & 1];
+                    const T c0 = cbuf[ly + 1][lx + 1];
+                    const T dxx = ((buf[ly + 1][lx] - q0) + (buf[ly + 1][lx + 2] - q0)) +
+                                  ((cbuf[ly + 1][lx] - c0) + (cbuf[ly + 1][lx + 2] - c0));
+                    const T dyy = ((buf[ly][lx + 1] - q0) + (buf[ly + 2][lx + 1] - q0)) +
+                                  ((cbuf[ly][lx + 1] - c0) + (cbuf[ly + 2][lx + 1] - c0));
+                    const T dzz = (qm - q0) + (qp - q0);
+                    next[c] = q0 + ((q0 - pm) + rx2 * dxx + ry2 * dyy + rz2 * dzz + sv);
+                } else {
+                    T v = a1 * q0 + a2 * (buf[ly + 1][lx + 2] + buf[ly + 1][lx]) +
+                          a4 * (buf[ly + 2][lx + 1] + buf[ly][lx + 1]) + a6 * (qp + qm) - pm + sv;
+                    next[c] = v;
+                }
             }
             qm = q0;
             q0 = qp;
@@ -231,6 +267,8 @@ struct SweepVec {
         // source sums: FP64 for FP64 fields and for compensated FP32 (hi + lo)
         using ST = typename std::conditional<LO || sizeof(T) == 8, double, T>::type;
         __shared__ __attribute__((aligned(16))) T sb[2][TY + 2][ROW];
+        // difference form (FP32): psi-bar - psi of the same node
+        __shared__ __attribute__((aligned(16))) T sbc[kDiffForm<T> ? 2 : 1][kDiffForm<T> ? TY + 2 : 1][ROW];
         // psi^n at the two outermost nodes of each row end (x-face update)
         __shared__ T rawe[2][TY + 2][4];
 
@@ -304,6 +342,7 @@ struct SweepVec {
 
         const T cA = (T)R.A, c1A = (T)(1.0 - 2.0 * R.A);
         const T a1 = (T)R.a1, a2 = (T)R.a2, a4 = (T)R.a4, a6 = (T)R.a6;
+        const T rx2 = (T)R.rx2, ry2 = (T)R.ry2, rz2 = (T)R.rz2;
 
         // psi^{n-1} and the sources of plane kk; the z component's back edge is
         // the previous plane's own edge, carried in registers (zero below the
@@ -398,17 +437,35 @@ struct SweepVec {
                     vstore_nt<T, V>(clr_lo + c, z);
             }
             T(*buf)[ROW] = sb[k & 1];
-            Vec<T, V> bar;
-            for (int e = 0; e < V; ++e)
-                bar.v[e] = cA * (qm.v[e] + qp.v[e]) + c1A * q0.v[e];
-            vstore<T, V>(&buf[ly + 1][V + lx * V], bar);
-            if (hrole == 0) {
-                Vec<T, V> hb;
+            Vec<T, V> bar;  // psi-bar, or (difference form) psi-bar - psi
+            if constexpr (kDiffForm<T>) {
+                T(*cbuf)[ROW] = sbc[k & 1];
                 for (int e = 0; e < V; ++e)
-                    hb.v[e] = cA * (hm.v[e] + hp.v[e]) + c1A * h0.v[e];
-                vstore<T, V>(&buf[hy + 1][V + hx], hb);
-            } else if (hrole == 1) {
-                buf[hy + 1][V + hx] = cA * (hm.v[0] + hp.v[0]) + c1A * h0.v[0];
+                    bar.v[e] = cA * ((qm.v[e] - q0.v[e]) + (qp.v[e] - q0.v[e]));
+                vstore<T, V>(&buf[ly + 1][V + lx * V], q0);
+                vstore<T, V>(&cbuf[ly + 1][V + lx * V], bar);
+                if (hrole == 0) {
+                    Vec<T, V> hb;
+                    for (int e = 0; e < V; ++e)
+                        hb.v[e] = cA * ((hm.v[e] - h0.v[e]) + (hp.v[e] - h0.v[e]));
+                    vstore<T, V>(&buf[hy + 1][V + hx], h0);
+                    vstore<T, V>(&cbuf[hy + 1][V + hx], hb);
+                } else if (hrole == 1) {
+                    buf[hy + 1][V + hx] = h0.v[0];
+                    cbuf[hy + 1][V + hx] = cA * ((hm.v[0] - h0.v[0]) + (hp.v[0] - h0.v[0]));
+                }
+            } else {
+                for (int e = 0; e < V; ++e)
+                    bar.v[e] = cA * (qm.v[e] + qp.v[e]) + c1A * q0.v[e];
+                vstore<T, V>(&buf[ly + 1][V + lx * V], bar);
+                if (hrole == 0) {
+                    Vec<T, V> hb;
+                    for (int e = 0; e < V; ++e)
+                        hb.v[e] = cA * (hm.v[e] + hp.v[e]) + c1A * h0.v[e];
+                    vstore<T, V>(&buf[hy + 1][V + hx], hb);
+                } else if (hrole == 1) {
+                    buf[hy + 1][V + hx] = cA * (hm.v[0] + hp.v[0]) + c1A * h0.v[0];
+                }
             }
             if (R.xface_fused) {
                 T(*raw)[4] = rawe[k & 1];
@@ -439,11 +496,28 @@ struct SweepVec {
                 const Vec<T, V> dn = vload<T, V>(&buf[ly][V + lx * V]);
                 const Vec<T, V> up = vload<T, V>(&buf[ly + 2][V + lx * V]);
                 Vec<T, V> out;
-                for (int e = 0; e < V; ++e) {
-                    const T xl = e == 0 ? left : bar.v[e - 1];
-                    const T xr = e == V - 1 ? right : bar.v[e + 1];
-                    out.v[e] = a1 * q0.v[e] + a2 * (xl + xr) + a4 * (dn.v[e] + up.v[e]) + a6 * (qp.v[e] + qm.v[e]) -
-                               ps.pm.v[e] + (T)(sfac * sv[e]);
+                if constexpr (kDiffForm<T>) {
+                    T(*cbuf)[ROW] = sbc[k & 1];
+                    const T cleft = cbuf[ly + 1][V + lx * V - 1];
+                    const T cright = cbuf[ly + 1][V + lx * V + V];
+                    const Vec<T, V> cdn = vload<T, V>(&cbuf[ly][V + lx * V]);
+                    const Vec<T, V> cup = vload<T, V>(&cbuf[ly + 2][V + lx * V]);
+                    for (int e = 0; e < V; ++e) {
+                        const T p0 = q0.v[e], c0 = bar.v[e];
+                        const T ql = e == 0 ? left : q0.v[e - 1], qr = e == V - 1 ? right : q0.v[e + 1];
+                        const T cl = e == 0 ? cleft : bar.v[e - 1], cr = e == V - 1 ? cright : bar.v[e + 1];
+                        const T dxx = ((ql - p0) + (qr - p0)) + ((cl - c0) + (cr - c0));
+                        const T dyy = ((dn.v[e] - p0) + (up.v[e] - p0)) + ((cdn.v[e] - c0) + (cup.v[e] - c0));
+                        const T dzz = (qm.v[e] - p0) + (qp.v[e] - p0);
+                        out.v[e] = p0 + ((p0 - ps.pm.v[e]) + rx2 * dxx + ry2 * dyy + rz2 * dzz + (T)(sfac * sv[e]));
+                    }
+                } else {
+                    for (int e = 0; e < V; ++e) {
+                        const T xl = e == 0 ? left : bar.v[e - 1];
+                        const T xr = e == V - 1 ? right : bar.v[e + 1];
+                        out.v[e] = a1 * q0.v[e] + a2 * (xl + xr) + a4 * (dn.v[e] + up.v[e]) +
+                                   a6 * (qp.v[e] + qm.v[e]) - ps.pm.v[e] + (T)(sfac * sv[e]);
+                    }
                 }
                 // the x-face nodes of the row: Mur update (faces of the x axis,
                 // transverse y and z), from this thread's own columns, the

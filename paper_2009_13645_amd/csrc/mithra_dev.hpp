@@ -58,6 +58,7 @@ struct RunDev {
     // NSFD interior update: next = a1 cur + a2 (bar_x+ + bar_x-) + a4 (bar_y+ + bar_y-)
     //                              + a6 (cur_k+ + cur_k-) - prev + S
     double A, a1, a2, a4, a6;
+    double rx2, ry2, rz2;  // (c dt / d_l)^2: the difference form of the FP32 sweeps
     double sfac_A;    // (c dt)^2 mu0, multiplies the node-averaged J
     double sfac_phi;  // (c dt)^2 / eps0, multiplies rho
     int space_charge;
