@@ -97,7 +97,7 @@ def main():
     n_ok = sum(r[-1] for r in rows)
     with open(a.out, "w") as f:
         f.write("# Oracle parity of the batched scan\n\n")
-        f.write(f"Command (from the repository root): `python3 tests/batch_parity.py {a.out} --runs {a.runs} "
+        f.write(f"Command (from the repository root): `python3 tests/batch_parity.py <out.md> --runs {a.runs} "
                 f"--steps {a.steps} --scale {a.scale}`\n\n")
         f.write(f"{len(runs)} runs of the batched-scan recipe were stepped {a.steps} steps as one GPU batch, "
                 f"with grouped launches and tiles from the autotuner ({t_gpu:.2f} s).\n"
