@@ -69,8 +69,8 @@ def _per_dispatch(rows, name_part, counter):
 
 def summarize(dir_f, dir_w):
     rf, rw = _rows(dir_f), _rows(dir_w)
-    sweep_f = _per_dispatch(rf, "k_sweep", "FETCH_SIZE")
-    sweep_w = _per_dispatch(rw, "k_sweep", "WRITE_SIZE")
+    sweep_f = _per_dispatch(rf, "Sweep", "FETCH_SIZE")
+    sweep_w = _per_dispatch(rw, "Sweep", "WRITE_SIZE")
     # torch's device-to-device copy_ runs as the runtime's copyBuffer kernel
     copy_f = _per_dispatch(rf, "copyBuffer", "FETCH_SIZE")
     copy_w = _per_dispatch(rw, "copyBuffer", "WRITE_SIZE")
@@ -82,7 +82,7 @@ def summarize(dir_f, dir_w):
     sw = sorted(sweep_w[-10:])[len(sweep_w[-10:]) // 2] * 1024.0 * cw
     src = os.path.join(ROOT, "paper_2009_13645_amd", "csrc", "k_fdtd.hip")
     rec = {
-        "kernel": "k_sweep_vec (NSFD sweep, FP32, 128x128x1024 nodes, 4 potentials)",
+        "kernel": "SweepVec (NSFD sweep, FP32, 128x128x1024 nodes, 4 potentials)",
         "fetch_bytes_per_launch": sf, "write_bytes_per_launch": sw, "bytes_per_launch": sf + sw,
         "copy_calibration": {"fetch_factor": cf, "write_factor": cw, "copy_bytes": COPY_BYTES},
         "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
