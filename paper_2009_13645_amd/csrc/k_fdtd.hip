@@ -692,63 +692,111 @@ __device__ double corner_np1(const RunDev &R, const Lv<T> &L, const int p[3], co
     return solve_summed(R, L, p, ax, sd, 3, np1);
 }
 
+// Boundary nodes, one thread each (per component), in two groups:
+//  - face nodes that lie on one boundary only (z faces, y faces, and the x
+//    faces unless the vector sweep updated them), with direct strides;
+//  - edge and corner nodes, through the summed first-order conditions
+//    (solve_summed), which recompute the face values they need.
+// Face threads come first and are laid out x fastest, so their accesses
+// coalesce; the few edge threads take the general path.
 template <typename T>
 struct Mur {
     static constexpr int kThreads = 256;
     static __device__ void run(const RunDev &R, Blk blk)
     {
-        const int64_t nzf = 2LL * R.nx * R.ny;
-        const int64_t nyf = 2LL * R.nx * (R.nz - 2);
-        const int64_t nxf = R.xface_fused ? 0 : 2LL * (R.ny - 2) * (R.nz - 2);
-        const int64_t nb = nzf + nyf + nxf;
+        const int nx = R.nx, ny = R.ny, nz = R.nz;
+        const int64_t fz = 2LL * (nx - 2) * (ny - 2);
+        const int64_t fy = 2LL * (nx - 2) * (nz - 2);
+        const int64_t fx = R.xface_fused ? 0 : 2LL * (ny - 2) * (nz - 2);
+        const int64_t ex = 4LL * nx, ey = 4LL * (ny - 2), ez = 4LL * (nz - 2);
+        const int64_t nb = fz + fy + fx + ex + ey + ez;
         const int ncomp = R.space_charge ? 4 : 3;
         const int64_t t = (int64_t)blk.id * blockDim.x + threadIdx.x;
         if (t >= nb * ncomp)
             return;
         const int comp = (int)(t / nb);
         int64_t r = t % nb;
-        int p[3];
-        if (r < nzf) {
-            const int64_t half = (int64_t)R.nx * R.ny;
-            p[2] = r < half ? 0 : R.nz - 1;
-            r %= half;
-            p[0] = (int)(r % R.nx);
-            p[1] = (int)(r / R.nx);
-        } else if (r < nzf + nyf) {
-            r -= nzf;
-            const int64_t half = (int64_t)R.nx * (R.nz - 2);
-            p[1] = r < half ? 0 : R.ny - 1;
-            r %= half;
-            p[0] = (int)(r % R.nx);
-            p[2] = 1 + (int)(r / R.nx);
-        } else {
-            r -= nzf + nyf;
-            const int64_t half = (int64_t)(R.ny - 2) * (R.nz - 2);
-            p[0] = r < half ? 0 : R.nx - 1;
-            r %= half;
-            p[1] = 1 + (int)(r % (R.ny - 2));
-            p[2] = 1 + (int)(r / (R.ny - 2));
-        }
         const int64_t s = R.ctl->step;
-        Lv<T> L{pot_ptr<T>(R, slot_prev(s), comp), pot_ptr<T>(R, slot_cur(s), comp),
-                pot_ptr<T>(R, slot_next(s), comp)};
-        int ax[3], sd[3], m = 0;
+        const T *pm = pot_ptr<T>(R, slot_prev(s), comp);
+        const T *p0 = pot_ptr<T>(R, slot_cur(s), comp);
+        T *pp = pot_ptr<T>(R, slot_next(s), comp);
+        const int64_t st[3] = {1, nx, (int64_t)nx * ny};
+        if (r < fz + fy + fx) {
+            int p[3], ax;
+            if (r < fz) {
+                const int64_t half = (int64_t)(nx - 2) * (ny - 2);
+                ax = 2;
+                p[2] = r < half ? 0 : nz - 1;
+                r %= half;
+                p[0] = 1 + (int)(r % (nx - 2));
+                p[1] = 1 + (int)(r / (nx - 2));
+            } else if (r < fz + fy) {
+                r -= fz;
+                const int64_t half = (int64_t)(nx - 2) * (nz - 2);
+                ax = 1;
+                p[1] = r < half ? 0 : ny - 1;
+                r %= half;
+                p[0] = 1 + (int)(r % (nx - 2));
+                p[2] = 1 + (int)(r / (nx - 2));
+            } else {
+                r -= fz + fy;
+                const int64_t half = (int64_t)(ny - 2) * (nz - 2);
+                ax = 0;
+                p[0] = r < half ? 0 : nx - 1;
+                r %= half;
+                p[1] = 1 + (int)(r % (ny - 2));
+                p[2] = 1 + (int)(r / (ny - 2));
+            }
+            const int n_ax = ax == 0 ? nx : (ax == 1 ? ny : nz);
+            const int side = p[ax] == 0 ? -1 : 1;
+            (void)n_ax;
+            const int64_t c = ((int64_t)p[2] * ny + p[1]) * nx + p[0];
+            const int64_t q = c - side * st[ax];  // first node inside
+            const int64_t s1 = st[(ax + 1) % 3], s2 = st[(ax + 2) % 3];
+            double v = R.mur_be0[ax] * ((double)pm[c] + (double)pp[q]) - (double)pm[q];
+            if (R.order == 1) {
+                v += R.mur_be1[ax] * ((double)p0[c] + (double)p0[q]);
+            } else {
+                v += R.mur_g1[ax] * ((double)p0[c] + (double)p0[q]);
+                const double a1 = ((double)p0[c - s1] + (double)p0[q - s1]) + ((double)p0[c + s1] + (double)p0[q + s1]);
+                const double a2 = ((double)p0[c - s2] + (double)p0[q - s2]) + ((double)p0[c + s2] + (double)p0[q + s2]);
+                v = v + R.mur_ga[ax] * a1 + R.mur_gb[ax] * a2;
+            }
+            pp[c] = (T)v;
+            return;
+        }
+        r -= fz + fy + fx;
+        int p[3];
+        if (r < ex) {
+            p[0] = (int)(r % nx);
+            const int e = (int)(r / nx);
+            p[1] = (e & 1) ? ny - 1 : 0;
+            p[2] = (e & 2) ? nz - 1 : 0;
+        } else if (r < ex + ey) {
+            r -= ex;
+            p[1] = 1 + (int)(r % (ny - 2));
+            const int e = (int)(r / (ny - 2));
+            p[0] = (e & 1) ? nx - 1 : 0;
+            p[2] = (e & 2) ? nz - 1 : 0;
+        } else {
+            r -= ex + ey;
+            p[2] = 1 + (int)(r % (nz - 2));
+            const int e = (int)(r / (nz - 2));
+            p[0] = (e & 1) ? nx - 1 : 0;
+            p[1] = (e & 2) ? ny - 1 : 0;
+        }
+        Lv<T> L{pm, p0, pp};
+        int axs[3], sd[3], m = 0;
         for (int a = 0; a < 3; ++a) {
             const int v = bside(R, a, p[a]);
             if (v != 0) {
-                ax[m] = a;
+                axs[m] = a;
                 sd[m] = v;
                 ++m;
             }
         }
-        double v;
-        if (m == 1)
-            v = face_np1(R, L, p, ax[0], sd[0]);
-        else if (m == 2)
-            v = edge_np1(R, L, p, ax, sd);
-        else
-            v = corner_np1(R, L, p, ax, sd);
-        pot_ptr<T>(R, slot_next(s), comp)[nid(R, p[0], p[1], p[2])] = (T)v;
+        const double v = m == 2 ? edge_np1(R, L, p, axs, sd) : corner_np1(R, L, p, axs, sd);
+        pp[nid(R, p[0], p[1], p[2])] = (T)v;
     }
 };
 
@@ -805,6 +853,7 @@ struct VertexFields {
             if (hi[a] < lo[a])
                 return;
         }
+        constexpr int V = 16 / sizeof(T);
         const int64_t ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
         const int64_t tot = ex * ey * ez;
         for (int64_t t = (int64_t)blk.id * blockDim.x + threadIdx.x; t < tot; t += (int64_t)blk.n * blockDim.x) {
@@ -813,7 +862,6 @@ struct VertexFields {
             const int k = lo[2] + (int)(t / (ex * ey));
             double E[3], B[3];
             vertex_eb<T>(R, s, i, j, k, E, B);
-            constexpr int V = 16 / sizeof(T);
             Vec<T, V> w[8 / V];
             const T all[8] = {(T)E[0], (T)E[1], (T)E[2], (T)B[0], (T)B[1], (T)B[2], (T)0, (T)0};
             for (int q = 0; q < 8; ++q)
@@ -968,6 +1016,14 @@ void sweep_shape_dims(int shape, int *tx, int *ty, int *tz)
     *tz = d[shape][2];
 }
 
+// boundary nodes the Mur kernel updates (see Mur)
+static int64_t mur_nodes(const RunDev &R)
+{
+    const int64_t nx = R.nx, ny = R.ny, nz = R.nz;
+    return 2 * (nx - 2) * (ny - 2) + 2 * (nx - 2) * (nz - 2) + (R.xface_fused ? 0 : 2 * (ny - 2) * (nz - 2)) +
+           4 * nx + 4 * (ny - 2) + 4 * (nz - 2);
+}
+
 hipError_t launch_sweep(const RunDev &R, int shape, hipStream_t st)
 {
     return R.precision == 32 ? launch_sweep_shape<float>(R, shape, st) : launch_sweep_shape<double>(R, shape, st);
@@ -975,8 +1031,7 @@ hipError_t launch_sweep(const RunDev &R, int shape, hipStream_t st)
 
 hipError_t launch_mur(const RunDev &R, hipStream_t st)
 {
-    const int64_t nb = 2LL * R.nx * R.ny + 2LL * R.nx * (R.nz - 2) + (R.xface_fused ? 0 : 2LL * (R.ny - 2) * (R.nz - 2));
-    const int64_t tot = nb * (R.space_charge ? 4 : 3);
+    const int64_t tot = mur_nodes(R) * (R.space_charge ? 4 : 3);
     const unsigned blocks = (unsigned)((tot + 255) / 256);
     if (R.precision == 32)
         hipLaunchKernelGGL((k_run<Mur<float>>), dim3(blocks), dim3(256), 0, st, R);
@@ -1088,11 +1143,7 @@ hipError_t launch_sweep_group(const Group &g, int64_t total, int precision, int 
                            : grp_sweep<double>(g, total, shape, false, st);
 }
 
-int64_t mur_blocks(const RunDev &R)
-{
-    const int64_t nb = 2LL * R.nx * R.ny + 2LL * R.nx * (R.nz - 2) + (R.xface_fused ? 0 : 2LL * (R.ny - 2) * (R.nz - 2));
-    return (nb * (R.space_charge ? 4 : 3) + 255) / 256;
-}
+int64_t mur_blocks(const RunDev &R) { return (mur_nodes(R) * (R.space_charge ? 4 : 3) + 255) / 256; }
 
 hipError_t launch_mur_group(const Group &g, int64_t total, int precision, hipStream_t st)
 {
