@@ -173,29 +173,50 @@ __device__ inline void radix_scatter_blk(const uint32_t *keys_in, const int32_t 
                                          int32_t *vals_out, int64_t n, int shift, const uint32_t *offs, int64_t nblocks,
                                          const uint32_t *tot, int64_t bid)
 {
-    __shared__ uint32_t run[256];
+    // The block's kSortChunk elements are ranked stably by digit into LDS
+    // (block-local sorted order), then written out in that order: each digit
+    // run is one contiguous range of the output, so consecutive threads
+    // write consecutive addresses.
+    __shared__ uint32_t gbase[256];   // output position of the block's first element of each digit
+    __shared__ uint32_t lstart[256];  // local position of the same
+    __shared__ uint32_t lrun[256];    // elements of each digit placed so far
     __shared__ uint32_t wcnt[kSortThreads / 64][256];
+    __shared__ uint32_t skey[kSortChunk];
+    __shared__ int32_t sval[kSortChunk];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    // digit base = sum of the totals of smaller digits (inclusive wave scan)
+    const int64_t base = (int64_t)bid * kSortChunk;
+    const int64_t cnt = min((int64_t)kSortChunk, n - base);
     {
-        const uint32_t t = tot[threadIdx.x];
-        uint32_t inc = t;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t u = __shfl_up(inc, o);
-            if (lane >= o)
+        const int d = threadIdx.x;
+        const uint32_t o = offs[(int64_t)d * nblocks + bid];
+        const uint32_t o1 = bid + 1 < nblocks ? offs[(int64_t)d * nblocks + bid + 1] : tot[d];
+        const uint32_t mine = o1 - o;  // this block's count of digit d
+        // digit bases (inclusive wave scans of the totals and of the counts)
+        const uint32_t t = tot[d];
+        uint32_t inc = t, linc = mine;
+        for (int q = 1; q < 64; q <<= 1) {
+            const uint32_t u = __shfl_up(inc, q), lu = __shfl_up(linc, q);
+            if (lane >= q) {
                 inc += u;
+                linc += lu;
+            }
         }
-        if (lane == 63)
+        if (lane == 63) {
             wcnt[0][wave] = inc;
+            wcnt[1][wave] = linc;
+        }
         __syncthreads();
-        uint32_t wb = 0;
-        for (int w = 0; w < wave; ++w)
+        uint32_t wb = 0, lwb = 0;
+        for (int w = 0; w < wave; ++w) {
             wb += wcnt[0][w];
-        run[threadIdx.x] = wb + inc - t + offs[(int64_t)threadIdx.x * nblocks + bid];
+            lwb += wcnt[1][w];
+        }
+        gbase[d] = wb + inc - t + o;
+        lstart[d] = lwb + linc - mine;
+        lrun[d] = 0;
         __syncthreads();
     }
-    const int64_t base = (int64_t)bid * kSortChunk;
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     for (int it = 0; it < kSortItems; ++it) {
         for (int w = 0; w < kSortThreads / 64; ++w)
@@ -222,18 +243,26 @@ __device__ inline void radix_scatter_blk(const uint32_t *keys_in, const int32_t 
             wcnt[wave][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (ok) {
-            uint32_t pos = run[d] + rank;
+            uint32_t pos = lstart[d] + lrun[d] + rank;
             for (int w = 0; w < wave; ++w)
                 pos += wcnt[w][d];
-            keys_out[pos] = key;
-            vals_out[pos] = val;
+            skey[pos] = key;
+            sval[pos] = val;
         }
         __syncthreads();
         uint32_t add = 0;
         for (int w = 0; w < kSortThreads / 64; ++w)
             add += wcnt[w][threadIdx.x];
-        run[threadIdx.x] += add;
+        lrun[threadIdx.x] += add;
         __syncthreads();
+    }
+    // block-local sorted order -> output, digit runs contiguous
+    for (int64_t i = threadIdx.x; i < cnt; i += kSortThreads) {
+        const uint32_t key = skey[i];
+        const uint32_t d = (key >> shift) & 0xFF;
+        const int64_t pos = (int64_t)gbase[d] + (i - (int64_t)lstart[d]);
+        keys_out[pos] = key;
+        vals_out[pos] = sval[i];
     }
 }
 
