@@ -422,7 +422,6 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.item_cap = (int64_t)L.items_n;
     R.ppart = (double *)(A + L.ppart);
     R.sort_blocks = sort_blocks((int64_t)c);
-    R.sorted_ids = R.sv[(sort_passes(R.key_inactive) - 1) & 1];
     R.power_hist = (double *)(A + L.power);
     R.power_cap = kPowerCap;
     R.k_plane = d->k_plane;
@@ -739,12 +738,17 @@ extern "C" int mithra_read_particles(mithra_handle h, double *xyz, double *u, in
     int32_t pb = 0;
     HIPCHK(h, hipMemcpy(&pb, &R.ctl->pbuf, 4, hipMemcpyDeviceToHost));
     // the state sits in buffer pb in the slots pid[pb]; the order of the
-    // last sort is R.sorted_ids (the per-block path does not move the state
+    // last sort is sv[sorted_buf] (the per-block path does not move the state
     // after sorting) or the gathered pid[pb] (tile-owned path)
     std::vector<int32_t> ids((size_t)n);
     HIPCHK(h, hipMemcpy(ids.data(), R.pid[pb], (size_t)n * 4, hipMemcpyDeviceToHost));
-    if (sort_perm)
-        HIPCHK(h, hipMemcpy(sort_perm, h->tiled ? R.pid[pb] : R.sorted_ids, (size_t)n * 4, hipMemcpyDeviceToHost));
+    {
+        int32_t sb = 0;
+        if (sort_perm && !h->tiled)
+            HIPCHK(h, hipMemcpy(&sb, &R.ctl->sorted_buf, 4, hipMemcpyDeviceToHost));
+        if (sort_perm)
+            HIPCHK(h, hipMemcpy(sort_perm, h->tiled ? R.pid[pb] : R.sv[sb], (size_t)n * 4, hipMemcpyDeviceToHost));
+    }
     std::vector<double> col((size_t)n);
     for (int a = 0; a < 6; ++a) {
         double *dst = a < 3 ? xyz : u;
@@ -1190,7 +1194,7 @@ static int build_tables(mithra_batch b)
     if (!rc)
         rc = make_tab(b, all, [](const RunDev &) { return (int64_t)256; }, &b->sort_d);
     if (!rc)
-        rc = make_tab(b, all, [](const RunDev &R) { return (R.np + 255) / 256; }, &b->sort_p);
+        rc = make_tab(b, all, [](const RunDev &) { return (int64_t)1; }, &b->sort_p);  // SortRange
     if (rc)
         return rc;
     b->max_passes = 0;

@@ -15,7 +15,7 @@ __host__ __device__ inline int64_t dep_blocks_dev(int64_t np) { return (np + kDe
 
 // Gather + undulator + N_b Boris sub-steps + deposit (MODE 0), or the load
 // deposit of the backward-drift move (MODE 1, set 0).  Rank p handles the
-// particle R.sorted_ids[p] of the last sort, read from its slot in buffer pbuf;
+// particle sv[sorted_buf][p] of the last sort, read from its slot in buffer pbuf;
 // MODE 0 writes the pushed state to rank p of the other buffer (the step's
 // last bookkeeping kernel flips pbuf), so the sort never moves the state.
 // The block's deposits are summed in LDS over its node box when the box
@@ -43,7 +43,7 @@ struct PushDeposit {
         if (p < R.np) {
             // rank p of the last sort: particle id, read where the previous
             // push (or the load) left it
-            const int32_t id = R.sorted_ids[p];
+            const int32_t id = R.sv[R.ctl->sorted_buf][p];
             const int32_t src = R.slot_of_id[id];
             double r[3], u[3];
             for (int a = 0; a < 3; ++a) {

@@ -99,8 +99,18 @@ __global__ __launch_bounds__(256) void k_sort_keys(RunDev R)
 }
 
 // per-block digit histogram, stored digit-major: hist[d * nblocks + b]
+// Digit d of pass ps is taken from the offset key: key - key_base for
+// active particles, key_span for inactive ones (same order as the keys; the
+// offset needs only the bits of key_span, so passes beyond ctl->npass are
+// skipped).
+__device__ inline uint32_t sort_digit(const Ctl *ctl, uint32_t inactive, uint32_t key, int shift)
+{
+    const uint32_t x = key == inactive ? ctl->key_span : key - ctl->key_base;
+    return (x >> shift) & 0xFF;
+}
+
 __device__ inline void radix_hist_blk(const uint32_t *keys, int64_t n, int shift, uint32_t *hist, int64_t nblocks,
-                                      int64_t bid)
+                                      int64_t bid, const Ctl *ctl, uint32_t inactive)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
@@ -109,16 +119,18 @@ __device__ inline void radix_hist_blk(const uint32_t *keys, int64_t n, int shift
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t e = base + (int64_t)it * kSortThreads + threadIdx.x;
         if (e < n)
-            atomicAdd(&h[(keys[e] >> shift) & 0xFF], 1u);
+            atomicAdd(&h[sort_digit(ctl, inactive, keys[e], shift)], 1u);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblocks + bid] = h[threadIdx.x];
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *keys, int64_t n, int shift, uint32_t *hist,
-                                                          int64_t nblocks)
+                                                          int64_t nblocks, const Ctl *ctl, uint32_t inactive, int ps)
 {
-    radix_hist_blk(keys, n, shift, hist, nblocks, blockIdx.x);
+    if (ps >= ctl->npass)
+        return;
+    radix_hist_blk(keys, n, shift, hist, nblocks, blockIdx.x, ctl, inactive);
 }
 
 // Per digit d (one block each): exclusive scan of hist[d][0..nblocks) in
@@ -163,15 +175,17 @@ __device__ inline void digit_scan_blk(uint32_t *hist, int64_t nblocks, uint32_t 
         tot[bid] = carry;
 }
 
-__global__ __launch_bounds__(256) void k_digit_scan(uint32_t *hist, int64_t nblocks, uint32_t *tot)
+__global__ __launch_bounds__(256) void k_digit_scan(uint32_t *hist, int64_t nblocks, uint32_t *tot, const Ctl *ctl, int ps)
 {
+    if (ps >= ctl->npass)
+        return;
     digit_scan_blk(hist, nblocks, tot, blockIdx.x);
 }
 
 // stable scatter of one pass.  vals_in == nullptr means identity values.
 __device__ inline void radix_scatter_blk(const uint32_t *keys_in, const int32_t *vals_in, uint32_t *keys_out,
                                          int32_t *vals_out, int64_t n, int shift, const uint32_t *offs, int64_t nblocks,
-                                         const uint32_t *tot, int64_t bid)
+                                         const uint32_t *tot, int64_t bid, const Ctl *ctl, uint32_t inactive)
 {
     // The block's kSortChunk elements are ranked stably by digit into LDS
     // (block-local sorted order), then written out in that order: each digit
@@ -229,7 +243,7 @@ __device__ inline void radix_scatter_blk(const uint32_t *keys_in, const int32_t 
         if (ok) {
             key = keys_in[e];
             val = vals_in ? vals_in[e] : (int32_t)e;
-            d = (key >> shift) & 0xFF;
+            d = sort_digit(ctl, inactive, key, shift);
         }
         // lanes of this wavefront holding the same digit
         uint64_t peers = __ballot(ok);
@@ -259,7 +273,7 @@ __device__ inline void radix_scatter_blk(const uint32_t *keys_in, const int32_t 
     // block-local sorted order -> output, digit runs contiguous
     for (int64_t i = threadIdx.x; i < cnt; i += kSortThreads) {
         const uint32_t key = skey[i];
-        const uint32_t d = (key >> shift) & 0xFF;
+        const uint32_t d = sort_digit(ctl, inactive, key, shift);
         const int64_t pos = (int64_t)gbase[d] + (i - (int64_t)lstart[d]);
         keys_out[pos] = key;
         vals_out[pos] = sval[i];
@@ -269,9 +283,12 @@ __device__ inline void radix_scatter_blk(const uint32_t *keys_in, const int32_t 
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *keys_in, const int32_t *vals_in,
                                                              uint32_t *keys_out, int32_t *vals_out, int64_t n,
                                                              int shift, const uint32_t *offs, int64_t nblocks,
-                                                             const uint32_t *tot)
+                                                             const uint32_t *tot, const Ctl *ctl, uint32_t inactive,
+                                                             int ps)
 {
-    radix_scatter_blk(keys_in, vals_in, keys_out, vals_out, n, shift, offs, nblocks, tot, blockIdx.x);
+    if (ps >= ctl->npass)
+        return;
+    radix_scatter_blk(keys_in, vals_in, keys_out, vals_out, n, shift, offs, nblocks, tot, blockIdx.x, ctl, inactive);
 }
 
 // gather particle state into the other buffer in sorted order
@@ -290,10 +307,42 @@ __device__ inline void sort_gather_blk(const RunDev &R, const uint32_t *keys, co
     R.key_sorted[r] = keys[r];
 }
 
-__global__ __launch_bounds__(256) void k_sort_gather(RunDev R, const uint32_t *keys, const int32_t *ids)
+__global__ __launch_bounds__(256) void k_sort_gather(RunDev R)
 {
-    sort_gather_blk(R, keys, ids, blockIdx.x);
+    const int b = R.ctl->sorted_buf;
+    sort_gather_blk(R, R.sk[b], R.sv[b], blockIdx.x);
 }
+
+// Offset and pass count of the current sort, from the box of the active
+// cells: active keys lie between the keys of the box's first and last tiles.
+struct SortRange {
+    static constexpr int kThreads = 1;
+    static __device__ void run(const RunDev &R, Blk)
+    {
+        Ctl *c = R.ctl;
+        uint32_t base = 0, span = 0;
+        if (c->cell_hi[0] >= c->cell_lo[0] && c->cell_hi[1] >= c->cell_lo[1] && c->cell_hi[2] >= c->cell_lo[2]) {
+            const uint32_t vol = (uint32_t)(R.tile[0] * R.tile[1] * R.tile[2]);
+            uint32_t t0[3], t1[3];
+            for (int a = 0; a < 3; ++a) {
+                t0[a] = (uint32_t)(c->cell_lo[a] / R.tile[a]);
+                t1[a] = (uint32_t)(c->cell_hi[a] / R.tile[a]);
+            }
+            const uint32_t l0 = (t0[2] * (uint32_t)R.ntile[1] + t0[1]) * (uint32_t)R.ntile[0] + t0[0];
+            const uint32_t l1 = (t1[2] * (uint32_t)R.ntile[1] + t1[1]) * (uint32_t)R.ntile[0] + t1[0];
+            base = l0 * vol;
+            span = (l1 + 1) * vol - base;
+        }
+        int bits = 0;
+        while (bits < 32 && (span >> bits) != 0)
+            ++bits;
+        const int np = bits <= 8 ? 1 : (bits + 7) / 8;
+        c->key_base = base;
+        c->key_span = span;
+        c->npass = np;
+        c->sorted_buf = (np - 1) & 1;
+    }
+};
 
 // The same passes with every pointer derived from the run, for grouped
 // launches over runs of different sizes and key ranges: pass ps of a run
@@ -311,10 +360,10 @@ struct RadixHistRun {
     static constexpr int kThreads = kSortThreads;
     static __device__ void run(const RunDev &R, Blk blk, int ps)
     {
-        if (ps >= sort_passes_of(R.key_inactive) || R.np <= 0)
+        if (ps >= R.ctl->npass || R.np <= 0)
             return;
         const uint32_t *kin = ps == 0 ? R.key_by_id : R.sk[(ps - 1) & 1];
-        radix_hist_blk(kin, R.np, 8 * ps, R.hist, R.sort_blocks, blk.id);
+        radix_hist_blk(kin, R.np, 8 * ps, R.hist, R.sort_blocks, blk.id, R.ctl, R.key_inactive);
     }
 };
 
@@ -322,7 +371,7 @@ struct DigitScanRun {
     static constexpr int kThreads = 256;
     static __device__ void run(const RunDev &R, Blk blk, int ps)
     {
-        if (ps >= sort_passes_of(R.key_inactive) || R.np <= 0)
+        if (ps >= R.ctl->npass || R.np <= 0)
             return;
         digit_scan_blk(R.hist, R.sort_blocks, R.hist + 256 * R.sort_blocks, blk.id);
     }
@@ -332,21 +381,12 @@ struct RadixScatterRun {
     static constexpr int kThreads = kSortThreads;
     static __device__ void run(const RunDev &R, Blk blk, int ps)
     {
-        if (ps >= sort_passes_of(R.key_inactive) || R.np <= 0)
+        if (ps >= R.ctl->npass || R.np <= 0)
             return;
         const uint32_t *kin = ps == 0 ? R.key_by_id : R.sk[(ps - 1) & 1];
         const int32_t *vin = ps == 0 ? nullptr : R.sv[(ps - 1) & 1];
         radix_scatter_blk(kin, vin, R.sk[ps & 1], R.sv[ps & 1], R.np, 8 * ps, R.hist, R.sort_blocks,
-                          R.hist + 256 * R.sort_blocks, blk.id);
-    }
-};
-
-struct SortGatherRun {
-    static constexpr int kThreads = 256;
-    static __device__ void run(const RunDev &R, Blk blk)
-    {
-        const int last = sort_passes_of(R.key_inactive) - 1;
-        sort_gather_blk(R, R.sk[last & 1], R.sv[last & 1], blk.id);
+                          R.hist + 256 * R.sort_blocks, blk.id, R.ctl, R.key_inactive);
     }
 };
 
@@ -374,6 +414,9 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
                                      st, CTL_ADDR(R.ctl, n_items));
     if (e != hipSuccess)
         return e;
+    hipLaunchKernelGGL((k_run<SortRange>), dim3(1), dim3(1), 0, st, R);
+    // as many passes as the widest key range needs; the ones the current
+    // range does not need return at once
     const int passes = sort_passes(R.key_inactive);
     const int64_t nb = R.sort_blocks;
     const uint32_t *kin = R.key_by_id;
@@ -381,17 +424,18 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
     for (int ps = 0; ps < passes; ++ps) {
         uint32_t *kout = R.sk[ps & 1];
         int32_t *vout = R.sv[ps & 1];
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, R.np, 8 * ps, R.hist, nb);
-        hipLaunchKernelGGL(k_digit_scan, dim3(256), dim3(256), 0, st, R.hist, nb, R.hist + 256 * nb);
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, R.np, 8 * ps, R.hist, nb,
+                           R.ctl, R.key_inactive, ps);
+        hipLaunchKernelGGL(k_digit_scan, dim3(256), dim3(256), 0, st, R.hist, nb, R.hist + 256 * nb, R.ctl, ps);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, R.np,
-                           8 * ps, R.hist, nb, R.hist + 256 * nb);
+                           8 * ps, R.hist, nb, R.hist + 256 * nb, R.ctl, R.key_inactive, ps);
         kin = kout;
         vin = vout;
     }
     // the tile-owned kernel reads the state in sorted slots; the per-block
-    // kernel reads it through R.sorted_ids
+    // kernel reads it through sv[ctl->sorted_buf]
     if (gather)
-        hipLaunchKernelGGL(k_sort_gather, dim3(pblocks), dim3(256), 0, st, R, kin, vin);
+        hipLaunchKernelGGL(k_sort_gather, dim3(pblocks), dim3(256), 0, st, R);
     return hipGetLastError();
 }
 
@@ -403,18 +447,18 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
 namespace mithra {
 
 // gs: members with sort_blocks workgroups; gd: 256 workgroups each (one
-// per digit); gp: one workgroup per 256 particles
+// per digit); gp: one workgroup each (the key range of the sort)
 hipError_t launch_sort_group(const Group &gs, int64_t total_s, const Group &gd, int64_t total_d, const Group &gp,
                              int64_t total_p, int max_passes, hipStream_t st)
 {
     if (total_p <= 0)
         return hipSuccess;
+    hipLaunchKernelGGL((k_group<SortRange>), dim3((unsigned)total_p), dim3(1), 0, st, gp);
     for (int ps = 0; ps < max_passes; ++ps) {
         hipLaunchKernelGGL((k_group<RadixHistRun, int>), dim3((unsigned)total_s), dim3(kSortThreads), 0, st, gs, ps);
         hipLaunchKernelGGL((k_group<DigitScanRun, int>), dim3((unsigned)total_d), dim3(256), 0, st, gd, ps);
         hipLaunchKernelGGL((k_group<RadixScatterRun, int>), dim3((unsigned)total_s), dim3(kSortThreads), 0, st, gs, ps);
     }
-    (void)gp;
     return hipGetLastError();
 }
 

@@ -38,6 +38,10 @@ struct Ctl {
     int32_t item_next;     // next work item to take (persistent push)
     int32_t pad_;
     int64_t target;        // step count at which a batched run stops (grouped launches only)
+    uint32_t key_base;     // sort keys of the current sort are offset by this (active keys >= it)
+    uint32_t key_span;     // active keys lie in [key_base, key_base + key_span); inactive sort as key_span
+    int32_t npass;         // radix passes the current sort needs (8-bit digits of key_span)
+    int32_t sorted_buf;    // sv[sorted_buf] holds the ids in the order of the last sort
 };
 
 constexpr int kMaxBatch = 1;  // one run per RunDev
@@ -72,7 +76,6 @@ struct RunDev {
     double h[3];      // dx dy dz
     double cdt;       // c dt
     int xface_fused;  // 1: the (vector) sweep also updates the x-face nodes
-    const int32_t *sorted_ids;  // particle ids in the order of the last sort (output of its last pass)
     int precision;    // 32 or 64
     int compensated;
     // particles
