@@ -508,6 +508,8 @@ extern "C" int mithra_load_bunch(mithra_handle h, int64_t n, const double *xyz, 
     R.np = n;
     R.q = q_macro;
     R.qV = q_macro / (h->d.dx * h->d.dy * h->d.dz);
+    for (int a = 0; a < 3; ++a)
+        R.qvh_dt[a] = R.qV * R.h[a] / R.dt;
     // sort first so that the first deposit runs in cell order
     hipLaunchKernelGGL(k_book_load, dim3(1), dim3(1), 0, h->stream, R.ctl);
     int rc = enqueue_sort_with_cells(h);

@@ -191,21 +191,21 @@ struct PushDeposit {
                 deposit_charge(R, acc, g2, c2);
             __syncthreads();
             const GlobalAcc<T, COMP> gacc = make_gacc<T, COMP>(R, set);
-            // four entries per thread per round, so that the returning atomics of
-            // the compensated mode are in flight together
-            for (int e0 = threadIdx.x; e0 < 4 * vol; e0 += 4 * kDepThreads) {
+            // one node per thread per round, its four components together (so
+            // that the returning atomics of the compensated mode are in flight
+            // together); the node's (i, j, k) is decoded once for the four
+            for (int e = threadIdx.x; e < vol; e += kDepThreads) {
+                const int i = e % ex, jk = e / ex;
+                const int j = jk % ey, k = jk / ey;
                 double v[4];
                 int idx[4][4];
     #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int e = e0 + q * kDepThreads;
-                    v[q] = e < 4 * vol ? lds[e] : 0.0;
-                    const int comp = e / vol;
-                    const int r = e - comp * vol;
-                    idx[q][0] = comp;
-                    idx[q][1] = L0 + r % ex;
-                    idx[q][2] = L1 + (r / ex) % ey;
-                    idx[q][3] = L2 + r / (ex * ey);
+                    v[q] = lds[q * vol + e];
+                    idx[q][0] = q;
+                    idx[q][1] = L0 + i;
+                    idx[q][2] = L1 + j;
+                    idx[q][3] = L2 + k;
                 }
                 gacc.add4(v, idx);
             }

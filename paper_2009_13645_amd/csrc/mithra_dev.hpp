@@ -63,6 +63,7 @@ struct RunDev {
     //                              + a6 (cur_k+ + cur_k-) - prev + S
     double A, a1, a2, a4, a6;
     double rx2, ry2, rz2;  // (c dt / d_l)^2: the difference form of the FP32 sweeps
+    double qvh_dt[3];      // q / (dx dy dz) * d_l / dt: edge current per unit grid displacement
     double sfac_A;    // (c dt)^2 mu0, multiplies the node-averaged J
     double sfac_phi;  // (c dt)^2 / eps0, multiplies rho
     int space_charge;

@@ -226,7 +226,7 @@ __device__ inline void segment_current(const RunDev &R, const Acc &acc, const do
     for (int l = 0; l < 3; ++l) {
         const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
         // J_l = q (displacement in metres) / (dt V) times the edge weights
-        const double F = R.qV * d[l] * R.h[l] / R.dt;
+        const double F = d[l] * R.qvh_dt[l];
         const double x = d[m1] * d[m2] * (1.0 / 12.0);
         const double u1 = W[m1], u2 = W[m2];
         int q[3] = {c[0], c[1], c[2]};
@@ -260,7 +260,7 @@ __device__ inline void deposit_move(const RunDev &R, const Acc &acc, const doubl
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
-            const double F1 = R.qV * d1[l] * R.h[l] / R.dt, F2 = R.qV * d2[l] * R.h[l] / R.dt;
+            const double F1 = d1[l] * R.qvh_dt[l], F2 = d2[l] * R.qvh_dt[l];
             const double x1 = d1[m1] * d1[m2] * (1.0 / 12.0), x2 = d2[m1] * d2[m2] * (1.0 / 12.0);
             const double a1 = W1[m1], b1 = W1[m2], a2 = W2[m1], b2 = W2[m2];
             int q[3] = {c1[0], c1[1], c1[2]};
