@@ -263,15 +263,22 @@ __device__ inline void deposit_move(const RunDev &R, const Acc &acc, const doubl
             const double F1 = d1[l] * R.qvh_dt[l], F2 = d2[l] * R.qvh_dt[l];
             const double x1 = d1[m1] * d1[m2] * (1.0 / 12.0), x2 = d2[m1] * d2[m2] * (1.0 / 12.0);
             const double a1 = W1[m1], b1 = W1[m2], a2 = W2[m1], b2 = W2[m2];
-            int q[3] = {c1[0], c1[1], c1[2]};
-            acc.add(l, q[0], q[1], q[2],
-                    F1 * ((1.0 - a1) * (1.0 - b1) + x1) + F2 * ((1.0 - a2) * (1.0 - b2) + x2));
-            q[m1] += 1;
-            acc.add(l, q[0], q[1], q[2], F1 * (a1 * (1.0 - b1) - x1) + F2 * (a2 * (1.0 - b2) - x2));
-            q[m2] += 1;
-            acc.add(l, q[0], q[1], q[2], F1 * (a1 * b1 + x1) + F2 * (a2 * b2 + x2));
-            q[m1] -= 1;
-            acc.add(l, q[0], q[1], q[2], F1 * ((1.0 - a1) * b1 - x1) + F2 * ((1.0 - a2) * b2 - x2));
+            // the four edges of component l: (0,0), (1,0), (1,1), (0,1) in
+            // (m1, m2); lanes take them in an order rotated by the lane, so
+            // that lanes of the same cell add to different edges at once
+            const double w[4] = {F1 * ((1.0 - a1) * (1.0 - b1) + x1) + F2 * ((1.0 - a2) * (1.0 - b2) + x2),
+                                 F1 * (a1 * (1.0 - b1) - x1) + F2 * (a2 * (1.0 - b2) - x2),
+                                 F1 * (a1 * b1 + x1) + F2 * (a2 * b2 + x2),
+                                 F1 * ((1.0 - a1) * b1 - x1) + F2 * ((1.0 - a2) * b2 - x2)};
+            const int rot = (int)(threadIdx.x & 3);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int q4 = (e + rot) & 3;
+                int q[3] = {c1[0], c1[1], c1[2]};
+                q[m1] += (q4 == 1 || q4 == 2) ? 1 : 0;
+                q[m2] += (q4 >= 2) ? 1 : 0;
+                acc.add(l, q[0], q[1], q[2], w[q4]);
+            }
         }
         return;
     }
@@ -290,13 +297,15 @@ __device__ inline void deposit_charge(const RunDev &R, const Acc &acc, const dou
 {
     const double dx = g[0] - c[0], dy = g[1] - c[1], dz = g[2] - c[2];
     const double wx[2] = {1.0 - dx, dx}, wy[2] = {1.0 - dy, dy}, wz[2] = {1.0 - dz, dz};
+    // the eight corners in an order rotated by the lane (lanes of the same
+    // cell add to different nodes at once); each value is formed as before
+    const int rot = (int)(threadIdx.x & 7);
 #pragma unroll
-    for (int K = 0; K < 2; ++K)
-#pragma unroll
-        for (int J = 0; J < 2; ++J)
-#pragma unroll
-            for (int I = 0; I < 2; ++I)
-                acc.add(3, c[0] + I, c[1] + J, c[2] + K, R.qV * wx[I] * wy[J] * wz[K]);
+    for (int e = 0; e < 8; ++e) {
+        const int q8 = (e + rot) & 7;
+        const int I = q8 & 1, J = (q8 >> 1) & 1, K = q8 >> 2;
+        acc.add(3, c[0] + I, c[1] + J, c[2] + K, R.qV * wx[I] * wy[J] * wz[K]);
+    }
 }
 
 __device__ inline int wave_min(int v)
