@@ -692,6 +692,15 @@ __device__ double corner_np1(const RunDev &R, const Lv<T> &L, const int p[3], co
     return solve_summed(R, L, p, ax, sd, 3, np1);
 }
 
+// r / d for 0 <= r < half (r = row * d + column of a face): multiply-high
+// when exact, else 64-bit division
+__device__ inline uint32_t face_div(int64_t r, int64_t half, int d)
+{
+    if ((uint64_t)half * (uint64_t)d < (1ull << 32))
+        return fdiv((uint32_t)r, fast_div((uint32_t)d));
+    return (uint32_t)(r / d);
+}
+
 // Boundary nodes, one thread each (per component), in two groups:
 //  - face nodes that lie on one boundary only (z faces, y faces, and the x
 //    faces unless the vector sweep updated them), with direct strides;
@@ -710,12 +719,12 @@ struct Mur {
         const int64_t fx = R.xface_fused ? 0 : 2LL * (ny - 2) * (nz - 2);
         const int64_t ex = 4LL * nx, ey = 4LL * (ny - 2), ez = 4LL * (nz - 2);
         const int64_t nb = fz + fy + fx + ex + ey + ez;
-        const int ncomp = R.space_charge ? 4 : 3;
-        const int64_t t = (int64_t)blk.id * blockDim.x + threadIdx.x;
-        if (t >= nb * ncomp)
+        // ceil(nb / 256) workgroups per component (component uniform per workgroup)
+        const int64_t bpc = (nb + 255) / 256;
+        const int comp = (int)(blk.id / bpc);
+        int64_t r = (blk.id - (int64_t)comp * bpc) * blockDim.x + threadIdx.x;
+        if (r >= nb)
             return;
-        const int comp = (int)(t / nb);
-        int64_t r = t % nb;
         const int64_t s = R.ctl->step;
         const T *pm = pot_ptr<T>(R, slot_prev(s), comp);
         const T *p0 = pot_ptr<T>(R, slot_cur(s), comp);
@@ -727,25 +736,31 @@ struct Mur {
                 const int64_t half = (int64_t)(nx - 2) * (ny - 2);
                 ax = 2;
                 p[2] = r < half ? 0 : nz - 1;
-                r %= half;
-                p[0] = 1 + (int)(r % (nx - 2));
-                p[1] = 1 + (int)(r / (nx - 2));
+                if (r >= half)
+                    r -= half;
+                const uint32_t q = face_div(r, half, nx - 2);
+                p[0] = 1 + (int)(r - (int64_t)q * (nx - 2));
+                p[1] = 1 + (int)q;
             } else if (r < fz + fy) {
                 r -= fz;
                 const int64_t half = (int64_t)(nx - 2) * (nz - 2);
                 ax = 1;
                 p[1] = r < half ? 0 : ny - 1;
-                r %= half;
-                p[0] = 1 + (int)(r % (nx - 2));
-                p[2] = 1 + (int)(r / (nx - 2));
+                if (r >= half)
+                    r -= half;
+                const uint32_t q = face_div(r, half, nx - 2);
+                p[0] = 1 + (int)(r - (int64_t)q * (nx - 2));
+                p[2] = 1 + (int)q;
             } else {
                 r -= fz + fy;
                 const int64_t half = (int64_t)(ny - 2) * (nz - 2);
                 ax = 0;
                 p[0] = r < half ? 0 : nx - 1;
-                r %= half;
-                p[1] = 1 + (int)(r % (ny - 2));
-                p[2] = 1 + (int)(r / (ny - 2));
+                if (r >= half)
+                    r -= half;
+                const uint32_t q = face_div(r, half, ny - 2);
+                p[1] = 1 + (int)(r - (int64_t)q * (ny - 2));
+                p[2] = 1 + (int)q;
             }
             const int n_ax = ax == 0 ? nx : (ax == 1 ? ny : nz);
             const int side = p[ax] == 0 ? -1 : 1;
@@ -856,10 +871,22 @@ struct VertexFields {
         constexpr int V = 16 / sizeof(T);
         const int64_t ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
         const int64_t tot = ex * ey * ez;
+        // 32-bit decoding by multiply-high when exact (t * max(ex, ey) < 2^32)
+        const bool fast = (uint64_t)tot * (uint64_t)(ex > ey ? ex : ey) < (1ull << 32);
+        const FastDiv fx = fast_div((uint32_t)ex), fy = fast_div((uint32_t)ey);
         for (int64_t t = (int64_t)blk.id * blockDim.x + threadIdx.x; t < tot; t += (int64_t)blk.n * blockDim.x) {
-            const int i = lo[0] + (int)(t % ex);
-            const int j = lo[1] + (int)((t / ex) % ey);
-            const int k = lo[2] + (int)(t / (ex * ey));
+            int i, j, k;
+            if (fast) {
+                const uint32_t t32 = (uint32_t)t, row = fdiv(t32, fx);
+                const uint32_t kk = fdiv(row, fy);
+                i = lo[0] + (int)(t32 - row * (uint32_t)ex);
+                j = lo[1] + (int)(row - kk * (uint32_t)ey);
+                k = lo[2] + (int)kk;
+            } else {
+                i = lo[0] + (int)(t % ex);
+                j = lo[1] + (int)((t / ex) % ey);
+                k = lo[2] + (int)(t / (ex * ey));
+            }
             double E[3], B[3];
             vertex_eb<T>(R, s, i, j, k, E, B);
             Vec<T, V> w[8 / V];
@@ -1031,8 +1058,7 @@ hipError_t launch_sweep(const RunDev &R, int shape, hipStream_t st)
 
 hipError_t launch_mur(const RunDev &R, hipStream_t st)
 {
-    const int64_t tot = mur_nodes(R) * (R.space_charge ? 4 : 3);
-    const unsigned blocks = (unsigned)((tot + 255) / 256);
+    const unsigned blocks = (unsigned)(((mur_nodes(R) + 255) / 256) * (R.space_charge ? 4 : 3));
     if (R.precision == 32)
         hipLaunchKernelGGL((k_run<Mur<float>>), dim3(blocks), dim3(256), 0, st, R);
     else
@@ -1040,18 +1066,22 @@ hipError_t launch_mur(const RunDev &R, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStream_t st)
+// workgroups of the vertex fields (a grid-stride loop over the box)
+int64_t vertex_blocks(const RunDev &R)
 {
     const int64_t inner = (int64_t)(R.nx - 2) * (R.ny - 2) * (R.nz - 2);
-    int64_t blocks = (inner + 255) / 256;
-    if (blocks > 8192)
-        blocks = 8192;
-    if (blocks < 1)
-        blocks = 1;
+    return std::min<int64_t>(8192, std::max<int64_t>(1, (inner + 255) / 256));
+}
+
+hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStream_t st)
+{
+    const int64_t blocks = vertex_blocks(R);
     if (R.precision == 32)
-        hipLaunchKernelGGL((k_run<VertexFields<float>, int, int>), dim3((unsigned)blocks), dim3(256), 0, st, R, step_bias, full);
+        hipLaunchKernelGGL((k_run<VertexFields<float>, int, int>), dim3((unsigned)blocks), dim3(256), 0, st, R, step_bias,
+                           full);
     else
-        hipLaunchKernelGGL((k_run<VertexFields<double>, int, int>), dim3((unsigned)blocks), dim3(256), 0, st, R, step_bias, full);
+        hipLaunchKernelGGL((k_run<VertexFields<double>, int, int>), dim3((unsigned)blocks), dim3(256), 0, st, R, step_bias,
+                           full);
     return hipGetLastError();
 }
 
@@ -1143,7 +1173,7 @@ hipError_t launch_sweep_group(const Group &g, int64_t total, int precision, int 
                            : grp_sweep<double>(g, total, shape, false, st);
 }
 
-int64_t mur_blocks(const RunDev &R) { return (mur_nodes(R) * (R.space_charge ? 4 : 3) + 255) / 256; }
+int64_t mur_blocks(const RunDev &R) { return ((mur_nodes(R) + 255) / 256) * (R.space_charge ? 4 : 3); }
 
 hipError_t launch_mur_group(const Group &g, int64_t total, int precision, hipStream_t st)
 {
@@ -1156,11 +1186,7 @@ hipError_t launch_mur_group(const Group &g, int64_t total, int precision, hipStr
     return hipGetLastError();
 }
 
-int64_t vertex_blocks(const RunDev &R)
-{
-    const int64_t inner = (int64_t)(R.nx - 2) * (R.ny - 2) * (R.nz - 2);
-    return std::min<int64_t>(8192, std::max<int64_t>(1, (inner + 255) / 256));
-}
+
 
 hipError_t launch_vertex_group(const Group &g, int64_t total, int precision, hipStream_t st)
 {

@@ -172,6 +172,17 @@ __device__ inline void vstore(T *p, const Vec<T, V> &a)
     }
 }
 
+// floor(t / d) by a multiply-high with m = ceil(2^32 / d): exact whenever
+// t * d < 2^32 (the error of m is below 1, so t m / 2^32 stays below the
+// next integer); for index decoding by a divisor that is uniform per launch.
+struct FastDiv {
+    uint32_t d, m;
+};
+
+__host__ __device__ inline FastDiv fast_div(uint32_t d) { return FastDiv{d, d == 1 ? 0u : 0xFFFFFFFFu / d + 1u}; }
+
+__device__ inline uint32_t fdiv(uint32_t t, FastDiv f) { return f.d == 1 ? t : __umulhi(t, f.m); }
+
 // E and B at the vertices are stored node-interleaved: node n holds
 // Ex Ey Ez Bx By Bz and two pad words at eb[8 n .. 8 n + 7] (32 bytes in FP32,
 // 64 in FP64), so that a corner of the gather is two or four 16-byte loads.
