@@ -4,8 +4,8 @@
 // and enqueues the step pipeline on the caller's stream:
 //
 //   sweep (A, phi; clears the stale source set) -> Mur -> vertex E,B on the
-//   active-particle box -> bookkeeping -> gather/push/deposit -> bin+sort ->
-//   radiated power -> bookkeeping (step counter, particle buffer).
+//   active-particle box -> gather/push/deposit -> bin+sort -> radiated
+//   power -> bookkeeping (step counter, particle buffer).
 //
 // Every kernel reads the step number from device memory, so one step is
 // captured once into a HIP graph and replayed for the following steps.
@@ -92,11 +92,6 @@ __device__ inline void book_end(Ctl *ctl, int advance)
 
 __global__ void k_book_mid(Ctl *ctl) { book_mid(ctl); }
 __global__ void k_book_end(Ctl *ctl, int advance) { book_end(ctl, advance); }
-
-struct BookMid {
-    static constexpr int kThreads = 1;
-    static __device__ void run(const RunDev &R, Blk) { book_mid(R.ctl); }
-};
 
 struct BookEnd {
     static constexpr int kThreads = 1;
@@ -569,8 +564,9 @@ static int enqueue_particles(mithra_handle h, hipStream_t st)
         HIPCHK(h, launch_sort(R, st, true, tile_partials(R), true));
         HIPCHK(h, launch_tile_items(R, st));
     } else {
+        // no mid-step bookkeeping: the box reductions after the push rewrite
+        // the deposit box, the active-cell box and the active count whole
         HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
-        hipLaunchKernelGGL(k_book_mid, dim3(1), dim3(1), 0, st, R.ctl);
         HIPCHK(h, launch_push_deposit(R, st));
         HIPCHK(h, launch_sort(R, st, true, dep_blocks(R.np), false));
     }
@@ -1213,7 +1209,6 @@ static int enqueue_batch_step(mithra_batch b, hipStream_t st)
         BHIPCHK(b, launch_mur_group(b->mur[pi].g, b->mur[pi].total, pi == 0 ? 32 : 64, st));
     for (int pi = 0; pi < 2; ++pi)
         BHIPCHK(b, launch_vertex_group(b->vertex[pi].g, b->vertex[pi].total, pi == 0 ? 32 : 64, st));
-    hipLaunchKernelGGL((k_group<BookMid>), dim3((unsigned)b->one.total), dim3(1), 0, st, b->one.g);
     for (int ci = 0; ci < 3; ++ci)
         BHIPCHK(b, launch_push_group(b->push[ci].g, b->push[ci].total, ci == 0 ? 64 : 32, ci == 2, st));
     BHIPCHK(b, launch_box_group(b->one.g, b->one.total, st));

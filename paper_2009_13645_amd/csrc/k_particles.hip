@@ -320,16 +320,25 @@ __global__ __launch_bounds__(1024) void k_box_reduce(const int32_t *part, int64_
 }
 
 // after the push of a step: the box of the active cells of the new
-// positions and their count, from the per-block partials; the tile work
-// item counter is reset (the sort that follows builds the new order)
+// positions and their count, from the per-block partials, and the key range
+// of the sort that follows; the tile work item counter is reset
 struct BoxReduceCells {
     static constexpr int kThreads = 1024;
     static __device__ void run(const RunDev &R, Blk blk)
     {
         box_reduce_blk(R.cellpart, dep_blocks_dev(R.np), R.ctl->cell_lo, R.ctl->cell_hi, &R.ctl->n_active,
                        &R.ctl->n_items);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            sort_range(R);  // the offset and pass count of this step's sort
     }
 };
+
+hipError_t launch_box_cells(const RunDev &R, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_run<BoxReduceCells>), dim3(1), dim3(BoxReduceCells::kThreads), 0, st, R);
+    return hipGetLastError();
+}
 
 struct BoxReduceSet {
     static constexpr int kThreads = 1024;

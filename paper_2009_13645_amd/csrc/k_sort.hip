@@ -313,35 +313,10 @@ __global__ __launch_bounds__(256) void k_sort_gather(RunDev R)
     sort_gather_blk(R, R.sk[b], R.sv[b], blockIdx.x);
 }
 
-// Offset and pass count of the current sort, from the box of the active
-// cells: active keys lie between the keys of the box's first and last tiles.
+// the sort range as a kernel of its own (after a generic box reduction)
 struct SortRange {
     static constexpr int kThreads = 1;
-    static __device__ void run(const RunDev &R, Blk)
-    {
-        Ctl *c = R.ctl;
-        uint32_t base = 0, span = 0;
-        if (c->cell_hi[0] >= c->cell_lo[0] && c->cell_hi[1] >= c->cell_lo[1] && c->cell_hi[2] >= c->cell_lo[2]) {
-            const uint32_t vol = (uint32_t)(R.tile[0] * R.tile[1] * R.tile[2]);
-            uint32_t t0[3], t1[3];
-            for (int a = 0; a < 3; ++a) {
-                t0[a] = (uint32_t)(c->cell_lo[a] / R.tile[a]);
-                t1[a] = (uint32_t)(c->cell_hi[a] / R.tile[a]);
-            }
-            const uint32_t l0 = (t0[2] * (uint32_t)R.ntile[1] + t0[1]) * (uint32_t)R.ntile[0] + t0[0];
-            const uint32_t l1 = (t1[2] * (uint32_t)R.ntile[1] + t1[1]) * (uint32_t)R.ntile[0] + t1[0];
-            base = l0 * vol;
-            span = (l1 + 1) * vol - base;
-        }
-        int bits = 0;
-        while (bits < 32 && (span >> bits) != 0)
-            ++bits;
-        const int np = bits <= 8 ? 1 : (bits + 7) / 8;
-        c->key_base = base;
-        c->key_span = span;
-        c->npass = np;
-        c->sorted_buf = (np - 1) & 1;
-    }
+    static __device__ void run(const RunDev &R, Blk) { sort_range(R); }
 };
 
 // The same passes with every pointer derived from the run, for grouped
@@ -394,6 +369,7 @@ struct RadixScatterRun {
 
 hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
                              int32_t *count, hipStream_t st, int32_t *zero);
+hipError_t launch_box_cells(const RunDev &R, hipStream_t st);
 
 int sort_passes(uint32_t key_inactive) { return sort_passes_of(key_inactive); }
 
@@ -409,12 +385,19 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
     const unsigned pblocks = (unsigned)((R.np + 255) / 256);
     if (!keys_ready)
         hipLaunchKernelGGL(k_sort_keys, dim3(pblocks), dim3(256), 0, st, R);
-    hipError_t e = launch_box_reduce(R, keys_ready ? nparts : pblocks, keys_ready ? R.cellpart : R.boxpart,
-                                     CTL_ADDR(R.ctl, cell_lo), CTL_ADDR(R.ctl, cell_hi), CTL_ADDR(R.ctl, n_active),
-                                     st, CTL_ADDR(R.ctl, n_items));
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL((k_run<SortRange>), dim3(1), dim3(1), 0, st, R);
+    if (keys_ready && !gather) {
+        // per-block push: its partials, the active count and the sort range in one kernel
+        hipError_t e = launch_box_cells(R, st);
+        if (e != hipSuccess)
+            return e;
+    } else {
+        hipError_t e = launch_box_reduce(R, keys_ready ? nparts : pblocks, keys_ready ? R.cellpart : R.boxpart,
+                                         CTL_ADDR(R.ctl, cell_lo), CTL_ADDR(R.ctl, cell_hi),
+                                         CTL_ADDR(R.ctl, n_active), st, CTL_ADDR(R.ctl, n_items));
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL((k_run<SortRange>), dim3(1), dim3(1), 0, st, R);
+    }
     // as many passes as the widest key range needs; the ones the current
     // range does not need return at once
     const int passes = sort_passes(R.key_inactive);
@@ -447,13 +430,14 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
 namespace mithra {
 
 // gs: members with sort_blocks workgroups; gd: 256 workgroups each (one
-// per digit); gp: one workgroup each (the key range of the sort)
+// per digit); the key range was set by the box reduction before (gp unused)
 hipError_t launch_sort_group(const Group &gs, int64_t total_s, const Group &gd, int64_t total_d, const Group &gp,
                              int64_t total_p, int max_passes, hipStream_t st)
 {
     if (total_p <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((k_group<SortRange>), dim3((unsigned)total_p), dim3(1), 0, st, gp);
+    (void)gp;
+    (void)total_p;
     for (int ps = 0; ps < max_passes; ++ps) {
         hipLaunchKernelGGL((k_group<RadixHistRun, int>), dim3((unsigned)total_s), dim3(kSortThreads), 0, st, gs, ps);
         hipLaunchKernelGGL((k_group<DigitScanRun, int>), dim3((unsigned)total_d), dim3(256), 0, st, gd, ps);

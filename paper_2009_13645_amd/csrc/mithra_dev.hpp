@@ -278,6 +278,35 @@ __global__ __launch_bounds__(F::kThreads) __attribute__((amdgpu_waves_per_eu(Wav
     F::run(R, Blk{id, G.nblk[m]}, a...);
 }
 
+// Offset and pass count of the current sort, from the box of the active
+// cells: active keys lie between the keys of the box's first and last tiles
+// (the key is increasing in each tile coordinate).  One thread.
+__device__ inline void sort_range(const RunDev &R)
+{
+    Ctl *c = R.ctl;
+    uint32_t base = 0, span = 0;
+    if (c->cell_hi[0] >= c->cell_lo[0] && c->cell_hi[1] >= c->cell_lo[1] && c->cell_hi[2] >= c->cell_lo[2]) {
+        const uint32_t vol = (uint32_t)(R.tile[0] * R.tile[1] * R.tile[2]);
+        uint32_t t0[3], t1[3];
+        for (int a = 0; a < 3; ++a) {
+            t0[a] = (uint32_t)(c->cell_lo[a] / R.tile[a]);
+            t1[a] = (uint32_t)(c->cell_hi[a] / R.tile[a]);
+        }
+        const uint32_t l0 = (t0[2] * (uint32_t)R.ntile[1] + t0[1]) * (uint32_t)R.ntile[0] + t0[0];
+        const uint32_t l1 = (t1[2] * (uint32_t)R.ntile[1] + t1[1]) * (uint32_t)R.ntile[0] + t1[0];
+        base = l0 * vol;
+        span = (l1 + 1) * vol - base;
+    }
+    int bits = 0;
+    while (bits < 32 && (span >> bits) != 0)
+        ++bits;
+    const int np = bits <= 8 ? 1 : (bits + 7) / 8;
+    c->key_base = base;
+    c->key_span = span;
+    c->npass = np;
+    c->sorted_buf = (np - 1) & 1;
+}
+
 // Tile-major sort key of an active cell c (see k_sort.hip for the order).
 __device__ inline uint32_t key_of_cell(const RunDev &R, const int c[3])
 {
