@@ -32,7 +32,7 @@ void sweep_shape_dims(int shape, int *tx, int *ty, int *tz);
 hipError_t launch_mur(const RunDev &R, hipStream_t st);
 int sweep_fuses_xfaces(const RunDev &R, int shape);
 hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStream_t st);
-hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st);
+hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st, int end_step = 0);
 hipError_t launch_push_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_load_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st);
@@ -583,8 +583,9 @@ static int enqueue_step(mithra_handle h)
     if (rc)
         return rc;
     if (R.record_power)
-        HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st));
-    hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);
+        HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st, 1));  // ends the step
+    else
+        hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);
     HIPCHK(h, hipGetLastError());
     return MITHRA_OK;
 }
@@ -896,8 +897,9 @@ extern "C" int mithra_step_timed(mithra_handle h, int64_t n, double *sweep_ms, d
         if (rc)
             return rc;
         if (R.record_power)
-            HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st));
-        hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);
+            HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st, 1));  // ends the step
+        else
+            hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);
         HIPCHK(h, hipGetLastError());
         HIPCHK(h, hipEventRecord(ev[(size_t)(3 * i + 2)], st));
         h->steps += 1;

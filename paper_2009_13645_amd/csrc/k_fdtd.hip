@@ -941,7 +941,7 @@ struct PlanePower {
 
 struct PlanePowerFinal {
     static constexpr int kThreads = 1;
-    static __device__ void run(const RunDev &R, Blk blk, int step_bias, double *out)
+    static __device__ void run(const RunDev &R, Blk blk, int step_bias, double *out, int end_step)
     {
         const int64_t s = R.ctl->step + step_bias;
         double sum = 0.0;
@@ -955,6 +955,11 @@ struct PlanePowerFinal {
             R.power_hist[s] = P;
         if (!isfinite(P))
             R.ctl->nan_flag = 1;
+        if (end_step) {  // last kernel of a step: the step's bookkeeping
+            R.ctl->pbuf ^= 1;
+            R.ctl->nsort += 1;
+            R.ctl->step += 1;
+        }
     }
 };
 
@@ -1085,13 +1090,13 @@ hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st)
+hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st, int end_step)
 {
     if (R.precision == 32)
         hipLaunchKernelGGL((k_run<PlanePower<float>, int, int>), dim3(kPowerBlocks), dim3(256), 0, st, R, step_bias, kp);
     else
         hipLaunchKernelGGL((k_run<PlanePower<double>, int, int>), dim3(kPowerBlocks), dim3(256), 0, st, R, step_bias, kp);
-    hipLaunchKernelGGL((k_run<PlanePowerFinal, int, double *>), dim3(1), dim3(1), 0, st, R, step_bias, out);
+    hipLaunchKernelGGL((k_run<PlanePowerFinal, int, double *, int>), dim3(1), dim3(1), 0, st, R, step_bias, out, end_step);
     return hipGetLastError();
 }
 
@@ -1210,8 +1215,8 @@ hipError_t launch_power_group(const Group &g, int64_t total, const Group &gf, in
         hipLaunchKernelGGL((k_group<PlanePower<float>, int, int>), dim3((unsigned)total), dim3(256), 0, st, g, 0, -1);
     else
         hipLaunchKernelGGL((k_group<PlanePower<double>, int, int>), dim3((unsigned)total), dim3(256), 0, st, g, 0, -1);
-    hipLaunchKernelGGL((k_group<PlanePowerFinal, int, double *>), dim3((unsigned)total_f), dim3(1), 0, st, gf, 0,
-                       (double *)nullptr);
+    hipLaunchKernelGGL((k_group<PlanePowerFinal, int, double *, int>), dim3((unsigned)total_f), dim3(1), 0, st, gf, 0,
+                       (double *)nullptr, 0);
     return hipGetLastError();
 }
 

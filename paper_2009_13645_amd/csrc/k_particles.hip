@@ -334,11 +334,6 @@ struct BoxReduceCells {
     }
 };
 
-hipError_t launch_box_cells(const RunDev &R, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_run<BoxReduceCells>), dim3(1), dim3(BoxReduceCells::kThreads), 0, st, R);
-    return hipGetLastError();
-}
 
 struct BoxReduceSet {
     static constexpr int kThreads = 1024;
@@ -373,6 +368,18 @@ struct BoxReduceSet {
     }
 };
 
+// both reductions after a push, in one kernel: the deposit box of set
+// (s+1)&1, then the active-cell box, the active count and the sort range
+struct BoxReduceStep {
+    static constexpr int kThreads = 1024;
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        BoxReduceSet::run(R, blk, -1);
+        __syncthreads();
+        BoxReduceCells::run(R, blk);
+    }
+};
+
 hipError_t launch_box_reduce_set(const RunDev &R, int64_t nblocks, hipStream_t st)
 {
     hipLaunchKernelGGL((k_run<BoxReduceSet, int64_t>), dim3(1), dim3(1024), 0, st, R, nblocks);
@@ -393,9 +400,10 @@ hipError_t launch_push_deposit(const RunDev &R, hipStream_t st)
     hipError_t e = launch_dep<0>(R, st);
     if (e != hipSuccess || R.np <= 0)
         return e;
-    // the box of set (s+1)&1 is written by a kernel that reads the step
-    // number on the device, like every other stage
-    return launch_box_reduce_set(R, dep_blocks(R.np), st);
+    // the boxes are written by a kernel that reads the step number on the
+    // device, like every other stage
+    hipLaunchKernelGGL((k_run<BoxReduceStep>), dim3(1), dim3(BoxReduceStep::kThreads), 0, st, R);
+    return hipGetLastError();
 }
 
 hipError_t launch_load_deposit(const RunDev &R, hipStream_t st)
@@ -438,8 +446,7 @@ hipError_t launch_box_group(const Group &g, int64_t total, hipStream_t st)
 {
     if (total <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((k_group<BoxReduceSet, int64_t>), dim3((unsigned)total), dim3(1024), 0, st, g, (int64_t)-1);
-    hipLaunchKernelGGL((k_group<BoxReduceCells>), dim3((unsigned)total), dim3(1024), 0, st, g);
+    hipLaunchKernelGGL((k_group<BoxReduceStep>), dim3((unsigned)total), dim3(BoxReduceStep::kThreads), 0, st, g);
     return hipGetLastError();
 }
 

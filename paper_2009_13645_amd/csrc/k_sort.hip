@@ -369,7 +369,6 @@ struct RadixScatterRun {
 
 hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
                              int32_t *count, hipStream_t st, int32_t *zero);
-hipError_t launch_box_cells(const RunDev &R, hipStream_t st);
 
 int sort_passes(uint32_t key_inactive) { return sort_passes_of(key_inactive); }
 
@@ -386,10 +385,8 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
     if (!keys_ready)
         hipLaunchKernelGGL(k_sort_keys, dim3(pblocks), dim3(256), 0, st, R);
     if (keys_ready && !gather) {
-        // per-block push: its partials, the active count and the sort range in one kernel
-        hipError_t e = launch_box_cells(R, st);
-        if (e != hipSuccess)
-            return e;
+        // per-block push: the active-cell box, count and sort range were
+        // reduced right after the push (BoxReduceStep)
     } else {
         hipError_t e = launch_box_reduce(R, keys_ready ? nparts : pblocks, keys_ready ? R.cellpart : R.boxpart,
                                          CTL_ADDR(R.ctl, cell_lo), CTL_ADDR(R.ctl, cell_hi),
