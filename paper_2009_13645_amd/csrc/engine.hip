@@ -182,7 +182,8 @@ struct mithra_engine {
     int sweep_shape = 0;
     bool tiled = false;
     int32_t *cell_by_id = nullptr;
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr;   // one step
+    hipGraphExec_t graph8 = nullptr;  // kGraphSteps steps
     int use_graph = 1;
     bool batched = false;              // the run belongs to a batch
     hipStream_t ext_stream = nullptr;  // that batch's stream
@@ -593,7 +594,10 @@ static int enqueue_step(mithra_handle h)
 // Capture one step on a private stream (the caller's stream may be the
 // legacy default stream, which cannot be captured); the graph is then
 // launched on the caller's stream.
-static int build_graph(mithra_handle h)
+// steps per graph of the long replay (fewer graph launches per step)
+static const int kGraphSteps = 8;
+
+static int build_graph(mithra_handle h, int nsteps, hipGraphExec_t *out)
 {
     hipStream_t cap = nullptr;
     HIPCHK(h, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -603,7 +607,8 @@ static int build_graph(mithra_handle h)
     int rc = MITHRA_OK;
     if (e == hipSuccess) {
         h->stream = cap;
-        rc = enqueue_step(h);
+        for (int i = 0; i < nsteps && rc == MITHRA_OK; ++i)
+            rc = enqueue_step(h);
         h->stream = user;
         e = hipStreamEndCapture(cap, &g);
     }
@@ -615,7 +620,7 @@ static int build_graph(mithra_handle h)
     }
     if (e != hipSuccess)
         return fail(h, MITHRA_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess)
         return fail(h, MITHRA_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
@@ -632,10 +637,23 @@ extern "C" int mithra_step(mithra_handle h, int64_t n_steps)
         return fail(h, MITHRA_EINVAL, "negative step count");
     if (h->batched)
         return fail(h, MITHRA_ESTATE, "the run belongs to a batch: step it with mithra_batch_run");
-    for (int64_t i = 0; i < n_steps; ++i) {
+    int64_t i = 0;
+    if (h->use_graph && n_steps >= kGraphSteps) {
+        // replays of a graph of kGraphSteps steps, then single steps
+        if (!h->graph8) {
+            int rc = build_graph(h, kGraphSteps, &h->graph8);
+            if (rc)
+                return rc;
+        }
+        for (; i + kGraphSteps <= n_steps; i += kGraphSteps) {
+            HIPCHK(h, hipGraphLaunch(h->graph8, h->stream));
+            h->steps += kGraphSteps;
+        }
+    }
+    for (; i < n_steps; ++i) {
         if (h->use_graph) {
             if (!h->graph) {
-                int rc = build_graph(h);
+                int rc = build_graph(h, 1, &h->graph);
                 if (rc)
                     return rc;
             }
@@ -848,6 +866,8 @@ extern "C" int mithra_destroy(mithra_handle h)
         return MITHRA_EINVAL;
     if (h->graph)
         (void)hipGraphExecDestroy(h->graph);
+    if (h->graph8)
+        (void)hipGraphExecDestroy(h->graph8);
     delete h;
     return MITHRA_OK;
 }
@@ -865,6 +885,10 @@ extern "C" int mithra_set_sweep_shape(mithra_handle h, int shape)
     if (h->graph) {
         (void)hipGraphExecDestroy(h->graph);
         h->graph = nullptr;
+    }
+    if (h->graph8) {
+        (void)hipGraphExecDestroy(h->graph8);
+        h->graph8 = nullptr;
     }
     return MITHRA_OK;
 }
