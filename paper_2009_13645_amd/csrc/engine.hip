@@ -945,8 +945,8 @@ extern "C" int mithra_step_timed(mithra_handle h, int64_t n, double *sweep_ms, d
 }
 
 // Time the field sweep alone: `iters` launches for the current step (the
-// sweep only rewrites the next time level and re-clears the stale source
-// set, so repeating it leaves the run's state unchanged).
+// sweep only rewrites the next time level, so repeating it leaves the run's
+// state unchanged).
 extern "C" int mithra_time_sweep(mithra_handle h, int shape, int iters, double *ms)
 {
     if (!h || !ms || iters < 1 || shape < -1 || shape >= sweep_shape_count())

@@ -8,10 +8,10 @@
 //    psi-bar of every column (plus a one-column halo ring) goes through a
 //    double-buffered LDS plane, so psi^n is read from HBM about once.  The
 //    source of the step (node-averaged edge current, or rho) is read only
-//    inside the bounding box of the last deposit, and the other source set is
-//    cleared inside its own box in the same pass.
+//    inside the bounding box of the last deposit.
 //  * k_mur: Mur absorbing boundaries (sec. "Boundary Truncation"), one
-//    thread per boundary node.  Faces use the printed first/second-order
+//    thread per boundary node; further workgroups of the same launch clear
+//    the other source set inside its own box for the coming deposit.  Faces use the printed first/second-order
 //    updates with permuted axes; edges and corners solve the sum of the
 //    first-order conditions of their faces discretised at the centre of the
 //    2x2 (2x2x2) node stencil, recomputing the neighbouring face/edge values
@@ -87,7 +87,7 @@ struct Sweep {
             return;  // grid larger than the tiling (never for the launchers here)
 
         const int64_t s = R.ctl->step;
-        const int set_r = (int)(s & 1), set_c = (int)((s + 1) & 1);
+        const int set_r = (int)(s & 1);
         const bool update = (comp < 3) || R.space_charge;
 
         const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
@@ -128,16 +128,11 @@ struct Sweep {
         T *next = pot_ptr<T>(R, slot_next(s), comp);
 
         // source box of the set read now (expanded by one node on the high side:
-        // a node average reaches the edge below it), clear box of the other set
+        // a node average reaches the edge below it)
         const int *rlo = R.ctl->dep_lo[set_r];
         const int *rhi = R.ctl->dep_hi[set_r];
-        const int *clo = R.ctl->dep_lo[set_c];
-        const int *chi = R.ctl->dep_hi[set_c];
         const bool src_col = valid && i >= rlo[0] && i <= rhi[0] + 1 && j >= rlo[1] && j <= rhi[1] + 1;
-        const bool clr_col = valid && i >= clo[0] && i <= chi[0] && j >= clo[1] && j <= chi[1];
         const int64_t back = comp == 0 ? 1 : (comp == 1 ? R.nx : plane);
-        T *clr = src_ptr<T>(R, set_c, comp);
-        T *clr_lo = R.compensated ? srclo_ptr<T>(R, set_c, comp) : nullptr;
 
         const T cA = (T)R.A, c1A = (T)(1.0 - 2.0 * R.A);
         const T a1 = (T)R.a1, a2 = (T)R.a2, a4 = (T)R.a4, a6 = (T)R.a6;
@@ -170,11 +165,6 @@ struct Sweep {
                 pm = prev[c];
                 if (src_col && k >= rlo[2] && k <= rhi[2] + 1)
                     sv = src_value<T>(R, comp, set_r, c, back);
-            }
-            if (clr_col && k >= clo[2] && k <= chi[2]) {
-                clr[c] = (T)0;
-                if (clr_lo)
-                    clr_lo[c] = (T)0;
             }
             T(*buf)[TX + 2] = sb[k & 1];
             if constexpr (kDiffForm<T>) {
@@ -224,7 +214,7 @@ struct Sweep {
 // x-neighbours and its y-neighbour vectors from LDS.  Needs nx % V == 0 so
 // that every row starts aligned.
 // Streaming (non-temporal) 16-byte accesses: data touched once per sweep
-// (psi^{n-1}, psi^{n+1}, the cleared source set) bypass cache retention so
+// (psi^{n-1} and psi^{n+1}) bypass cache retention so
 // that the psi^n stencil planes stay in L2.
 typedef unsigned int nt_u32x4 __attribute__((ext_vector_type(4)));
 
@@ -286,7 +276,7 @@ struct SweepVec {
             return;  // grid larger than the tiling (never for the launchers here)
 
         const int64_t s = R.ctl->step;
-        const int set_r = (int)(s & 1), set_c = (int)((s + 1) & 1);
+        const int set_r = (int)(s & 1);
         const bool update = (comp < 3) || R.space_charge;
 
         const int lx = threadIdx.x % TXV, ly = threadIdx.x / TXV;
@@ -329,15 +319,10 @@ struct SweepVec {
 
         const int *rlo = R.ctl->dep_lo[set_r];
         const int *rhi = R.ctl->dep_hi[set_r];
-        const int *clo = R.ctl->dep_lo[set_c];
-        const int *chi = R.ctl->dep_hi[set_c];
         const bool src_col = rowvalid && i0 + V - 1 >= rlo[0] && i0 <= rhi[0] + 1 && j >= rlo[1] && j <= rhi[1] + 1;
-        const bool clr_col = rowvalid && i0 + V - 1 >= clo[0] && i0 <= chi[0] && j >= clo[1] && j <= chi[1];
         const int sk_lo = rlo[2], sk_hi = rhi[2] + 1;
         const T *J = src_ptr<T>(R, set_r, comp);
         const T *Jl = LO ? srclo_ptr<T>(R, set_r, comp) : nullptr;
-        T *clr = src_ptr<T>(R, set_c, comp);
-        T *clr_lo = LO ? srclo_ptr<T>(R, set_c, comp) : nullptr;
         const ST sfac = (ST)(comp < 3 ? 0.5 * R.sfac_A : R.sfac_phi);
 
         const T cA = (T)R.A, c1A = (T)(1.0 - 2.0 * R.A);
@@ -429,12 +414,6 @@ struct SweepVec {
                 for (int e = 0; e < V; ++e)
                     sv[e] = LO ? ((ST)ps.a.v[e] + (ST)ps.al.v[e]) + ((ST)ps.b.v[e] + (ST)ps.bl.v[e])
                                : (ST)ps.a.v[e] + (ST)ps.b.v[e];
-            }
-            if (clr_col && k >= clo[2] && k <= chi[2]) {
-                const Vec<T, V> z{};
-                vstore_nt<T, V>(clr + c, z);
-                if constexpr (LO)
-                    vstore_nt<T, V>(clr_lo + c, z);
             }
             T(*buf)[ROW] = sb[k & 1];
             Vec<T, V> bar;  // psi-bar, or (difference form) psi-bar - psi
@@ -701,13 +680,66 @@ __device__ inline uint32_t face_div(int64_t r, int64_t half, int d)
     return (uint32_t)(r / d);
 }
 
+// The source set that this step's deposit accumulates into is zeroed on the
+// node box of its previous deposit, every component.  The set was last read
+// by the previous step's sweep, and the deposit runs after this kernel.
+// One wavefront per x-row of the box; row indices are wavefront-uniform.
+template <typename T>
+__device__ inline void clear_next_sources(const RunDev &R, int64_t b, int64_t nb)
+{
+    const int64_t s = R.ctl->step;
+    const int set_c = (int)((s + 1) & 1);
+    const int *lo = R.ctl->dep_lo[set_c];
+    const int *hi = R.ctl->dep_hi[set_c];
+    const int l0 = lo[0], l1 = lo[1], l2 = lo[2];
+    const int ex = hi[0] - l0 + 1, ey = hi[1] - l1 + 1, ez = hi[2] - l2 + 1;
+    if (ex <= 0 || ey <= 0 || ez <= 0)
+        return;
+    const uint32_t rows = (uint32_t)ey * (uint32_t)ez;
+    const uint32_t nw = (uint32_t)nb * (blockDim.x / 64);
+    const uint32_t w0 = __builtin_amdgcn_readfirstlane((uint32_t)b * (blockDim.x / 64) + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    // row r = k ey + j; the stride nw advances (j, k) by (nw % ey, nw / ey)
+    // with a carry, so only the first row of a wavefront needs a division
+    const uint32_t dk = nw / (uint32_t)ey, dj = nw - dk * (uint32_t)ey;
+    const uint32_t k0 = w0 / (uint32_t)ey, j0 = w0 - k0 * (uint32_t)ey;
+    const int64_t sy = R.nx, sz = (int64_t)R.nx * R.ny;
+    for (int comp = 0; comp < 4; ++comp) {
+        T *dst = src_ptr<T>(R, set_c, comp) + nid(R, l0, l1, l2);
+        T *dlo = R.compensated ? srclo_ptr<T>(R, set_c, comp) + nid(R, l0, l1, l2) : nullptr;
+        uint32_t j = j0, k = k0;
+        for (uint32_t r = w0; r < rows; r += nw) {
+            const int64_t row = (int64_t)k * sz + (int64_t)j * sy;
+            for (int i = lane; i < ex; i += 64) {
+                dst[row + i] = (T)0;
+                if (dlo)
+                    dlo[row + i] = (T)0;
+            }
+            j += dj;
+            k += dk;
+            if (j >= (uint32_t)ey) {
+                j -= (uint32_t)ey;
+                ++k;
+            }
+        }
+    }
+}
+
+// workgroups that clear the next source set, after the Mur workgroups
+static __host__ __device__ inline int64_t clear_blocks_of(int ny, int nz)
+{
+    const int64_t r = (int64_t)ny * nz / 64;
+    return r < 8 ? 8 : (r > 1024 ? 1024 : r);
+}
+
 // Boundary nodes, one thread each (per component), in two groups:
 //  - face nodes that lie on one boundary only (z faces, y faces, and the x
 //    faces unless the vector sweep updated them), with direct strides;
 //  - edge and corner nodes, through the summed first-order conditions
 //    (solve_summed), which recompute the face values they need.
 // Face threads come first and are laid out x fastest, so their accesses
-// coalesce; the few edge threads take the general path.
+// coalesce; the few edge threads take the general path.  The workgroups
+// after the boundary ones clear the next source set (clear_next_sources).
 template <typename T>
 struct Mur {
     static constexpr int kThreads = 256;
@@ -719,8 +751,14 @@ struct Mur {
         const int64_t fx = R.xface_fused ? 0 : 2LL * (ny - 2) * (nz - 2);
         const int64_t ex = 4LL * nx, ey = 4LL * (ny - 2), ez = 4LL * (nz - 2);
         const int64_t nb = fz + fy + fx + ex + ey + ez;
-        // ceil(nb / 256) workgroups per component (component uniform per workgroup)
+        // ceil(nb / 256) workgroups per component (component uniform per
+        // workgroup), then the workgroups that clear the next source set
         const int64_t bpc = (nb + 255) / 256;
+        const int64_t nmur = bpc * (R.space_charge ? 4 : 3);
+        if (blk.id >= nmur) {
+            clear_next_sources<T>(R, blk.id - nmur, blk.n - nmur);
+            return;
+        }
         const int comp = (int)(blk.id / bpc);
         int64_t r = (blk.id - (int64_t)comp * bpc) * blockDim.x + threadIdx.x;
         if (r >= nb)
@@ -1061,9 +1099,15 @@ hipError_t launch_sweep(const RunDev &R, int shape, hipStream_t st)
     return R.precision == 32 ? launch_sweep_shape<float>(R, shape, st) : launch_sweep_shape<double>(R, shape, st);
 }
 
+// Mur workgroups (per component) plus the source-clearing workgroups
+int64_t mur_blocks(const RunDev &R)
+{
+    return ((mur_nodes(R) + 255) / 256) * (R.space_charge ? 4 : 3) + clear_blocks_of(R.ny, R.nz);
+}
+
 hipError_t launch_mur(const RunDev &R, hipStream_t st)
 {
-    const unsigned blocks = (unsigned)(((mur_nodes(R) + 255) / 256) * (R.space_charge ? 4 : 3));
+    const unsigned blocks = (unsigned)mur_blocks(R);
     if (R.precision == 32)
         hipLaunchKernelGGL((k_run<Mur<float>>), dim3(blocks), dim3(256), 0, st, R);
     else
@@ -1178,7 +1222,7 @@ hipError_t launch_sweep_group(const Group &g, int64_t total, int precision, int 
                            : grp_sweep<double>(g, total, shape, false, st);
 }
 
-int64_t mur_blocks(const RunDev &R) { return ((mur_nodes(R) + 255) / 256) * (R.space_charge ? 4 : 3); }
+
 
 hipError_t launch_mur_group(const Group &g, int64_t total, int precision, hipStream_t st)
 {

@@ -109,20 +109,46 @@ __device__ inline uint32_t sort_digit(const Ctl *ctl, uint32_t inactive, uint32_
     return (x >> shift) & 0xFF;
 }
 
+// Lanes of the calling wavefront whose digit equals this lane's (all lanes
+// must call it; lanes with ok == false match nothing and are matched by
+// nothing).
+__device__ inline uint64_t digit_peers(uint32_t d, bool ok)
+{
+    uint64_t peers = __ballot(ok);
+    for (int b = 0; b < 8; ++b) {
+        const uint64_t m = __ballot((d >> b) & 1);
+        peers &= ((d >> b) & 1) ? m : ~m;
+    }
+    return peers;
+}
+
+// Each wavefront of a block takes a contiguous quarter of the block's
+// chunk, 64 consecutive elements per iteration, and counts digits in a
+// histogram of its own with LDS atomics whose results nothing waits for.
 __device__ inline void radix_hist_blk(const uint32_t *keys, int64_t n, int shift, uint32_t *hist, int64_t nblocks,
                                       int64_t bid, const Ctl *ctl, uint32_t inactive)
 {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)bid * kSortChunk;
+    constexpr int kWaves = kSortThreads / 64;
+    __shared__ uint32_t wh[kWaves][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int w = 0; w < kWaves; ++w)
+        wh[w][threadIdx.x] = 0;
+    const int64_t wbase = (int64_t)bid * kSortChunk + (int64_t)wave * (kSortChunk / kWaves);
+    uint32_t k[kSortItems];
     for (int it = 0; it < kSortItems; ++it) {
-        const int64_t e = base + (int64_t)it * kSortThreads + threadIdx.x;
-        if (e < n)
-            atomicAdd(&h[sort_digit(ctl, inactive, keys[e], shift)], 1u);
+        const int64_t e = wbase + 64 * it + lane;
+        k[it] = e < n ? keys[e] : 0u;
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + bid] = h[threadIdx.x];
+    for (int it = 0; it < kSortItems; ++it) {
+        if (wbase + 64 * it + lane < n)
+            atomicAdd(&wh[wave][sort_digit(ctl, inactive, k[it], shift)], 1u);
+    }
+    __syncthreads();
+    uint32_t c = 0;
+    for (int w = 0; w < kWaves; ++w)
+        c += wh[w][threadIdx.x];
+    hist[(int64_t)threadIdx.x * nblocks + bid] = c;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t *keys, int64_t n, int shift, uint32_t *hist,
@@ -187,20 +213,36 @@ __device__ inline void radix_scatter_blk(const uint32_t *keys_in, const int32_t 
                                          int32_t *vals_out, int64_t n, int shift, const uint32_t *offs, int64_t nblocks,
                                          const uint32_t *tot, int64_t bid, const Ctl *ctl, uint32_t inactive)
 {
-    // The block's kSortChunk elements are ranked stably by digit into LDS
-    // (block-local sorted order), then written out in that order: each digit
-    // run is one contiguous range of the output, so consecutive threads
-    // write consecutive addresses.
-    __shared__ uint32_t gbase[256];   // output position of the block's first element of each digit
-    __shared__ uint32_t lstart[256];  // local position of the same
-    __shared__ uint32_t lrun[256];    // elements of each digit placed so far
-    __shared__ uint32_t wcnt[kSortThreads / 64][256];
+    // The block's kSortChunk elements are held in registers, each wavefront
+    // a contiguous quarter of the chunk.  A wavefront ranks its elements
+    // among equal digits with ballots and a digit counter of its own, which
+    // needs no barrier; the counters of the four wavefronts then give each
+    // wavefront its start inside every digit's run of the block, in element
+    // order.  The elements go to LDS in block-local sorted order and are
+    // written out in that order: each digit run is one contiguous range of
+    // the output, so consecutive threads write consecutive addresses.
+    constexpr int kWaves = kSortThreads / 64;
+    __shared__ uint32_t gbase[256];       // output position of the block's first element of each digit
+    __shared__ uint32_t lstart[256];      // local position of the same
+    __shared__ uint32_t wc[kWaves][256];  // per-wavefront digit counts, then starts
+    __shared__ uint32_t scan_tmp[2][kWaves];
     __shared__ uint32_t skey[kSortChunk];
     __shared__ int32_t sval[kSortChunk];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t base = (int64_t)bid * kSortChunk;
     const int64_t cnt = min((int64_t)kSortChunk, n - base);
+    const int64_t wbase = base + (int64_t)wave * (kSortChunk / kWaves);
+    uint32_t k[kSortItems];
+    int32_t v[kSortItems];
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t e = wbase + 64 * it + lane;
+        const bool ok = e < n;
+        k[it] = ok ? keys_in[e] : 0u;
+        v[it] = ok ? (vals_in ? vals_in[e] : (int32_t)e) : 0;
+    }
+    for (int w = 0; w < kWaves; ++w)
+        wc[w][threadIdx.x] = 0;
     {
         const int d = threadIdx.x;
         const uint32_t o = offs[(int64_t)d * nblocks + bid];
@@ -217,59 +259,61 @@ __device__ inline void radix_scatter_blk(const uint32_t *keys_in, const int32_t 
             }
         }
         if (lane == 63) {
-            wcnt[0][wave] = inc;
-            wcnt[1][wave] = linc;
+            scan_tmp[0][wave] = inc;
+            scan_tmp[1][wave] = linc;
         }
         __syncthreads();
         uint32_t wb = 0, lwb = 0;
         for (int w = 0; w < wave; ++w) {
-            wb += wcnt[0][w];
-            lwb += wcnt[1][w];
+            wb += scan_tmp[0][w];
+            lwb += scan_tmp[1][w];
         }
         gbase[d] = wb + inc - t + o;
         lstart[d] = lwb + linc - mine;
-        lrun[d] = 0;
-        __syncthreads();
     }
+    // Rank within the wavefront: position among the wavefront's earlier
+    // elements of the same digit.  The lowest lane of each group of equal
+    // digits adds the group's size to the wavefront's counter and gets the
+    // count before it; LDS executes one wavefront's atomics in issue order,
+    // so all 16 can be in flight before the first result is used.
+    // dp: digit (bits 0-7), leader lane (8-13), rank in the group (14-20).
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    uint32_t dp[kSortItems], before[kSortItems];
     for (int it = 0; it < kSortItems; ++it) {
-        for (int w = 0; w < kSortThreads / 64; ++w)
-            wcnt[w][threadIdx.x] = 0;
-        const int64_t e = base + (int64_t)it * kSortThreads + threadIdx.x;
-        const bool ok = e < n;
-        uint32_t key = 0;
-        int32_t val = 0;
-        uint32_t d = 0;
-        if (ok) {
-            key = keys_in[e];
-            val = vals_in ? vals_in[e] : (int32_t)e;
-            d = sort_digit(ctl, inactive, key, shift);
-        }
-        // lanes of this wavefront holding the same digit
-        uint64_t peers = __ballot(ok);
-        for (int b = 0; b < 8; ++b) {
-            const uint64_t m = __ballot((d >> b) & 1);
-            peers &= ((d >> b) & 1) ? m : ~m;
-        }
-        __syncthreads();
-        const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (ok && rank == 0)
-            wcnt[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (ok) {
-            uint32_t pos = lstart[d] + lrun[d] + rank;
-            for (int w = 0; w < wave; ++w)
-                pos += wcnt[w][d];
-            skey[pos] = key;
-            sval[pos] = val;
-        }
-        __syncthreads();
-        uint32_t add = 0;
-        for (int w = 0; w < kSortThreads / 64; ++w)
-            add += wcnt[w][threadIdx.x];
-        lrun[threadIdx.x] += add;
-        __syncthreads();
+        const bool ok = wbase + 64 * it + lane < n;
+        const uint32_t d = ok ? sort_digit(ctl, inactive, k[it], shift) : 0u;
+        const uint64_t peers = digit_peers(d, ok);
+        const uint32_t r = (uint32_t)__popcll(peers & lt);
+        const uint32_t leader = peers ? (uint32_t)__builtin_ctzll(peers) : 0u;
+        before[it] = 0;
+        if (ok && r == 0)
+            before[it] = atomicAdd(&wc[wave][d], (uint32_t)__popcll(peers));
+        dp[it] = (r << 14) | (leader << 8) | d;
     }
+    for (int it = 0; it < kSortItems; ++it) {
+        const uint32_t b = (uint32_t)__shfl((int)before[it], (int)((dp[it] >> 8) & 63));
+        dp[it] = ((b + (dp[it] >> 14)) << 8) | (dp[it] & 0xFF);
+    }
+    __syncthreads();
+    {
+        // per digit: start of each wavefront's elements inside the block's run
+        const int d = threadIdx.x;
+        uint32_t run = lstart[d];
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = wc[w][d];
+            wc[w][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int it = 0; it < kSortItems; ++it) {
+        if (wbase + 64 * it + lane < n) {
+            const uint32_t p = wc[wave][dp[it] & 0xFF] + (dp[it] >> 8);
+            skey[p] = k[it];
+            sval[p] = v[it];
+        }
+    }
+    __syncthreads();
     // block-local sorted order -> output, digit runs contiguous
     for (int64_t i = threadIdx.x; i < cnt; i += kSortThreads) {
         const uint32_t key = skey[i];
