@@ -388,7 +388,19 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
         const int cells = (a == 0 ? d->nx : (a == 1 ? d->ny : d->nz)) - 1;
         R.ntile[a] = (cells + d->tile[a] - 1) / d->tile[a];
     }
-    R.key_inactive = (uint32_t)R.ntile[0] * R.ntile[1] * R.ntile[2] * (uint32_t)(d->tile[0] * d->tile[1] * d->tile[2]);
+    {
+        // one past the largest active key: the key of the active cell
+        // (n-3, n-3, n-3), which lies in the last tile of every axis at the
+        // largest local offset (keys grow with each tile and local coordinate);
+        // the smallest value keeps the radix sort to the fewest passes
+        const int last[3] = {d->nx - 3, d->ny - 3, d->nz - 3};
+        uint32_t tl = 0, loc = 0;
+        for (int a = 2; a >= 0; --a) {
+            tl = tl * (uint32_t)R.ntile[a] + (uint32_t)(last[a] / R.tile[a]);
+            loc = loc * (uint32_t)R.tile[a] + (uint32_t)(last[a] % R.tile[a]);
+        }
+        R.key_inactive = tl * (uint32_t)(R.tile[0] * R.tile[1] * R.tile[2]) + loc + 1;
+    }
 
     char *A = h->arena;
     const Layout &L = h->L;

@@ -278,24 +278,36 @@ __global__ __launch_bounds__(F::kThreads) __attribute__((amdgpu_waves_per_eu(Wav
     F::run(R, Blk{id, G.nblk[m]}, a...);
 }
 
+// Tile-major sort key of an active cell c (see k_sort.hip for the order).
+__device__ inline uint32_t key_of_cell(const RunDev &R, const int c[3])
+{
+    const int Tx = R.tile[0], Ty = R.tile[1], Tz = R.tile[2];
+    const uint32_t tl = ((uint32_t)(c[2] / Tz) * (uint32_t)R.ntile[1] + (uint32_t)(c[1] / Ty)) * (uint32_t)R.ntile[0] +
+                        (uint32_t)(c[0] / Tx);
+    const uint32_t loc = ((uint32_t)(c[2] % Tz) * Ty + (uint32_t)(c[1] % Ty)) * Tx + (uint32_t)(c[0] % Tx);
+    return tl * (uint32_t)(Tx * Ty * Tz) + loc;
+}
+
 // Offset and pass count of the current sort, from the box of the active
-// cells: active keys lie between the keys of the box's first and last tiles
-// (the key is increasing in each tile coordinate).  One thread.
+// cells: active keys lie between the first key of the box's first tile and
+// the key of the box's high corner (the key is increasing in each tile
+// coordinate and in each offset inside a tile).  Inactive particles sort as
+// one past that range.  One thread.
 __device__ inline void sort_range(const RunDev &R)
 {
     Ctl *c = R.ctl;
     uint32_t base = 0, span = 0;
     if (c->cell_hi[0] >= c->cell_lo[0] && c->cell_hi[1] >= c->cell_lo[1] && c->cell_hi[2] >= c->cell_lo[2]) {
         const uint32_t vol = (uint32_t)(R.tile[0] * R.tile[1] * R.tile[2]);
-        uint32_t t0[3], t1[3];
-        for (int a = 0; a < 3; ++a) {
+        uint32_t t0[3];
+        for (int a = 0; a < 3; ++a)
             t0[a] = (uint32_t)(c->cell_lo[a] / R.tile[a]);
-            t1[a] = (uint32_t)(c->cell_hi[a] / R.tile[a]);
-        }
         const uint32_t l0 = (t0[2] * (uint32_t)R.ntile[1] + t0[1]) * (uint32_t)R.ntile[0] + t0[0];
-        const uint32_t l1 = (t1[2] * (uint32_t)R.ntile[1] + t1[1]) * (uint32_t)R.ntile[0] + t1[0];
         base = l0 * vol;
-        span = (l1 + 1) * vol - base;
+        // the box's largest key is that of its high corner (the corner's
+        // tile and its offset inside that tile are the largest in each axis)
+        const int hi[3] = {c->cell_hi[0], c->cell_hi[1], c->cell_hi[2]};
+        span = key_of_cell(R, hi) + 1u - base;
     }
     int bits = 0;
     while (bits < 32 && (span >> bits) != 0)
@@ -305,16 +317,6 @@ __device__ inline void sort_range(const RunDev &R)
     c->key_span = span;
     c->npass = np;
     c->sorted_buf = (np - 1) & 1;
-}
-
-// Tile-major sort key of an active cell c (see k_sort.hip for the order).
-__device__ inline uint32_t key_of_cell(const RunDev &R, const int c[3])
-{
-    const int Tx = R.tile[0], Ty = R.tile[1], Tz = R.tile[2];
-    const uint32_t tl = ((uint32_t)(c[2] / Tz) * (uint32_t)R.ntile[1] + (uint32_t)(c[1] / Ty)) * (uint32_t)R.ntile[0] +
-                        (uint32_t)(c[0] / Tx);
-    const uint32_t loc = ((uint32_t)(c[2] % Tz) * Ty + (uint32_t)(c[1] % Ty)) * Tx + (uint32_t)(c[0] % Tx);
-    return tl * (uint32_t)(Tx * Ty * Tz) + loc;
 }
 
 }  // namespace mithra
