@@ -220,6 +220,19 @@ int mithra_batch_create(const mithra_handle *runs, int32_t n_runs, void *dev_wor
  * batched step and returns without waiting.  Errors: EINVAL, EDEVICE. */
 int mithra_batch_run(mithra_batch b, const int64_t *n_steps);
 
+/* Choose the sweep tile shape of the batch's members with the whole batch
+ * on the device: per member class (precision, compensation), every shape is
+ * timed as the class's grouped sweep and Mur launches (`iters` >= 1 timed
+ * repetitions after one warm-up), the fastest is kept for all members of
+ * the class, and the batched step is captured again.  A small grid timed
+ * alone (mithra_autotune_sweep) leaves most of the GPU idle, so the two
+ * choices differ.  The runs' state is unchanged (sweep and Mur only
+ * rewrite the next time level and re-clear the next source set).  Waits
+ * for the batch's previous work.  If `shapes_out` is not NULL it receives
+ * each member's shape (n_runs entries).  Errors: EINVAL, ENOMEM, EDEVICE;
+ * after an error, destroy the batch. */
+int mithra_batch_autotune_sweep(mithra_batch b, int iters, int32_t *shapes_out);
+
 /* Wait for the batch's enqueued work. */
 int mithra_batch_sync(mithra_batch b);
 

@@ -1331,6 +1331,115 @@ extern "C" int mithra_batch_create(const mithra_handle *runs, int32_t n_runs, vo
     return MITHRA_OK;
 }
 
+// Member shape and the x-face flag it implies; the member's own graphs,
+// captured with the old shape, are dropped.
+static void member_set_shape(mithra_handle h, int shape)
+{
+    h->sweep_shape = shape;
+    h->R.xface_fused = sweep_fuses_xfaces(h->R, shape);
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    if (h->graph8) {
+        (void)hipGraphExecDestroy(h->graph8);
+        h->graph8 = nullptr;
+    }
+}
+
+static int rebuild_tables(mithra_batch b)
+{
+    b->ws_used = 0;
+    b->sweep.clear();
+    return build_tables(b);
+}
+
+// Per member class (precision, compensation), time every sweep tile shape
+// as the class's grouped sweep and Mur launches with the whole batch on the
+// device, and keep the fastest.  A small grid timed alone leaves most of the
+// GPU idle, so the shape that wins alone is often not the one that wins in a
+// full batch.  Sweep and Mur only rewrite the next time level and re-clear
+// the next source set, so the runs' state is unchanged.
+extern "C" int mithra_batch_autotune_sweep(mithra_batch b, int iters, int32_t *shapes_out)
+{
+    if (!b || iters < 1)
+        return MITHRA_EINVAL;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    const int n = (int)b->runs.size();
+    // let every member's kernels run while timing, and none afterwards
+    const int64_t open = INT64_MAX;
+    for (auto h : b->runs)
+        BHIPCHK(b, hipMemcpy(&h->R.ctl->target, &open, sizeof(int64_t), hipMemcpyHostToDevice));
+    std::map<std::pair<int, int>, std::vector<int>> cls;
+    for (int i = 0; i < n; ++i)
+        cls[{b->runs[i]->R.precision, b->runs[i]->R.compensated}].push_back(i);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BHIPCHK(b, hipEventCreate(&e0));
+    BHIPCHK(b, hipEventCreate(&e1));
+    int rc = MITHRA_OK;
+    for (auto &kv : cls) {
+        const int prec = kv.first.first, comp = kv.first.second;
+        const int V = prec == 32 ? 4 : 2;
+        bool any_vec = false;
+        for (int i : kv.second)
+            any_vec = any_vec || b->runs[i]->R.nx % V == 0;
+        int best = b->runs[kv.second[0]]->sweep_shape;
+        float best_t = 1e30f;
+        for (int sh = 0; sh < sweep_shape_count() && !rc; ++sh) {
+            if (sh >= 8 && !any_vec)
+                continue;  // every member would fall back to shape 0
+            for (int i : kv.second)
+                member_set_shape(b->runs[i], sh);
+            rc = rebuild_tables(b);
+            if (rc)
+                break;
+            auto launch = [&]() -> int {
+                for (auto &c : b->sweep)
+                    if (c.precision == prec && c.comp == comp)
+                        BHIPCHK(b, launch_sweep_group(c.t.g, c.t.total, c.precision, c.comp, c.shape, b->stream));
+                const int pi = prec == 32 ? 0 : 1;
+                BHIPCHK(b, launch_mur_group(b->mur[pi].g, b->mur[pi].total, prec, b->stream));
+                return MITHRA_OK;
+            };
+            rc = launch();  // warm
+            BHIPCHK(b, hipEventRecord(e0, b->stream));
+            for (int it = 0; it < iters && !rc; ++it)
+                rc = launch();
+            BHIPCHK(b, hipEventRecord(e1, b->stream));
+            BHIPCHK(b, hipEventSynchronize(e1));
+            float t = 0.f;
+            BHIPCHK(b, hipEventElapsedTime(&t, e0, e1));
+            if (!rc && t < best_t) {
+                best_t = t;
+                best = sh;
+            }
+        }
+        if (rc)
+            break;
+        for (int i : kv.second)
+            member_set_shape(b->runs[i], best);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (auto h : b->runs)
+        BHIPCHK(b, hipMemcpy(&h->R.ctl->target, &h->steps, sizeof(int64_t), hipMemcpyHostToDevice));
+    if (!rc)
+        rc = rebuild_tables(b);
+    if (!rc) {
+        if (b->graph) {
+            (void)hipGraphExecDestroy(b->graph);
+            b->graph = nullptr;
+        }
+        rc = build_batch_graph(b);
+    }
+    if (rc)
+        return rc;
+    if (shapes_out)
+        for (int i = 0; i < n; ++i)
+            shapes_out[i] = b->runs[i]->sweep_shape;
+    return MITHRA_OK;
+}
+
 extern "C" int mithra_batch_run(mithra_batch b, const int64_t *n_steps)
 {
     if (!b || !n_steps)

@@ -250,18 +250,22 @@ struct PlaneSrc {
 template <typename T, int V, int TXV, int TY, int TZ, bool LO>
 struct SweepVec {
     static constexpr int kThreads = TXV * TY;
-    static __device__ void run(const RunDev &R, Blk blk)
-    {
-        constexpr int TW = TXV * V;                          // tile width in nodes
-        constexpr int ROW = ((V + TW + 1) + V - 1) / V * V;  // LDS row: pad(V-1), left halo, tile, right halo
-        // source sums: FP64 for FP64 fields and for compensated FP32 (hi + lo)
-        using ST = typename std::conditional<LO || sizeof(T) == 8, double, T>::type;
-        __shared__ __attribute__((aligned(16))) T sb[2][TY + 2][ROW];
+    static_assert(TZ % 4 == 0, "planes are processed four at a time");
+    static constexpr int TW = TXV * V;                          // tile width in nodes
+    static constexpr int ROW = ((V + TW + 1) + V - 1) / V * V;  // LDS row: pad(V-1), left halo, tile, right halo
+    // source sums: FP64 for FP64 fields and for compensated FP32 (hi + lo)
+    using ST = typename std::conditional<LO || sizeof(T) == 8, double, T>::type;
+    struct Lds {
+        __attribute__((aligned(16))) T sb[2][TY + 2][ROW];
         // difference form (FP32): psi-bar - psi of the same node
-        __shared__ __attribute__((aligned(16))) T sbc[kDiffForm<T> ? 2 : 1][kDiffForm<T> ? TY + 2 : 1][ROW];
+        __attribute__((aligned(16))) T sbc[kDiffForm<T> ? 2 : 1][kDiffForm<T> ? TY + 2 : 1][ROW];
         // psi^n at the two outermost nodes of each row end (x-face update)
-        __shared__ T rawe[2][TY + 2][4];
+        T rawe[2][TY + 2][4];
+    };
 
+    static __device__ __attribute__((always_inline)) void run(const RunDev &R, Blk blk)
+    {
+        __shared__ Lds L;
         const int ntx = (R.nx + TW - 1) / TW;
         const int nty = (R.ny + TY - 1) / TY;
         const int nch = (R.nz - 2 + TZ - 1) / TZ;
@@ -274,25 +278,41 @@ struct SweepVec {
         const int comp = (int)(lb / nch);
         if (comp >= 4)
             return;  // grid larger than the tiling (never for the launchers here)
+        if (comp == 3 && !R.space_charge)
+            return;  // phi is not advanced without space charge (uniform per workgroup)
+        // the component is a compile-time constant inside the body, so the
+        // source loads of the other components do not exist there
+        switch (comp) {
+        case 0: body<0>(R, L, tile_x, tile_y, chunk); break;
+        case 1: body<1>(R, L, tile_x, tile_y, chunk); break;
+        case 2: body<2>(R, L, tile_x, tile_y, chunk); break;
+        default: body<3>(R, L, tile_x, tile_y, chunk); break;
+        }
+    }
 
+    template <int COMP>
+    static __device__ __attribute__((always_inline)) void body(const RunDev &R, Lds &L, int tile_x, int tile_y,
+                                                               int chunk)
+    {
         const int64_t s = R.ctl->step;
         const int set_r = (int)(s & 1);
-        const bool update = (comp < 3) || R.space_charge;
 
         const int lx = threadIdx.x % TXV, ly = threadIdx.x / TXV;
         const int i0 = tile_x * TW + lx * V;  // first node of this thread
         const int j = tile_y * TY + ly;
         const bool inb = (i0 < R.nx) && (j < R.ny);
-        const bool rowvalid = inb && j >= 1 && j <= R.ny - 2;
-        const bool work = rowvalid && update;
+        const bool work = inb && j >= 1 && j <= R.ny - 2;
         const int64_t plane = (int64_t)R.nx * R.ny;
         const int64_t col = inb ? ((int64_t)j * R.nx + i0) : 0;
 
-        // halo: bottom/top rows (vector, TXV threads each), left/right columns
-        // (scalar, TY threads each)
+        // Halo: bottom/top rows (TXV threads each), left/right columns (TY
+        // threads each).  Every thread issues one aligned 16-byte halo load
+        // per plane, so that no load is conditional: a column thread loads
+        // the vector holding its node (element hsel), a thread without a
+        // halo node reloads its own vector.
         const int t = threadIdx.x;
-        int hrole = -1, hx = 0, hy = 0;
-        int64_t hcol = 0;
+        int hrole = -1, hx = 0, hy = 0, hsel = 0;
+        int64_t hv = col;
         bool hval = false;
         if (t < 2 * TXV) {
             hrole = 0;
@@ -300,7 +320,8 @@ struct SweepVec {
             hy = t < TXV ? -1 : TY;
             const int hi_ = tile_x * TW + hx, hj_ = tile_y * TY + hy;
             hval = hj_ >= 0 && hj_ < R.ny && hi_ < R.nx;
-            hcol = hval ? (int64_t)hj_ * R.nx + hi_ : 0;
+            if (hval)
+                hv = (int64_t)hj_ * R.nx + hi_;
         } else if (t < 2 * TXV + 2 * TY) {
             hrole = 1;
             const int u = t - 2 * TXV;
@@ -308,102 +329,90 @@ struct SweepVec {
             hx = u < TY ? -1 : TW;
             const int hi_ = tile_x * TW + hx, hj_ = tile_y * TY + hy;
             hval = hi_ >= 0 && hi_ < R.nx && hj_ < R.ny;
-            hcol = hval ? (int64_t)hj_ * R.nx + hi_ : 0;
+            hsel = hx < 0 ? V - 1 : 0;
+            if (hval)
+                hv = (int64_t)hj_ * R.nx + hi_ - hsel;
         }
 
         const int kb = 1 + chunk * TZ;
         const int ke = min(kb + TZ, R.nz - 1);
-        const T *cur = pot_ptr<T>(R, slot_cur(s), comp);
-        const T *prev = pot_ptr<T>(R, slot_prev(s), comp);
-        T *next = pot_ptr<T>(R, slot_next(s), comp);
+        const T *cur = pot_ptr<T>(R, slot_cur(s), COMP);
+        const T *prev = pot_ptr<T>(R, slot_prev(s), COMP);
+        T *next = pot_ptr<T>(R, slot_next(s), COMP);
 
         const int *rlo = R.ctl->dep_lo[set_r];
         const int *rhi = R.ctl->dep_hi[set_r];
-        const bool src_col = rowvalid && i0 + V - 1 >= rlo[0] && i0 <= rhi[0] + 1 && j >= rlo[1] && j <= rhi[1] + 1;
+        const bool src_col = work && i0 + V - 1 >= rlo[0] && i0 <= rhi[0] + 1 && j >= rlo[1] && j <= rhi[1] + 1;
         const int sk_lo = rlo[2], sk_hi = rhi[2] + 1;
-        const T *J = src_ptr<T>(R, set_r, comp);
-        const T *Jl = LO ? srclo_ptr<T>(R, set_r, comp) : nullptr;
-        const ST sfac = (ST)(comp < 3 ? 0.5 * R.sfac_A : R.sfac_phi);
+        const T *J = src_ptr<T>(R, set_r, COMP);
+        const T *Jl = LO ? srclo_ptr<T>(R, set_r, COMP) : nullptr;
+        const ST sfac = (ST)(COMP < 3 ? 0.5 * R.sfac_A : R.sfac_phi);
 
         const T cA = (T)R.A, c1A = (T)(1.0 - 2.0 * R.A);
         const T a1 = (T)R.a1, a2 = (T)R.a2, a4 = (T)R.a4, a6 = (T)R.a6;
         const T rx2 = (T)R.rx2, ry2 = (T)R.ry2, rz2 = (T)R.rz2;
+        const int kmax = R.nz - 1;
 
-        // psi^{n-1} and the sources of plane kk; the z component's back edge is
-        // the previous plane's own edge, carried in registers (zero below the
-        // source box, where the source is zero)
-        auto fetch = [&](int kk, const PlaneSrc<T, V, LO> &prv) {
-            PlaneSrc<T, V, LO> r{};
-            if (!work)
-                return r;
+        // psi^n of plane kk (own vector and halo vector); every plane index
+        // is clamped into the array, so the loads need no guard
+        auto load_cur = [&](int kk, Vec<T, V> &q, Vec<T, V> &h) {
+            const int64_t o = (int64_t)min(kk, kmax) * plane;
+            q = vload<T, V>(cur + o + col);
+            h = vload<T, V>(cur + o + hv);
+        };
+        // psi^{n-1} and the sources of plane kk (kk <= nz - 1).  Outside the
+        // source box the source loads read node 0, which no deposit reaches
+        // and which therefore holds zero; the z component's back edge is the
+        // previous plane's own edge, carried in registers.
+        auto fetch = [&](int kk, const PlaneSrc<T, V, LO> &prv, PlaneSrc<T, V, LO> &r) {
             const int64_t c = (int64_t)kk * plane + col;
             r.pm = vload_nt<T, V>(prev + c);
-            if (src_col && kk >= sk_lo && kk <= sk_hi) {
-                r.a = vload<T, V>(J + c);
+            const bool in = src_col && kk >= sk_lo && kk <= sk_hi;
+            const int64_t ca = in ? c : 0;
+            r.a = vload<T, V>(J + ca);
+            if constexpr (LO)
+                r.al = vload<T, V>(Jl + ca);
+            if constexpr (COMP == 0) {
+                const int64_t cl = in ? c - 1 : 0;
+                r.lf = J[cl];
                 if constexpr (LO)
-                    r.al = vload<T, V>(Jl + c);
-                if (comp == 0) {
-                    r.lf = J[c - 1];
+                    r.lfl = Jl[cl];
+            } else if constexpr (COMP == 1) {
+                const int64_t cb = in ? c - R.nx : 0;
+                r.b = vload<T, V>(J + cb);
+                if constexpr (LO)
+                    r.bl = vload<T, V>(Jl + cb);
+            } else if constexpr (COMP == 2) {
+                if (kk > kb) {
+                    r.b = prv.a;
                     if constexpr (LO)
-                        r.lfl = Jl[c - 1];
-                } else if (comp == 1) {
-                    r.b = vload<T, V>(J + c - R.nx);
-                    if constexpr (LO)
-                        r.bl = vload<T, V>(Jl + c - R.nx);
-                } else if (comp == 2) {
-                    if (kk > kb && kk - 1 >= sk_lo) {
-                        r.b = prv.a;
                         r.bl = prv.al;
-                    } else {
-                        r.b = vload<T, V>(J + c - plane);
-                        if constexpr (LO)
-                            r.bl = vload<T, V>(Jl + c - plane);
-                    }
+                } else {
+                    const int64_t cb = in ? c - plane : 0;
+                    r.b = vload<T, V>(J + cb);
+                    if constexpr (LO)
+                        r.bl = vload<T, V>(Jl + cb);
                 }
             }
-            return r;
         };
 
-        Vec<T, V> qm{}, q0{}, qp{}, hm{}, h0{}, hp{};
-        if (inb) {
-            qm = vload<T, V>(cur + (int64_t)(kb - 1) * plane + col);
-            q0 = vload<T, V>(cur + (int64_t)kb * plane + col);
-            qp = vload<T, V>(cur + (int64_t)(kb + 1) * plane + col);
-        }
-        if (hval) {
-            if (hrole == 0) {
-                hm = vload<T, V>(cur + (int64_t)(kb - 1) * plane + hcol);
-                h0 = vload<T, V>(cur + (int64_t)kb * plane + hcol);
-                hp = vload<T, V>(cur + (int64_t)(kb + 1) * plane + hcol);
-            } else {
-                hm.v[0] = cur[(int64_t)(kb - 1) * plane + hcol];
-                h0.v[0] = cur[(int64_t)kb * plane + hcol];
-                hp.v[0] = cur[(int64_t)(kb + 1) * plane + hcol];
-            }
-        }
-        PlaneSrc<T, V, LO> ps = fetch(kb, PlaneSrc<T, V, LO>{});
-
-        for (int k = kb; k < ke; ++k) {
+        // Plane k from the psi^n planes k-1, k, k+1 (qm, q0, qp; halo hm,
+        // h0, hp) and the psi^{n-1} / source plane ps; the loads of plane
+        // k+2 (pf, hpf) and of plane k+1 (pn) are issued first.  The caller
+        // rotates the roles of the variables instead of copying them, so a
+        // prefetch stays in flight across planes.  Planes at or beyond ke
+        // (only in the last chunk) are computed and not stored.
+        auto plane_step = [&](int k, const Vec<T, V> &qm, const Vec<T, V> &q0, const Vec<T, V> &qp, Vec<T, V> &pf,
+                              const Vec<T, V> &hm, const Vec<T, V> &h0, const Vec<T, V> &hp, Vec<T, V> &hpf,
+                              const PlaneSrc<T, V, LO> &ps, PlaneSrc<T, V, LO> &pn) {
             const int64_t c = (int64_t)k * plane + col;
-            // prefetch: psi^n two planes up, psi^{n-1} and sources one plane up
-            Vec<T, V> pf{}, hpf{};
-            PlaneSrc<T, V, LO> pn{};
-            if (k + 1 < ke) {
-                if (inb)
-                    pf = vload<T, V>(cur + c + 2 * plane);
-                if (hval) {
-                    if (hrole == 0)
-                        hpf = vload<T, V>(cur + (int64_t)(k + 2) * plane + hcol);
-                    else
-                        hpf.v[0] = cur[(int64_t)(k + 2) * plane + hcol];
-                }
-                pn = fetch(k + 1, ps);
-            }
+            load_cur(k + 2, pf, hpf);
+            fetch(min(k + 1, kmax), ps, pn);
             ST sv[V];
-            if (comp == 3) {
+            if constexpr (COMP == 3) {
                 for (int e = 0; e < V; ++e)
                     sv[e] = (ST)ps.a.v[e] + (LO ? (ST)ps.al.v[e] : (ST)0);
-            } else if (comp == 0) {
+            } else if constexpr (COMP == 0) {
                 ST left = (ST)ps.lf + (LO ? (ST)ps.lfl : (ST)0);
                 for (int e = 0; e < V; ++e) {
                     const ST own = (ST)ps.a.v[e] + (LO ? (ST)ps.al.v[e] : (ST)0);
@@ -415,10 +424,13 @@ struct SweepVec {
                     sv[e] = LO ? ((ST)ps.a.v[e] + (ST)ps.al.v[e]) + ((ST)ps.b.v[e] + (ST)ps.bl.v[e])
                                : (ST)ps.a.v[e] + (ST)ps.b.v[e];
             }
-            T(*buf)[ROW] = sb[k & 1];
+            T(*buf)[ROW] = L.sb[k & 1];
+            // a column thread's halo node is element hsel of its vector
+            const bool hl = hsel != 0;
+            const T h0s = hl ? h0.v[V - 1] : h0.v[0], hms = hl ? hm.v[V - 1] : hm.v[0], hps = hl ? hp.v[V - 1] : hp.v[0];
             Vec<T, V> bar;  // psi-bar, or (difference form) psi-bar - psi
             if constexpr (kDiffForm<T>) {
-                T(*cbuf)[ROW] = sbc[k & 1];
+                T(*cbuf)[ROW] = L.sbc[k & 1];
                 for (int e = 0; e < V; ++e)
                     bar.v[e] = cA * ((qm.v[e] - q0.v[e]) + (qp.v[e] - q0.v[e]));
                 vstore<T, V>(&buf[ly + 1][V + lx * V], q0);
@@ -430,8 +442,8 @@ struct SweepVec {
                     vstore<T, V>(&buf[hy + 1][V + hx], h0);
                     vstore<T, V>(&cbuf[hy + 1][V + hx], hb);
                 } else if (hrole == 1) {
-                    buf[hy + 1][V + hx] = h0.v[0];
-                    cbuf[hy + 1][V + hx] = cA * ((hm.v[0] - h0.v[0]) + (hp.v[0] - h0.v[0]));
+                    buf[hy + 1][V + hx] = h0s;
+                    cbuf[hy + 1][V + hx] = cA * ((hms - h0s) + (hps - h0s));
                 }
             } else {
                 for (int e = 0; e < V; ++e)
@@ -443,11 +455,11 @@ struct SweepVec {
                         hb.v[e] = cA * (hm.v[e] + hp.v[e]) + c1A * h0.v[e];
                     vstore<T, V>(&buf[hy + 1][V + hx], hb);
                 } else if (hrole == 1) {
-                    buf[hy + 1][V + hx] = cA * (hm.v[0] + hp.v[0]) + c1A * h0.v[0];
+                    buf[hy + 1][V + hx] = cA * (hms + hps) + c1A * h0s;
                 }
             }
-            if (R.xface_fused) {
-                T(*raw)[4] = rawe[k & 1];
+            {
+                T(*raw)[4] = L.rawe[k & 1];
                 if (inb && i0 == 0) {
                     raw[ly + 1][0] = q0.v[0];
                     raw[ly + 1][1] = q0.v[1];
@@ -469,14 +481,14 @@ struct SweepVec {
                 }
             }
             __syncthreads();
-            if (work) {
+            if (work && k < ke) {
                 const T left = buf[ly + 1][V + lx * V - 1];
                 const T right = buf[ly + 1][V + lx * V + V];
                 const Vec<T, V> dn = vload<T, V>(&buf[ly][V + lx * V]);
                 const Vec<T, V> up = vload<T, V>(&buf[ly + 2][V + lx * V]);
                 Vec<T, V> out;
                 if constexpr (kDiffForm<T>) {
-                    T(*cbuf)[ROW] = sbc[k & 1];
+                    T(*cbuf)[ROW] = L.sbc[k & 1];
                     const T cleft = cbuf[ly + 1][V + lx * V - 1];
                     const T cright = cbuf[ly + 1][V + lx * V + V];
                     const Vec<T, V> cdn = vload<T, V>(&cbuf[ly][V + lx * V]);
@@ -498,20 +510,18 @@ struct SweepVec {
                                    a6 * (qp.v[e] + qm.v[e]) - ps.pm.v[e] + (T)(sfac * sv[e]);
                     }
                 }
-                // the x-face nodes of the row: Mur update (faces of the x axis,
-                // transverse y and z), from this thread's own columns, the
-                // neighbouring rows' values in LDS and the new inner value; or
-                // left to the Mur kernel
+                // the x-face nodes of the row: Mur update (faces of the x
+                // axis, transverse y and z), from this thread's own columns,
+                // the neighbouring rows' values in LDS and the new inner
+                // value.  When the Mur kernel also updates the x faces (a
+                // scalar shape is the run's own), it runs after this kernel
+                // and its values replace these.
                 if (i0 == 0 || i0 + V == R.nx) {
-                    const T(*raw)[4] = rawe[k & 1];
+                    const T(*raw)[4] = L.rawe[k & 1];
                     for (int side = 0; side < 2; ++side) {
                         if ((side == 0 && i0 != 0) || (side == 1 && i0 + V != R.nx))
                             continue;
                         const int eb = side == 0 ? 0 : V - 1, ei = side == 0 ? 1 : V - 2;
-                        if (!R.xface_fused) {
-                            out.v[eb] = next[c + eb];
-                            continue;
-                        }
                         const int ro = side == 0 ? 0 : 2;
                         const int rb = side == 0 ? ro : ro + 1, ri = side == 0 ? ro + 1 : ro;
                         const Vec<T, V> &pm = ps.pm;
@@ -531,13 +541,22 @@ struct SweepVec {
                 }
                 vstore_nt<T, V>(next + c, out);
             }
-            qm = q0;
-            q0 = qp;
-            qp = pf;
-            hm = h0;
-            h0 = hp;
-            hp = hpf;
-            ps = pn;
+        };
+
+        Vec<T, V> qm, q0, qp, pf, hm, h0, hp, hpf;
+        load_cur(kb - 1, qm, hm);
+        load_cur(kb, q0, h0);
+        load_cur(kb + 1, qp, hp);
+        PlaneSrc<T, V, LO> ps{}, pn{};
+        fetch(kb, pn, ps);
+        // four planes per iteration, the variables' roles rotating by one
+        // plane each time (a period of four for the psi^n queues, two for
+        // the psi^{n-1} / source planes); a chunk always runs TZ planes
+        for (int k = kb; k < kb + TZ; k += 4) {
+            plane_step(k, qm, q0, qp, pf, hm, h0, hp, hpf, ps, pn);
+            plane_step(k + 1, q0, qp, pf, qm, h0, hp, hpf, hm, pn, ps);
+            plane_step(k + 2, qp, pf, qm, q0, hp, hpf, hm, h0, ps, pn);
+            plane_step(k + 3, pf, qm, q0, qp, hpf, hm, h0, hp, pn, ps);
         }
     }
 };

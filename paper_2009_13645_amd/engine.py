@@ -97,6 +97,8 @@ def lib():
         L.mithra_batch_run.restype = C.c_int
         L.mithra_batch_sync.argtypes = [H]
         L.mithra_batch_sync.restype = C.c_int
+        L.mithra_batch_autotune_sweep.argtypes = [H, C.c_int, C.POINTER(C.c_int32)]
+        L.mithra_batch_autotune_sweep.restype = C.c_int
         L.mithra_batch_last_error.argtypes = [H]
         L.mithra_batch_last_error.restype = C.c_char_p
         L.mithra_batch_destroy.argtypes = [H]
@@ -294,6 +296,14 @@ class Batch:
             steps = [int(steps)] * n
         arr = (C.c_int64 * n)(*[int(x) for x in steps])
         self._check(self._L.mithra_batch_run(self._b, arr))
+
+    def autotune_sweep(self, iters: int = 3):
+        """Choose the members' sweep tile shapes by timing grouped launches
+        with the whole batch on the device; returns each member's shape."""
+        n = len(self.engines)
+        out = (C.c_int32 * n)()
+        self._check(self._L.mithra_batch_autotune_sweep(self._b, int(iters), out))
+        return [int(x) for x in out]
 
     def sync(self):
         self._check(self._L.mithra_batch_sync(self._b))

@@ -6,7 +6,9 @@ while the device has room: the sum of the active runs' exact arena sizes
 slot limit.  Admitted runs stay resident on the device until they finish.
 All active runs advance together in ticks: one batch (grouped launches, one
 captured graph per batched step) advances each run by up to `tick_steps`
-steps.  Between ticks finished runs are read back and released, and arrived
+steps.  Sweep tile shapes come from the batch-level tuner, run once when
+the batch first holds `tune_min` runs; later admissions of the same
+precision class take the tuned shape.  Between ticks finished runs are read back and released, and arrived
 requests are admitted, so new work joins while other runs are mid-flight.
 The batch is rebuilt only when its membership changed.
 
@@ -69,12 +71,16 @@ class Server:
     cap_bytes: admission limit on the sum of active arena sizes.
     max_active: slot limit (runs per batch).
     tick_steps: steps per tick (the granularity of admission and retirement).
-    autotune: pick each run's sweep tile shape with the library's autotuner.
+    autotune: pick each run's sweep tile shape with the library's autotuner
+        (runs timed alone), until the batch-level tuner has chosen a shape
+        for the run's precision class.
+    tune_min: batch size at which the batch-level shape tuner runs (once);
+        0 disables it.
     """
 
     def __init__(self, cap_bytes: float = 250e9, max_active: int = 64, tick_steps: int = 50,
                  autotune: bool = True, device: str = "cuda:0", clock: Optional[Callable[[], float]] = None,
-                 backend=None):
+                 backend=None, tune_min: int = 16):
         if backend is None:
             from . import engine as backend
         self.backend = backend  # provides Engine, Batch, footprint_bytes
@@ -82,6 +88,8 @@ class Server:
         self.max_active = int(max_active)
         self.tick_steps = int(tick_steps)
         self.autotune = autotune
+        self.tune_min = int(tune_min)
+        self.class_shape: Dict[tuple, int] = {}  # (precision, compensated) -> tuned sweep shape
         self.device = device
         self.clock = clock or time.perf_counter
         self.stats = {"ticks": 0, "rebuilds": 0, "peak_active": 0, "peak_bytes": 0}
@@ -90,9 +98,16 @@ class Server:
         xyz, u, q = req.bunch()
         eng = self.backend.Engine(req.desc, max_particles=len(xyz), device=self.device)
         eng.load_bunch(xyz, u, q)
-        if self.autotune:
+        shape = self.class_shape.get(self._class(req))
+        if shape is not None:
+            eng.set_sweep_shape(shape)
+        elif self.autotune:
             eng.autotune_sweep(2)
         return _Active(req, eng, now, eng.footprint)
+
+    @staticmethod
+    def _class(req: Request) -> tuple:
+        return (req.desc.get("field_precision"), req.desc.get("compensated"))
 
     def _retire(self, a: _Active, now: float) -> Result:
         e = a.eng
@@ -146,6 +161,11 @@ class Server:
             if batch is None or changed:
                 batch = Batch([a.eng for a in active])
                 self.stats["rebuilds"] += 1
+                if self.tune_min > 0 and not self.class_shape and len(active) >= self.tune_min:
+                    shapes = batch.autotune_sweep(2)
+                    for a, sh in zip(active, shapes):
+                        self.class_shape[self._class(a.req)] = int(sh)
+                    self.stats["tuned_shapes"] = dict((str(k), v) for k, v in self.class_shape.items())
             n = [min(self.tick_steps, a.req.steps - a.done) for a in active]
             batch.run(n)
             batch.sync()

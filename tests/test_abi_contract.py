@@ -86,4 +86,5 @@ def test_batch_workspace_and_argument_checks_without_device():
     assert L.mithra_batch_create(None, 0, None, 0, None, C.byref(out)) == -1
     assert out.value is None
     assert L.mithra_batch_run(None, None) == -1
+    assert L.mithra_batch_autotune_sweep(None, 3, None) == -1
     assert L.mithra_batch_destroy(None) == -1

@@ -124,3 +124,42 @@ def test_autotune_is_cached_and_valid():
     s2 = e2.autotune_sweep(3)
     assert 0 <= s1 < Engine.sweep_shape_count()
     assert s1 == s2
+
+
+def test_batch_autotune_keeps_state_and_results():
+    """The batch-level shape tuner leaves every member's state untouched and
+    the tuned batch still gives each member its solo result."""
+    from paper_2009_13645_amd.engine import Batch, Engine
+    runs = members()
+    batched = [make(w) for w in runs]
+    b = Batch([e for e, _, _ in batched])
+    b.run(10)
+    b.sync()
+    names = ["Ax", "Ay", "Az", "F", "Jx", "Jy", "Jz", "Q"]
+    before = [{f: e.read_field(f) for f in names} for e, _, _ in batched]
+    parts = [e.read_particles() for e, _, _ in batched]
+    shapes = b.autotune_sweep(2)
+    print(f"[batch-tune] shapes {shapes}", flush=True)
+    assert all(0 <= s < Engine.sweep_shape_count() for s in shapes)
+    # one shape per (precision, compensation) class
+    by_cls = {}
+    for w, s in zip(runs, shapes):
+        by_cls.setdefault((w.field_precision, w.compensated), set()).add(s)
+    assert all(len(v) == 1 for v in by_cls.values()), by_cls
+    for (e, _, _), snap, pa in zip(batched, before, parts):
+        for f in names:
+            assert np.array_equal(e.read_field(f), snap[f]), f
+        for x, y in zip(e.read_particles(), pa):
+            assert np.array_equal(x, y)
+    b.run(15)
+    b.sync()
+    for (e, d, _), w, sh in zip(batched, runs, shapes):
+        s, _, _ = make(w)
+        s.set_sweep_shape(sh)
+        s.step(25)
+        worst = {f: rel_l2(e.read_field(f), s.read_field(f)) for f in FIELDS}
+        print(f"[batch-tune] {w.name}:", {k: f"{v:.1e}" for k, v in worst.items()}, flush=True)
+        for k, v in worst.items():
+            assert v < tol(w), (w.name, k, v)
+        s.close()
+    b.close()

@@ -26,7 +26,11 @@ class FakeEngine:
         self.seed = float(np.sum(xyz))
 
     def autotune_sweep(self, iters):
+        self.shape_id = 0
         return 0
+
+    def set_sweep_shape(self, shape):
+        self.shape_id = shape
 
     def power_history(self, n):
         # a deterministic function of the run's own inputs and step count
@@ -53,6 +57,11 @@ class FakeBatch:
             e.batched = True
         FakeBatch.open_batches += 1
         assert FakeBatch.open_batches == 1
+
+    def autotune_sweep(self, iters):
+        for e in self.engines:
+            e.shape_id = 7
+        return [7] * len(self.engines)
 
     def run(self, steps):
         for e, n in zip(self.engines, steps):
@@ -149,3 +158,22 @@ def test_summary_counts_work_and_latency_percentiles():
     assert s["cell_updates_per_s"] == pytest.approx(10 * 120 * 8 / 2.0)
     assert s["particle_steps_per_s"] == pytest.approx(10 * 5 * 8 / 2.0)
     assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
+
+
+def test_batch_tuner_runs_once_and_later_admissions_take_its_shape():
+    shapes = []
+    orig = FakeEngine.close
+
+    def close(self):
+        shapes.append(self.shape_id)
+        orig(self)
+    FakeEngine.close = close
+    try:
+        reqs = [req(i, 0.02 * i, steps=30, fp=10, nxyz=(8, 8, 8)) for i in range(10)]
+        srv, res = run(reqs, tick_steps=5, max_active=4, tune_min=3)
+    finally:
+        FakeEngine.close = orig
+    assert len(res) == 10
+    assert srv.stats.get("tuned_shapes")
+    # every run admitted after the tuning took the tuned shape without its own autotune
+    assert shapes.count(7) >= 7
