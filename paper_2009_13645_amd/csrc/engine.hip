@@ -468,11 +468,12 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
         HIPCHK(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         R.tile_grid = std::min(cus * tile_blocks_per_cu(d->field_precision, d->compensated), kPartials - 128);
     }
-    // default sweep tile: vector tiles about as wide as the rows when the
-    // row length allows 16-byte vectors, else the scalar tiles
+    // default sweep tile: vector tiles 32 nodes wide for short rows, else 64
+    // nodes wide over 16 planes (the measured best at 128-node rows), when
+    // the row length allows 16-byte vectors; else the scalar tiles
     const int vec = d->field_precision == 32 ? 4 : 2;
     if (d->nx % vec == 0)
-        h->sweep_shape = d->nx <= 48 ? 13 : (d->nx <= 80 ? 17 : 14);
+        h->sweep_shape = d->nx <= 48 ? 13 : 17;
     else
         h->sweep_shape = (d->nx - 2 <= 40) ? 2 : 0;
     const char *sh = getenv("MITHRA_SWEEP_SHAPE");
