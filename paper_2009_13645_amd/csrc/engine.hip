@@ -468,14 +468,17 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
         HIPCHK(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         R.tile_grid = std::min(cus * tile_blocks_per_cu(d->field_precision, d->compensated), kPartials - 128);
     }
-    // default sweep tile: vector tiles 32 nodes wide for short rows, else 64
-    // nodes wide over 16 planes (the measured best at 128-node rows), when
-    // the row length allows 16-byte vectors; else the scalar tiles
+    // default sweep tile (measured): grids of up to 2^20 nodes take chunks
+    // of 8 or 16 planes, so that enough workgroups run (vector tiles when the
+    // row length allows 16-byte vectors, else the scalar tiles); larger grids
+    // take vector tiles 32 nodes wide for short rows, else 64 nodes wide over
+    // 16 planes (the best at 128-node rows)
     const int vec = d->field_precision == 32 ? 4 : 2;
+    const bool small = (double)d->nx * d->ny * d->nz <= 1048576.0;
     if (d->nx % vec == 0)
-        h->sweep_shape = d->nx <= 48 ? 13 : 17;
+        h->sweep_shape = small ? 15 : (d->nx <= 48 ? 13 : 17);
     else
-        h->sweep_shape = (d->nx - 2 <= 40) ? 2 : 0;
+        h->sweep_shape = small ? 6 : ((d->nx - 2 <= 40) ? 2 : 0);
     const char *sh = getenv("MITHRA_SWEEP_SHAPE");
     if (sh)
         h->sweep_shape = atoi(sh) % sweep_shape_count();

@@ -335,6 +335,105 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
     radix_scatter_blk(keys_in, vals_in, keys_out, vals_out, n, shift, offs, nblocks, tot, blockIdx.x, ctl, inactive);
 }
 
+// The whole sort in one workgroup when every particle fits one chunk: each
+// pass ranks the keys in LDS exactly as the scatter does (wavefront slices
+// in element order, ballots, per-wavefront digit counters), with the
+// workgroup's own digit counts as the only offsets.  One launch replaces
+// three per pass, which is most of a small run's sort time; 1024 threads
+// hold four keys each.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallItems = kSortChunk / kSmallThreads;
+
+__global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R)
+{
+    constexpr int kWaves = kSmallThreads / 64;
+    __shared__ uint32_t skey[2][kSortChunk];
+    __shared__ int32_t sval[2][kSortChunk];
+    __shared__ uint32_t wc[kWaves][256];
+    __shared__ uint32_t scan_tmp[4];
+    const int n = (int)R.np;  // 1..kSortChunk (checked by the launcher)
+    const Ctl *ctl = R.ctl;
+    const int npass = ctl->npass;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int i = t; i < n; i += kSmallThreads) {
+        skey[0][i] = R.key_by_id[i];
+        sval[0][i] = i;
+    }
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    const int wbase = wave * (kSortChunk / kWaves);
+    for (int ps = 0; ps < npass; ++ps) {
+        const int src = ps & 1, dst = src ^ 1;
+        for (int i = t; i < kWaves * 256; i += kSmallThreads)
+            (&wc[0][0])[i] = 0;
+        __syncthreads();  // the input of the pass and the cleared counters
+        uint32_t k[kSmallItems], dp[kSmallItems], before[kSmallItems];
+        int32_t v[kSmallItems];
+        for (int it = 0; it < kSmallItems; ++it) {
+            const int e = wbase + 64 * it + lane;
+            const bool ok = e < n;
+            k[it] = ok ? skey[src][e] : 0u;
+            v[it] = ok ? sval[src][e] : 0;
+        }
+        for (int it = 0; it < kSmallItems; ++it) {
+            const bool ok = wbase + 64 * it + lane < n;
+            const uint32_t d = ok ? sort_digit(ctl, R.key_inactive, k[it], 8 * ps) : 0u;
+            const uint64_t peers = digit_peers(d, ok);
+            const uint32_t r = (uint32_t)__popcll(peers & lt);
+            const uint32_t leader = peers ? (uint32_t)__builtin_ctzll(peers) : 0u;
+            before[it] = 0;
+            if (ok && r == 0)
+                before[it] = atomicAdd(&wc[wave][d], (uint32_t)__popcll(peers));
+            dp[it] = (r << 14) | (leader << 8) | d;
+        }
+        for (int it = 0; it < kSmallItems; ++it) {
+            const uint32_t b = (uint32_t)__shfl((int)before[it], (int)((dp[it] >> 8) & 63));
+            dp[it] = ((b + (dp[it] >> 14)) << 8) | (dp[it] & 0xFF);
+        }
+        __syncthreads();
+        // digit d (threads 0..255): its start in the pass's output (exclusive
+        // scan of the digit totals), then each wavefront's start inside it
+        uint32_t tot = 0, inc = 0;
+        if (t < 256) {
+            for (int w = 0; w < kWaves; ++w)
+                tot += wc[w][t];
+            inc = tot;
+            for (int q = 1; q < 64; q <<= 1) {
+                const uint32_t u = __shfl_up(inc, q);
+                if (lane >= q)
+                    inc += u;
+            }
+            if (lane == 63)
+                scan_tmp[wave] = inc;
+        }
+        __syncthreads();
+        if (t < 256) {
+            uint32_t run = inc - tot;
+            for (int w = 0; w < wave; ++w)
+                run += scan_tmp[w];
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t c = wc[w][t];
+                wc[w][t] = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+        for (int it = 0; it < kSmallItems; ++it) {
+            if (wbase + 64 * it + lane < n) {
+                const uint32_t p = wc[wave][dp[it] & 0xFF] + (dp[it] >> 8);
+                skey[dst][p] = k[it];
+                sval[dst][p] = v[it];
+            }
+        }
+        __syncthreads();  // every read of the starts is done before they are cleared
+    }
+    // the result goes where the multi-workgroup passes would leave it
+    const int fin = npass & 1, ob = (npass - 1) & 1;
+    for (int i = t; i < n; i += kSmallThreads) {
+        R.sk[ob][i] = skey[fin][i];
+        R.sv[ob][i] = sval[fin][i];
+    }
+}
+
 // gather particle state into the other buffer in sorted order
 __device__ inline void sort_gather_blk(const RunDev &R, const uint32_t *keys, const int32_t *ids, int64_t bid)
 {
@@ -439,22 +538,26 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
             return e;
         hipLaunchKernelGGL((k_run<SortRange>), dim3(1), dim3(1), 0, st, R);
     }
-    // as many passes as the widest key range needs; the ones the current
-    // range does not need return at once
-    const int passes = sort_passes(R.key_inactive);
-    const int64_t nb = R.sort_blocks;
-    const uint32_t *kin = R.key_by_id;
-    const int32_t *vin = nullptr;
-    for (int ps = 0; ps < passes; ++ps) {
-        uint32_t *kout = R.sk[ps & 1];
-        int32_t *vout = R.sv[ps & 1];
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, R.np, 8 * ps, R.hist, nb,
-                           R.ctl, R.key_inactive, ps);
-        hipLaunchKernelGGL(k_digit_scan, dim3(256), dim3(256), 0, st, R.hist, nb, R.hist + 256 * nb, R.ctl, ps);
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout, R.np,
-                           8 * ps, R.hist, nb, R.hist + 256 * nb, R.ctl, R.key_inactive, ps);
-        kin = kout;
-        vin = vout;
+    if (R.np <= kSortChunk) {
+        hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSmallThreads), 0, st, R);
+    } else {
+        // as many passes as the widest key range needs; the ones the current
+        // range does not need return at once
+        const int passes = sort_passes(R.key_inactive);
+        const int64_t nb = R.sort_blocks;
+        const uint32_t *kin = R.key_by_id;
+        const int32_t *vin = nullptr;
+        for (int ps = 0; ps < passes; ++ps) {
+            uint32_t *kout = R.sk[ps & 1];
+            int32_t *vout = R.sv[ps & 1];
+            hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, R.np, 8 * ps,
+                               R.hist, nb, R.ctl, R.key_inactive, ps);
+            hipLaunchKernelGGL(k_digit_scan, dim3(256), dim3(256), 0, st, R.hist, nb, R.hist + 256 * nb, R.ctl, ps);
+            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin, vin, kout, vout,
+                               R.np, 8 * ps, R.hist, nb, R.hist + 256 * nb, R.ctl, R.key_inactive, ps);
+            kin = kout;
+            vin = vout;
+        }
     }
     // the tile-owned kernel reads the state in sorted slots; the per-block
     // kernel reads it through sv[ctl->sorted_buf]
