@@ -180,41 +180,66 @@ struct PushDeposit {
             return;  // nothing deposited by this block (uniform)
         const int ex = bb[3] - L0 + 1, ey = bb[4] - L1 + 1, ez = bb[5] - L2 + 1;
         const int vol = ex * ey * ez;
-        if (vol <= kLdsNodes) {
-            for (int e = threadIdx.x; e < 4 * vol; e += kDepThreads)
-                lds[e] = 0.0;
-            __syncthreads();
-            const LdsAcc<double> acc{lds, L0, L1, L2, ex, ey, vol};
+        const GlobalAcc<T, COMP> gacc = make_gacc<T, COMP>(R, set);
+        // Zero an LDS box, deposit into it, then flush its nonzero nodes with
+        // global atomics: one node per thread per round, its four components
+        // together (so that the returning atomics of the compensated mode are
+        // in flight together), the node's (i, j, k) decoded once for the four.
+        // first / stride: this thread's share; sync orders the three phases.
+        auto lds_deposit = [&](double *base, int B0, int B1, int B2, int bx, int by, int bv, int first, int stride,
+                               auto sync) {
+            for (int e = first; e < 4 * bv; e += stride)
+                base[e] = 0.0;
+            sync();
+            const LdsAcc<double> acc{base, B0, B1, B2, bx, by, bv};
             if (dep_j)
                 deposit_move(R, acc, g1, c1, g2, c2);
             if (dep_q)
                 deposit_charge(R, acc, g2, c2);
-            __syncthreads();
-            const GlobalAcc<T, COMP> gacc = make_gacc<T, COMP>(R, set);
-            // one node per thread per round, its four components together (so
-            // that the returning atomics of the compensated mode are in flight
-            // together); the node's (i, j, k) is decoded once for the four
-            for (int e = threadIdx.x; e < vol; e += kDepThreads) {
-                const int i = e % ex, jk = e / ex;
-                const int j = jk % ey, k = jk / ey;
+            sync();
+            for (int e = first; e < bv; e += stride) {
+                const int i = e % bx, jk = e / bx;
+                const int j = jk % by, k = jk / by;
                 double v[4];
                 int idx[4][4];
     #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    v[q] = lds[q * vol + e];
+                    v[q] = base[q * bv + e];
                     idx[q][0] = q;
-                    idx[q][1] = L0 + i;
-                    idx[q][2] = L1 + j;
-                    idx[q][3] = L2 + k;
+                    idx[q][1] = B0 + i;
+                    idx[q][2] = B1 + j;
+                    idx[q][3] = B2 + k;
                 }
                 gacc.add4(v, idx);
             }
+        };
+        if (vol <= kLdsNodes) {
+            lds_deposit(lds, L0, L1, L2, ex, ey, vol, threadIdx.x, kDepThreads, [] { __syncthreads(); });
         } else {
-            const GlobalAcc<T, COMP> gacc = make_gacc<T, COMP>(R, set);
-            if (dep_j)
-                deposit_move(R, gacc, g1, c1, g2, c2);
-            if (dep_q)
-                deposit_charge(R, gacc, g2, c2);
+            // The block's particles straddle rows of sort tiles, so its box is
+            // too large.  Each wavefront then uses a quarter of the LDS for its
+            // own box (lo, hi: the wavefront's box, the same in every lane)
+            // when that fits, and global atomics when it does not.  LDS
+            // accesses of one wavefront complete in order; the fences keep the
+            // compiler from moving them across the phases.
+            constexpr int kWaveNodes = kLdsNodes / (kDepThreads / 64);
+            const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+            if (hi[0] >= 0) {
+                const int wx = hi[0] - lo[0] + 1, wy = hi[1] - lo[1] + 1, wz = hi[2] - lo[2] + 1;
+                const int wvol = wx * wy * wz;
+                if (wvol <= kWaveNodes) {
+                    lds_deposit(lds + (size_t)wave * 4 * kWaveNodes, lo[0], lo[1], lo[2], wx, wy, wvol, lane, 64, [] {
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    });
+                } else {
+                    if (dep_j)
+                        deposit_move(R, gacc, g1, c1, g2, c2);
+                    if (dep_q)
+                        deposit_charge(R, gacc, g2, c2);
+                }
+            }
         }
     }
 };

@@ -321,7 +321,7 @@ def config2(field_precision: int = 32, compensated: int = 0, steps: int = 4000) 
                  bunch="flattop", sigma_cells=(8.0, 8.0, 0.0), flat_len_cells=512.0,
                  center_frac_z=0.4, sigma_gamma_rel=1e-4, shot_noise=True, seed=2,
                  field_precision=field_precision, compensated=compensated,
-                 tile=(8, 8, 8))
+                 tile=(4, 2, 2))
     w.charge_C = _cfg2_charge(w)
     return w
 
