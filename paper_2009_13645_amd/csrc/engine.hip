@@ -45,7 +45,9 @@ int64_t sweep_blocks(const RunDev &R, int shape);
 hipError_t launch_sweep_group(const Group &g, int64_t total, int precision, int compensated, int shape,
                               hipStream_t st);
 int64_t mur_blocks(const RunDev &R);
-hipError_t launch_mur_group(const Group &g, int64_t total, int precision, hipStream_t st);
+int64_t mur_edge_blocks(const RunDev &R);
+hipError_t launch_mur_group(const Group &g, int64_t total, const Group &ge, int64_t total_e, int precision,
+                            hipStream_t st);
 int64_t vertex_blocks(const RunDev &R);
 hipError_t launch_vertex_group(const Group &g, int64_t total, int precision, hipStream_t st);
 int64_t power_blocks();
@@ -1092,7 +1094,7 @@ struct mithra_batch_s {
         GroupTab t;
     };
     std::vector<SweepCls> sweep;
-    GroupTab mur[2], vertex[2], power[2], power_final[2], push[3], one, sort_s, sort_d, sort_p;
+    GroupTab mur[2], mur_edge[2], vertex[2], power[2], power_final[2], push[3], one, sort_s, sort_d, sort_p;
     int max_passes = 0;
     hipGraphExec_t graph = nullptr;
     std::vector<int64_t> host_targets;
@@ -1131,7 +1133,7 @@ extern "C" size_t mithra_batch_workspace_bytes(int32_t n_runs)
     const size_t n = (size_t)n_runs;
     // every stage kind holds each member at most once; sweep classes add at
     // most one table per member
-    return 10 * tab_bytes(n) + (n + 16) * 3 * 256 + 256;
+    return 11 * tab_bytes(n) + (n + 18) * 3 * 256 + 256;
 }
 
 // table of members `mem` (indices into b->runs), nb(member) workgroups each
@@ -1208,6 +1210,8 @@ static int build_tables(mithra_batch b)
             }
         int rc = make_tab(b, mem, [](const RunDev &R) { return mur_blocks(R); }, &b->mur[pi]);
         if (!rc)
+            rc = make_tab(b, mem, [](const RunDev &R) { return mur_edge_blocks(R); }, &b->mur_edge[pi]);
+        if (!rc)
             rc = make_tab(b, mem, [](const RunDev &R) { return vertex_blocks(R); }, &b->vertex[pi]);
         if (!rc)
             rc = make_tab(b, memp, [](const RunDev &) { return power_blocks(); }, &b->power[pi]);
@@ -1248,7 +1252,8 @@ static int enqueue_batch_step(mithra_batch b, hipStream_t st)
     for (auto &c : b->sweep)
         BHIPCHK(b, launch_sweep_group(c.t.g, c.t.total, c.precision, c.comp, c.shape, st));
     for (int pi = 0; pi < 2; ++pi)
-        BHIPCHK(b, launch_mur_group(b->mur[pi].g, b->mur[pi].total, pi == 0 ? 32 : 64, st));
+        BHIPCHK(b, launch_mur_group(b->mur[pi].g, b->mur[pi].total, b->mur_edge[pi].g, b->mur_edge[pi].total,
+                                    pi == 0 ? 32 : 64, st));
     for (int pi = 0; pi < 2; ++pi)
         BHIPCHK(b, launch_vertex_group(b->vertex[pi].g, b->vertex[pi].total, pi == 0 ? 32 : 64, st));
     for (int ci = 0; ci < 3; ++ci)
@@ -1402,7 +1407,8 @@ extern "C" int mithra_batch_autotune_sweep(mithra_batch b, int iters, int32_t *s
                     if (c.precision == prec && c.comp == comp)
                         BHIPCHK(b, launch_sweep_group(c.t.g, c.t.total, c.precision, c.comp, c.shape, b->stream));
                 const int pi = prec == 32 ? 0 : 1;
-                BHIPCHK(b, launch_mur_group(b->mur[pi].g, b->mur[pi].total, prec, b->stream));
+                BHIPCHK(b, launch_mur_group(b->mur[pi].g, b->mur[pi].total, b->mur_edge[pi].g, b->mur_edge[pi].total,
+                                            prec, b->stream));
                 return MITHRA_OK;
             };
             rc = launch();  // warm

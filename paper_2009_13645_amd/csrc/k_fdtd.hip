@@ -10,13 +10,13 @@
 //    source of the step (node-averaged edge current, or rho) is read only
 //    inside the bounding box of the last deposit.
 //  * k_mur: Mur absorbing boundaries (sec. "Boundary Truncation"), one
-//    thread per boundary node; further workgroups of the same launch clear
-//    the other source set inside its own box for the coming deposit.  Faces use the printed first/second-order
-//    updates with permuted axes; edges and corners solve the sum of the
-//    first-order conditions of their faces discretised at the centre of the
-//    2x2 (2x2x2) node stencil, recomputing the neighbouring face/edge values
-//    they need so that one launch suffices.  Three time levels make all
-//    reads race-free.
+//    thread per boundary node, in two launches.  Faces use the printed
+//    first/second-order updates with permuted axes; further workgroups of
+//    the face launch clear the other source set inside its own box for the
+//    coming deposit.  Then edges and corners solve the sum of the first-order
+//    conditions of their faces discretised at the centre of the 2x2 (2x2x2)
+//    node stencil, reading the new face values (a corner recomputes its edge
+//    neighbours).  Three time levels make all reads race-free.
 //  * k_vertex_fields: E and B at vertices (sec. "Field Evaluation"):
 //    E = -(A^{n+1} - A^n)/dt - grad phi, B = mean of curl A^n and curl A^{n+1}.
 #include "mithra_dev.hpp"
@@ -584,32 +584,6 @@ __device__ inline double ld(const T *a, const RunDev &R, const int p[3])
     return (double)a[nid(R, p[0], p[1], p[2])];
 }
 
-// n+1 value of a face node p (normal axis ax, side -1/+1)
-template <typename T>
-__device__ double face_np1(const RunDev &R, const Lv<T> &L, const int p[3], int ax, int side)
-{
-    int q[3] = {p[0], p[1], p[2]};
-    q[ax] -= side;  // first node inside
-    const double be0 = R.mur_be0[ax];
-    double v = be0 * (ld(L.pm, R, p) + ld(L.pp, R, q)) - ld(L.pm, R, q);
-    if (R.order == 1)
-        return v + R.mur_be1[ax] * (ld(L.p0, R, p) + ld(L.p0, R, q));
-    v += R.mur_g1[ax] * (ld(L.p0, R, p) + ld(L.p0, R, q));
-    const int t1 = (ax + 1) % 3, t2 = (ax + 2) % 3;
-    double s1 = 0.0, s2 = 0.0;
-    for (int d = -1; d <= 1; d += 2) {
-        int a[3] = {p[0], p[1], p[2]}, b[3] = {q[0], q[1], q[2]};
-        a[t1] += d;
-        b[t1] += d;
-        s1 += ld(L.p0, R, a) + ld(L.p0, R, b);
-        int c2[3] = {p[0], p[1], p[2]}, d2[3] = {q[0], q[1], q[2]};
-        c2[t2] += d;
-        d2[t2] += d;
-        s2 += ld(L.p0, R, c2) + ld(L.p0, R, d2);
-    }
-    return v + R.mur_ga[ax] * s1 + R.mur_gb[ax] * s2;
-}
-
 // Summed first-order conditions over the 2^m stencil of node p whose
 // boundary axes are ax[0..m-1].  Per stencil node X, with sigma_b = +1 on
 // the boundary side of axis b and -1 on the inner side, the conditions
@@ -641,17 +615,9 @@ __device__ double solve_summed(const RunDev &R, const Lv<T> &L, const int p[3], 
     return -rest / cu;
 }
 
-template <typename T>
-__device__ double np1_face_or_interior(const RunDev &R, const Lv<T> &L, const int q[3])
-{
-    for (int a = 0; a < 3; ++a) {
-        const int sd = bside(R, a, q[a]);
-        if (sd != 0)
-            return face_np1(R, L, q, a, sd);
-    }
-    return ld(L.pp, R, q);
-}
-
+// The face and interior nodes of an edge's or a corner's stencil already
+// hold their n+1 values when this runs (the sweep and the face kernel come
+// first), so they are read; a corner recomputes its three edge neighbours.
 template <typename T>
 __device__ double edge_np1(const RunDev &R, const Lv<T> &L, const int p[3], const int *ax, const int *sd)
 {
@@ -661,7 +627,7 @@ __device__ double edge_np1(const RunDev &R, const Lv<T> &L, const int p[3], cons
         for (int b = 0; b < 2; ++b)
             if ((st >> b) & 1)
                 q[ax[b]] -= sd[b];
-        np1[st] = np1_face_or_interior(R, L, q);
+        np1[st] = ld(L.pp, R, q);
     }
     return solve_summed(R, L, p, ax, sd, 2, np1);
 }
@@ -685,7 +651,7 @@ __device__ double corner_np1(const RunDev &R, const Lv<T> &L, const int p[3], co
         if (me == 2)
             np1[st] = edge_np1(R, L, q, eax, esd);
         else
-            np1[st] = np1_face_or_interior(R, L, q);
+            np1[st] = ld(L.pp, R, q);
     }
     return solve_summed(R, L, p, ax, sd, 3, np1);
 }
@@ -751,14 +717,11 @@ static __host__ __device__ inline int64_t clear_blocks_of(int ny, int nz)
     return r < 8 ? 8 : (r > 1024 ? 1024 : r);
 }
 
-// Boundary nodes, one thread each (per component), in two groups:
-//  - face nodes that lie on one boundary only (z faces, y faces, and the x
-//    faces unless the vector sweep updated them), with direct strides;
-//  - edge and corner nodes, through the summed first-order conditions
-//    (solve_summed), which recompute the face values they need.
-// Face threads come first and are laid out x fastest, so their accesses
-// coalesce; the few edge threads take the general path.  The workgroups
-// after the boundary ones clear the next source set (clear_next_sources).
+// Face nodes of the boundary, one thread each (per component): z faces, y
+// faces, and the x faces unless the vector sweep updated them, with direct
+// strides, laid out x fastest so that their accesses coalesce.  The
+// workgroups after the boundary ones clear the next source set
+// (clear_next_sources).  Edge and corner nodes follow in MurEdge.
 template <typename T>
 struct Mur {
     static constexpr int kThreads = 256;
@@ -768,8 +731,7 @@ struct Mur {
         const int64_t fz = 2LL * (nx - 2) * (ny - 2);
         const int64_t fy = 2LL * (nx - 2) * (nz - 2);
         const int64_t fx = R.xface_fused ? 0 : 2LL * (ny - 2) * (nz - 2);
-        const int64_t ex = 4LL * nx, ey = 4LL * (ny - 2), ez = 4LL * (nz - 2);
-        const int64_t nb = fz + fy + fx + ex + ey + ez;
+        const int64_t nb = fz + fy + fx;
         // ceil(nb / 256) workgroups per component (component uniform per
         // workgroup), then the workgroups that clear the next source set
         const int64_t bpc = (nb + 255) / 256;
@@ -786,58 +748,85 @@ struct Mur {
         const T *pm = pot_ptr<T>(R, slot_prev(s), comp);
         const T *p0 = pot_ptr<T>(R, slot_cur(s), comp);
         T *pp = pot_ptr<T>(R, slot_next(s), comp);
-        const int64_t st[3] = {1, nx, (int64_t)nx * ny};
-        if (r < fz + fy + fx) {
-            int p[3], ax;
-            if (r < fz) {
-                const int64_t half = (int64_t)(nx - 2) * (ny - 2);
-                ax = 2;
-                p[2] = r < half ? 0 : nz - 1;
-                if (r >= half)
-                    r -= half;
-                const uint32_t q = face_div(r, half, nx - 2);
-                p[0] = 1 + (int)(r - (int64_t)q * (nx - 2));
-                p[1] = 1 + (int)q;
-            } else if (r < fz + fy) {
-                r -= fz;
-                const int64_t half = (int64_t)(nx - 2) * (nz - 2);
-                ax = 1;
-                p[1] = r < half ? 0 : ny - 1;
-                if (r >= half)
-                    r -= half;
-                const uint32_t q = face_div(r, half, nx - 2);
-                p[0] = 1 + (int)(r - (int64_t)q * (nx - 2));
-                p[2] = 1 + (int)q;
-            } else {
-                r -= fz + fy;
-                const int64_t half = (int64_t)(ny - 2) * (nz - 2);
-                ax = 0;
-                p[0] = r < half ? 0 : nx - 1;
-                if (r >= half)
-                    r -= half;
-                const uint32_t q = face_div(r, half, ny - 2);
-                p[1] = 1 + (int)(r - (int64_t)q * (ny - 2));
-                p[2] = 1 + (int)q;
-            }
-            const int n_ax = ax == 0 ? nx : (ax == 1 ? ny : nz);
-            const int side = p[ax] == 0 ? -1 : 1;
-            (void)n_ax;
-            const int64_t c = ((int64_t)p[2] * ny + p[1]) * nx + p[0];
-            const int64_t q = c - side * st[ax];  // first node inside
-            const int64_t s1 = st[(ax + 1) % 3], s2 = st[(ax + 2) % 3];
-            double v = R.mur_be0[ax] * ((double)pm[c] + (double)pp[q]) - (double)pm[q];
-            if (R.order == 1) {
-                v += R.mur_be1[ax] * ((double)p0[c] + (double)p0[q]);
-            } else {
-                v += R.mur_g1[ax] * ((double)p0[c] + (double)p0[q]);
-                const double a1 = ((double)p0[c - s1] + (double)p0[q - s1]) + ((double)p0[c + s1] + (double)p0[q + s1]);
-                const double a2 = ((double)p0[c - s2] + (double)p0[q - s2]) + ((double)p0[c + s2] + (double)p0[q + s2]);
-                v = v + R.mur_ga[ax] * a1 + R.mur_gb[ax] * a2;
-            }
-            pp[c] = (T)v;
-            return;
+        int p[3], ax;
+        if (r < fz) {
+            const int64_t half = (int64_t)(nx - 2) * (ny - 2);
+            ax = 2;
+            p[2] = r < half ? 0 : nz - 1;
+            if (r >= half)
+                r -= half;
+            const uint32_t q = face_div(r, half, nx - 2);
+            p[0] = 1 + (int)(r - (int64_t)q * (nx - 2));
+            p[1] = 1 + (int)q;
+        } else if (r < fz + fy) {
+            r -= fz;
+            const int64_t half = (int64_t)(nx - 2) * (nz - 2);
+            ax = 1;
+            p[1] = r < half ? 0 : ny - 1;
+            if (r >= half)
+                r -= half;
+            const uint32_t q = face_div(r, half, nx - 2);
+            p[0] = 1 + (int)(r - (int64_t)q * (nx - 2));
+            p[2] = 1 + (int)q;
+        } else {
+            r -= fz + fy;
+            const int64_t half = (int64_t)(ny - 2) * (nz - 2);
+            ax = 0;
+            p[0] = r < half ? 0 : nx - 1;
+            if (r >= half)
+                r -= half;
+            const uint32_t q = face_div(r, half, ny - 2);
+            p[1] = 1 + (int)(r - (int64_t)q * (ny - 2));
+            p[2] = 1 + (int)q;
         }
-        r -= fz + fy + fx;
+        // strides and coefficients of the normal axis by selects (no array
+        // indexed at run time)
+        const int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
+        const int64_t sn = ax == 0 ? sx : (ax == 1 ? sy : sz);
+        const int64_t s1 = ax == 0 ? sy : (ax == 1 ? sz : sx), s2 = ax == 0 ? sz : (ax == 1 ? sx : sy);
+        auto co = [ax](const double (&a)[3]) { return ax == 0 ? a[0] : (ax == 1 ? a[1] : a[2]); };
+        const int pa = ax == 0 ? p[0] : (ax == 1 ? p[1] : p[2]);
+        const int side = pa == 0 ? -1 : 1;
+        const int64_t c = ((int64_t)p[2] * ny + p[1]) * nx + p[0];
+        const int64_t q = c - side * sn;  // first node inside
+        double v = co(R.mur_be0) * ((double)pm[c] + (double)pp[q]) - (double)pm[q];
+        if (R.order == 1) {
+            v += co(R.mur_be1) * ((double)p0[c] + (double)p0[q]);
+        } else {
+            v += co(R.mur_g1) * ((double)p0[c] + (double)p0[q]);
+            const double a1 = ((double)p0[c - s1] + (double)p0[q - s1]) + ((double)p0[c + s1] + (double)p0[q + s1]);
+            const double a2 = ((double)p0[c - s2] + (double)p0[q - s2]) + ((double)p0[c + s2] + (double)p0[q + s2]);
+            v = v + co(R.mur_ga) * a1 + co(R.mur_gb) * a2;
+        }
+        pp[c] = (T)v;
+    }
+};
+
+// Edge and corner nodes of the boundary (one thread each, per component):
+// the summed first-order conditions of their faces (solve_summed), with the
+// face values the face kernel has just written; a corner recomputes its
+// three edge neighbours.  A launch of its own, after the face kernel: this
+// path needs far more registers than the face path, and in one kernel it
+// set the face threads' occupancy too.
+template <typename T>
+struct MurEdge {
+    static constexpr int kThreads = 256;
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        const int nx = R.nx, ny = R.ny, nz = R.nz;
+        const int64_t ex = 4LL * nx, ey = 4LL * (ny - 2), ez = 4LL * (nz - 2);
+        const int64_t nb = ex + ey + ez;
+        const int64_t bpc = (nb + 255) / 256;
+        const int comp = (int)(blk.id / bpc);
+        if (comp >= (R.space_charge ? 4 : 3))
+            return;
+        int64_t r = (blk.id - (int64_t)comp * bpc) * blockDim.x + threadIdx.x;
+        if (r >= nb)
+            return;
+        const int64_t s = R.ctl->step;
+        const T *pm = pot_ptr<T>(R, slot_prev(s), comp);
+        const T *p0 = pot_ptr<T>(R, slot_cur(s), comp);
+        T *pp = pot_ptr<T>(R, slot_next(s), comp);
         int p[3];
         if (r < ex) {
             p[0] = (int)(r % nx);
@@ -1106,31 +1095,39 @@ void sweep_shape_dims(int shape, int *tx, int *ty, int *tz)
 }
 
 // boundary nodes the Mur kernel updates (see Mur)
+// face nodes of the boundary (per component), and edge and corner nodes
 static int64_t mur_nodes(const RunDev &R)
 {
     const int64_t nx = R.nx, ny = R.ny, nz = R.nz;
-    return 2 * (nx - 2) * (ny - 2) + 2 * (nx - 2) * (nz - 2) + (R.xface_fused ? 0 : 2 * (ny - 2) * (nz - 2)) +
-           4 * nx + 4 * (ny - 2) + 4 * (nz - 2);
+    return 2 * (nx - 2) * (ny - 2) + 2 * (nx - 2) * (nz - 2) + (R.xface_fused ? 0 : 2 * (ny - 2) * (nz - 2));
 }
+
+static int64_t mur_edge_nodes(const RunDev &R) { return 4LL * R.nx + 4LL * (R.ny - 2) + 4LL * (R.nz - 2); }
 
 hipError_t launch_sweep(const RunDev &R, int shape, hipStream_t st)
 {
     return R.precision == 32 ? launch_sweep_shape<float>(R, shape, st) : launch_sweep_shape<double>(R, shape, st);
 }
 
-// Mur workgroups (per component) plus the source-clearing workgroups
+// Mur face workgroups (per component) plus the source-clearing workgroups
 int64_t mur_blocks(const RunDev &R)
 {
     return ((mur_nodes(R) + 255) / 256) * (R.space_charge ? 4 : 3) + clear_blocks_of(R.ny, R.nz);
 }
 
+// Mur edge and corner workgroups (per component)
+int64_t mur_edge_blocks(const RunDev &R) { return ((mur_edge_nodes(R) + 255) / 256) * (R.space_charge ? 4 : 3); }
+
 hipError_t launch_mur(const RunDev &R, hipStream_t st)
 {
-    const unsigned blocks = (unsigned)mur_blocks(R);
-    if (R.precision == 32)
+    const unsigned blocks = (unsigned)mur_blocks(R), eblocks = (unsigned)mur_edge_blocks(R);
+    if (R.precision == 32) {
         hipLaunchKernelGGL((k_run<Mur<float>>), dim3(blocks), dim3(256), 0, st, R);
-    else
+        hipLaunchKernelGGL((k_run<MurEdge<float>>), dim3(eblocks), dim3(256), 0, st, R);
+    } else {
         hipLaunchKernelGGL((k_run<Mur<double>>), dim3(blocks), dim3(256), 0, st, R);
+        hipLaunchKernelGGL((k_run<MurEdge<double>>), dim3(eblocks), dim3(256), 0, st, R);
+    }
     return hipGetLastError();
 }
 
@@ -1243,14 +1240,19 @@ hipError_t launch_sweep_group(const Group &g, int64_t total, int precision, int 
 
 
 
-hipError_t launch_mur_group(const Group &g, int64_t total, int precision, hipStream_t st)
+// ge: the same members with their edge and corner workgroup counts
+hipError_t launch_mur_group(const Group &g, int64_t total, const Group &ge, int64_t total_e, int precision,
+                            hipStream_t st)
 {
     if (total <= 0)
         return hipSuccess;
-    if (precision == 32)
+    if (precision == 32) {
         hipLaunchKernelGGL((k_group<Mur<float>>), dim3((unsigned)total), dim3(256), 0, st, g);
-    else
+        hipLaunchKernelGGL((k_group<MurEdge<float>>), dim3((unsigned)total_e), dim3(256), 0, st, ge);
+    } else {
         hipLaunchKernelGGL((k_group<Mur<double>>), dim3((unsigned)total), dim3(256), 0, st, g);
+        hipLaunchKernelGGL((k_group<MurEdge<double>>), dim3((unsigned)total_e), dim3(256), 0, st, ge);
+    }
     return hipGetLastError();
 }
 
