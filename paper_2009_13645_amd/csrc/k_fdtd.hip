@@ -401,7 +401,7 @@ struct SweepVec {
         // k+2 (pf, hpf) and of plane k+1 (pn) are issued first.  The caller
         // rotates the roles of the variables instead of copying them, so a
         // prefetch stays in flight across planes.  Planes at or beyond ke
-        // (only in the last chunk) are computed and not stored.
+        // (only in a chunk's last group of four) are computed and not stored.
         auto plane_step = [&](int k, const Vec<T, V> &qm, const Vec<T, V> &q0, const Vec<T, V> &qp, Vec<T, V> &pf,
                               const Vec<T, V> &hm, const Vec<T, V> &h0, const Vec<T, V> &hp, Vec<T, V> &hpf,
                               const PlaneSrc<T, V, LO> &ps, PlaneSrc<T, V, LO> &pn) {
@@ -551,8 +551,9 @@ struct SweepVec {
         fetch(kb, pn, ps);
         // four planes per iteration, the variables' roles rotating by one
         // plane each time (a period of four for the psi^n queues, two for
-        // the psi^{n-1} / source planes); a chunk always runs TZ planes
-        for (int k = kb; k < kb + TZ; k += 4) {
+        // the psi^{n-1} / source planes); the last group of a chunk may run
+        // up to three planes past ke, computed and not stored
+        for (int k = kb; k < ke; k += 4) {
             plane_step(k, qm, q0, qp, pf, hm, h0, hp, hpf, ps, pn);
             plane_step(k + 1, q0, qp, pf, qm, h0, hp, hpf, hm, pn, ps);
             plane_step(k + 2, qp, pf, qm, q0, hp, hpf, hm, h0, ps, pn);
