@@ -239,3 +239,46 @@ def test_tile_owned_particle_path(case, monkeypatch):
     cg, co, pg, po = compare(d, o, g, 1e-10)
     assert int(np.sum(cg != co)) == 0
     assert int(np.sum(pg != po)) == 0
+
+
+def _block_boxes(d, xyz, tile, per):
+    """Node boxes of consecutive groups of `per` particles in the sort order
+    (tile-major cell key, ties by id), from the cells at load; the deposit
+    box of the first push is this box grown by at most one cell."""
+    n = np.array([d["nx"], d["ny"], d["nz"]])
+    o = np.array([d["x0"], d["y0"], d["z0"]])
+    h = np.array([d["dx"], d["dy"], d["dz"]])
+    c = np.floor((xyz - o) / h).astype(np.int64)
+    act = np.all((c >= 1) & (c <= n - 3), axis=1)
+    T = np.array(tile)
+    nt = (n - 1 + T - 1) // T
+    t = c // T
+    loc = c % T
+    key = ((t[:, 2] * nt[1] + t[:, 1]) * nt[0] + t[:, 0]) * int(np.prod(T)) + \
+        (loc[:, 2] * T[1] + loc[:, 1]) * T[0] + loc[:, 0]
+    key = np.where(act, key, np.iinfo(np.int64).max)
+    order = np.lexsort((np.arange(len(key)), key))
+    cs = c[order][act[order]]
+    vols = []
+    for b in range(0, len(cs), per):
+        g = cs[b:b + per]
+        vols.append(int(np.prod(g.max(0) - g.min(0) + 2)))
+    return np.array(vols)
+
+
+def test_deposit_box_overflow_paths_fp64():
+    """8x8x8 sort tiles on a dense bunch: workgroups whose particles straddle
+    rows of tiles overflow the LDS box and deposit through per-wavefront
+    boxes, or global atomics for a wavefront that does not fit either."""
+    w = W.Workload(name="box-overflow", nx=96, ny=96, nz=48, gamma=100.0, K=1.0, lambda_u=0.03, n_periods=20,
+                   n_particles=60000, sigma_cells=(12.0, 12.0, 6.0), seed=31, tile=(8, 8, 8))
+    d = w.descriptor()
+    xyz, _, _ = W.make_bunch(w)
+    blocks = _block_boxes(d, xyz, (8, 8, 8), 256)
+    waves = _block_boxes(d, xyz, (8, 8, 8), 64)
+    print(f"[parity] box-overflow: {int(np.sum(blocks > 1536))} of {len(blocks)} workgroups overflow; "
+          f"{int(np.sum(waves <= 384))} of {len(waves)} wavefront boxes fit a quarter", flush=True)
+    assert np.sum(blocks > 1536) > 0 and np.sum(waves > 384) > 0
+    d, o, g = run_both(w, 30)
+    cg, co, pg, po = compare(d, o, g, 1e-10)
+    assert int(np.sum(cg != co)) == 0 and int(np.sum(pg != po)) == 0
