@@ -773,16 +773,21 @@ extern "C" int mithra_read_particles(mithra_handle h, double *xyz, double *u, in
     int32_t pb = 0;
     HIPCHK(h, hipMemcpy(&pb, &R.ctl->pbuf, 4, hipMemcpyDeviceToHost));
     // the state sits in buffer pb in the slots pid[pb]; the order of the
-    // last sort is sv[sorted_buf] (the per-block path does not move the state
-    // after sorting) or the gathered pid[pb] (tile-owned path)
+    // last sort is the slot list sv[sorted_buf] (the per-block path does not
+    // move the state after sorting) or the gathered pid[pb] (tile-owned path)
     std::vector<int32_t> ids((size_t)n);
     HIPCHK(h, hipMemcpy(ids.data(), R.pid[pb], (size_t)n * 4, hipMemcpyDeviceToHost));
-    {
-        int32_t sb = 0;
-        if (sort_perm && !h->tiled)
+    if (sort_perm) {
+        if (h->tiled) {
+            memcpy(sort_perm, ids.data(), (size_t)n * 4);
+        } else {
+            int32_t sb = 0;
             HIPCHK(h, hipMemcpy(&sb, &R.ctl->sorted_buf, 4, hipMemcpyDeviceToHost));
-        if (sort_perm)
-            HIPCHK(h, hipMemcpy(sort_perm, h->tiled ? R.pid[pb] : R.sv[sb], (size_t)n * 4, hipMemcpyDeviceToHost));
+            std::vector<int32_t> slots((size_t)n);
+            HIPCHK(h, hipMemcpy(slots.data(), R.sv[sb], (size_t)n * 4, hipMemcpyDeviceToHost));
+            for (int64_t r = 0; r < n; ++r)
+                sort_perm[r] = ids[(size_t)slots[(size_t)r]];
+        }
     }
     std::vector<double> col((size_t)n);
     for (int a = 0; a < 6; ++a) {

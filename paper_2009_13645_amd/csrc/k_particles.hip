@@ -15,7 +15,7 @@ __host__ __device__ inline int64_t dep_blocks_dev(int64_t np) { return (np + kDe
 
 // Gather + undulator + N_b Boris sub-steps + deposit (MODE 0), or the load
 // deposit of the backward-drift move (MODE 1, set 0).  Rank p handles the
-// particle sv[sorted_buf][p] of the last sort, read from its slot in buffer pbuf;
+// particle in slot sv[sorted_buf][p] of buffer pbuf (the last sort's order);
 // MODE 0 writes the pushed state to rank p of the other buffer (the step's
 // last bookkeeping kernel flips pbuf), so the sort never moves the state.
 // The block's deposits are summed in LDS over its node box when the box
@@ -41,10 +41,10 @@ struct PushDeposit {
         int c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
         bool dep_j = false, dep_q = false;
         if (p < R.np) {
-            // rank p of the last sort: particle id, read where the previous
-            // push (or the load) left it
-            const int32_t id = R.sv[R.ctl->sorted_buf][p];
-            const int32_t src = R.slot_of_id[id];
+            // rank p of the last sort: the slot where the previous push (or
+            // the load) left the particle, and its id
+            const int32_t src = R.sv[R.ctl->sorted_buf][p];
+            const int32_t id = R.pid[pb][src];
             double r[3], u[3];
             for (int a = 0; a < 3; ++a) {
                 r[a] = R.pr[pb][a][src];

@@ -11,8 +11,10 @@
 // result is bit-exact whatever the previous order was.
 //
 // Method: keys are scattered to id order, then an LSD radix sort with
-// 8-bit digits and stable passes runs on (key, id) pairs starting from the
-// identity order, which makes ties come out in id order.  Each pass is a
+// 8-bit digits and stable passes runs on (key, slot) pairs starting from id
+// order, which makes ties come out in id order.  The value carried is the
+// particle's slot in the buffer the next push reads (slot_of_id), so the
+// push reaches the state without looking the slot up.  Each pass is a
 // per-block digit histogram, 256 independent per-digit scans over the
 // blocks, and a stable scatter that ranks equal digits within a wavefront
 // with ballots.  Finally the particle state is gathered into the other
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R)
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     for (int i = t; i < n; i += kSmallThreads) {
         skey[0][i] = R.key_by_id[i];
-        sval[0][i] = i;
+        sval[0][i] = R.slot_of_id[i];
     }
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     const int wbase = wave * (kSortChunk / kWaves);
@@ -435,15 +437,15 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R)
 }
 
 // gather particle state into the other buffer in sorted order
-__device__ inline void sort_gather_blk(const RunDev &R, const uint32_t *keys, const int32_t *ids, int64_t bid)
+__device__ inline void sort_gather_blk(const RunDev &R, const uint32_t *keys, const int32_t *slots, int64_t bid)
 {
     const int pb = R.ctl->pbuf;
     const int nb = pb ^ 1;
     const int64_t r = (int64_t)bid * blockDim.x + threadIdx.x;
     if (r >= R.np)
         return;
-    const int32_t id = ids[r];
-    const int32_t src = R.slot_of_id[id];
+    const int32_t src = slots[r];
+    const int32_t id = R.pid[pb][src];
     for (int a = 0; a < 6; ++a)
         R.pr[nb][a][r] = R.pr[pb][a][src];
     R.pid[nb][r] = id;
@@ -502,7 +504,7 @@ struct RadixScatterRun {
         if (ps >= R.ctl->npass || R.np <= 0)
             return;
         const uint32_t *kin = ps == 0 ? R.key_by_id : R.sk[(ps - 1) & 1];
-        const int32_t *vin = ps == 0 ? nullptr : R.sv[(ps - 1) & 1];
+        const int32_t *vin = ps == 0 ? R.slot_of_id : R.sv[(ps - 1) & 1];
         radix_scatter_blk(kin, vin, R.sk[ps & 1], R.sv[ps & 1], R.np, 8 * ps, R.hist, R.sort_blocks,
                           R.hist + 256 * R.sort_blocks, blk.id, R.ctl, R.key_inactive);
     }
@@ -546,7 +548,7 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
         const int passes = sort_passes(R.key_inactive);
         const int64_t nb = R.sort_blocks;
         const uint32_t *kin = R.key_by_id;
-        const int32_t *vin = nullptr;
+        const int32_t *vin = R.slot_of_id;
         for (int ps = 0; ps < passes; ++ps) {
             uint32_t *kout = R.sk[ps & 1];
             int32_t *vout = R.sv[ps & 1];

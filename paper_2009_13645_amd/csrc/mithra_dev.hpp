@@ -41,7 +41,7 @@ struct Ctl {
     uint32_t key_base;     // sort keys of the current sort are offset by this (active keys >= it)
     uint32_t key_span;     // active keys lie in [key_base, key_base + key_span); inactive sort as key_span
     int32_t npass;         // radix passes the current sort needs (8-bit digits of key_span)
-    int32_t sorted_buf;    // sv[sorted_buf] holds the ids in the order of the last sort
+    int32_t sorted_buf;    // sv[sorted_buf] holds the particles' slots in the order of the last sort
 };
 
 constexpr int kMaxBatch = 1;  // one run per RunDev
