@@ -125,7 +125,7 @@ static const int kBunchBlocks = 256;
 
 struct Layout {
     size_t ctl, pot, src, src_lo, eb, pr, pid, key_by_id, slot_of_id, cell_by_id, key_sorted, sk, sv, hist, boxpart,
-        cellpart, items, items_n, ppart, power, scratch, total;
+        cellpart, items, items_n, ppart, power, scratch, tile_flag, ntiles, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -169,6 +169,8 @@ static Layout make_layout(const mithra_grid_desc *d, int64_t cap)
     L.ppart = take(256 * 8);
     L.power = take((size_t)kPowerCap * 8);
     L.scratch = take((size_t)(3 * kBunchBlocks + 8) * 8);
+    L.ntiles = ntiles;
+    L.tile_flag = take(ntiles * 4);
     L.total = off;
     return L;
 }
@@ -421,6 +423,7 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.slot_of_id = (int32_t *)(A + L.slot_of_id);
     h->cell_by_id = (int32_t *)(A + L.cell_by_id);
     R.key_sorted = (uint32_t *)(A + L.key_sorted);
+    R.tile_flag = (uint32_t *)(A + L.tile_flag);
     R.sk[0] = (uint32_t *)(A + L.sk);
     R.sk[1] = R.sk[0] + c;
     R.sv[0] = (int32_t *)(A + L.sv);
@@ -446,6 +449,8 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
         HIPCHK(h, hipMemsetAsync(R.src_lo, 0, 8 * nn * pf, h->stream));
     HIPCHK(h, hipMemsetAsync(R.eb, 0, 8 * nn * pf, h->stream));
     HIPCHK(h, hipMemsetAsync(R.power_hist, 0, (size_t)kPowerCap * 8, h->stream));
+    // no tile marked for any step (the load marks those of step 0)
+    HIPCHK(h, hipMemsetAsync(R.tile_flag, 0xFF, L.ntiles * 4, h->stream));
     Ctl c0;
     memset(&c0, 0, sizeof c0);
     for (int s = 0; s < 2; ++s)

@@ -893,6 +893,26 @@ __device__ inline void vertex_eb(const RunDev &R, int64_t s, int i, int j, int k
         E[c] = -((double)Ap[c][c0] - (double)An[c][c0]) / R.dt - g[c];
 }
 
+// Is node (i, j, k) a corner of an active cell whose sort tile holds a
+// particle at step s?  The push of step s-1 (or the load) marks the tiles of
+// the cells its particles end in with s; a node's cells are i-1..i on each
+// axis, within the active range 1..n-3.
+__device__ inline bool node_needed(const RunDev &R, int64_t s, int i, int j, int k)
+{
+    const uint32_t want = (uint32_t)s;
+    const int c0[3] = {max(i - 1, 1), max(j - 1, 1), max(k - 1, 1)};
+    const int c1[3] = {min(i, R.nx - 3), min(j, R.ny - 3), min(k, R.nz - 3)};
+    const int tx0 = c0[0] / R.tile[0], tx1 = c1[0] / R.tile[0];
+    const int ty0 = c0[1] / R.tile[1], ty1 = c1[1] / R.tile[1];
+    const int tz0 = c0[2] / R.tile[2], tz1 = c1[2] / R.tile[2];
+    for (int tz = tz0; tz <= tz1; ++tz)
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx)
+                if (R.tile_flag[((int64_t)tz * R.ntile[1] + ty) * R.ntile[0] + tx] == want)
+                    return true;
+    return false;
+}
+
 // E, B over the active-particle box of the last sort (full == 0) or over
 // all interior nodes (full == 1).  step_bias selects the step whose levels
 // are used (0 during a step, -1 after it for read-back).
@@ -934,6 +954,8 @@ struct VertexFields {
                 j = lo[1] + (int)((t / ex) % ey);
                 k = lo[2] + (int)(t / (ex * ey));
             }
+            if (!full && !node_needed(R, s, i, j, k))
+                continue;  // no particle of this step gathers at this node
             double E[3], B[3];
             vertex_eb<T>(R, s, i, j, k, E, B);
             Vec<T, V> w[8 / V];

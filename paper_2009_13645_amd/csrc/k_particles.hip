@@ -59,6 +59,8 @@ struct PushDeposit {
                 const bool a2 = cell_of(R, r, g2, c2);
                 dep_j = a1 && a2;
                 dep_q = a2;
+                if (a2)  // the vertex fields of this step are needed around this cell
+                    R.tile_flag[tile_of_cell(R, c2)] = (uint32_t)s;
             } else {
                 const bool act1 = cell_of(R, r, g1, c1);
                 double Eg[3] = {0, 0, 0}, Bg[3] = {0, 0, 0};
@@ -119,6 +121,8 @@ struct PushDeposit {
                 // sort key of the new position, in id order, for this step's sort
                 R.key_by_id[id] = act2 ? key_of_cell(R, c2) : R.key_inactive;
                 R.slot_of_id[id] = (int32_t)p;
+                if (act2)  // the next step's vertex fields are needed around this cell
+                    R.tile_flag[tile_of_cell(R, c2)] = (uint32_t)(s + 1);
             }
         }
         if (MODE == 0) {

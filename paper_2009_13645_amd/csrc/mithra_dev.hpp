@@ -96,6 +96,7 @@ struct RunDev {
     uint32_t *key_by_id;
     int32_t *slot_of_id;
     uint32_t *key_sorted;
+    uint32_t *tile_flag;  // per sort tile: the step whose vertex fields the tile's particles gather
     uint32_t *sk[2];
     int32_t *sv[2];
     uint32_t *hist;
@@ -276,6 +277,14 @@ __global__ __launch_bounds__(F::kThreads) __attribute__((amdgpu_waves_per_eu(Wav
     if (R.ctl->step >= R.ctl->target)
         return;
     F::run(R, Blk{id, G.nblk[m]}, a...);
+}
+
+// Linear index of the sort tile of an active cell c (tile-major order).
+__device__ inline uint32_t tile_of_cell(const RunDev &R, const int c[3])
+{
+    return ((uint32_t)(c[2] / R.tile[2]) * (uint32_t)R.ntile[1] + (uint32_t)(c[1] / R.tile[1])) *
+               (uint32_t)R.ntile[0] +
+           (uint32_t)(c[0] / R.tile[0]);
 }
 
 // Tile-major sort key of an active cell c (see k_sort.hip for the order).
