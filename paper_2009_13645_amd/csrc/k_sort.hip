@@ -344,16 +344,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t *
 // three per pass, which is most of a small run's sort time; 1024 threads
 // hold four keys each.
 constexpr int kSmallThreads = 1024;
-constexpr int kSmallItems = kSortChunk / kSmallThreads;
+constexpr int kSmallChunk = 4096;  // particles the one-workgroup sort takes
+constexpr int kSmallItems = kSmallChunk / kSmallThreads;
 
 __global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R)
 {
     constexpr int kWaves = kSmallThreads / 64;
-    __shared__ uint32_t skey[2][kSortChunk];
-    __shared__ int32_t sval[2][kSortChunk];
+    __shared__ uint32_t skey[2][kSmallChunk];
+    __shared__ int32_t sval[2][kSmallChunk];
     __shared__ uint32_t wc[kWaves][256];
     __shared__ uint32_t scan_tmp[4];
-    const int n = (int)R.np;  // 1..kSortChunk (checked by the launcher)
+    const int n = (int)R.np;  // 1..kSmallChunk (checked by the launcher)
     const Ctl *ctl = R.ctl;
     const int npass = ctl->npass;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R)
         sval[0][i] = R.slot_of_id[i];
     }
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    const int wbase = wave * (kSortChunk / kWaves);
+    const int wbase = wave * (kSmallChunk / kWaves);
     for (int ps = 0; ps < npass; ++ps) {
         const int src = ps & 1, dst = src ^ 1;
         for (int i = t; i < kWaves * 256; i += kSmallThreads)
@@ -540,7 +541,7 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
             return e;
         hipLaunchKernelGGL((k_run<SortRange>), dim3(1), dim3(1), 0, st, R);
     }
-    if (R.np <= kSortChunk) {
+    if (R.np <= kSmallChunk) {
         hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSmallThreads), 0, st, R);
     } else {
         // as many passes as the widest key range needs; the ones the current
