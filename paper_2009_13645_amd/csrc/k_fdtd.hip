@@ -250,6 +250,7 @@ struct PlaneSrc {
 template <typename T, int V, int TXV, int TY, int TZ, bool LO>
 struct SweepVec {
     static constexpr int kThreads = TXV * TY;
+    static constexpr bool kCopyRun = true;  // see CopyRunOf
     static_assert(TZ % 4 == 0, "planes are processed four at a time");
     static constexpr int TW = TXV * V;                          // tile width in nodes
     static constexpr int ROW = ((V + TW + 1) + V - 1) / V * V;  // LDS row: pad(V-1), left halo, tile, right halo

@@ -265,6 +265,21 @@ __global__ __launch_bounds__(F::kThreads) __attribute__((amdgpu_waves_per_eu(Wav
     F::run(R, Blk{(int64_t)blockIdx.x, (int64_t)gridDim.x}, a...);
 }
 
+// Stages with F::kCopyRun read their member's descriptor through a
+// by-value copy in k_group.  Through the reference, a field read after a
+// store to device memory cannot be shown unchanged, so it is reloaded into
+// vector registers (the sweeps needed 6-15 more VGPRs that way); stages
+// that index the descriptor's arrays at run time would put the copy in
+// scratch memory instead, so the copy is opt-in.
+template <class F, class = void>
+struct CopyRunOf {
+    static constexpr bool value = false;
+};
+template <class F>
+struct CopyRunOf<F, std::void_t<decltype(F::kCopyRun)>> {
+    static constexpr bool value = F::kCopyRun;
+};
+
 template <class F, class... A>
 __global__ __launch_bounds__(F::kThreads) __attribute__((amdgpu_waves_per_eu(WavesOf<F>::value))) void k_group(
     Group G, A... a)
@@ -273,10 +288,19 @@ __global__ __launch_bounds__(F::kThreads) __attribute__((amdgpu_waves_per_eu(Wav
     const int64_t id = (int64_t)blockIdx.x - G.boff[m];
     if (id >= G.nblk[m])
         return;
-    const RunDev &R = G.runs[m];
-    if (R.ctl->step >= R.ctl->target)
-        return;
-    F::run(R, Blk{id, G.nblk[m]}, a...);
+    if constexpr (CopyRunOf<F>::value) {
+        // a copy taken before any store: the fields the stage uses load
+        // through the scalar cache once, as from the argument of k_run
+        const RunDev R = G.runs[m];
+        if (R.ctl->step >= R.ctl->target)
+            return;
+        F::run(R, Blk{id, G.nblk[m]}, a...);
+    } else {
+        const RunDev &R = G.runs[m];
+        if (R.ctl->step >= R.ctl->target)
+            return;
+        F::run(R, Blk{id, G.nblk[m]}, a...);
+    }
 }
 
 // Linear index of the sort tile of an active cell c (tile-major order).
