@@ -265,12 +265,16 @@ __global__ __launch_bounds__(F::kThreads) __attribute__((amdgpu_waves_per_eu(Wav
     F::run(R, Blk{(int64_t)blockIdx.x, (int64_t)gridDim.x}, a...);
 }
 
-// Stages with F::kCopyRun read their member's descriptor through a
-// by-value copy in k_group.  Through the reference, a field read after a
-// store to device memory cannot be shown unchanged, so it is reloaded into
-// vector registers (the sweeps needed 6-15 more VGPRs that way); stages
-// that index the descriptor's arrays at run time would put the copy in
-// scratch memory instead, so the copy is opt-in.
+// How k_group reaches its member's descriptor.  Through a plain reference a
+// field read after a store to device memory cannot be shown unchanged, so
+// it is reloaded into vector registers.  Two remedies:
+//  * stages with F::kCopyRun take a by-value copy before any store (the
+//    sweeps: 6-15 fewer VGPRs, a fourth wave per SIMD at FP64); stages that
+//    index the descriptor's arrays at run time would put such a copy in
+//    scratch memory, so it is opt-in;
+//  * the others read it through a restrict pointer: the table is never
+//    written by a kernel, so its loads stay scalar (vertex fields: 107 -> 96
+//    VGPRs at FP32).
 template <class F, class = void>
 struct CopyRunOf {
     static constexpr bool value = false;
@@ -279,6 +283,16 @@ template <class F>
 struct CopyRunOf<F, std::void_t<decltype(F::kCopyRun)>> {
     static constexpr bool value = F::kCopyRun;
 };
+
+template <class F, class... A>
+__device__ __attribute__((always_inline)) inline void group_stage(const RunDev *__restrict__ runs, int m, Blk blk,
+                                                                  A... a)
+{
+    const RunDev &R = runs[m];
+    if (R.ctl->step >= R.ctl->target)
+        return;
+    F::run(R, blk, a...);
+}
 
 template <class F, class... A>
 __global__ __launch_bounds__(F::kThreads) __attribute__((amdgpu_waves_per_eu(WavesOf<F>::value))) void k_group(
@@ -296,10 +310,7 @@ __global__ __launch_bounds__(F::kThreads) __attribute__((amdgpu_waves_per_eu(Wav
             return;
         F::run(R, Blk{id, G.nblk[m]}, a...);
     } else {
-        const RunDev &R = G.runs[m];
-        if (R.ctl->step >= R.ctl->target)
-            return;
-        F::run(R, Blk{id, G.nblk[m]}, a...);
+        group_stage<F>(G.runs, m, Blk{id, G.nblk[m]}, a...);
     }
 }
 
