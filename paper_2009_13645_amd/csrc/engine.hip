@@ -51,7 +51,8 @@ hipError_t launch_mur_group(const Group &g, int64_t total, const Group &ge, int6
 int64_t vertex_blocks(const RunDev &R);
 hipError_t launch_vertex_group(const Group &g, int64_t total, int precision, hipStream_t st);
 int64_t power_blocks();
-hipError_t launch_power_group(const Group &g, int64_t total, int precision, hipStream_t st);
+hipError_t launch_power_group(const Group &g, int64_t total, const Group &gf, int64_t total_f, int precision,
+                              hipStream_t st);
 hipError_t launch_push_group(const Group &g, int64_t total, int precision, int compensated, hipStream_t st);
 hipError_t launch_box_group(const Group &g, int64_t total, hipStream_t st);
 hipError_t launch_sort_group(const Group &gs, int64_t total_s, const Group &gd, int64_t total_d, const Group &gp,
@@ -1103,7 +1104,7 @@ struct mithra_batch_s {
         GroupTab t;
     };
     std::vector<SweepCls> sweep;
-    GroupTab mur[2], mur_edge[2], vertex[2], power[2], push[3], one, sort_s, sort_d, sort_p;
+    GroupTab mur[2], mur_edge[2], vertex[2], power[2], power_final[2], push[3], one, sort_s, sort_d, sort_p;
     int max_passes = 0;
     hipGraphExec_t graph = nullptr;
     std::vector<int64_t> host_targets;
@@ -1142,7 +1143,7 @@ extern "C" size_t mithra_batch_workspace_bytes(int32_t n_runs)
     const size_t n = (size_t)n_runs;
     // every stage kind holds each member at most once; sweep classes add at
     // most one table per member
-    return 10 * tab_bytes(n) + (n + 18) * 3 * 256 + 256;
+    return 11 * tab_bytes(n) + (n + 18) * 3 * 256 + 256;
 }
 
 // table of members `mem` (indices into b->runs), nb(member) workgroups each
@@ -1224,6 +1225,8 @@ static int build_tables(mithra_batch b)
             rc = make_tab(b, mem, [](const RunDev &R) { return vertex_blocks(R); }, &b->vertex[pi]);
         if (!rc)
             rc = make_tab(b, memp, [](const RunDev &) { return power_blocks(); }, &b->power[pi]);
+        if (!rc)
+            rc = make_tab(b, memp, [](const RunDev &) { return (int64_t)1; }, &b->power_final[pi]);
         if (rc)
             return rc;
     }
@@ -1269,7 +1272,8 @@ static int enqueue_batch_step(mithra_batch b, hipStream_t st)
     BHIPCHK(b, launch_sort_group(b->sort_s.g, b->sort_s.total, b->sort_d.g, b->sort_d.total, b->sort_p.g,
                                  b->sort_p.total, b->max_passes, st));
     for (int pi = 0; pi < 2; ++pi)
-        BHIPCHK(b, launch_power_group(b->power[pi].g, b->power[pi].total, pi == 0 ? 32 : 64, st));
+        BHIPCHK(b, launch_power_group(b->power[pi].g, b->power[pi].total, b->power_final[pi].g,
+                                      b->power_final[pi].total, pi == 0 ? 32 : 64, st));
     hipLaunchKernelGGL((k_group<BookEnd>), dim3((unsigned)b->one.total), dim3(1), 0, st, b->one.g);
     BHIPCHK(b, hipGetLastError());
     return MITHRA_OK;

@@ -972,18 +972,19 @@ struct VertexFields {
 
 // Radiated power through node plane k_plane of the fields at t_{s+1/2}
 // (lab-frame Poynting flux).  kPowerBlocks blocks write partial sums over
-// a fixed node partition; the block that finishes last (a device-scope
-// counter in Ctl) adds them in fixed order, so the result does not depend
-// on scheduling, and stores it.
+// a fixed node partition; one block adds them in fixed order, so the
+// result does not depend on scheduling.  (A single launch whose last block
+// adds the partial sums needs a device-scope release fence in every block,
+// which writes back the XCD's L2: in a grouped launch of 32 runs that made
+// the stage six times slower.)
 constexpr int kPowerBlocks = 64;
 
 template <typename T>
 struct PlanePower {
     static constexpr int kThreads = 256;
-    static __device__ void run(const RunDev &R, Blk blk, int step_bias, int kp_arg, double *out, int end_step)
+    static __device__ void run(const RunDev &R, Blk blk, int step_bias, int kp_arg)
     {
         __shared__ double red[256];
-        __shared__ int last;
         const int kp = kp_arg < 0 ? R.k_plane : kp_arg;  // < 0: the run's diagnostic plane
         const int64_t s = R.ctl->step + step_bias;
         const double g0 = R.gamma0, b0 = R.beta0;
@@ -1006,19 +1007,19 @@ struct PlanePower {
                 red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0)
             R.ppart[blk.id] = red[0];
-            __threadfence();  // the partial sum is visible device-wide before the count
-            last = atomicAdd(&R.ctl->power_done, 1) == kPowerBlocks - 1;
-        }
-        __syncthreads();
-        if (!last || threadIdx.x != 0)
-            return;
-        __threadfence();  // every block's partial sum is visible here
+    }
+};
+
+struct PlanePowerFinal {
+    static constexpr int kThreads = 1;
+    static __device__ void run(const RunDev &R, Blk blk, int step_bias, double *out, int end_step)
+    {
+        const int64_t s = R.ctl->step + step_bias;
         double sum = 0.0;
         for (int b = 0; b < kPowerBlocks; ++b)
             sum += R.ppart[b];
-        R.ctl->power_done = 0;  // ready for the next launch
         const double mu0 = 1.0 / (kEps0 * kC * kC);
         const double P = sum * R.dx * R.dy / mu0;
         if (out)
@@ -1179,11 +1180,10 @@ hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStr
 hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st, int end_step)
 {
     if (R.precision == 32)
-        hipLaunchKernelGGL((k_run<PlanePower<float>, int, int, double *, int>), dim3(kPowerBlocks), dim3(256), 0, st, R,
-                           step_bias, kp, out, end_step);
+        hipLaunchKernelGGL((k_run<PlanePower<float>, int, int>), dim3(kPowerBlocks), dim3(256), 0, st, R, step_bias, kp);
     else
-        hipLaunchKernelGGL((k_run<PlanePower<double>, int, int, double *, int>), dim3(kPowerBlocks), dim3(256), 0, st, R,
-                           step_bias, kp, out, end_step);
+        hipLaunchKernelGGL((k_run<PlanePower<double>, int, int>), dim3(kPowerBlocks), dim3(256), 0, st, R, step_bias, kp);
+    hipLaunchKernelGGL((k_run<PlanePowerFinal, int, double *, int>), dim3(1), dim3(1), 0, st, R, step_bias, out, end_step);
     return hipGetLastError();
 }
 
@@ -1298,16 +1298,17 @@ hipError_t launch_vertex_group(const Group &g, int64_t total, int precision, hip
 
 int64_t power_blocks() { return kPowerBlocks; }
 
-hipError_t launch_power_group(const Group &g, int64_t total, int precision, hipStream_t st)
+hipError_t launch_power_group(const Group &g, int64_t total, const Group &gf, int64_t total_f, int precision,
+                              hipStream_t st)
 {
     if (total <= 0)
         return hipSuccess;
     if (precision == 32)
-        hipLaunchKernelGGL((k_group<PlanePower<float>, int, int, double *, int>), dim3((unsigned)total), dim3(256), 0, st,
-                           g, 0, -1, (double *)nullptr, 0);
+        hipLaunchKernelGGL((k_group<PlanePower<float>, int, int>), dim3((unsigned)total), dim3(256), 0, st, g, 0, -1);
     else
-        hipLaunchKernelGGL((k_group<PlanePower<double>, int, int, double *, int>), dim3((unsigned)total), dim3(256), 0,
-                           st, g, 0, -1, (double *)nullptr, 0);
+        hipLaunchKernelGGL((k_group<PlanePower<double>, int, int>), dim3((unsigned)total), dim3(256), 0, st, g, 0, -1);
+    hipLaunchKernelGGL((k_group<PlanePowerFinal, int, double *, int>), dim3((unsigned)total_f), dim3(1), 0, st, gf, 0,
+                       (double *)nullptr, 0);
     return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ struct Ctl {
     int32_t sorted_active; // n_active of the sort the current push works on
     int32_t n_items;       // tile work items built after the last sort
     int32_t item_next;     // next work item to take (persistent push)
-    int32_t power_done;    // plane-power workgroups finished in the current launch
+    int32_t pad_;
     int64_t target;        // step count at which a batched run stops (grouped launches only)
     uint32_t key_base;     // sort keys of the current sort are offset by this (active keys >= it)
     uint32_t key_span;     // active keys lie in [key_base, key_base + key_span); inactive sort as key_span
