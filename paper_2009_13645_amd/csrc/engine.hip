@@ -53,6 +53,8 @@ hipError_t launch_vertex_group(const Group &g, int64_t total, int precision, hip
 int64_t power_blocks();
 hipError_t launch_power_group(const Group &g, int64_t total, const Group &gf, int64_t total_f, int precision,
                               hipStream_t st);
+hipError_t launch_vertex_power(const RunDev &R, hipStream_t st);
+hipError_t launch_power_final(const RunDev &R, hipStream_t st, int end_step);
 hipError_t launch_push_group(const Group &g, int64_t total, int precision, int compensated, hipStream_t st);
 hipError_t launch_box_group(const Group &g, int64_t total, hipStream_t st);
 hipError_t launch_sort_group(const Group &gs, int64_t total_s, const Group &gd, int64_t total_d, const Group &gp,
@@ -590,7 +592,10 @@ static int enqueue_particles(mithra_handle h, hipStream_t st)
     } else {
         // no mid-step bookkeeping: the box reductions after the push rewrite
         // the deposit box, the active-cell box and the active count whole
-        HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
+        if (R.record_power)  // the power's partial sums ride on the vertex launch
+            HIPCHK(h, launch_vertex_power(R, st));
+        else
+            HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
         HIPCHK(h, launch_push_deposit(R, st));
         HIPCHK(h, launch_sort(R, st, true, dep_blocks(R.np), false));
     }
@@ -606,8 +611,10 @@ static int enqueue_step(mithra_handle h)
     int rc = enqueue_particles(h, st);
     if (rc)
         return rc;
-    if (R.record_power)
+    if (R.record_power && h->tiled)
         HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st, 1));  // ends the step
+    else if (R.record_power)
+        HIPCHK(h, launch_power_final(R, st, 1));  // sums the partials of the vertex launch; ends the step
     else
         hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);
     HIPCHK(h, hipGetLastError());
@@ -948,8 +955,10 @@ extern "C" int mithra_step_timed(mithra_handle h, int64_t n, double *sweep_ms, d
         int rc = enqueue_particles(h, st);
         if (rc)
             return rc;
-        if (R.record_power)
+        if (R.record_power && h->tiled)
             HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st, 1));  // ends the step
+        else if (R.record_power)
+            HIPCHK(h, launch_power_final(R, st, 1));
         else
             hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);
         HIPCHK(h, hipGetLastError());

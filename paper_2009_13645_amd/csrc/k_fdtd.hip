@@ -1036,6 +1036,32 @@ struct PlanePowerFinal {
     }
 };
 
+// Workgroups of the vertex-field launch (the same count on host and device).
+__host__ __device__ inline int64_t vertex_blocks_of(const RunDev &R)
+{
+    const int64_t inner = (int64_t)(R.nx - 2) * (R.ny - 2) * (R.nz - 2);
+    const int64_t b = (inner + 255) / 256;
+    return b < 1 ? 1 : (b > 8192 ? 8192 : b);
+}
+
+// The step's vertex fields and the plane-power partial sums in one launch:
+// both read only the potentials of step s, which the push and the sort do
+// not change, so the partial sums equal those of a launch after the sort.
+// The power's workgroups come first, so that they do not form the launch's
+// tail.  Single-run steps only: in a grouped launch the merged body needs
+// 12-15 more VGPRs than the vertex fields alone, one wave per SIMD fewer.
+template <typename T>
+struct VertexPower {
+    static constexpr int kThreads = 256;
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        if (blk.id < kPowerBlocks)
+            PlanePower<T>::run(R, Blk{blk.id, kPowerBlocks}, 0, -1);
+        else
+            VertexFields<T>::run(R, Blk{blk.id - kPowerBlocks, vertex_blocks_of(R)}, 0, 0);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -1159,10 +1185,23 @@ hipError_t launch_mur(const RunDev &R, hipStream_t st)
 }
 
 // workgroups of the vertex fields (a grid-stride loop over the box)
-int64_t vertex_blocks(const RunDev &R)
+int64_t vertex_blocks(const RunDev &R) { return vertex_blocks_of(R); }
+
+hipError_t launch_vertex_power(const RunDev &R, hipStream_t st)
 {
-    const int64_t inner = (int64_t)(R.nx - 2) * (R.ny - 2) * (R.nz - 2);
-    return std::min<int64_t>(8192, std::max<int64_t>(1, (inner + 255) / 256));
+    const int64_t blocks = vertex_blocks_of(R) + kPowerBlocks;
+    if (R.precision == 32)
+        hipLaunchKernelGGL((k_run<VertexPower<float>>), dim3((unsigned)blocks), dim3(256), 0, st, R);
+    else
+        hipLaunchKernelGGL((k_run<VertexPower<double>>), dim3((unsigned)blocks), dim3(256), 0, st, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_final(const RunDev &R, hipStream_t st, int end_step)
+{
+    hipLaunchKernelGGL((k_run<PlanePowerFinal, int, double *, int>), dim3(1), dim3(1), 0, st, R, 0, (double *)nullptr,
+                       end_step);
+    return hipGetLastError();
 }
 
 hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStream_t st)
