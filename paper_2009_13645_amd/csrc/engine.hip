@@ -36,7 +36,9 @@ hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *ou
 hipError_t launch_push_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_load_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st);
-hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts, bool gather);
+hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts, bool gather,
+                       int end_step = 0);
+bool sort_ends_step(const RunDev &R);  // launch_sort with end_step ends the step itself
 hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
                              int32_t *count, hipStream_t st, int32_t *zero);
 hipError_t launch_box_reduce_set(const RunDev &R, int64_t nblocks, hipStream_t st);
@@ -597,7 +599,7 @@ static int enqueue_particles(mithra_handle h, hipStream_t st)
         else
             HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
         HIPCHK(h, launch_push_deposit(R, st));
-        HIPCHK(h, launch_sort(R, st, true, dep_blocks(R.np), false));
+        HIPCHK(h, launch_sort(R, st, true, dep_blocks(R.np), false, 1));
     }
     return MITHRA_OK;
 }
@@ -611,7 +613,9 @@ static int enqueue_step(mithra_handle h)
     int rc = enqueue_particles(h, st);
     if (rc)
         return rc;
-    if (R.record_power && h->tiled)
+    if (!h->tiled && sort_ends_step(R))
+        ;  // the small sort ended the step
+    else if (R.record_power && h->tiled)
         HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st, 1));  // ends the step
     else if (R.record_power)
         HIPCHK(h, launch_power_final(R, st, 1));  // sums the partials of the vertex launch; ends the step
@@ -955,7 +959,9 @@ extern "C" int mithra_step_timed(mithra_handle h, int64_t n, double *sweep_ms, d
         int rc = enqueue_particles(h, st);
         if (rc)
             return rc;
-        if (R.record_power && h->tiled)
+        if (!h->tiled && sort_ends_step(R))
+            ;  // the small sort ended the step
+        else if (R.record_power && h->tiled)
             HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st, 1));  // ends the step
         else if (R.record_power)
             HIPCHK(h, launch_power_final(R, st, 1));

@@ -977,8 +977,6 @@ struct VertexFields {
 // adds the partial sums needs a device-scope release fence in every block,
 // which writes back the XCD's L2: in a grouped launch of 32 runs that made
 // the stage six times slower.)
-constexpr int kPowerBlocks = 64;
-
 template <typename T>
 struct PlanePower {
     static constexpr int kThreads = 256;
@@ -1016,23 +1014,7 @@ struct PlanePowerFinal {
     static constexpr int kThreads = 1;
     static __device__ void run(const RunDev &R, Blk blk, int step_bias, double *out, int end_step)
     {
-        const int64_t s = R.ctl->step + step_bias;
-        double sum = 0.0;
-        for (int b = 0; b < kPowerBlocks; ++b)
-            sum += R.ppart[b];
-        const double mu0 = 1.0 / (kEps0 * kC * kC);
-        const double P = sum * R.dx * R.dy / mu0;
-        if (out)
-            *out = P;
-        else if (s >= 0 && s < R.power_cap)
-            R.power_hist[s] = P;
-        if (!isfinite(P))
-            R.ctl->nan_flag = 1;
-        if (end_step) {  // last kernel of a step: the step's bookkeeping
-            R.ctl->pbuf ^= 1;
-            R.ctl->nsort += 1;
-            R.ctl->step += 1;
-        }
+        plane_power_final(R, R.ctl->step + step_bias, out, end_step);
     }
 };
 

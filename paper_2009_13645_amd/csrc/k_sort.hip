@@ -350,7 +350,10 @@ constexpr int kSmallThreads = 1024;
 constexpr int kSmallChunk = 4096;  // particles the one-workgroup sort takes
 constexpr int kSmallItems = kSmallChunk / kSmallThreads;
 
-__global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R)
+// With end_step, the workgroup also ends the step afterwards (the power of
+// the step from the vertex launch's partial sums when the run records it,
+// then the bookkeeping), so a small run's step needs no launch after it.
+__global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R, int end_step)
 {
     constexpr int kWaves = kSmallThreads / 64;
     __shared__ uint32_t skey[2][kSmallChunk];
@@ -438,7 +441,31 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R)
         R.sk[ob][i] = skey[fin][i];
         R.sv[ob][i] = sval[fin][i];
     }
+    if (end_step) {
+        __syncthreads();  // every read of the control block is done
+        if (t < 64) {
+            // the first wavefront adds the 64 partial sums (a fixed butterfly)
+            double x = 0.0;
+            if (R.record_power) {
+                static_assert(kPowerBlocks == 64, "one partial sum per lane");
+                x = R.ppart[t];
+                for (int o = 1; o < 64; o <<= 1)
+                    x += __shfl_xor(x, o);
+            }
+            if (t == 0) {
+                if (R.record_power)
+                    plane_power_store(R, R.ctl->step, x, nullptr, 1);
+                else {
+                    R.ctl->pbuf ^= 1;
+                    R.ctl->nsort += 1;
+                    R.ctl->step += 1;
+                }
+            }
+        }
+    }
 }
+
+bool sort_ends_step(const RunDev &R) { return R.np > 0 && R.np <= kSmallChunk; }
 
 // gather particle state into the other buffer in sorted order
 __device__ inline void sort_gather_blk(const RunDev &R, const uint32_t *keys, const int32_t *slots, int64_t bid)
@@ -526,7 +553,7 @@ int64_t sort_blocks(int64_t n) { return (n + kSortChunk - 1) / kSortChunk; }
 // keys_ready: the push kernels have already written the keys, the slots
 // and `nparts` per-block active-cell boxes in R.cellpart.  The tile work
 // item counter is reset here, before the items of the new order are built.
-hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts, bool gather)
+hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts, bool gather, int end_step)
 {
     if (R.np <= 0)
         return hipSuccess;
@@ -545,7 +572,7 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
         hipLaunchKernelGGL((k_run<SortRange>), dim3(1), dim3(1), 0, st, R);
     }
     if (R.np <= kSmallChunk) {
-        hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSmallThreads), 0, st, R);
+        hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSmallThreads), 0, st, R, end_step);
     } else {
         // as many passes as the widest key range needs; the ones the current
         // range does not need return at once

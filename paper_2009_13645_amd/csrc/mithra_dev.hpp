@@ -314,6 +314,39 @@ __global__ __launch_bounds__(F::kThreads) __attribute__((amdgpu_waves_per_eu(Wav
     }
 }
 
+// Plane-power workgroups (partial sums in ppart, fixed node partition).
+constexpr int kPowerBlocks = 64;
+
+// The radiated power of step s from the sum of the plane-power partial sums
+// (lab-frame Poynting flux times the node area), stored to *out or to the
+// run's power history; with end_step, the step's bookkeeping follows
+// (particle buffer, sort count, step counter).  One thread.
+__device__ inline void plane_power_store(const RunDev &R, int64_t s, double sum, double *out, int end_step)
+{
+    const double mu0 = 1.0 / (kEps0 * kC * kC);
+    const double P = sum * R.dx * R.dy / mu0;
+    if (out)
+        *out = P;
+    else if (s >= 0 && s < R.power_cap)
+        R.power_hist[s] = P;
+    if (!isfinite(P))
+        R.ctl->nan_flag = 1;
+    if (end_step) {
+        R.ctl->pbuf ^= 1;
+        R.ctl->nsort += 1;
+        R.ctl->step += 1;
+    }
+}
+
+// The same with the partial sums added in fixed order by one thread.
+__device__ inline void plane_power_final(const RunDev &R, int64_t s, double *out, int end_step)
+{
+    double sum = 0.0;
+    for (int b = 0; b < kPowerBlocks; ++b)
+        sum += R.ppart[b];
+    plane_power_store(R, s, sum, out, end_step);
+}
+
 // Linear index of the sort tile of an active cell c (tile-major order).
 __device__ inline uint32_t tile_of_cell(const RunDev &R, const int c[3])
 {
