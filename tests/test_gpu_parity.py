@@ -80,6 +80,38 @@ def test_config1_fp64_parity_200_steps():
     assert g.bunching() == pytest.approx(o.bunching(), rel=1e-10)
 
 
+@pytest.mark.parametrize("which", ["tiny", "small"])
+def test_power_history_matches_oracle_each_step(which):
+    """The power recorded inside each step (partial sums in the vertex-field
+    launch; the tiny run's one-workgroup sort adds them, a separate kernel
+    otherwise) against the oracle's plane power after the same step."""
+    if which == "tiny":
+        w, steps = W.config1(), 24            # 4096 e-: one-workgroup sort ends the step
+    else:
+        w, steps = W.config2_small(field_precision=64), 12  # 20000 e-: multi-block sort
+    d = w.descriptor()
+    xyz, u, q = W.make_bunch(w)
+    o = Oracle(d)
+    o.load_bunch(xyz, u, q)
+    g = engine(d, len(xyz))
+    g.load_bunch(xyz, u, q)
+    want, asked = [], []
+    for _ in range(steps):
+        o.step(1)
+        g.step(1)
+        want.append(o.radiated_power())
+        asked.append(g.radiated_power())  # the on-request path, same fields
+    hist = g.power_history(steps)
+    print(f"[parity] power history {which}: {steps} steps, last {hist[-1]:.6e} W", flush=True)
+    assert len(hist) == steps
+    assert np.all(np.isfinite(hist))
+    np.testing.assert_allclose(hist, np.array(asked), rtol=1e-12, atol=0.0)
+    scale = max(np.max(np.abs(want)), 1e-300)
+    np.testing.assert_allclose(hist, np.array(want), rtol=1e-9, atol=1e-9 * scale)
+    o.close()
+    g.close()
+
+
 @pytest.mark.parametrize("comp", [0, 1])
 def test_config1_fp32_parity_200_steps(comp):
     w = W.config1()
