@@ -33,12 +33,14 @@ hipError_t launch_mur(const RunDev &R, hipStream_t st);
 int sweep_fuses_xfaces(const RunDev &R, int shape);
 hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStream_t st);
 hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st, int end_step = 0);
-hipError_t launch_push_deposit(const RunDev &R, hipStream_t st);
+hipError_t launch_push_deposit(const RunDev &R, hipStream_t st, bool box);
 hipError_t launch_load_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st);
 hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts, bool gather,
-                       int end_step = 0);
-bool sort_ends_step(const RunDev &R);  // launch_sort with end_step ends the step itself
+                       int step_tail = 0);
+// launch_sort with step_tail runs the box reductions before the sort and
+// ends the step after it, in one workgroup, when this holds
+bool sort_ends_step(const RunDev &R);
 hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
                              int32_t *count, hipStream_t st, int32_t *zero);
 hipError_t launch_box_reduce_set(const RunDev &R, int64_t nblocks, hipStream_t st);
@@ -598,7 +600,7 @@ static int enqueue_particles(mithra_handle h, hipStream_t st)
             HIPCHK(h, launch_vertex_power(R, st));
         else
             HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
-        HIPCHK(h, launch_push_deposit(R, st));
+        HIPCHK(h, launch_push_deposit(R, st, !sort_ends_step(R)));
         HIPCHK(h, launch_sort(R, st, true, dep_blocks(R.np), false, 1));
     }
     return MITHRA_OK;

@@ -350,11 +350,14 @@ constexpr int kSmallThreads = 1024;
 constexpr int kSmallChunk = 4096;  // particles the one-workgroup sort takes
 constexpr int kSmallItems = kSmallChunk / kSmallThreads;
 
-// With end_step, the workgroup also ends the step afterwards (the power of
-// the step from the vertex launch's partial sums when the run records it,
-// then the bookkeeping), so a small run's step needs no launch after it.
-__global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R, int end_step)
+// With step_tail, the workgroup is the whole tail of a step after the push:
+// first the box reductions (BoxReduceStep, which the push launcher then
+// skips), then the sort, then the end of the step (the power of the step
+// from the vertex launch's partial sums when the run records it, and the
+// bookkeeping).  A small run's push is then followed by this launch only.
+__global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R, int step_tail)
 {
+    static_assert(kSmallThreads == BoxReduceStep::kThreads, "the box reductions run in this workgroup");
     constexpr int kWaves = kSmallThreads / 64;
     __shared__ uint32_t skey[2][kSmallChunk];
     __shared__ int32_t sval[2][kSmallChunk];
@@ -362,6 +365,10 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R, int end_
     __shared__ uint32_t scan_tmp[4];
     const int n = (int)R.np;  // 1..kSmallChunk (checked by the launcher)
     const Ctl *ctl = R.ctl;
+    if (step_tail) {
+        BoxReduceStep::run(R, Blk{0, 1});
+        __syncthreads();  // the sort range is in the control block
+    }
     const int npass = ctl->npass;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     for (int i = t; i < n; i += kSmallThreads) {
@@ -441,7 +448,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R, int end_
         R.sk[ob][i] = skey[fin][i];
         R.sv[ob][i] = sval[fin][i];
     }
-    if (end_step) {
+    if (step_tail) {
         __syncthreads();  // every read of the control block is done
         if (t < 64) {
             // the first wavefront adds the 64 partial sums (a fixed butterfly)
@@ -553,7 +560,7 @@ int64_t sort_blocks(int64_t n) { return (n + kSortChunk - 1) / kSortChunk; }
 // keys_ready: the push kernels have already written the keys, the slots
 // and `nparts` per-block active-cell boxes in R.cellpart.  The tile work
 // item counter is reset here, before the items of the new order are built.
-hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts, bool gather, int end_step)
+hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts, bool gather, int step_tail)
 {
     if (R.np <= 0)
         return hipSuccess;
@@ -572,7 +579,7 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
         hipLaunchKernelGGL((k_run<SortRange>), dim3(1), dim3(1), 0, st, R);
     }
     if (R.np <= kSmallChunk) {
-        hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSmallThreads), 0, st, R, end_step);
+        hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(kSmallThreads), 0, st, R, step_tail);
     } else {
         // as many passes as the widest key range needs; the ones the current
         // range does not need return at once

@@ -396,4 +396,75 @@ __device__ inline void sort_range(const RunDev &R)
     c->sorted_buf = (np - 1) & 1;
 }
 
+// particles per workgroup of the push (one per thread)
+constexpr int kDepThreads = 256;
+__host__ __device__ inline int64_t dep_blocks_dev(int64_t np) { return (np + kDepThreads - 1) / kDepThreads; }
+
+// both reductions after a push, in one pass over the per-block partials:
+// the deposit box of set (s+1)&1, the active-cell box and the active count,
+// then the key range of the sort that follows; the tile work item counter
+// is reset.  Each thread loads its blocks' two partials as 16-byte vectors,
+// wavefronts reduce with cross-lane operations and one LDS round combines
+// them (min, max and integer sums: the order does not change the result).
+struct BoxReduceStep {
+    static constexpr int kThreads = 1024;
+    static constexpr int kQ = 13;  // dep lo[3], dep hi[3], cell lo[3], cell hi[3], active count
+    static __device__ inline int kind(int a) { return a == 12 ? 2 : ((a / 3) & 1); }  // 0 min, 1 max, 2 sum
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        const int64_t nb = dep_blocks_dev(R.np);
+        const int set = (int)((R.ctl->step + 1) & 1);
+        int32_t v[kQ];
+#pragma unroll
+        for (int a = 0; a < kQ; ++a)
+            v[a] = kind(a) == 0 ? 0x7fffffff : (kind(a) == 1 ? -1 : 0);
+#pragma unroll 2
+        for (int64_t b = threadIdx.x; b < nb; b += kThreads) {
+            const int4 d0 = *(const int4 *)(R.boxpart + 8 * b), d1 = *(const int4 *)(R.boxpart + 8 * b + 4);
+            const int4 c0 = *(const int4 *)(R.cellpart + 8 * b), c1 = *(const int4 *)(R.cellpart + 8 * b + 4);
+            const int32_t q[kQ] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z};
+#pragma unroll
+            for (int a = 0; a < kQ; ++a)
+                v[a] = kind(a) == 0 ? min(v[a], q[a]) : (kind(a) == 1 ? max(v[a], q[a]) : v[a] + q[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < kQ; ++a)
+            for (int o = 32; o > 0; o >>= 1) {
+                const int32_t x = __shfl_xor(v[a], o);
+                v[a] = kind(a) == 0 ? min(v[a], x) : (kind(a) == 1 ? max(v[a], x) : v[a] + x);
+            }
+        __shared__ int32_t sh[kThreads / 64][kQ];
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int a = 0; a < kQ; ++a)
+                sh[wave][a] = v[a];
+        __syncthreads();
+        Ctl *c = R.ctl;
+        if ((int)threadIdx.x < kQ) {
+            const int a = threadIdx.x;
+            int32_t r = sh[0][a];
+            for (int w = 1; w < kThreads / 64; ++w) {
+                const int32_t x = sh[w][a];
+                r = kind(a) == 0 ? min(r, x) : (kind(a) == 1 ? max(r, x) : r + x);
+            }
+            if (a < 3)
+                c->dep_lo[set][a] = r;
+            else if (a < 6)
+                c->dep_hi[set][a - 3] = r;
+            else if (a < 9)
+                c->cell_lo[a - 6] = r;
+            else if (a < 12)
+                c->cell_hi[a - 9] = r;
+            else
+                c->n_active = r;
+        }
+        if (threadIdx.x == 0)
+            c->n_items = 0;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            sort_range(R);  // the offset and pass count of this step's sort
+    }
+};
+
 }  // namespace mithra
