@@ -131,7 +131,7 @@ static const int kBunchBlocks = 256;
 
 struct Layout {
     size_t ctl, pot, src, src_lo, eb, pr, pid, key_by_id, slot_of_id, cell_by_id, key_sorted, sk, sv, hist, boxpart,
-        cellpart, items, items_n, ppart, power, scratch, tile_flag, ntiles, total;
+        cellpart, boxslot, items, items_n, ppart, power, scratch, tile_flag, ntiles, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -165,6 +165,7 @@ static Layout make_layout(const mithra_grid_desc *d, int64_t cap)
     const size_t nparts = std::max((size_t)((c + 255) / 256), (size_t)kPartials);
     L.boxpart = take(8 * 4 * nparts);
     L.cellpart = take(8 * 4 * nparts);
+    L.boxslot = take(16 * 4 * kBoxSlots);
     size_t ntiles = 1;
     for (int a = 0; a < 3; ++a) {
         const size_t cells = (size_t)((a == 0 ? d->nx : (a == 1 ? d->ny : d->nz)) - 1);
@@ -437,6 +438,7 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.hist = (uint32_t *)(A + L.hist);
     R.boxpart = (int32_t *)(A + L.boxpart);
     R.cellpart = (int32_t *)(A + L.cellpart);
+    R.boxslot = (int32_t *)(A + L.boxslot);
     R.items = (int32_t *)(A + L.items);
     R.item_cap = (int64_t)L.items_n;
     R.ppart = (double *)(A + L.ppart);
@@ -469,6 +471,10 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
         c0.cell_hi[a] = -1;
     }
     HIPCHK(h, hipMemcpyAsync(R.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, h->stream));
+    std::vector<int32_t> slots(16 * kBoxSlots);  // every push box slot empty
+    for (int b = 0; b < kBoxSlots; ++b)
+        box_slot_empty(&slots[16 * b]);
+    HIPCHK(h, hipMemcpyAsync(R.boxslot, slots.data(), slots.size() * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, sync_run(h));
     // persistent grid of the tile-owned particle kernel
     // particle kernel: per-block LDS-staged deposit (default; measured faster

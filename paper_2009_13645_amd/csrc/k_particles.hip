@@ -148,7 +148,17 @@ struct PushDeposit {
                     const int32_t x = cw[w][threadIdx.x];
                     v = threadIdx.x < 3 ? min(v, x) : (threadIdx.x < 6 ? max(v, x) : v + x);
                 }
-                R.cellpart[8 * (int64_t)blk.id + threadIdx.x] = v;
+                // into this block's slot (cell box at words 6-11, count at 12)
+                int32_t *slot = R.boxslot + 16 * (blk.id & (kBoxSlots - 1));
+                if (threadIdx.x < 3) {
+                    if (v != 0x7fffffff)
+                        atomicMin(&slot[6 + threadIdx.x], v);
+                } else if (threadIdx.x < 6) {
+                    if (v >= 0)
+                        atomicMax(&slot[6 + threadIdx.x], v);
+                } else if (v != 0) {
+                    atomicAdd(&slot[12], v);
+                }
             }
         }
         // node box of this thread's deposits
@@ -173,9 +183,19 @@ struct PushDeposit {
                 atomicMax(&bb[3 + l], hi[l]);
             }
         __syncthreads();
-        // this block's box goes to its partial slot (reduced by k_box_reduce)
-        if (threadIdx.x < 7)
+        // this block's box: the push reduces it into its slot (BoxReduceStep),
+        // the load deposit writes its partial (k_box_reduce)
+        if (MODE == 0) {
+            if (threadIdx.x < 6 && bb[3] >= 0) {
+                int32_t *slot = R.boxslot + 16 * (blk.id & (kBoxSlots - 1));
+                if (threadIdx.x < 3)
+                    atomicMin(&slot[threadIdx.x], bb[threadIdx.x]);
+                else
+                    atomicMax(&slot[threadIdx.x], bb[threadIdx.x]);
+            }
+        } else if (threadIdx.x < 7) {
             R.boxpart[8 * (int64_t)blk.id + threadIdx.x] = threadIdx.x < 6 ? bb[threadIdx.x] : 0;
+        }
         const int L0 = bb[0], L1 = bb[1], L2 = bb[2];
         if (bb[3] < 0)
             return;  // nothing deposited by this block (uniform)

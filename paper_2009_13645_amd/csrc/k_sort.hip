@@ -357,7 +357,7 @@ constexpr int kSmallItems = kSmallChunk / kSmallThreads;
 // bookkeeping).  A small run's push is then followed by this launch only.
 __global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R, int step_tail)
 {
-    static_assert(kSmallThreads == BoxReduceStep::kThreads, "the box reductions run in this workgroup");
+    static_assert(kSmallThreads >= kBoxSlots, "the box reductions run in this workgroup");
     constexpr int kWaves = kSmallThreads / 64;
     __shared__ uint32_t skey[2][kSmallChunk];
     __shared__ int32_t sval[2][kSmallChunk];

@@ -103,6 +103,7 @@ struct RunDev {
     int64_t sort_blocks;
     int32_t *boxpart;  // per-block partial boxes: [block][8] = lo[3], hi[3], count, pad
     int32_t *cellpart; // per-block partial active-cell boxes of the push kernel, same layout
+    int32_t *boxslot;  // kBoxSlots x 16 boxes of the per-block push, reduced with atomics (layout: BoxReduceStep)
     int32_t *items;    // tile work items [n][4] = tile, begin, end, pad
     int64_t item_cap;
     int tile_grid;     // persistent blocks of the tile push kernel (0: tile kernel not used)
@@ -400,70 +401,60 @@ __device__ inline void sort_range(const RunDev &R)
 constexpr int kDepThreads = 256;
 __host__ __device__ inline int64_t dep_blocks_dev(int64_t np) { return (np + kDepThreads - 1) / kDepThreads; }
 
-// both reductions after a push, in one pass over the per-block partials:
-// the deposit box of set (s+1)&1, the active-cell box and the active count,
-// then the key range of the sort that follows; the tile work item counter
-// is reset.  Each thread loads its blocks' two partials as 16-byte vectors,
-// wavefronts reduce with cross-lane operations and one LDS round combines
-// them (min, max and integer sums: the order does not change the result).
+// After a per-block push: the deposit box of set (s+1)&1, the active-cell
+// box and the active count, then the key range of the sort that follows;
+// the tile work item counter is reset.  The push's workgroups reduce their
+// boxes into kBoxSlots slots with integer atomics (min, max, add: the order
+// does not change the result); here the first wavefront reduces the slots,
+// leaves them empty for the next push, and one thread stores the result.
+// Slot layout (16 words): dep lo[3], dep hi[3], cell lo[3], cell hi[3],
+// active count, pad[3].  Every thread of the block must call it (barriers).
+constexpr int kBoxSlots = 64;
+
+__host__ __device__ inline void box_slot_empty(int32_t q[16])
+{
+    for (int a = 0; a < 16; ++a)
+        q[a] = (a < 3 || (a >= 6 && a < 9)) ? 0x7fffffff : ((a < 12) ? -1 : 0);
+}
+
 struct BoxReduceStep {
-    static constexpr int kThreads = 1024;
-    static constexpr int kQ = 13;  // dep lo[3], dep hi[3], cell lo[3], cell hi[3], active count
-    static __device__ inline int kind(int a) { return a == 12 ? 2 : ((a / 3) & 1); }  // 0 min, 1 max, 2 sum
+    static constexpr int kThreads = 64;
     static __device__ void run(const RunDev &R, Blk blk)
     {
-        const int64_t nb = dep_blocks_dev(R.np);
         const int set = (int)((R.ctl->step + 1) & 1);
-        int32_t v[kQ];
-#pragma unroll
-        for (int a = 0; a < kQ; ++a)
-            v[a] = kind(a) == 0 ? 0x7fffffff : (kind(a) == 1 ? -1 : 0);
-#pragma unroll 2
-        for (int64_t b = threadIdx.x; b < nb; b += kThreads) {
-            const int4 d0 = *(const int4 *)(R.boxpart + 8 * b), d1 = *(const int4 *)(R.boxpart + 8 * b + 4);
-            const int4 c0 = *(const int4 *)(R.cellpart + 8 * b), c1 = *(const int4 *)(R.cellpart + 8 * b + 4);
-            const int32_t q[kQ] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z};
-#pragma unroll
-            for (int a = 0; a < kQ; ++a)
-                v[a] = kind(a) == 0 ? min(v[a], q[a]) : (kind(a) == 1 ? max(v[a], q[a]) : v[a] + q[a]);
-        }
-#pragma unroll
-        for (int a = 0; a < kQ; ++a)
-            for (int o = 32; o > 0; o >>= 1) {
-                const int32_t x = __shfl_xor(v[a], o);
-                v[a] = kind(a) == 0 ? min(v[a], x) : (kind(a) == 1 ? max(v[a], x) : v[a] + x);
-            }
-        __shared__ int32_t sh[kThreads / 64][kQ];
-        const int wave = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0)
-#pragma unroll
-            for (int a = 0; a < kQ; ++a)
-                sh[wave][a] = v[a];
-        __syncthreads();
         Ctl *c = R.ctl;
-        if ((int)threadIdx.x < kQ) {
-            const int a = threadIdx.x;
-            int32_t r = sh[0][a];
-            for (int w = 1; w < kThreads / 64; ++w) {
-                const int32_t x = sh[w][a];
-                r = kind(a) == 0 ? min(r, x) : (kind(a) == 1 ? max(r, x) : r + x);
+        if (threadIdx.x < (unsigned)kBoxSlots) {
+            static_assert(kBoxSlots == 64, "one slot per lane of the first wavefront");
+            int4 *q = (int4 *)(R.boxslot + 16 * threadIdx.x);
+            const int4 a0 = q[0], a1 = q[1], a2 = q[2], a3 = q[3];
+            int32_t v[13] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w, a2.x, a2.y, a2.z, a2.w, a3.x};
+            int32_t e[16];
+            box_slot_empty(e);
+            q[0] = make_int4(e[0], e[1], e[2], e[3]);
+            q[1] = make_int4(e[4], e[5], e[6], e[7]);
+            q[2] = make_int4(e[8], e[9], e[10], e[11]);
+            q[3] = make_int4(e[12], e[13], e[14], e[15]);
+#pragma unroll
+            for (int a = 0; a < 13; ++a) {
+                const int kind = a == 12 ? 2 : ((a / 3) & 1);  // 0 min, 1 max, 2 sum
+                for (int o = 32; o > 0; o >>= 1) {
+                    const int32_t x = __shfl_xor(v[a], o);
+                    v[a] = kind == 0 ? min(v[a], x) : (kind == 1 ? max(v[a], x) : v[a] + x);
+                }
             }
-            if (a < 3)
-                c->dep_lo[set][a] = r;
-            else if (a < 6)
-                c->dep_hi[set][a - 3] = r;
-            else if (a < 9)
-                c->cell_lo[a - 6] = r;
-            else if (a < 12)
-                c->cell_hi[a - 9] = r;
-            else
-                c->n_active = r;
+            if (threadIdx.x == 0) {
+                for (int a = 0; a < 3; ++a) {
+                    c->dep_lo[set][a] = v[a];
+                    c->dep_hi[set][a] = v[3 + a];
+                    c->cell_lo[a] = v[6 + a];
+                    c->cell_hi[a] = v[9 + a];
+                }
+                c->n_active = v[12];
+                c->n_items = 0;
+                sort_range(R);  // the offset and pass count of this step's sort
+            }
         }
-        if (threadIdx.x == 0)
-            c->n_items = 0;
         __syncthreads();
-        if (threadIdx.x == 0)
-            sort_range(R);  // the offset and pass count of this step's sort
     }
 };
 
