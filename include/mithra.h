@@ -66,7 +66,7 @@ enum mithra_dtype { MITHRA_DTYPE_F32 = 0, MITHRA_DTYPE_F64 = 1 };
  * step) and UNDULATOR group (undulator parameter, period, length,
  * polarization angle), with the mesh already in the boosted frame. */
 typedef struct mithra_grid_desc {
-    int32_t nx, ny, nz;          /* nodes per axis, >= 6 each */
+    int32_t nx, ny, nz;          /* nodes per axis, 6..2^20 each */
     int32_t truncation_order;    /* Mur order: 1 or 2 */
     int32_t space_charge;        /* 1: solve for phi; 0: phi = 0 */
     int32_t solver;              /* 0: NSFD (only NSFD is built) */

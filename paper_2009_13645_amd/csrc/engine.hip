@@ -245,6 +245,8 @@ static const char *validate(const mithra_grid_desc *d)
         return "each of nx, ny, nz must be >= 6";
     if ((double)d->nx * d->ny * d->nz > 4.0e9)
         return "grid too large";
+    if (d->nx > (1 << 20) || d->ny > (1 << 20) || d->nz > (1 << 20))
+        return "each of nx, ny, nz must be <= 2^20";
     if (d->truncation_order != 1 && d->truncation_order != 2)
         return "truncation_order must be 1 or 2";
     if (d->space_charge != 0 && d->space_charge != 1)
@@ -396,6 +398,7 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.np_cap = d->max_particles;
     for (int a = 0; a < 3; ++a) {
         R.tile[a] = d->tile[a];
+        R.tdiv[a] = fast_div((uint32_t)d->tile[a]);
         const int cells = (a == 0 ? d->nx : (a == 1 ? d->ny : d->nz)) - 1;
         R.ntile[a] = (cells + d->tile[a] - 1) / d->tile[a];
     }

@@ -903,9 +903,9 @@ __device__ inline bool node_needed(const RunDev &R, int64_t s, int i, int j, int
     const uint32_t want = (uint32_t)s;
     const int c0[3] = {max(i - 1, 1), max(j - 1, 1), max(k - 1, 1)};
     const int c1[3] = {min(i, R.nx - 3), min(j, R.ny - 3), min(k, R.nz - 3)};
-    const int tx0 = c0[0] / R.tile[0], tx1 = c1[0] / R.tile[0];
-    const int ty0 = c0[1] / R.tile[1], ty1 = c1[1] / R.tile[1];
-    const int tz0 = c0[2] / R.tile[2], tz1 = c1[2] / R.tile[2];
+    const int tx0 = (int)fdiv((uint32_t)c0[0], R.tdiv[0]), tx1 = (int)fdiv((uint32_t)c1[0], R.tdiv[0]);
+    const int ty0 = (int)fdiv((uint32_t)c0[1], R.tdiv[1]), ty1 = (int)fdiv((uint32_t)c1[1], R.tdiv[1]);
+    const int tz0 = (int)fdiv((uint32_t)c0[2], R.tdiv[2]), tz1 = (int)fdiv((uint32_t)c1[2], R.tdiv[2]);
     for (int tz = tz0; tz <= tz1; ++tz)
         for (int ty = ty0; ty <= ty1; ++ty)
             for (int tx = tx0; tx <= tx1; ++tx)

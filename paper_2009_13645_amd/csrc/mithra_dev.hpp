@@ -46,6 +46,17 @@ struct Ctl {
 
 constexpr int kMaxBatch = 1;  // one run per RunDev
 
+// floor(t / d) by a multiply-high with m = ceil(2^32 / d): exact whenever
+// t * d < 2^32 (the error of m is below 1, so t m / 2^32 stays below the
+// next integer); for index decoding by a divisor that is uniform per launch.
+struct FastDiv {
+    uint32_t d, m;
+};
+
+__host__ __device__ inline FastDiv fast_div(uint32_t d) { return FastDiv{d, d == 1 ? 0u : 0xFFFFFFFFu / d + 1u}; }
+
+__device__ inline uint32_t fdiv(uint32_t t, FastDiv f) { return f.d == 1 ? t : __umulhi(t, f.m); }
+
 struct RunDev {
     // mesh
     int nx, ny, nz;
@@ -104,6 +115,7 @@ struct RunDev {
     int32_t *boxpart;  // per-block partial boxes: [block][8] = lo[3], hi[3], count, pad
     int32_t *cellpart; // per-block partial active-cell boxes of the push kernel, same layout
     int32_t *boxslot;  // kBoxSlots x 16 boxes of the per-block push, reduced with atomics (layout: BoxReduceStep)
+    FastDiv tdiv[3];   // division by the sort tile dims (exact: cell index x tile dim < 2^32)
     int32_t *items;    // tile work items [n][4] = tile, begin, end, pad
     int64_t item_cap;
     int tile_grid;     // persistent blocks of the tile push kernel (0: tile kernel not used)
@@ -174,16 +186,6 @@ __device__ inline void vstore(T *p, const Vec<T, V> &a)
     }
 }
 
-// floor(t / d) by a multiply-high with m = ceil(2^32 / d): exact whenever
-// t * d < 2^32 (the error of m is below 1, so t m / 2^32 stays below the
-// next integer); for index decoding by a divisor that is uniform per launch.
-struct FastDiv {
-    uint32_t d, m;
-};
-
-__host__ __device__ inline FastDiv fast_div(uint32_t d) { return FastDiv{d, d == 1 ? 0u : 0xFFFFFFFFu / d + 1u}; }
-
-__device__ inline uint32_t fdiv(uint32_t t, FastDiv f) { return f.d == 1 ? t : __umulhi(t, f.m); }
 
 // E and B at the vertices are stored node-interleaved: node n holds
 // Ex Ey Ez Bx By Bz and two pad words at eb[8 n .. 8 n + 7] (32 bytes in FP32,
