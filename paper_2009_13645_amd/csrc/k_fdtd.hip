@@ -716,7 +716,7 @@ __device__ inline void clear_next_sources(const RunDev &R, int64_t b, int64_t nb
 static __host__ __device__ inline int64_t clear_blocks_of(int ny, int nz)
 {
     const int64_t r = (int64_t)ny * nz / 64;
-    return r < 8 ? 8 : (r > 1024 ? 1024 : r);
+    return r < 8 ? 8 : (r > 2048 ? 2048 : r);
 }
 
 // Face nodes of the boundary, one thread each (per component): z faces, y
