@@ -1011,7 +1011,7 @@ struct PlanePower {
 };
 
 struct PlanePowerFinal {
-    static constexpr int kThreads = 1;
+    static constexpr int kThreads = 64;
     static __device__ void run(const RunDev &R, Blk blk, int step_bias, double *out, int end_step)
     {
         plane_power_final(R, R.ctl->step + step_bias, out, end_step);
@@ -1181,7 +1181,7 @@ hipError_t launch_vertex_power(const RunDev &R, hipStream_t st)
 
 hipError_t launch_power_final(const RunDev &R, hipStream_t st, int end_step)
 {
-    hipLaunchKernelGGL((k_run<PlanePowerFinal, int, double *, int>), dim3(1), dim3(1), 0, st, R, 0, (double *)nullptr,
+    hipLaunchKernelGGL((k_run<PlanePowerFinal, int, double *, int>), dim3(1), dim3(64), 0, st, R, 0, (double *)nullptr,
                        end_step);
     return hipGetLastError();
 }
@@ -1204,7 +1204,7 @@ hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *ou
         hipLaunchKernelGGL((k_run<PlanePower<float>, int, int>), dim3(kPowerBlocks), dim3(256), 0, st, R, step_bias, kp);
     else
         hipLaunchKernelGGL((k_run<PlanePower<double>, int, int>), dim3(kPowerBlocks), dim3(256), 0, st, R, step_bias, kp);
-    hipLaunchKernelGGL((k_run<PlanePowerFinal, int, double *, int>), dim3(1), dim3(1), 0, st, R, step_bias, out, end_step);
+    hipLaunchKernelGGL((k_run<PlanePowerFinal, int, double *, int>), dim3(1), dim3(64), 0, st, R, step_bias, out, end_step);
     return hipGetLastError();
 }
 
@@ -1328,7 +1328,7 @@ hipError_t launch_power_group(const Group &g, int64_t total, const Group &gf, in
         hipLaunchKernelGGL((k_group<PlanePower<float>, int, int>), dim3((unsigned)total), dim3(256), 0, st, g, 0, -1);
     else
         hipLaunchKernelGGL((k_group<PlanePower<double>, int, int>), dim3((unsigned)total), dim3(256), 0, st, g, 0, -1);
-    hipLaunchKernelGGL((k_group<PlanePowerFinal, int, double *, int>), dim3((unsigned)total_f), dim3(1), 0, st, gf, 0,
+    hipLaunchKernelGGL((k_group<PlanePowerFinal, int, double *, int>), dim3((unsigned)total_f), dim3(64), 0, st, gf, 0,
                        (double *)nullptr, 0);
     return hipGetLastError();
 }

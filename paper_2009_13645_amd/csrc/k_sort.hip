@@ -451,22 +451,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R, int step
     if (step_tail) {
         __syncthreads();  // every read of the control block is done
         if (t < 64) {
-            // the first wavefront adds the 64 partial sums (a fixed butterfly)
-            double x = 0.0;
-            if (R.record_power) {
-                static_assert(kPowerBlocks == 64, "one partial sum per lane");
-                x = R.ppart[t];
-                for (int o = 1; o < 64; o <<= 1)
-                    x += __shfl_xor(x, o);
-            }
-            if (t == 0) {
-                if (R.record_power)
-                    plane_power_store(R, R.ctl->step, x, nullptr, 1);
-                else {
-                    R.ctl->pbuf ^= 1;
-                    R.ctl->nsort += 1;
-                    R.ctl->step += 1;
-                }
+            if (R.record_power)
+                plane_power_final(R, R.ctl->step, nullptr, 1);  // the first wavefront adds the partial sums
+            else if (t == 0) {
+                R.ctl->pbuf ^= 1;
+                R.ctl->nsort += 1;
+                R.ctl->step += 1;
             }
         }
     }

@@ -341,13 +341,18 @@ __device__ inline void plane_power_store(const RunDev &R, int64_t s, double sum,
     }
 }
 
-// The same with the partial sums added in fixed order by one thread.
+// The same with the partial sums added by the calling wavefront (lane l
+// loads partial l, a fixed butterfly adds them, lane 0 stores).  The whole
+// first wavefront of the block must call it.
 __device__ inline void plane_power_final(const RunDev &R, int64_t s, double *out, int end_step)
 {
-    double sum = 0.0;
-    for (int b = 0; b < kPowerBlocks; ++b)
-        sum += R.ppart[b];
-    plane_power_store(R, s, sum, out, end_step);
+    static_assert(kPowerBlocks == 64, "one partial sum per lane");
+    const int lane = threadIdx.x & 63;
+    double x = R.ppart[lane];
+    for (int o = 1; o < 64; o <<= 1)
+        x += __shfl_xor(x, o);
+    if (lane == 0)
+        plane_power_store(R, s, x, out, end_step);
 }
 
 // Linear index of the sort tile of an active cell c (tile-major order).
