@@ -491,7 +491,7 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
         R.tile_grid = std::min(cus * tile_blocks_per_cu(d->field_precision, d->compensated), kPartials - 128);
     }
     // default sweep tile (measured): grids of up to 2^20 nodes take chunks
-    // of 8 or 16 planes, so that enough workgroups run (vector tiles when the
+    // of 4 or 16 planes, so that enough workgroups run (vector tiles when the
     // row length allows 16-byte vectors, else the scalar tiles); larger grids
     // take vector tiles 32 nodes wide for short rows, else 64 nodes wide over
     // 16 planes (the best at 128-node rows)

@@ -1099,7 +1099,7 @@ static hipError_t launch_sweep_shape(const RunDev &R, int shape, hipStream_t st)
     case 12: return launch_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 64>(R, st);
     case 13: return launch_sweep_vec_t<T, V, 32 / V, 256 * V / 32, 32>(R, st);
     case 14: return launch_sweep_vec_t<T, V, 128 / V, 256 * V / 128, 16>(R, st);
-    case 15: return launch_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 8>(R, st);
+    case 15: return launch_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 4>(R, st);
     case 16: return launch_sweep_vec_t<T, V, 128 / V, 1024 * V / 128, 16>(R, st);
     case 17: return launch_sweep_vec_t<T, V, 64 / V, 512 * V / 64, 16>(R, st);
     case 0: return launch_sweep_t<T, 64, 8, 32>(R, st);
@@ -1123,7 +1123,7 @@ void sweep_shape_dims(int shape, int *tx, int *ty, int *tz)
     static const int d[18][3] = {{64, 8, 32},  {64, 4, 32},  {32, 8, 32},  {64, 8, 64},  {128, 4, 32},
                                  {64, 16, 32}, {32, 4, 16},  {64, 8, 16},  {128, 16, 32}, {128, 8, 32},
                                  {64, 32, 32}, {128, 16, 16}, {128, 16, 64}, {32, 32, 32}, {128, 8, 16},
-                                 {128, 16, 8}, {128, 32, 16}, {64, 32, 16}};
+                                 {128, 16, 4}, {128, 32, 16}, {64, 32, 16}};
     *tx = d[shape][0];
     *ty = d[shape][1];
     *tz = d[shape][2];
@@ -1260,7 +1260,7 @@ static hipError_t grp_sweep(const Group &g, int64_t total, int shape, bool lo, h
     case 12: grp_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 64>(g, total, lo, st); break;
     case 13: grp_sweep_vec_t<T, V, 32 / V, 256 * V / 32, 32>(g, total, lo, st); break;
     case 14: grp_sweep_vec_t<T, V, 128 / V, 256 * V / 128, 16>(g, total, lo, st); break;
-    case 15: grp_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 8>(g, total, lo, st); break;
+    case 15: grp_sweep_vec_t<T, V, 128 / V, 512 * V / 128, 4>(g, total, lo, st); break;
     case 16: grp_sweep_vec_t<T, V, 128 / V, 1024 * V / 128, 16>(g, total, lo, st); break;
     case 17: grp_sweep_vec_t<T, V, 64 / V, 512 * V / 64, 16>(g, total, lo, st); break;
     case 0: grp_sweep_t<T, 64, 8, 32>(g, total, st); break;
