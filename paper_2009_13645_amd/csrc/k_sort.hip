@@ -25,7 +25,7 @@
 namespace mithra {
 
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 8;
 constexpr int kSortChunk = kSortThreads * kSortItems;  // elements per block
 
 __device__ inline uint32_t particle_key(const RunDev &R, double x, double y, double z, int c[3], bool &act)
@@ -280,7 +280,7 @@ __device__ __attribute__((always_inline)) inline void radix_scatter_blk(const ui
     // elements of the same digit.  The lowest lane of each group of equal
     // digits adds the group's size to the wavefront's counter and gets the
     // count before it; LDS executes one wavefront's atomics in issue order,
-    // so all 16 can be in flight before the first result is used.
+    // so all of them can be in flight before the first result is used.
     // dp: digit (bits 0-7), leader lane (8-13), rank in the group (14-20).
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     uint32_t dp[kSortItems], before[kSortItems];
