@@ -77,6 +77,19 @@ typedef struct {
     int64_t step;
     int loaded;
     int generic_faces;                  /* test hook: first-order faces via the residual solve */
+    /* undulator extensions (ora_set_undulator) */
+    int n_modules;                      /* static array: modules, K_m = K + m dK */
+    double gap, dK;                     /* lab gap between modules (m), tapering step of K */
+    int opt_signal;                     /* optical: signal type (0 Neumann, 1 Gaussian, 2 sech, 3 sinusoidal) */
+    double opt_a0, opt_lambda, opt_ctau, opt_ct0, opt_cep; /* strength, wavelength, pulse length, offset, CEP (deg) */
+    double opt_w0[2], opt_zf;           /* Gaussian beam: waists along / across the polarisation, focus (lab z') */
+    /* TF/SF seed (ora_set_seed) */
+    int seed_on, seed_type, seed_signal;
+    double seed_a0, seed_lambda, seed_ctau, seed_ct0, seed_cep, seed_pol_deg, seed_w0, seed_zf;
+    /* spectral power through the diagnostic plane (ora_set_spectrum) */
+    int nf;
+    double *omega;                      /* boosted angular frequencies */
+    double *spec;                       /* [nf][8][nx*ny]: re/im of Ex' Ey' Bx' By' (lab) */
 } ora_state;
 
 static inline int64_t IDX(const ora_state *S, int i, int j, int k)
@@ -103,8 +116,14 @@ void *ora_create(const ora_desc *d)
     else
         S->gamma0 = d->gamma / sqrt(1.0 + 0.5 * d->K * d->K);
     S->beta0 = sqrt(1.0 - 1.0 / (S->gamma0 * S->gamma0));
-    /* dispersion-free along z: dt = dz / c; bunch step dt_b = dt / N */
-    S->dt = d->dz / c_light;
+    /* NSFD: dispersion-free along z with dt = dz / c.  Standard FD cannot
+     * take that step (it violates the stability condition, eq.
+     * CFLcondition); reading: it takes 0.99 of the largest stable step
+     * 1 / (c sqrt(1/dx^2 + 1/dy^2 + 1/dz^2)).  Bunch step dt_b = dt / N. */
+    if (d->solver == 1)
+        S->dt = 0.99 / (c_light * sqrt(1.0 / (d->dx * d->dx) + 1.0 / (d->dy * d->dy) + 1.0 / (d->dz * d->dz)));
+    else
+        S->dt = d->dz / c_light;
     S->dtb = S->dt / (double)(d->n_sub > 0 ? d->n_sub : 1);
 
     double cdt = c_light * S->dt;
@@ -139,6 +158,7 @@ void *ora_create(const ora_desc *d)
         S->B[c] = (double *)calloc((size_t)S->nn, sizeof(double));
     }
     S->rho = (double *)calloc((size_t)S->nn, sizeof(double));
+    S->n_modules = 1;
     return S;
 }
 
@@ -159,6 +179,8 @@ void ora_destroy(void *h)
         free(S->r_old[c]);
     }
     free(S->rho);
+    free(S->omega);
+    free(S->spec);
     free(S->key);
     free(S->perm);
     free(S->cell);
@@ -492,29 +514,153 @@ static void gather(const ora_state *S, const double r[3], double E[3], double B[
 /* upstream by a quarter period.                                        */
 /* ------------------------------------------------------------------ */
 
+/* Window of the fringe fields inside the gap of an undulator array (eq.
+ * fringingFieldGap and the window function after it): 1 at the module
+ * edge (dz = 0), about 6e-5 at the far end of the gap (dz = g). */
+static double gap_window(double dz, double g)
+{
+    double t = PI_ * dz / g;
+    return 0.35875 + 0.48829 * cos(t) + 0.14128 * cos(2.0 * t) + 0.01168 * cos(3.0 * t);
+}
+
+/* Longitudinal profile of the planar pattern at lab position zl (entrance
+ * of the first module at 0): *gB multiplies cosh(k_u eta) for the
+ * transverse field, *hB multiplies sinh(k_u eta) for B'_z; both include
+ * the module's field amplitude B0_m = 2 pi m c K_m / (e lambda_u),
+ * K_m = K + m dK (tapering).  Modules of N_u periods are separated by
+ * gaps g.  Inside a module: sin and cos of k_u (zl - entrance).  Before the
+ * first entrance and after the last exit: the fringe of eq. fringingField
+ * (reading: the exit mirrors the entrance).  Inside a gap: the exit fringe
+ * of the module before and the entrance fringe of the module after, each
+ * times the gap window of its distance to its own edge. */
+static void array_profile(const ora_state *S, double zl, double *gB, double *hB)
+{
+    const double ku = 2.0 * PI_ / S->d.lambda_u;
+    const double Lu = S->d.n_periods * S->d.lambda_u;
+    const int M = S->n_modules > 0 ? S->n_modules : 1;
+    const double pitch = Lu + S->gap;
+    double B0[2];
+    int m = (int)floor(zl / pitch);
+    if (m < 0)
+        m = 0;
+    if (m > M - 1)
+        m = M - 1;
+    const double ent = m * pitch, ext = ent + Lu;
+    B0[0] = 2.0 * PI_ * m_e * c_light * (S->d.K + m * S->dK) / (q_e * S->d.lambda_u);
+    if (zl >= ent && zl <= ext) {
+        *gB = B0[0] * sin(ku * (zl - ent));
+        *hB = B0[0] * cos(ku * (zl - ent));
+        return;
+    }
+    if (zl < ent) { /* before the first module (m == 0) */
+        double a = ku * (zl - ent), e = exp(-0.5 * a * a);
+        *gB = B0[0] * (a * e);
+        *hB = B0[0] * e;
+        return;
+    }
+    /* after module m's exit */
+    double a1 = ku * (zl - ext), e1 = exp(-0.5 * a1 * a1);
+    if (m == M - 1) {
+        *gB = B0[0] * (a1 * e1);
+        *hB = B0[0] * e1;
+        return;
+    }
+    const double ent2 = (m + 1) * pitch;
+    B0[1] = 2.0 * PI_ * m_e * c_light * (S->d.K + (m + 1) * S->dK) / (q_e * S->d.lambda_u);
+    double a2 = ku * (zl - ent2), e2 = exp(-0.5 * a2 * a2);
+    double f1 = gap_window(zl - ext, S->gap), f2 = gap_window(ent2 - zl, S->gap);
+    *gB = B0[0] * (a1 * e1) * f1 + B0[1] * (a2 * e2) * f2;
+    *hB = B0[0] * e1 * f1 + B0[1] * e2 * f2;
+}
+
 static void lab_planar(const ora_state *S, double x, double y, double zl, double theta, double Bl[3])
 {
     double ku = 2.0 * PI_ / S->d.lambda_u;
-    double B0 = 2.0 * PI_ * m_e * c_light * S->d.K / (q_e * S->d.lambda_u);
-    double Lu = S->d.n_periods * S->d.lambda_u;
     double eta = x * sin(theta) + y * cos(theta);
-    double gfun, hfun;
-    if (zl < 0.0) {
-        double s = ku * zl;
-        gfun = s * exp(-0.5 * s * s);
-        hfun = exp(-0.5 * s * s);
-    } else if (zl > Lu) {
-        double s = ku * (zl - Lu);
-        gfun = s * exp(-0.5 * s * s);
-        hfun = exp(-0.5 * s * s);
-    } else {
-        gfun = sin(ku * zl);
-        hfun = cos(ku * zl);
-    }
-    double Bperp = B0 * cosh(ku * eta) * gfun;
+    double gB, hB;
+    array_profile(S, zl, &gB, &hB);
+    double Bperp = gB * cosh(ku * eta);
     Bl[0] = Bperp * sin(theta);
     Bl[1] = Bperp * cos(theta);
-    Bl[2] = B0 * sinh(ku * eta) * hfun;
+    Bl[2] = hB * sinh(ku * eta);
+}
+
+/* Time signature of an optical pulse (eq. signalTypes) with unit
+ * amplitude: tau is the retarded time, f the carrier frequency, tp the
+ * pulse duration (FWHM of the intensity), t0 the offset, ph the phase.
+ * The modulated Neumann form is scaled by tp so that it is dimensionless
+ * (reading: the printed form carries a 1/time factor). */
+static double signal_value(int type, double tau, double f, double tp, double t0, double ph)
+{
+    double d = tau - t0;
+    double car = cos(2.0 * PI_ * f * d + ph);
+    double ln2 = log(2.0);
+    switch (type) {
+    case 0:
+        return -4.0 * ln2 * car * (d / tp) * exp(-2.0 * ln2 * d * d / (tp * tp));
+    case 1:
+        return car * exp(-2.0 * ln2 * d * d / (tp * tp));
+    case 2:
+        return car / cosh(d / tp);
+    default:
+        return d <= 0.0 ? car * exp(-2.0 * ln2 * d * d / (tp * tp)) : car;
+    }
+}
+
+/* Lab-frame fields of the optical undulator (sec. "Optical Undulator
+ * Field"), a wave propagating along -z with strength a0 = K and
+ * wavelength lambda_l = 2 lambda_u (the static undulator it matches).
+ * Its magnetic field points along (sin theta, cos theta, 0) like the static
+ * field, its electric field along p = (-cos theta, sin theta, 0).
+ * Field amplitude E0 = a0 m c omega / e.  Plane wave (und_type 2): eq.
+ * opticalUndulatorPW.  Gaussian beam (und_type 3): eq. opticalUndulatorGB
+ * with w(l) = w0 sqrt(1 + (l/z_R)^2) and R(l) = l (1 + (z_R/l)^2)
+ * (reading of the printed r/z_R), l = z_f - z' the distance along the
+ * propagation from the focus, E_perp = B_par = 0. */
+static void lab_optical(const ora_state *S, double x, double y, double zl, double tl, double El[3], double Bl[3])
+{
+    const double th = S->d.pol_angle_deg * PI_ / 180.0;
+    const double lam = 2.0 * S->d.lambda_u;
+    const double om = 2.0 * PI_ * c_light / lam;
+    const double E0 = S->d.K * m_e * c_light * om / q_e;
+    const double f = c_light / lam, tp = S->opt_ctau / c_light, t0 = S->opt_ct0 / c_light;
+    const double cep = S->opt_cep * PI_ / 180.0;
+    const double p[3] = {-cos(th), sin(th), 0.0}; /* E direction */
+    const double q[3] = {sin(th), cos(th), 0.0};  /* B direction, (-z) x p */
+    if (S->d.und_type == 2) {
+        double sv = signal_value(S->opt_signal, tl + zl / c_light, f, tp, t0, cep);
+        for (int a = 0; a < 3; ++a) {
+            El[a] = E0 * sv * p[a];
+            Bl[a] = (E0 / c_light) * sv * q[a];
+        }
+        return;
+    }
+    const double k0 = 2.0 * PI_ / lam;
+    const double l = S->opt_zf - zl;
+    const double rp = x * p[0] + y * p[1], rq = x * q[0] + y * q[1]; /* along / across the polarisation */
+    const double w0p = S->opt_w0[0], w0q = S->opt_w0[1];
+    const double zRp = PI_ * w0p * w0p / lam, zRq = PI_ * w0q * w0q / lam;
+    const double wp = w0p * sqrt(1.0 + (l / zRp) * (l / zRp)), wq = w0q * sqrt(1.0 + (l / zRq) * (l / zRq));
+    const double iRp = l / (l * l + zRp * zRp), iRq = l / (l * l + zRq * zRq);
+    const double amp = sqrt((w0p * w0q) / (wp * wq)) * exp(-rq * rq / (wq * wq) - rp * rp / (wp * wp));
+    const double curv = -0.5 * k0 * rp * rp * iRp - 0.5 * k0 * rq * rq * iRq;
+    const double Gp = atan(l / zRp), Gq = atan(l / zRq);
+    const double tau = tl - l / c_light; /* retarded time along the propagation */
+    const double Epar = E0 * amp * signal_value(S->opt_signal, tau, f, tp, t0, cep + curv - 0.5 * PI_ + 0.5 * (Gp + Gq));
+    const double Elon = E0 * (rp * w0p / (zRp * wp)) * amp *
+                        signal_value(S->opt_signal, tau, f, tp, t0, cep + curv + 0.5 * (3.0 * Gp + Gq));
+    const double Blon = (E0 / c_light) * (rq * w0q / (zRq * wq)) * amp *
+                        signal_value(S->opt_signal, tau, f, tp, t0, cep + curv + 0.5 * (Gp + 3.0 * Gq));
+    /* propagation direction -z: E = E_par p + E_l (-z), B = (E_par / c) q + B_l (-z);
+     * with l along the propagation, r_par along p and r_perp along q the
+     * printed longitudinal components make both fields divergence-free to
+     * paraxial order */
+    for (int a = 0; a < 2; ++a) {
+        El[a] = Epar * p[a];
+        Bl[a] = (Epar / c_light) * q[a];
+    }
+    El[2] = -Elon;
+    Bl[2] = -Blon;
 }
 
 void ora_external_field(void *h, const double r[3], double t, double E[3], double B[3])
@@ -522,9 +668,13 @@ void ora_external_field(void *h, const double r[3], double t, double E[3], doubl
     ora_state *S = (ora_state *)h;
     double g0 = S->gamma0, b0 = S->beta0;
     double zl = g0 * (r[2] - S->d.z_entrance + b0 * c_light * t);
-    double Bl[3] = {0, 0, 0}, tmp[3];
+    double Bl[3] = {0, 0, 0}, El[3] = {0, 0, 0}, tmp[3];
     double th = S->d.pol_angle_deg * PI_ / 180.0;
-    if (S->d.und_type == 1) {
+    if (S->d.und_type >= 2) {
+        /* lab time of the event: t' = gamma0 (t + beta0 (z - z_entrance) / c) */
+        double tl = g0 * (t + b0 * (r[2] - S->d.z_entrance) / c_light);
+        lab_optical(S, r[0], r[1], zl, tl, El, Bl);
+    } else if (S->d.und_type == 1) {
         lab_planar(S, r[0], r[1], zl, 0.0, tmp);
         for (int a = 0; a < 3; ++a)
             Bl[a] += tmp[a];
@@ -534,13 +684,34 @@ void ora_external_field(void *h, const double r[3], double t, double E[3], doubl
     } else {
         lab_planar(S, r[0], r[1], zl, th, Bl);
     }
-    /* E = g0 (E' + c beta0 z x B') - (g0-1) E'_z z ; B = g0 B' - (g0-1) B'_z z */
-    E[0] = g0 * (c_light * b0 * (-Bl[1]));
-    E[1] = g0 * (c_light * b0 * (Bl[0]));
-    E[2] = 0.0;
-    B[0] = g0 * Bl[0];
-    B[1] = g0 * Bl[1];
+    /* eqs. LorentzTransformElectric/Magnetic with beta0 along z:
+     * E = g0 (E' + c beta0 z x B') - (g0-1) E'_z z ; B = g0 (B' - beta0 z x E' / c) - (g0-1) B'_z z */
+    E[0] = g0 * (El[0] + c_light * b0 * (-Bl[1]));
+    E[1] = g0 * (El[1] + c_light * b0 * (Bl[0]));
+    E[2] = g0 * El[2] - (g0 - 1.0) * El[2];
+    B[0] = g0 * (Bl[0] - b0 * (-El[1]) / c_light);
+    B[1] = g0 * (Bl[1] - b0 * (El[0]) / c_light);
     B[2] = g0 * Bl[2] - (g0 - 1.0) * Bl[2];
+}
+
+/* Undulator extensions: p[0] modules, p[1] gap (lab, m), p[2] tapering
+ * step dK, p[3] optical signal type, p[4] pulse length c tau (lab, m),
+ * p[5] offset c t0 (lab, m), p[6] CEP (deg), p[7] Gaussian-beam waist along
+ * the polarisation, p[8] waist across it (m), p[9] focus (lab z' relative to
+ * the undulator reference, m). */
+void ora_set_undulator(void *h, const double *p)
+{
+    ora_state *S = (ora_state *)h;
+    S->n_modules = (int)p[0];
+    S->gap = p[1];
+    S->dK = p[2];
+    S->opt_signal = (int)p[3];
+    S->opt_ctau = p[4];
+    S->opt_ct0 = p[5];
+    S->opt_cep = p[6];
+    S->opt_w0[0] = p[7];
+    S->opt_w0[1] = p[8];
+    S->opt_zf = p[9];
 }
 
 /* ------------------------------------------------------------------ */
@@ -802,6 +973,184 @@ static void rotate_levels(ora_state *S)
     }
 }
 
+/* ------------------------------------------------------------------ */
+/* Seed field by total-field / scattered-field injection (sec. "Seed   */
+/* Field").  Nodes k = 1 (scattered-field boundary) and k = 2 (total-    */
+/* field boundary) next to the z_min face: after the update of A, the   */
+/* terms through which each used the other region's values are          */
+/* corrected by the incident wave f at time level n.  Reading of the    */
+/* signs: the printed corrections add the incident wave at the SF node  */
+/* and subtract it at the TF node, which injects -f into the total      */
+/* field; the corrections are taken with the opposite signs so that the */
+/* total-field region (k >= 2) holds +f, the wave the seed describes.   */
+/*                                                                      */
+/* Incident wave (boosted frame, propagating along +z): transverse      */
+/* vector potential A = A0 p s(t - (z - z_2)/c), p = (cos psi, sin psi,  */
+/* 0), A0 = a0 m c / e, z_2 the TF plane.  The lab signal (wavelength,  */
+/* duration, offset) is Doppler-scaled by D = gamma0 (1 + beta0), since */
+/* t' - z'/c = (t - z/c) / D.  Gaussian seed: transverse amplitude      */
+/* (w0/w(l)) exp(-r^2/w^2), phase -k r^2 / (2 R(l)) + atan(l / z_R),    */
+/* l = z - z_f, with the boosted wavelength lambda D and z_R = pi w0^2  */
+/* / (lambda D).                                                        */
+/* ------------------------------------------------------------------ */
+
+static double seed_incident(const ora_state *S, int comp, double x, double y, double z, double t)
+{
+    const double psi = S->seed_pol_deg * PI_ / 180.0;
+    const double pc = comp == 0 ? cos(psi) : sin(psi);
+    const double D = S->gamma0 * (1.0 + S->beta0);
+    const double lam = S->seed_lambda * D;
+    const double f = c_light / lam, tp = S->seed_ctau / c_light * D, t0 = S->seed_ct0 / c_light * D;
+    const double A0 = S->seed_a0 * m_e * c_light / q_e;
+    const double z2 = S->d.z0 + 2.0 * S->d.dz;
+    const double tau = t - (z - z2) / c_light;
+    double amp = 1.0, ph = S->seed_cep * PI_ / 180.0;
+    if (S->seed_type == 1) {
+        const double zR = PI_ * S->seed_w0 * S->seed_w0 / lam;
+        const double l = z - S->seed_zf;
+        const double w = S->seed_w0 * sqrt(1.0 + (l / zR) * (l / zR));
+        const double r2 = x * x + y * y;
+        amp = (S->seed_w0 / w) * exp(-r2 / (w * w));
+        ph += -0.5 * (2.0 * PI_ / lam) * r2 * l / (l * l + zR * zR) + atan(l / zR);
+    }
+    return pc * A0 * amp * signal_value(S->seed_signal, tau, f, tp, t0, ph);
+}
+
+static void seed_inject(ora_state *S)
+{
+    if (!S->seed_on)
+        return;
+    const int nx = S->d.nx, ny = S->d.ny;
+    const double t = (double)S->step * S->dt; /* time level n of the update */
+    const double A = S->nsfd_A;
+    for (int comp = 0; comp < 2; ++comp) {
+        double *pp = S->pot[2][comp];
+#define FI(ii, jj, kk) seed_incident(S, comp, S->d.x0 + (ii) * S->d.dx, S->d.y0 + (jj) * S->d.dy, S->d.z0 + (kk) * S->d.dz, t)
+        for (int j = 1; j < ny - 1; ++j)
+            for (int i = 1; i < nx - 1; ++i) {
+                /* SF node (k = 1) used total-field values at k = 2 */
+                double c1 = A * (S->a2 * FI(i + 1, j, 2) + S->a3 * FI(i - 1, j, 2) + S->a4 * FI(i, j + 1, 2) +
+                                 S->a5 * FI(i, j - 1, 2)) + S->a6 * FI(i, j, 2);
+                /* TF node (k = 2) used scattered-field values at k = 1 */
+                double c2 = A * (S->a2 * FI(i + 1, j, 1) + S->a3 * FI(i - 1, j, 1) + S->a4 * FI(i, j + 1, 1) +
+                                 S->a5 * FI(i, j - 1, 1)) + S->a7 * FI(i, j, 1);
+                pp[IDX(S, i, j, 1)] -= c1;
+                pp[IDX(S, i, j, 2)] += c2;
+            }
+#undef FI
+    }
+}
+
+/* Seed: p[0] type (0 plane wave, 1 Gaussian beam), p[1] signal type, p[2]
+ * a0, p[3] wavelength (lab, m), p[4] pulse length c tau (lab, m), p[5]
+ * offset c t0 (lab, m), p[6] CEP (deg), p[7] polarisation angle psi of A
+ * from x toward y (deg), p[8] waist (m), p[9] focus (boosted z, m). */
+void ora_set_seed(void *h, const double *p)
+{
+    ora_state *S = (ora_state *)h;
+    S->seed_on = 1;
+    S->seed_type = (int)p[0];
+    S->seed_signal = (int)p[1];
+    S->seed_a0 = p[2];
+    S->seed_lambda = p[3];
+    S->seed_ctau = p[4];
+    S->seed_ct0 = p[5];
+    S->seed_cep = p[6];
+    S->seed_pol_deg = p[7];
+    S->seed_w0 = p[8];
+    S->seed_zf = p[9];
+}
+
+/* Incident seed potential at a point (for tests). */
+double ora_seed_incident(void *h, int comp, const double r[3], double t)
+{
+    return seed_incident((ora_state *)h, comp, r[0], r[1], r[2], t);
+}
+
+/* ------------------------------------------------------------------ */
+/* Spectral radiated power (ch. 4 FEL-OUTPUT, radiation power at a       */
+/* normalised frequency).  Reading: running Fourier transforms, over     */
+/* the boosted time t_{n+1/2} of the vertex fields, of the lab-frame     */
+/* fields E'_x E'_y B'_x B'_y at every interior node of the diagnostic   */
+/* plane, F(omega) = sum_n F(t_n) exp(-i omega t_n) dt, at omega =        */
+/* nu omega_r (omega_r = 2 pi c / lambda*, the boosted resonant          */
+/* frequency).  The spectral energy through the plane per unit angular   */
+/* frequency is dW/domega = (1/pi) (dx dy / mu0) sum Re(E'_x B'_y* -     */
+/* E'_y B'_x*), so that its integral over omega >= 0 is the time         */
+/* integral of the instantaneous power (Parseval).                       */
+/* ------------------------------------------------------------------ */
+
+void ora_set_spectrum(void *h, int nf, double nu_min, double nu_max)
+{
+    ora_state *S = (ora_state *)h;
+    free(S->omega);
+    free(S->spec);
+    S->omega = NULL;
+    S->spec = NULL;
+    S->nf = nf > 0 ? nf : 0;
+    if (!S->nf)
+        return;
+    const double om_r = 2.0 * PI_ * c_light * S->gamma0 * S->beta0 / S->d.lambda_u;
+    S->omega = (double *)malloc(sizeof(double) * (size_t)nf);
+    for (int f = 0; f < nf; ++f) {
+        double nu = nf == 1 ? nu_min : nu_min + (nu_max - nu_min) * f / (double)(nf - 1);
+        S->omega[f] = nu * om_r;
+    }
+    S->spec = (double *)calloc((size_t)nf * 8 * (size_t)S->d.nx * S->d.ny, sizeof(double));
+}
+
+static void spectrum_accumulate(ora_state *S)
+{
+    if (!S->nf)
+        return;
+    const int nx = S->d.nx, ny = S->d.ny, k = S->d.k_plane;
+    const double g0 = S->gamma0, b0 = S->beta0;
+    const double t = ((double)S->step + 0.5) * S->dt;
+    const size_t plane = (size_t)nx * ny;
+    for (int f = 0; f < S->nf; ++f) {
+        const double c = cos(S->omega[f] * t) * S->dt, sn = -sin(S->omega[f] * t) * S->dt;
+        double *acc = S->spec + (size_t)f * 8 * plane;
+        for (int j = 1; j < ny - 1; ++j)
+            for (int i = 1; i < nx - 1; ++i) {
+                int64_t n = IDX(S, i, j, k);
+                double Ex = S->E[0][n], Ey = S->E[1][n], Bx = S->B[0][n], By = S->B[1][n];
+                double F[4];
+                F[0] = g0 * (Ex + b0 * c_light * By);
+                F[1] = g0 * (Ey - b0 * c_light * Bx);
+                F[2] = g0 * (Bx - b0 * Ey / c_light);
+                F[3] = g0 * (By + b0 * Ex / c_light);
+                size_t p = (size_t)j * nx + i;
+                for (int q = 0; q < 4; ++q) {
+                    acc[(size_t)(2 * q) * plane + p] += F[q] * c;
+                    acc[(size_t)(2 * q + 1) * plane + p] += F[q] * sn;
+                }
+            }
+    }
+}
+
+/* dW/domega (J s) at each frequency, accumulated over the steps so far. */
+void ora_spectral_power(void *h, double *out)
+{
+    ora_state *S = (ora_state *)h;
+    const int nx = S->d.nx, ny = S->d.ny;
+    const size_t plane = (size_t)nx * ny;
+    for (int f = 0; f < S->nf; ++f) {
+        const double *acc = S->spec + (size_t)f * 8 * plane;
+        double sum = 0.0;
+        for (int j = 1; j < ny - 1; ++j)
+            for (int i = 1; i < nx - 1; ++i) {
+                size_t p = (size_t)j * nx + i;
+                double exr = acc[0 * plane + p], exi = acc[1 * plane + p];
+                double eyr = acc[2 * plane + p], eyi = acc[3 * plane + p];
+                double bxr = acc[4 * plane + p], bxi = acc[5 * plane + p];
+                double byr = acc[6 * plane + p], byi = acc[7 * plane + p];
+                /* Re(Ex By* - Ey Bx*) */
+                sum += (exr * byr + exi * byi) - (eyr * bxr + eyi * bxi);
+            }
+        out[f] = sum * S->d.dx * S->d.dy / (MU_0 * PI_);
+    }
+}
+
 /* One full PIC step in the order: potentials, Mur, vertex fields, push,
  * sort, deposit. */
 void ora_step(void *h, int64_t nsteps)
@@ -810,9 +1159,11 @@ void ora_step(void *h, int64_t nsteps)
     for (int64_t it = 0; it < nsteps; ++it) {
         for (int c = 0; c < S->ncomp; ++c)
             sweep_component(S, c);
+        seed_inject(S);
         for (int c = 0; c < S->ncomp; ++c)
             mur_component(S, c);
         fields_at_vertices(S);
+        spectrum_accumulate(S);
         if (S->np > 0) {
             push_particles(S);
             sort_particles(S);
@@ -830,11 +1181,159 @@ void ora_field_step(void *h, int64_t nsteps)
     for (int64_t it = 0; it < nsteps; ++it) {
         for (int c = 0; c < S->ncomp; ++c)
             sweep_component(S, c);
+        seed_inject(S);
         for (int c = 0; c < S->ncomp; ++c)
             mur_component(S, c);
         fields_at_vertices(S);
+        spectrum_accumulate(S);
         rotate_levels(S);
         S->step += 1;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Bunch generation (sec. "Electron Bunch Generation").                 */
+/* Quasi-random filling by Halton sequences: the value of element j of  */
+/* sequence i is 1 minus the radical inverse of j in the base of the    */
+/* i-th prime (the digits of j in that base mirrored behind the point). */
+/* Uniform coordinates by eq. uniform1D, Gaussian ones by eqs.          */
+/* gaussian1D and gaussian2D (Box-Muller on two sequences).             */
+/* ------------------------------------------------------------------ */
+
+double ora_halton(int i, uint64_t j)
+{
+    static const int prime[20] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53, 59, 61, 67, 71};
+    const uint64_t b = (uint64_t)prime[i];
+    double scale = 1.0, x = 0.0;
+    for (uint64_t k = j; k > 0; k /= b) {
+        scale /= (double)b;
+        x += (double)(k % b) * scale;
+    }
+    return 1.0 - x;
+}
+
+/* Box-Muller pair from Halton sequences ia, ib at element j */
+static void halton_normal(int ia, int ib, uint64_t j, double *c, double *s)
+{
+    double r = sqrt(-2.0 * log(ora_halton(ia, j)));
+    double a = 2.0 * PI_ * ora_halton(ib, j);
+    *c = r * cos(a);
+    *s = r * sin(a);
+}
+
+/* Generate n macro-electrons in the boosted frame at the first half step.
+ * p[0] longitudinal profile (0 flat-top, 1 Gaussian), p[1] transverse
+ * profile (0 uniform, 1 Gaussian), p[2..4] bunch centre (boosted, m),
+ * p[5], p[6] transverse sizes (lab: full widths if uniform, sigma if
+ * Gaussian), p[7] longitudinal size (lab: flat-top length or sigma),
+ * p[8] gamma, p[9] relative energy spread, p[10] transverse spread of u,
+ * p[11] bunching factor b_f, p[12] its phase (rad), p[13] shot noise
+ * (0/1), p[14] electrons represented, p[15] flat-top tapers (0/1).
+ *
+ * Sequences: x, y: 0, 1; z: 2 (and 3 for a Gaussian or a taper); energy:
+ * 4, 5; transverse momentum: 6, 7; shot-noise slices: 8, 9 (by slice).
+ * Flat-top with tapers (reading of the CSE remedy): a Gaussian of the
+ * same density with rms width one lab radiation wavelength lambda* /
+ * (gamma0 (1 + beta0)) is split, its lower half put behind the tail and
+ * its upper half ahead of the head; the first round(n L / (L + sqrt(2
+ * pi) sigma_t)) particles fill the flat part.
+ * Lab lengths along z map to the boosted frame at fixed boosted time by
+ * 1 / (gamma0 (1 - beta beta0)) (beta of the beam energy).  Momenta: lab
+ * gamma' and u'_perp, u'_z = sqrt(gamma'^2 - 1 - u'_perp^2), boosted
+ * u_z = gamma0 (u'_z - beta0 gamma') (4-velocity boost).
+ * Bunching (eq. bunchingFactor; reading of the garbled form): the
+ * modulation that becomes resonant after the undulator entrance has, at
+ * load, the wavenumber k = k_r gamma0^2 (1 - beta beta0) beta0 / beta
+ * (k_r = 2 pi gamma0 beta0 / lambda_u; the entrance compresses the bunch
+ * by that factor), and dz = -(2 b_f / k) sin(k z + phase) gives
+ * <exp(i k z)> = b_f exp(-i phase) to first order.  Shot noise: slices
+ * 2 pi / k long; slice s has b_s = sqrt(-2 ln x_s) / sqrt(N_s), x_s from
+ * sequence 8, phase 2 pi y_s from sequence 9 (reading: the printed [0, pi]
+ * range is taken as [0, 2 pi)), N_s the electrons of the slice, and the
+ * same displacement form. */
+void ora_generate_bunch(void *h, const double *p, int64_t n, double *xyz, double *u)
+{
+    ora_state *S = (ora_state *)h;
+    const double g0 = S->gamma0, b0 = S->beta0;
+    const double gam = p[8];
+    const double beta = sqrt(1.0 - 1.0 / (gam * gam));
+    const double lz = 1.0 / (g0 * (1.0 - beta * b0));
+    const double kr = 2.0 * PI_ * g0 * b0 / S->d.lambda_u;
+    const double k = kr * g0 * g0 * (1.0 - beta * b0) * b0 / beta;
+    const double lam_lab = (2.0 * PI_ / kr) / (g0 * (1.0 + b0));
+    const double L = p[7];
+    const double sig_t = lam_lab;
+    int64_t n_flat = n;
+    if ((int)p[0] == 0 && (int)p[15] == 1)
+        n_flat = (int64_t)llround((double)n * L / (L + sqrt(2.0 * PI_) * sig_t));
+    for (int64_t q = 0; q < n; ++q) {
+        const uint64_t j = (uint64_t)q;
+        double x, y, zl, c, sn;
+        if ((int)p[1] == 0) {
+            x = p[5] * (ora_halton(0, j) - 0.5);
+            y = p[6] * (ora_halton(1, j) - 0.5);
+        } else {
+            halton_normal(0, 1, j, &c, &sn);
+            x = p[5] * c;
+            y = p[6] * sn;
+        }
+        if ((int)p[0] == 1) {
+            halton_normal(2, 3, j, &c, &sn);
+            zl = L * c;
+        } else if (q < n_flat) {
+            zl = L * (ora_halton(2, j) - 0.5);
+        } else {
+            halton_normal(2, 3, j, &c, &sn);
+            zl = (q & 1) ? 0.5 * L + sig_t * fabs(c) : -0.5 * L - sig_t * fabs(c);
+        }
+        double ge, ux, uy;
+        halton_normal(4, 5, j, &c, &sn);
+        ge = gam * (1.0 + p[9] * c);
+        halton_normal(6, 7, j, &c, &sn);
+        ux = p[10] * c;
+        uy = p[10] * sn;
+        double uzl = sqrt(ge * ge - 1.0 - ux * ux - uy * uy);
+        xyz[3 * q + 0] = p[2] + x;
+        xyz[3 * q + 1] = p[3] + y;
+        xyz[3 * q + 2] = p[4] + zl * lz;
+        u[3 * q + 0] = ux;
+        u[3 * q + 1] = uy;
+        u[3 * q + 2] = g0 * (uzl - b0 * ge);
+    }
+    /* bunching factor and shot noise act on the boosted z at load */
+    if (p[11] != 0.0)
+        for (int64_t q = 0; q < n; ++q) {
+            double z = xyz[3 * q + 2];
+            xyz[3 * q + 2] = z - (2.0 * p[11] / k) * sin(k * z + p[12]);
+        }
+    if ((int)p[13] == 1 && n > 0) {
+        double zmin = xyz[2];
+        for (int64_t q = 1; q < n; ++q)
+            if (xyz[3 * q + 2] < zmin)
+                zmin = xyz[3 * q + 2];
+        const double sl = 2.0 * PI_ / k;
+        int64_t ns = 0;
+        for (int64_t q = 0; q < n; ++q) {
+            int64_t s_ = (int64_t)floor((xyz[3 * q + 2] - zmin) / sl);
+            if (s_ + 1 > ns)
+                ns = s_ + 1;
+        }
+        int64_t *cnt = (int64_t *)calloc((size_t)ns, sizeof(int64_t));
+        for (int64_t q = 0; q < n; ++q)
+            cnt[(int64_t)floor((xyz[3 * q + 2] - zmin) / sl)] += 1;
+        double *dz = (double *)malloc(sizeof(double) * (size_t)n);
+        for (int64_t q = 0; q < n; ++q) {
+            double z = xyz[3 * q + 2];
+            int64_t s_ = (int64_t)floor((z - zmin) / sl);
+            double ne = fmax((double)cnt[s_] * p[14] / (double)n, 1.0);
+            double bs = sqrt(-2.0 * log(ora_halton(8, (uint64_t)s_ + 1))) / sqrt(ne);
+            double ph = 2.0 * PI_ * ora_halton(9, (uint64_t)s_ + 1);
+            dz[q] = -(2.0 * bs / k) * sin(k * z + ph);
+        }
+        for (int64_t q = 0; q < n; ++q)
+            xyz[3 * q + 2] += dz[q];
+        free(dz);
+        free(cnt);
     }
 }
 
@@ -976,5 +1475,16 @@ int ora_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Thread count of the OpenMP loops (sweep and push) for later calls. */
+void ora_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

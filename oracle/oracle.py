@@ -76,7 +76,17 @@ def lib():
         L.ora_bunching.argtypes = [P]
         L.ora_bunching.restype = C.c_double
         L.ora_threads.restype = C.c_int
+        L.ora_set_threads.argtypes = [C.c_int]
         L.ora_set_generic_faces.argtypes = [P, C.c_int]
+        L.ora_set_undulator.argtypes = [P, dp]
+        L.ora_set_seed.argtypes = [P, dp]
+        L.ora_seed_incident.argtypes = [P, C.c_int, dp, C.c_double]
+        L.ora_seed_incident.restype = C.c_double
+        L.ora_set_spectrum.argtypes = [P, C.c_int, C.c_double, C.c_double]
+        L.ora_spectral_power.argtypes = [P, dp]
+        L.ora_halton.argtypes = [C.c_int, C.c_uint64]
+        L.ora_halton.restype = C.c_double
+        L.ora_generate_bunch.argtypes = [P, dp, C.c_int64, dp, dp]
         L.ora_compute_fields.argtypes = [P]
         _lib = L
     return _lib
@@ -96,8 +106,29 @@ def boris(u, E, B, dtb) -> np.ndarray:
     return out
 
 
+def halton(i: int, j: int) -> float:
+    """Element j of the i-th Halton sequence (1 - radical inverse, base prime i)."""
+    return float(lib().ora_halton(int(i), int(j)))
+
+
+UNDULATOR_KEYS = ("n_modules", "gap", "dK", "signal", "ctau", "ct0", "cep_deg", "w0_par", "w0_perp", "z_focus")
+SEED_KEYS = ("type", "signal", "a0", "wavelength", "ctau", "ct0", "cep_deg", "pol_deg", "w0", "z_focus")
+BUNCH_KEYS = ("long_profile", "trans_profile", "xc", "yc", "zc", "size_x", "size_y", "size_z", "gamma",
+              "sigma_gamma_rel", "sigma_u_perp", "bunching", "bunching_phase", "shot_noise", "n_electrons",
+              "tapers")
+
+
+def _params(keys, d: dict) -> np.ndarray:
+    return np.array([float(d.get(k, 0.0)) for k in keys], dtype=np.float64)
+
+
 def threads() -> int:
     return int(lib().ora_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's OpenMP loops for later calls."""
+    lib().ora_set_threads(int(n))
 
 
 class Oracle:
@@ -205,6 +236,40 @@ class Oracle:
 
     def compute_fields(self):
         lib().ora_compute_fields(self._h)
+
+    def set_undulator(self, params: dict):
+        """Undulator arrays (modules, gap, tapering) and optical-undulator
+        pulse parameters; keys UNDULATOR_KEYS."""
+        d = dict(params)
+        d.setdefault("n_modules", 1)
+        a = _params(UNDULATOR_KEYS, d)
+        lib().ora_set_undulator(self._h, _dp(a))
+
+    def set_seed(self, params: dict):
+        """TF/SF seed wave; keys SEED_KEYS."""
+        a = _params(SEED_KEYS, params)
+        lib().ora_set_seed(self._h, _dp(a))
+
+    def seed_incident(self, comp: int, r, t: float) -> float:
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        return float(lib().ora_seed_incident(self._h, int(comp), _dp(r), float(t)))
+
+    def set_spectrum(self, nf: int, nu_min: float, nu_max: float):
+        lib().ora_set_spectrum(self._h, int(nf), float(nu_min), float(nu_max))
+        self.nf = int(nf)
+
+    def spectral_power(self) -> np.ndarray:
+        out = np.zeros(max(getattr(self, "nf", 0), 1))
+        lib().ora_spectral_power(self._h, _dp(out))
+        return out[:getattr(self, "nf", 0)]
+
+    def generate_bunch(self, params: dict, n: int):
+        """Halton quiet-start bunch (keys BUNCH_KEYS): returns (xyz, u)."""
+        a = _params(BUNCH_KEYS, params)
+        xyz = np.zeros((n, 3))
+        u = np.zeros((n, 3))
+        lib().ora_generate_bunch(self._h, _dp(a), int(n), _dp(xyz), _dp(u))
+        return xyz, u
 
     def set_generic_faces(self, on: bool):
         lib().ora_set_generic_faces(self._h, 1 if on else 0)

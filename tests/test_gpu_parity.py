@@ -254,25 +254,6 @@ def test_full_size_config2_against_oracle_few_steps():
     assert int(np.sum(pg != po)) == 0
 
 
-@pytest.mark.parametrize("case", ["config1", "tiny-6"])
-def test_tile_owned_particle_path(case, monkeypatch):
-    """The alternative particle kernel (one workgroup per sort tile, fields
-    and accumulators staged in LDS), selected at handle creation, against
-    the oracle at FP64."""
-    monkeypatch.setenv("MITHRA_PARTICLE_PATH", "tile")
-    if case == "config1":
-        w, steps = W.config1(), 200
-    else:
-        w = W.Workload(name="tiny-6", nx=8, ny=8, nz=10, gamma=60.0, K=1.0, lambda_u=0.03, n_periods=20,
-                       und_type=0, n_sub=1, truncation_order=2, space_charge=1, n_particles=700,
-                       sigma_cells=(8 / 12, 8 / 12, 10 / 24), seed=21, tile=(4, 4, 4))
-        steps = 60
-    d, o, g = run_both(w, steps)
-    cg, co, pg, po = compare(d, o, g, 1e-10)
-    assert int(np.sum(cg != co)) == 0
-    assert int(np.sum(pg != po)) == 0
-
-
 def _block_boxes(d, xyz, tile, per):
     """Node boxes of consecutive groups of `per` particles in the sort order
     (tile-major cell key, ties by id), from the cells at load; the deposit
