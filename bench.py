@@ -8,8 +8,11 @@ undulator K = 1.4, gamma = 200, FP32 fields and sources, FP64 particles.
 Inputs are synthetic (seeded) and resident in HBM before timing starts.
 
 Prints one JSON line: cell-updates/s of the whole step (value), particle-
-steps/s, the sweep's HBM roofline, run-latency percentiles of the small
-undulator run, and the FP64 CPU oracle timed on a bounded sample.
+steps/s, the sweep's HBM roofline, the per-stage times and the particle
+phase's and whole step's rooflines, the same run with FP64 fields,
+run-latency percentiles of the small undulator run, the FP64 CPU oracle
+timed on a bounded sample (1 thread and all threads) and the error of the
+GPU run against that oracle after the same steps.
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 20]
 """
@@ -26,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -74,27 +78,81 @@ def stored_traffic(kernel_src: str):
         return None
 
 
-def cpu_baseline(w, seconds: float) -> dict:
-    """The FP64 oracle on the same workload, timed on the host cores for a
-    bounded number of steps (load excluded)."""
-    from oracle.oracle import Oracle, threads
-    from paper_2009_13645_amd import workloads as W
-    d = w.descriptor()
-    xyz, u, q = W.make_bunch(w)
-    o = Oracle(d)
-    o.load_bunch(xyz, u, q)
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_steps(o, seconds: float, max_steps: int):
     steps, t = 0, 0.0
-    while t < seconds and steps < 50:
+    while t < seconds and steps < max_steps:
         t0 = time.perf_counter()
         o.step(1)
         t += time.perf_counter() - t0
         steps += 1
-    o.close()
-    return {"value": w.n_nodes * steps / t, "unit": "cell-updates/s", "cores": threads(),
-            "kind": "oracle",
-            "particle_steps_per_s": w.n_particles * steps / t,
-            "sample": f"{steps} steps of the same 128x128x1024 / 2^21-particle run "
-                      f"(FP64 oracle, {t:.1f} s of CPU time, load excluded)"}
+    return steps, t
+
+
+def cpu_baseline(w, seconds: float):
+    """The FP64 oracle on the same workload, timed on the host cores for a
+    bounded number of steps (load excluded): once on one thread, then on all
+    the host's threads, continuing the same run.  Returns the record and
+    the oracle (kept for the error of the GPU run against it)."""
+    from oracle.oracle import Oracle, set_threads, threads
+    from paper_2009_13645_amd import workloads as W
+    d = w.descriptor()
+    xyz, u, q = W.make_bunch(w)
+    n_all = threads()
+    o = Oracle(d)
+    o.load_bunch(xyz, u, q)
+    set_threads(1)
+    s1, t1 = _oracle_steps(o, seconds, 50)
+    set_threads(n_all)
+    sn, tn = _oracle_steps(o, seconds, 50)
+    rec = {"value": w.n_nodes * sn / tn, "unit": "cell-updates/s", "cores": n_all, "kind": "oracle",
+           "particle_steps_per_s": w.n_particles * sn / tn,
+           "value_1_thread": w.n_nodes * s1 / t1,
+           "particle_steps_per_s_1_thread": w.n_particles * s1 / t1,
+           "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+           "sample": f"steps 1..{s1} of the same 128x128x1024 / 2^21-particle run on 1 thread "
+                     f"({t1:.1f} s), then steps {s1 + 1}..{s1 + sn} on {n_all} threads ({tn:.1f} s); "
+                     f"FP64 oracle, load excluded"}
+    return rec, o, s1 + sn, (xyz, u, q)
+
+
+def error_vs_oracle(d, bunch, o, steps: int) -> dict:
+    """The benchmark's GPU configuration stepped from the same inputs for the
+    same number of steps as the oracle leg, compared with it."""
+    import numpy as np
+    from paper_2009_13645_amd.engine import Engine
+    xyz, u, q = bunch
+    g = Engine(d, max_particles=len(xyz))
+    g.load_bunch(xyz, u, q)
+    g.step(steps)
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+    E2g = sum(g.read_field(f) ** 2 for f in ("Ex", "Ey", "Ez"))
+    E2o = sum(o.field(f) ** 2 for f in ("Ex", "Ey", "Ez"))
+    out = {"steps": steps, "rel_l2_E2": rel(E2g, E2o)}
+    for f in ("Ax", "Az", "F", "Jz", "Q", "By"):
+        out["rel_l2_" + f] = rel(g.read_field(f), o.field(f))
+    _, ug, cg, _ = g.read_particles()
+    _, uo, co, _ = o.particles()
+    out["rel_l2_u"] = rel(ug, uo)
+    out["cell_mismatches"] = int(np.sum(cg != co))
+    bo = o.bunching()
+    out["rel_bunching"] = abs(g.bunching() - bo) / max(bo, 1e-300)
+    po = o.radiated_power()
+    out["rel_power"] = abs(g.radiated_power() - po) / max(abs(po), 1e-300)
+    g.close()
+    return out
 
 
 def run_latency(runs: int) -> dict:
@@ -279,25 +337,69 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_step = elapsed * 1e3 / args.steps
 
-    # same run continued: K steps by direct launches with HIP events around
-    # each sweep launch (the dominant kernel) on the engine's stream
-    sweep_ms, step_ms_ev = eng.step_timed(args.steps)
-    sweep_avg_s = sweep_ms / args.steps * 1e-3
+    # same run continued: K steps by direct launches with HIP events between
+    # the stages of every step, on the engine's stream
+    prof = eng.step_profile(args.steps)
+    stage_us = {k: v / args.steps * 1e3 for k, v in prof.items()}
 
     f_occ = source_occupancy(eng, d)
     C = 4
-    pf = 4
-    alg_bytes = C * pf * (3.0 + f_occ) * w.n_nodes
-    achieved = alg_bytes / sweep_avg_s / 1e9
+    alg_sweep = C * 4 * (3.0 + f_occ) * w.n_nodes          # bytes per sweep launch (FP32 words)
+    alg_part = 96.0 * w.n_particles                         # FP64 r and u read and written
+    flops_part = 600.0 * w.n_particles                      # estimated FP64 flops per particle-step
+    sweep_s = stage_us["sweep"] * 1e-6
+    push_s = stage_us["push"] * 1e-6
+    step_s = stage_us["step"] * 1e-6
+    achieved = alg_sweep / sweep_s / 1e9
     traffic = stored_traffic(os.path.join(ROOT, "paper_2009_13645_amd", "csrc", "k_fdtd.hip"))
-
-    lat = run_latency(args.latency_runs)
+    rooflines = {
+        "push_deposit_hbm": {"bound": "hbm", "achieved": alg_part / push_s / 1e9, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": alg_part / push_s / 1e9 / HBM_PEAK_GBS,
+                             "alg_bytes_per_launch": alg_part, "avg_launch_us": stage_us["push"]},
+        "push_deposit_fp64": {"bound": "alu", "achieved": flops_part / push_s / 1e12, "peak": FP64_PEAK_TFLOPS,
+                              "unit": "TFLOP/s", "frac": flops_part / push_s / 1e12 / FP64_PEAK_TFLOPS,
+                              "flops_per_particle_step": 600.0, "note": "flop count is an estimate"},
+        "whole_step_hbm": {"bound": "hbm", "achieved": (alg_sweep + alg_part) / step_s / 1e9,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": (alg_sweep + alg_part) / step_s / 1e9 / HBM_PEAK_GBS,
+                           "alg_bytes_per_step": alg_sweep + alg_part,
+                           "what": "sweep algorithmic bytes + 96 B per particle over the whole step"},
+    }
     del eng
     torch.cuda.empty_cache()
 
+    # the same run with FP64 fields (the paper's precision)
+    d64 = W.config2(field_precision=64, compensated=0).descriptor()
+    e64 = Engine(d64, max_particles=len(xyz))
+    e64.load_bunch(xyz, u, q)
+    e64.step(args.warmup)
+    torch.cuda.synchronize()
+    k64 = max(args.steps // 2, 1)
+    t0 = time.perf_counter()
+    e64.step(k64)
+    torch.cuda.synchronize()
+    el64 = time.perf_counter() - t0
+    prof64 = e64.step_profile(k64)
+    f_occ64 = source_occupancy(e64, d64)
+    alg64 = C * 8 * (3.0 + f_occ64) * w.n_nodes
+    sw64 = prof64["sweep"] / k64 * 1e-3
+    fp64 = {"ms_per_step": el64 * 1e3 / k64, "value": w.n_nodes * k64 / el64,
+            "particle_steps_per_s": w.n_particles * k64 / el64, "steps": k64,
+            "stages_us": {k: v / k64 * 1e3 for k, v in prof64.items()},
+            "roofline": {"bound": "hbm", "kernel": "NSFD sweep, FP64 words", "achieved": alg64 / sw64 / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg64 / sw64 / 1e9 / HBM_PEAK_GBS,
+                         "alg_bytes_per_launch": alg64, "f_occ": f_occ64, "avg_launch_us": sw64 * 1e6}}
+    del e64
+    torch.cuda.empty_cache()
+
+    lat = run_latency(args.latency_runs)
+
     cpu = None
+    err = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_seconds)
+        cpu, ora, n_ora, bunch = cpu_baseline(w, args.cpu_seconds)
+        err = error_vs_oracle(d, bunch, ora, n_ora)
+        ora.close()
 
     out = {
         "metric": "cell-updates/s + particle-steps/s per GPU (% HBM roofline); p50/p99 run latency",
@@ -322,11 +424,14 @@ def main():
             "bound": "hbm", "kernel": "NSFD sweep (A_x, A_y, A_z, phi)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "alg_bytes_per_launch": alg_bytes, "f_occ": f_occ,
-            "avg_launch_us": sweep_avg_s * 1e6,
+            "alg_bytes_per_launch": alg_sweep, "f_occ": f_occ,
+            "avg_launch_us": stage_us["sweep"],
         },
-        "step_ms_events": step_ms_ev / args.steps,
+        "rooflines": rooflines,
+        "stages_us": stage_us,
+        "fp64": fp64,
         "latency": lat,
+        "error_vs_oracle": err,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -177,6 +177,16 @@ int mithra_time_sweep(mithra_handle h, int shape, int iters, double *ms);
  * EDEVICE. */
 int mithra_step_timed(mithra_handle h, int64_t n_steps, double *sweep_ms, double *step_ms);
 
+/* Measurement call: run n_steps exactly as mithra_step would, by direct
+ * launches with HIP events on the handle's stream between the stages of
+ * every step; synchronises, then adds the summed milliseconds per stage to
+ * stage_ms[0..5] (0 field sweep, 1 Mur boundaries, 2 vertex E and B with
+ * the plane-power partial sums, 3 gather + push + deposit, 4 box
+ * reductions + bin and sort, 5 step tail) and of the whole steps to
+ * stage_ms[6] (seven doubles, caller-owned).  Errors: EINVAL, ESTATE,
+ * EDEVICE. */
+int mithra_step_profile(mithra_handle h, int64_t n_steps, double *stage_ms);
+
 /* Sweep-shape autotuner: times every distinct sweep tile shape on this
  * run's grid, each with the boundary kernel it implies, over `iters`
  * launches, selects the fastest for the handle and writes it to
@@ -206,8 +216,8 @@ typedef struct mithra_batch_s *mithra_batch;
  * n <= 0.  Pure function. */
 size_t mithra_batch_workspace_bytes(int32_t n_runs);
 
-/* Create a batch of n distinct loaded handles (not using the tile-owned
- * particle kernel, not in another batch) on `hip_stream`, borrowing
+/* Create a batch of n distinct loaded handles (not in another batch) on
+ * `hip_stream`, borrowing
  * `dev_workspace` (256-byte aligned, at least the size above) for the
  * batch's lifetime.  Synchronises the members' streams.  Errors: EINVAL,
  * ENOMEM (workspace), ESTATE (a member not loaded or already batched),

@@ -13,7 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmithra.so")
-SOURCES = ["engine.hip", "k_fdtd.hip", "k_particles.hip", "k_sort.hip", "k_tiles.hip"]
+SOURCES = ["engine.hip", "k_fdtd.hip", "k_particles.hip", "k_sort.hip"]
 
 HIPCC_FLAGS = [
     "-I" + os.path.join(os.path.dirname(HERE), "include"),

@@ -36,15 +36,13 @@ hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *ou
 hipError_t launch_push_deposit(const RunDev &R, hipStream_t st, bool box);
 hipError_t launch_load_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st);
-hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts, bool gather,
-                       int step_tail = 0);
+hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int step_tail = 0);
 // launch_sort with step_tail runs the box reductions before the sort and
 // ends the step after it, in one workgroup, when this holds
 bool sort_ends_step(const RunDev &R);
 hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
                              int32_t *count, hipStream_t st, int32_t *zero);
 hipError_t launch_box_reduce_set(const RunDev &R, int64_t nblocks, hipStream_t st);
-bool tile_kernel_fits(const int tile[3]);
 int64_t sweep_blocks(const RunDev &R, int shape);
 hipError_t launch_sweep_group(const Group &g, int64_t total, int precision, int compensated, int shape,
                               hipStream_t st);
@@ -63,32 +61,11 @@ hipError_t launch_push_group(const Group &g, int64_t total, int precision, int c
 hipError_t launch_box_group(const Group &g, int64_t total, hipStream_t st);
 hipError_t launch_sort_group(const Group &gs, int64_t total_s, const Group &gd, int64_t total_d, const Group &gp,
                              int64_t total_p, int max_passes, hipStream_t st);
-int tile_partials(const RunDev &R);
-hipError_t launch_tile_items(const RunDev &R, hipStream_t st);
-hipError_t launch_tile_step(const RunDev &R, hipStream_t st);
-hipError_t launch_tile_load(const RunDev &R, hipStream_t st);
-int tile_blocks_per_cu(int precision, int compensated);
 int64_t dep_blocks(int64_t np);
 int sort_passes(uint32_t key_inactive);
 int64_t sort_blocks(int64_t n);
 
 // --- bookkeeping kernels (single thread) -----------------------------------
-
-// after the vertex fields of step s: empty the deposit box of set (s+1)&1
-// (its stale entries were cleared by the sweep) and the active-cell box
-__device__ inline void book_mid(Ctl *ctl)
-{
-    const int set = (int)((ctl->step + 1) & 1);
-    ctl->sorted_active = ctl->n_active;
-    ctl->item_next = 0;
-    for (int a = 0; a < 3; ++a) {
-        ctl->dep_lo[set][a] = 0x7fffffff;
-        ctl->dep_hi[set][a] = -1;
-        ctl->cell_lo[a] = 0x7fffffff;
-        ctl->cell_hi[a] = -1;
-    }
-    ctl->n_active = 0;
-}
 
 __device__ inline void book_end(Ctl *ctl, int advance)
 {
@@ -98,19 +75,12 @@ __device__ inline void book_end(Ctl *ctl, int advance)
         ctl->step += 1;
 }
 
-__global__ void k_book_mid(Ctl *ctl) { book_mid(ctl); }
 __global__ void k_book_end(Ctl *ctl, int advance) { book_end(ctl, advance); }
 
 struct BookEnd {
     static constexpr int kThreads = 1;
     static __device__ void run(const RunDev &R, Blk) { book_end(R.ctl, 1); }
 };
-
-__global__ void k_book_mid_load(Ctl *ctl)
-{
-    ctl->sorted_active = ctl->n_active;
-    ctl->item_next = 0;
-}
 
 __global__ void k_book_load(Ctl *ctl)
 {
@@ -131,7 +101,7 @@ static const int kBunchBlocks = 256;
 
 struct Layout {
     size_t ctl, pot, src, src_lo, eb, pr, pid, key_by_id, slot_of_id, cell_by_id, key_sorted, sk, sv, hist, boxpart,
-        cellpart, boxslot, items, items_n, ppart, power, scratch, tile_flag, ntiles, total;
+        boxslot, ppart, power, scratch, tile_flag, ntiles, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -164,15 +134,12 @@ static Layout make_layout(const mithra_grid_desc *d, int64_t cap)
     L.hist = take((256 * (size_t)sort_blocks((int64_t)c) + 256) * 4);
     const size_t nparts = std::max((size_t)((c + 255) / 256), (size_t)kPartials);
     L.boxpart = take(8 * 4 * nparts);
-    L.cellpart = take(8 * 4 * nparts);
     L.boxslot = take(16 * 4 * kBoxSlots);
     size_t ntiles = 1;
     for (int a = 0; a < 3; ++a) {
         const size_t cells = (size_t)((a == 0 ? d->nx : (a == 1 ? d->ny : d->nz)) - 1);
         ntiles *= (cells + d->tile[a] - 1) / d->tile[a];
     }
-    L.items_n = c / 512 + std::min(c, ntiles) + 16;
-    L.items = take(16 * L.items_n);
     L.ppart = take(256 * 8);
     L.power = take((size_t)kPowerCap * 8);
     L.scratch = take((size_t)(3 * kBunchBlocks + 8) * 8);
@@ -191,7 +158,6 @@ struct mithra_engine {
     int64_t steps = 0;
     bool loaded = false;
     int sweep_shape = 0;
-    bool tiled = false;
     int32_t *cell_by_id = nullptr;
     hipGraphExec_t graph = nullptr;   // one step
     hipGraphExec_t graph8 = nullptr;  // kGraphSteps steps
@@ -440,10 +406,7 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.sv[1] = R.sv[0] + c;
     R.hist = (uint32_t *)(A + L.hist);
     R.boxpart = (int32_t *)(A + L.boxpart);
-    R.cellpart = (int32_t *)(A + L.cellpart);
     R.boxslot = (int32_t *)(A + L.boxslot);
-    R.items = (int32_t *)(A + L.items);
-    R.item_cap = (int64_t)L.items_n;
     R.ppart = (double *)(A + L.ppart);
     R.sort_blocks = sort_blocks((int64_t)c);
     R.power_hist = (double *)(A + L.power);
@@ -479,17 +442,6 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
         box_slot_empty(&slots[16 * b]);
     HIPCHK(h, hipMemcpyAsync(R.boxslot, slots.data(), slots.size() * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, sync_run(h));
-    // persistent grid of the tile-owned particle kernel
-    // particle kernel: per-block LDS-staged deposit (default; measured faster
-    // on the benchmark run) or the tile-owned kernel ("tile")
-    const char *pp = getenv("MITHRA_PARTICLE_PATH");
-    h->tiled = pp && strcmp(pp, "tile") == 0 && tile_kernel_fits(d->tile);
-    if (h->tiled) {
-        int dev = 0, cus = 0;
-        HIPCHK(h, hipGetDevice(&dev));
-        HIPCHK(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        R.tile_grid = std::min(cus * tile_blocks_per_cu(d->field_precision, d->compensated), kPartials - 128);
-    }
     // default sweep tile (measured): grids of up to 2^20 nodes take chunks
     // of 4 or 16 planes, so that enough workgroups run (vector tiles when the
     // row length allows 16-byte vectors, else the scalar tiles); larger grids
@@ -549,18 +501,8 @@ extern "C" int mithra_load_bunch(mithra_handle h, int64_t n, const double *xyz, 
     int rc = enqueue_sort_with_cells(h);
     if (rc)
         return rc;
-    if (h->tiled)  // the gathered state is in the other buffer
-        hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, h->stream, R.ctl, 0);
     HIPCHK(h, hipGetLastError());
-    if (h->tiled) {
-        HIPCHK(h, launch_tile_items(R, h->stream));
-        hipLaunchKernelGGL(k_book_mid_load, dim3(1), dim3(1), 0, h->stream, R.ctl);
-        HIPCHK(h, launch_tile_load(R, h->stream));
-        HIPCHK(h, launch_box_reduce(R, R.tile_grid, R.boxpart, CTL_ADDR(R.ctl, dep_lo), CTL_ADDR(R.ctl, dep_hi),
-                                    nullptr, h->stream, nullptr));
-    } else {
-        HIPCHK(h, launch_load_deposit(R, h->stream));
-    }
+    HIPCHK(h, launch_load_deposit(R, h->stream));
     HIPCHK(h, sync_run(h));
     h->loaded = true;
     return MITHRA_OK;
@@ -588,53 +530,47 @@ __global__ void k_cells_by_id(RunDev R, int32_t *cell_by_id)
 
 static int enqueue_sort_with_cells(mithra_handle h)
 {
-    HIPCHK(h, launch_sort(h->R, h->stream, false, 0, h->tiled));
+    HIPCHK(h, launch_sort(h->R, h->stream, false));
     return MITHRA_OK;
 }
 
-// the particle part of a step: push + deposit, bin + sort, next work items
-static int enqueue_particles(mithra_handle h, hipStream_t st)
+// One step on stream `st`: sweep, Mur, vertex fields (with the power's
+// partial sums), push + deposit, bin + sort, step tail.  With `ev` (seven
+// events), ev[i] is recorded before stage i and ev[6] after the last one:
+// stages 0 sweep, 1 Mur, 2 vertex fields, 3 push + deposit, 4 sort (with
+// the box reductions), 5 step tail (power sum, bookkeeping).
+static int enqueue_step_on(mithra_handle h, hipStream_t st, hipEvent_t *ev)
 {
     RunDev &R = h->R;
-    if (h->tiled) {
-        hipLaunchKernelGGL(k_book_mid, dim3(1), dim3(1), 0, st, R.ctl);
-        HIPCHK(h, launch_tile_step(R, st));
-        HIPCHK(h, launch_box_reduce_set(R, tile_partials(R), st));
-        HIPCHK(h, launch_sort(R, st, true, tile_partials(R), true));
-        HIPCHK(h, launch_tile_items(R, st));
-    } else {
-        // no mid-step bookkeeping: the box reductions after the push rewrite
-        // the deposit box, the active-cell box and the active count whole
-        if (R.record_power)  // the power's partial sums ride on the vertex launch
-            HIPCHK(h, launch_vertex_power(R, st));
-        else
-            HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
-        HIPCHK(h, launch_push_deposit(R, st, !sort_ends_step(R)));
-        HIPCHK(h, launch_sort(R, st, true, dep_blocks(R.np), false, 1));
-    }
-    return MITHRA_OK;
-}
-
-static int enqueue_step(mithra_handle h)
-{
-    RunDev &R = h->R;
-    hipStream_t st = h->stream;
+    auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
+    HIPCHK(h, mark(0));
     HIPCHK(h, launch_sweep(R, h->sweep_shape, st));
+    HIPCHK(h, mark(1));
     HIPCHK(h, launch_mur(R, st));
-    int rc = enqueue_particles(h, st);
-    if (rc)
-        return rc;
-    if (!h->tiled && sort_ends_step(R))
+    HIPCHK(h, mark(2));
+    // no mid-step bookkeeping: the box reductions after the push rewrite the
+    // deposit box, the active-cell box and the active count whole
+    if (R.record_power)  // the power's partial sums ride on the vertex launch
+        HIPCHK(h, launch_vertex_power(R, st));
+    else
+        HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
+    HIPCHK(h, mark(3));
+    HIPCHK(h, launch_push_deposit(R, st, !sort_ends_step(R)));
+    HIPCHK(h, mark(4));
+    HIPCHK(h, launch_sort(R, st, true, 1));
+    HIPCHK(h, mark(5));
+    if (sort_ends_step(R))
         ;  // the small sort ended the step
-    else if (R.record_power && h->tiled)
-        HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st, 1));  // ends the step
     else if (R.record_power)
         HIPCHK(h, launch_power_final(R, st, 1));  // sums the partials of the vertex launch; ends the step
     else
         hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);
     HIPCHK(h, hipGetLastError());
+    HIPCHK(h, mark(6));
     return MITHRA_OK;
 }
+
+static int enqueue_step(mithra_handle h) { return enqueue_step_on(h, h->stream, nullptr); }
 
 // Capture one step on a private stream (the caller's stream may be the
 // legacy default stream, which cannot be captured); the graph is then
@@ -800,21 +736,17 @@ extern "C" int mithra_read_particles(mithra_handle h, double *xyz, double *u, in
     int32_t pb = 0;
     HIPCHK(h, hipMemcpy(&pb, &R.ctl->pbuf, 4, hipMemcpyDeviceToHost));
     // the state sits in buffer pb in the slots pid[pb]; the order of the
-    // last sort is the slot list sv[sorted_buf] (the per-block path does not
-    // move the state after sorting) or the gathered pid[pb] (tile-owned path)
+    // last sort is the slot list sv[sorted_buf] (the push does not move the
+    // state after sorting)
     std::vector<int32_t> ids((size_t)n);
     HIPCHK(h, hipMemcpy(ids.data(), R.pid[pb], (size_t)n * 4, hipMemcpyDeviceToHost));
     if (sort_perm) {
-        if (h->tiled) {
-            memcpy(sort_perm, ids.data(), (size_t)n * 4);
-        } else {
-            int32_t sb = 0;
-            HIPCHK(h, hipMemcpy(&sb, &R.ctl->sorted_buf, 4, hipMemcpyDeviceToHost));
-            std::vector<int32_t> slots((size_t)n);
-            HIPCHK(h, hipMemcpy(slots.data(), R.sv[sb], (size_t)n * 4, hipMemcpyDeviceToHost));
-            for (int64_t r = 0; r < n; ++r)
-                sort_perm[r] = ids[(size_t)slots[(size_t)r]];
-        }
+        int32_t sb = 0;
+        HIPCHK(h, hipMemcpy(&sb, &R.ctl->sorted_buf, 4, hipMemcpyDeviceToHost));
+        std::vector<int32_t> slots((size_t)n);
+        HIPCHK(h, hipMemcpy(slots.data(), R.sv[sb], (size_t)n * 4, hipMemcpyDeviceToHost));
+        for (int64_t r = 0; r < n; ++r)
+            sort_perm[r] = ids[(size_t)slots[(size_t)r]];
     }
     std::vector<double> col((size_t)n);
     for (int a = 0; a < 6; ++a) {
@@ -945,56 +877,65 @@ extern "C" int mithra_set_sweep_shape(mithra_handle h, int shape)
 
 extern "C" int mithra_sweep_shape_count(void) { return sweep_shape_count(); }
 
-// Run n steps by direct launches with HIP events around every sweep launch
-// and around every whole step, on the handle's stream; adds the summed
-// milliseconds to *sweep_ms and *step_ms.  Same state evolution as
-// mithra_step.
-extern "C" int mithra_step_timed(mithra_handle h, int64_t n, double *sweep_ms, double *step_ms)
+// Run n steps by direct launches with HIP events between the stages of
+// every step (see enqueue_step_on) on the handle's stream, and add the
+// summed milliseconds of each stage to stage_ms[0..5] and of the whole
+// steps to stage_ms[6].  Same state evolution as mithra_step.
+static int step_profile(mithra_handle h, int64_t n, double *stage_ms)
 {
-    if (!h || !sweep_ms || !step_ms || n < 0)
+    if (!h || !stage_ms || n < 0)
         return MITHRA_EINVAL;
     if (!h->loaded)
         return fail(h, MITHRA_ESTATE, "no bunch loaded");
     if (h->batched)
         return fail(h, MITHRA_ESTATE, "the run belongs to a batch: step it with mithra_batch_run");
-    std::vector<hipEvent_t> ev((size_t)(3 * n + 1));
+    std::vector<hipEvent_t> ev((size_t)(7 * n));
     for (auto &e : ev)
         HIPCHK(h, hipEventCreate(&e));
-    RunDev &R = h->R;
-    hipStream_t st = h->stream;
-    for (int64_t i = 0; i < n; ++i) {
-        HIPCHK(h, hipEventRecord(ev[(size_t)(3 * i)], st));
-        HIPCHK(h, launch_sweep(R, h->sweep_shape, st));
-        HIPCHK(h, hipEventRecord(ev[(size_t)(3 * i + 1)], st));
-        HIPCHK(h, launch_mur(R, st));
-        int rc = enqueue_particles(h, st);
-        if (rc)
-            return rc;
-        if (!h->tiled && sort_ends_step(R))
-            ;  // the small sort ended the step
-        else if (R.record_power && h->tiled)
-            HIPCHK(h, launch_plane_power(R, 0, R.k_plane, nullptr, st, 1));  // ends the step
-        else if (R.record_power)
-            HIPCHK(h, launch_power_final(R, st, 1));
-        else
-            hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);
-        HIPCHK(h, hipGetLastError());
-        HIPCHK(h, hipEventRecord(ev[(size_t)(3 * i + 2)], st));
-        h->steps += 1;
+    int rc = MITHRA_OK;
+    for (int64_t i = 0; i < n && rc == MITHRA_OK; ++i) {
+        rc = enqueue_step_on(h, h->stream, &ev[(size_t)(7 * i)]);
+        if (rc == MITHRA_OK)
+            h->steps += 1;
     }
-    HIPCHK(h, hipStreamSynchronize(st));
-    double sw = 0.0, tot = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        float a = 0.f, b = 0.f;
-        HIPCHK(h, hipEventElapsedTime(&a, ev[(size_t)(3 * i)], ev[(size_t)(3 * i + 1)]));
-        HIPCHK(h, hipEventElapsedTime(&b, ev[(size_t)(3 * i)], ev[(size_t)(3 * i + 2)]));
-        sw += a;
-        tot += b;
+    if (rc == MITHRA_OK)
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = 0; rc == MITHRA_OK && i < n; ++i) {
+        const hipEvent_t *e = &ev[(size_t)(7 * i)];
+        for (int st = 0; st < 6; ++st) {
+            float ms = 0.f;
+            HIPCHK(h, hipEventElapsedTime(&ms, e[st], e[st + 1]));
+            acc[st] += ms;
+        }
+        float tot = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&tot, e[0], e[6]));
+        acc[6] += tot;
     }
     for (auto &e : ev)
         (void)hipEventDestroy(e);
-    *sweep_ms += sw;
-    *step_ms += tot;
+    if (rc)
+        return rc;
+    for (int st = 0; st < 7; ++st)
+        stage_ms[st] += acc[st];
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_step_profile(mithra_handle h, int64_t n_steps, double *stage_ms)
+{
+    return step_profile(h, n_steps, stage_ms);
+}
+
+extern "C" int mithra_step_timed(mithra_handle h, int64_t n, double *sweep_ms, double *step_ms)
+{
+    if (!sweep_ms || !step_ms)
+        return MITHRA_EINVAL;
+    double st[7] = {0, 0, 0, 0, 0, 0, 0};
+    int rc = step_profile(h, n, st);
+    if (rc)
+        return rc;
+    *sweep_ms += st[0];
+    *step_ms += st[6];
     return MITHRA_OK;
 }
 
@@ -1342,7 +1283,7 @@ extern "C" int mithra_batch_create(const mithra_handle *runs, int32_t n_runs, vo
     if (workspace_bytes < mithra_batch_workspace_bytes(n_runs))
         return MITHRA_ENOMEM;
     for (int i = 0; i < n_runs; ++i) {
-        if (!runs[i] || !runs[i]->loaded || runs[i]->batched || runs[i]->tiled)
+        if (!runs[i] || !runs[i]->loaded || runs[i]->batched)
             return MITHRA_ESTATE;
         for (int j = 0; j < i; ++j)
             if (runs[j] == runs[i])

@@ -464,28 +464,6 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R, int step
 
 bool sort_ends_step(const RunDev &R) { return R.np > 0 && R.np <= kSmallChunk; }
 
-// gather particle state into the other buffer in sorted order
-__device__ inline void sort_gather_blk(const RunDev &R, const uint32_t *keys, const int32_t *slots, int64_t bid)
-{
-    const int pb = R.ctl->pbuf;
-    const int nb = pb ^ 1;
-    const int64_t r = (int64_t)bid * blockDim.x + threadIdx.x;
-    if (r >= R.np)
-        return;
-    const int32_t src = slots[r];
-    const int32_t id = R.pid[pb][src];
-    for (int a = 0; a < 6; ++a)
-        R.pr[nb][a][r] = R.pr[pb][a][src];
-    R.pid[nb][r] = id;
-    R.key_sorted[r] = keys[r];
-}
-
-__global__ __launch_bounds__(256) void k_sort_gather(RunDev R)
-{
-    const int b = R.ctl->sorted_buf;
-    sort_gather_blk(R, R.sk[b], R.sv[b], blockIdx.x);
-}
-
 // the sort range as a kernel of its own (after a generic box reduction)
 struct SortRange {
     static constexpr int kThreads = 1;
@@ -547,22 +525,19 @@ int sort_passes(uint32_t key_inactive) { return sort_passes_of(key_inactive); }
 
 int64_t sort_blocks(int64_t n) { return (n + kSortChunk - 1) / kSortChunk; }
 
-// keys_ready: the push kernels have already written the keys, the slots
-// and `nparts` per-block active-cell boxes in R.cellpart.  The tile work
-// item counter is reset here, before the items of the new order are built.
-hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t nparts, bool gather, int step_tail)
+// keys_ready: the push has already written the keys and the slots, and the
+// box reduction after it has set the active-cell box, the count and the
+// sort range.  Otherwise (the load) the keys, the box and the range are
+// computed here.
+hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int step_tail)
 {
     if (R.np <= 0)
         return hipSuccess;
     const unsigned pblocks = (unsigned)((R.np + 255) / 256);
     if (!keys_ready)
         hipLaunchKernelGGL(k_sort_keys, dim3(pblocks), dim3(256), 0, st, R);
-    if (keys_ready && !gather) {
-        // per-block push: the active-cell box, count and sort range were
-        // reduced right after the push (BoxReduceStep)
-    } else {
-        hipError_t e = launch_box_reduce(R, keys_ready ? nparts : pblocks, keys_ready ? R.cellpart : R.boxpart,
-                                         CTL_ADDR(R.ctl, cell_lo), CTL_ADDR(R.ctl, cell_hi),
+    if (!keys_ready) {
+        hipError_t e = launch_box_reduce(R, pblocks, R.boxpart, CTL_ADDR(R.ctl, cell_lo), CTL_ADDR(R.ctl, cell_hi),
                                          CTL_ADDR(R.ctl, n_active), st, CTL_ADDR(R.ctl, n_items));
         if (e != hipSuccess)
             return e;
@@ -589,10 +564,7 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int64_t
             vin = vout;
         }
     }
-    // the tile-owned kernel reads the state in sorted slots; the per-block
-    // kernel reads it through sv[ctl->sorted_buf]
-    if (gather)
-        hipLaunchKernelGGL(k_sort_gather, dim3(pblocks), dim3(256), 0, st, R);
+    // the push reads the state through sv[ctl->sorted_buf]
     return hipGetLastError();
 }
 

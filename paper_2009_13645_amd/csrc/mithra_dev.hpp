@@ -112,13 +112,9 @@ struct RunDev {
     int32_t *sv[2];
     uint32_t *hist;
     int64_t sort_blocks;
-    int32_t *boxpart;  // per-block partial boxes (load deposit, key pass, tile kernel): [block][8] = lo[3], hi[3], count, pad
-    int32_t *cellpart; // per-block partial active-cell boxes of the tile-owned kernel, same layout
+    int32_t *boxpart;  // per-block partial boxes (load deposit, key pass): [block][8] = lo[3], hi[3], count, pad
     int32_t *boxslot;  // kBoxSlots x 16 boxes of the per-block push, reduced with atomics (layout: BoxReduceStep)
     FastDiv tdiv[3];   // division by the sort tile dims (exact: cell index x tile dim < 2^32)
-    int32_t *items;    // tile work items [n][4] = tile, begin, end, pad
-    int64_t item_cap;
-    int tile_grid;     // persistent blocks of the tile push kernel (0: tile kernel not used)
     double *ppart;     // partial sums of the plane-power kernel
     double *power_hist;
     int64_t power_cap;

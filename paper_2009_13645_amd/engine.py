@@ -86,6 +86,8 @@ def lib():
         L.mithra_time_sweep.restype = C.c_int
         L.mithra_step_timed.argtypes = [H, C.c_int64, dp, dp]
         L.mithra_step_timed.restype = C.c_int
+        L.mithra_step_profile.argtypes = [H, C.c_int64, dp]
+        L.mithra_step_profile.restype = C.c_int
         L.mithra_autotune_sweep.argtypes = [H, C.c_int, C.POINTER(C.c_int)]
         L.mithra_autotune_sweep.restype = C.c_int
         L.mithra_batch_workspace_bytes.argtypes = [C.c_int32]
@@ -246,6 +248,15 @@ class Engine:
         a, b = C.c_double(0.0), C.c_double(0.0)
         self._check(self._L.mithra_step_timed(self._h, int(n), C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    STAGES = ("sweep", "mur", "vertex", "push", "sort", "tail", "step")
+
+    def step_profile(self, n: int) -> dict:
+        """n steps with HIP events between the stages of every step: summed
+        ms per stage (sweep, mur, vertex, push, sort, tail) and per step."""
+        out = np.zeros(7)
+        self._check(self._L.mithra_step_profile(self._h, int(n), _dp(out)))
+        return dict(zip(self.STAGES, out.tolist()))
 
     def autotune_sweep(self, iters: int = 10) -> int:
         """Time every sweep tile shape on this run's grid, keep the fastest."""
