@@ -40,8 +40,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--latency-runs", type=int, default=12)
-    ap.add_argument("--workload", choices=["fel-amplifier", "batched-scan", "served-stream"],
+    ap.add_argument("--workload", choices=["fel-amplifier", "batched-scan", "served-stream", "example1"],
                     default="fel-amplifier")
+    ap.add_argument("--ex1-steps", type=int, default=12000, help="example1: field steps per run")
+    ap.add_argument("--ex1-parity-steps", type=int, default=4, help="example1: oracle prefix steps")
     ap.add_argument("--requests", type=int, default=1000, help="served stream: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="served stream: Poisson arrival rate (1/s)")
     ap.add_argument("--tick", type=int, default=50, help="batched scan / served stream: steps per tick")
@@ -302,6 +304,124 @@ def bench_served_stream(args) -> dict:
     }
 
 
+def _gain_fit(power, dt, g0, b0, steps_per_period):
+    """Gain length and saturation power from a power history: the power
+    averaged over one radiation period, the saturation power its maximum,
+    the gain length the inverse slope of ln P against the undulator length
+    z = gamma0 beta0 c t over the stretch where P rises from 1e-3 to 3e-2 of
+    its maximum (the exponential regime, well before saturation)."""
+    import numpy as np
+    p = np.asarray(power, dtype=float)
+    w = max(int(round(steps_per_period)), 1)
+    if len(p) < 4 * w:
+        return None
+    ps = np.convolve(p, np.ones(w) / w, mode="valid")
+    z = g0 * b0 * 299792458.0 * dt * (np.arange(len(ps)) + 0.5 * w)
+    i_sat = int(np.argmax(ps))
+    p_sat = float(ps[i_sat])
+    lo, hi = 1e-3 * p_sat, 3e-2 * p_sat
+    # the last upward crossing of lo before saturation, then the first of hi
+    below = np.nonzero(ps[:i_sat] < lo)[0]
+    i0 = int(below[-1]) + 1 if len(below) else 0
+    above = np.nonzero(ps[i0:i_sat] > hi)[0]
+    i1 = i0 + int(above[0]) if len(above) else i_sat
+    if i1 - i0 < 4 * w:
+        return {"p_sat_W": p_sat, "z_sat_m": float(z[i_sat]), "gain_length_m": None}
+    sl, ic = np.polyfit(z[i0:i1], np.log(ps[i0:i1]), 1)
+    resid = np.log(ps[i0:i1]) - (sl * z[i0:i1] + ic)
+    return {"p_sat_W": p_sat, "z_sat_m": float(z[i_sat]), "gain_length_m": float(1.0 / sl),
+            "fit_z_m": [float(z[i0]), float(z[i1 - 1])], "fit_rms_ln": float(np.std(resid)),
+            "curve_z_m": [float(v) for v in z[::max(len(z) // 200, 1)]],
+            "curve_P_W": [float(v) for v in ps[::max(len(z) // 200, 1)]]}
+
+
+def bench_example1(args) -> dict:
+    """The manual's Example 1 (infrared FEL, 64 x 64 x 2800 nodes, 131072
+    e-, uniform bunch with bunching factor 0.01, NSFD, Mur-2, no space
+    charge, FP64 as the paper's code) run through the undulator on the GPU
+    with NSFD and with standard FD; the gain length and saturation power
+    are fitted from the plane power and set against the manual's numbers
+    (MITHRA 22 cm and 2.6 GW; 1-D theory 22.4 cm and 2.7 GW).  The oracle
+    checks a prefix of steps of the same run."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2009_13645_amd import workloads as W
+    from paper_2009_13645_amd.engine import Engine, adapt_mesh
+    out = {"metric": "Example 1 gain length and saturation power", "runs": {}}
+    for solver, name in ((0, "NSFD"), (1, "FD")):
+        d, b, n, q = W.example1(solver=solver)
+        g0 = W.EX1_GAMMA / math.sqrt(1.0 + 0.5 * W.EX1_K ** 2)
+        d, _ = adapt_mesh(d, W.EX1_BUNCH_STEP_LAB / g0)
+        e = Engine(d, max_particles=n)
+        e.generate_bunch(b, n, q)
+        c = e.constants()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < args.ex1_steps:
+            k = min(1000, args.ex1_steps - done)
+            e.step(k)
+            torch.cuda.synchronize()
+            done += k
+            print(f"[example1] {name}: {done}/{args.ex1_steps} steps, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        pw = e.power_history(args.ex1_steps)
+        spec = e.spectral_power()
+        b_end = e.bunching()
+        lam_star = W.EX1_LAMBDA_U / (c["gamma0"] * c["beta0"])
+        fit = _gain_fit(pw, c["dt"], c["gamma0"], c["beta0"], lam_star / (299792458.0 * c["dt"]))
+        out["runs"][name] = {"steps": args.ex1_steps, "ms_per_step": wall * 1e3 / args.ex1_steps,
+                             "cell_updates_per_s": np.prod(W.EX1_NODES) * args.ex1_steps / wall,
+                             "dt_s": c["dt"], "n_sub": d["n_sub"], "bunching_end": b_end,
+                             "dW_domega_nu1_Js": float(spec[0]) if len(spec) else None, "fit": fit}
+        e.close()
+        del e
+        torch.cuda.empty_cache()
+    # 1-D theory from the table's density (the same formula pinned against the table)
+    rho = W.fel_rho_1d(W.EX1_GAMMA, W.EX1_K, W.EX1_LAMBDA_U, 2.72e19, helical=False)
+    lg_1d = W.EX1_LAMBDA_U / (4.0 * math.pi * math.sqrt(3.0) * rho)
+    out["theory_1d"] = {"rho": rho, "gain_length_m": lg_1d, "manual_gain_length_m": 0.224,
+                        "manual_p_sat_W": 2.7e9, "mithra_gain_length_m": 0.22, "mithra_p_sat_W": 2.6e9}
+    f = out["runs"]["NSFD"]["fit"] or {}
+    if f.get("gain_length_m"):
+        out["gain_length_rel_to_1d"] = f["gain_length_m"] / 0.224 - 1.0
+    if f.get("p_sat_W"):
+        out["p_sat_rel_to_1d"] = f["p_sat_W"] / 2.7e9 - 1.0
+    # prefix parity against the oracle (same device-generated bunch, FP64)
+    if args.ex1_parity_steps > 0 and not args.no_cpu_baseline:
+        from oracle.oracle import Oracle
+        d, b, n, q = W.example1(solver=0)
+        e = Engine(d, max_particles=n)
+        e.generate_bunch(b, n, q)
+        o = Oracle(d)
+        ob = dict(long_profile=b["long_profile"], trans_profile=b["trans_profile"], xc=b["center"][0],
+                  yc=b["center"][1], zc=b["center"][2], size_x=b["size"][0], size_y=b["size"][1],
+                  size_z=b["size"][2], gamma=b["gamma"], sigma_gamma_rel=b["sigma_gamma_rel"],
+                  sigma_u_perp=b["sigma_u_perp"], bunching=b["bunching"], bunching_phase=b["bunching_phase"],
+                  shot_noise=b["shot_noise"], n_electrons=b["n_electrons"], tapers=b["tapers"])
+        xyz, u = o.generate_bunch(ob, n)
+        xg, ug, _, _ = e.read_particles()
+        o.load_bunch(xyz, u, q)
+        o.set_spectrum(1, 1.0, 1.0)
+        k = args.ex1_parity_steps
+        e.step(k)
+        o.step(k)
+        par = {"steps": k, "bunch_max_dz_cells": float(np.max(np.abs(xg - xyz)[:, 2]) / d["dz"])}
+        for fld in ("Ax", "Ay", "Jx", "Jz", "Q", "Ex", "By"):
+            a_, b_ = e.read_field(fld), o.field(fld)
+            par["rel_l2_" + fld] = float(np.linalg.norm(a_ - b_) / max(np.linalg.norm(b_), 1e-300))
+        ug2, uo2 = e.read_particles()[1], o.particles()[1]
+        par["rel_l2_u"] = float(np.linalg.norm(ug2 - uo2) / np.linalg.norm(uo2))
+        so, sg = o.spectral_power(), e.spectral_power()
+        par["rel_spectral_nu1"] = float(abs(sg[0] - so[0]) / max(abs(so[0]), 1e-300))
+        out["oracle_prefix_parity"] = par
+        e.close()
+        o.close()
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -315,6 +435,9 @@ def main():
         return
     if args.workload == "served-stream":
         print(json.dumps(bench_served_stream(args)))
+        return
+    if args.workload == "example1":
+        print(json.dumps(bench_example1(args)))
         return
 
     import numpy as np

@@ -61,19 +61,22 @@ enum mithra_field_id {
 
 enum mithra_dtype { MITHRA_DTYPE_F32 = 0, MITHRA_DTYPE_F64 = 1 };
 
-/* Run descriptor.  Parameter names follow the manual's MESH group
- * (mesh resolution, truncation order, space charge, solver, bunch time
- * step) and UNDULATOR group (undulator parameter, period, length,
- * polarization angle), with the mesh already in the boosted frame. */
+/* Run descriptor.  Parameter names follow the manual's MESH group (ch. 4
+ * "MESH": mesh resolution, mesh-truncation-order, space-charge, solver,
+ * bunch-time-step), UNDULATOR group (ch. 4 "UNDULATOR": undulator-parameter,
+ * period, length, polarization-angle) and the radiation-power group of
+ * FEL-OUTPUT (ch. 4: plane-position, normalized frequencies), with the
+ * mesh already in the boosted frame. */
 typedef struct mithra_grid_desc {
     int32_t nx, ny, nz;          /* nodes per axis, 6..2^20 each */
     int32_t truncation_order;    /* Mur order: 1 or 2 */
     int32_t space_charge;        /* 1: solve for phi; 0: phi = 0 */
-    int32_t solver;              /* 0: NSFD (only NSFD is built) */
+    int32_t solver;              /* 0: NSFD (dt = dz/c); 1: standard FD (dt = 0.99 of the stable step of eq. CFLcondition) */
     int32_t n_sub;               /* bunch sub-steps per field step, dt_b = dt / n_sub, >= 1 */
     int32_t field_precision;     /* 32 or 64: storage of potentials, sources, E, B */
     int32_t compensated;         /* 1 (with 32): two-sum compensated current/charge sums */
-    int32_t und_type;            /* 0 planar, 1 helical */
+    int32_t und_type;            /* 0 planar, 1 helical, 2 optical plane wave, 3 optical Gaussian beam
+                                    (optical: strength a0 = K, wavelength 2 lambda_u, see mithra_set_undulator) */
     int32_t n_periods;           /* undulator length in periods, >= 1 */
     int32_t k_plane;             /* node plane of the radiated-power diagnostic, 1..nz-2 */
     int32_t tile[3];             /* sort tile, cells per axis, each 1..64 */
@@ -84,30 +87,122 @@ typedef struct mithra_grid_desc {
     double gamma;                /* beam Lorentz factor in the lab, > 1 */
     double K;                    /* undulator parameter, > 0 */
     double lambda_u;             /* undulator period, lab frame (m) */
-    double pol_angle_deg;        /* planar field direction: 0 = along y */
+    double pol_angle_deg;        /* field direction (sin, cos, 0) of this angle: 0 = along y, > 0 toward +x */
     double z_entrance;           /* boosted-frame z of the undulator entrance at t = 0 (m) */
+    int32_t n_freq;              /* spectral power: number of normalised frequencies (0: none, <= 64) */
+    int32_t pad_;
+    double nu_min, nu_max;       /* normalised frequencies nu_min..nu_max (equally spaced; one: nu_min) */
 } mithra_grid_desc;
+
+/* Undulator extensions (ch. 3 "Static Undulator Array Field", "Optical
+ * Undulator Field"; ch. 4 UNDULATOR static-undulator-array and
+ * optical-undulator).  Static undulators: n_modules modules of n_periods
+ * periods separated by `gap` (lab, m), K of module m = K + m dK
+ * (tapering-parameter); the fringes inside a gap are damped by the
+ * window of eq. fringingFieldGap.  Optical undulators (und_type 2, 3): a
+ * wave propagating along -z with strength a0 = K and wavelength
+ * 2 lambda_u, magnetic field along the polarisation direction of
+ * pol_angle_deg; signal type of eq. signalTypes (0 modulated Neumann,
+ * 1 modulated Gaussian, 2 modulated hyperbolic secant, 3 sinusoidal pulse),
+ * pulse length c tau, offset c t0 and CEP as in the manual; Gaussian beam:
+ * waists along and across the polarisation and the focus (lab z' from the
+ * undulator reference). */
+typedef struct mithra_undulator_desc {
+    int32_t n_modules;           /* >= 1 */
+    int32_t signal;              /* 0..3 */
+    double gap;                  /* lab gap between modules (m), >= 0; > 0 when n_modules > 1 */
+    double dK;                   /* tapering step of K */
+    double ctau, ct0, cep_deg;   /* optical pulse length, offset (m, lab) and CEP (deg) */
+    double w0_par, w0_perp;      /* Gaussian-beam waists (m) */
+    double z_focus;              /* Gaussian-beam focus (lab z' from the undulator reference, m) */
+} mithra_undulator_desc;
+
+/* Seed field injected by total-field / scattered-field boundaries on the
+ * node planes k = 1 (scattered) and k = 2 (total) next to z_min (ch. 3
+ * "Seed Field"; ch. 4 FIELD seed).  Incident transverse vector potential
+ * A = A0 p s(t - (z - z_2)/c) propagating along +z, A0 = a0 m c / e,
+ * p = (cos psi, sin psi, 0); the lab wavelength, pulse length and offset
+ * are Doppler-scaled by gamma0 (1 + beta0) to the boosted frame.  Gaussian
+ * beam: amplitude (w0/w(l)) exp(-r^2/w^2), phase -k r^2 / (2 R(l)) +
+ * atan(l / z_R), l = z - z_focus (boosted). */
+typedef struct mithra_seed_desc {
+    int32_t type;                /* 0 plane wave, 1 Gaussian beam */
+    int32_t signal;              /* 0..3, as for the optical undulator */
+    double a0;                   /* normalised amplitude */
+    double wavelength;           /* lab wavelength (m) */
+    double ctau, ct0, cep_deg;   /* pulse length, offset (lab, m), CEP (deg) */
+    double pol_deg;              /* direction of A from x toward y (deg) */
+    double w0;                   /* Gaussian waist (m) */
+    double z_focus;              /* Gaussian focus, boosted z (m) */
+} mithra_seed_desc;
+
+/* Bunch generated on the device by Halton quasi-random filling (ch. 3
+ * "Electron Bunch Generation"; ch. 4 BUNCH bunch-initialization).
+ * Element j of sequence i is 1 minus the radical inverse of j in the base
+ * of the i-th prime.  Coordinates: x, y from sequences 0, 1 (uniform: eq.
+ * uniform1D over full widths; Gaussian: eq. gaussian2D); z from sequence
+ * 2 (flat-top, eq. uniform1D) or 2 and 3 (Gaussian, eq. gaussian1D); lab
+ * energy gamma (1 + spread g), g from sequences 4, 5; transverse momentum
+ * from 6, 7.  Flat-top tapers against coherent scattering emission: a
+ * Gaussian of the same density, rms one lab radiation wavelength, split
+ * behind the tail and ahead of the head.  Lab lengths along z map to the
+ * boosted frame by 1 / (gamma0 (1 - beta beta0)); u_z = gamma0 (u'_z -
+ * beta0 gamma').  Bunching factor (eq. bunchingFactor) and shot noise
+ * (slices one load wavelength long, b_s = sqrt(-2 ln x_s)/sqrt(N_s), x_s
+ * and phase / 2 pi from sequences 8 and 9) displace z by
+ * -(2 b / k) sin(k z + phase), k the load wavenumber that the undulator
+ * entrance compresses to the resonant one. */
+typedef struct mithra_bunch_desc {
+    int32_t long_profile;        /* 0 flat-top, 1 Gaussian */
+    int32_t trans_profile;       /* 0 uniform, 1 Gaussian */
+    int32_t shot_noise;          /* 0 / 1 */
+    int32_t tapers;              /* flat-top tapers: 0 / 1 */
+    double center[3];            /* bunch centre, boosted frame (m) */
+    double size[3];              /* lab: transverse full widths or sigmas; flat-top length or sigma_z (m) */
+    double gamma;                /* mean lab Lorentz factor */
+    double sigma_gamma_rel;      /* relative energy spread */
+    double sigma_u_perp;         /* transverse spread of gamma beta */
+    double bunching, bunching_phase; /* b_f and its phase (rad) */
+    double n_electrons;          /* electrons represented (shot noise) */
+} mithra_bunch_desc;
 
 typedef struct mithra_engine *mithra_handle;
 
 /* Exact device bytes of the run's arena: potentials (3 time levels),
  * sources (2 sets, plus compensation terms), vertex fields, particle
- * state (2 buffers), sort scratch and diagnostics.  Returns 0 for an
- * invalid descriptor.  Pure function; no device call. */
+ * state (2 buffers), sort scratch and diagnostics (power history,
+ * spectral accumulators).  Returns 0 for an invalid descriptor.  Pure
+ * function; no device call. */
 size_t mithra_footprint_bytes(const mithra_grid_desc *d, int64_t n_particles);
 
-/* Validate `d`, derive the boost (gamma0 from the undulator, dt = dz/c,
- * dt_b = dt/n_sub) and the NSFD and Mur coefficients, carve `dev_arena`
- * and zero the fields.  `hip_stream` is a hipStream_t (NULL = default
+/* Mesh auto-adjustment of the MESH group (ch. 4 "MESH", the conditions
+ * checked before a run): for NSFD, if sqrt((dz/dx)^2 + (dz/dy)^2) >= 1,
+ * dx and dy are scaled up by one common factor to the closest values
+ * meeting it (the sum of squares becomes 0.98); the field step is then
+ * dz/c (NSFD) or the FD step, and n_sub becomes the integer closest to
+ * dt / bunch_time_step (at least 1), so that the bunch step divides the
+ * field step.  bunch_time_step <= 0 keeps n_sub.  The adapted values are
+ * written back to *d; *changed (nullable) receives a bit mask (1: dx, dy;
+ * 2: n_sub).  Pure host function.  Errors: EINVAL (null or non-positive
+ * spacings). */
+int mithra_adapt_mesh(mithra_grid_desc *d, double bunch_time_step, int32_t *changed);
+
+/* Validate `d`, derive the boost (gamma0 from the first undulator as in
+ * ch. 3 "Lorentz Transformation"; dt = dz/c for NSFD, eq. CFLcondition for
+ * FD; dt_b = dt/n_sub), the update coefficients (eqs. NSFDCoefficient and
+ * updateEquation) and the Mur coefficients (sec. "Boundary Truncation"),
+ * carve `dev_arena` and zero the fields.  `hip_stream` is a hipStream_t (NULL = default
  * stream).  On success *out is a new handle.  Errors: EINVAL (bad
  * descriptor: sizes, NSFD condition, precision, tiles, key range),
  * ENOMEM (arena_bytes < footprint or misaligned), EDEVICE. */
 int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size_t arena_bytes,
                      void *hip_stream, mithra_handle *out);
 
-/* Load n macro-electrons (ids 0..n-1 in input order).  Host arrays n x 3
- * row-major, copied: xyz = boosted-frame positions at t = dt/2 (m),
- * u = gamma*beta at t = 0.  q_macro = charge per macro-particle (C,
+/* Load n macro-electrons (ids 0..n-1 in input order) in the manual's
+ * six-column particle format (ch. 4 BUNCH, bunch-initialization type
+ * file: x, y, z, gamma beta_x, gamma beta_y, gamma beta_z), here in the
+ * boosted frame.  Host arrays n x 3 row-major, copied: xyz = positions at
+ * t = dt/2 (m), u = gamma*beta at t = 0.  q_macro = charge per macro-particle (C,
  * negative for electrons).  Deposits the first current from the backward
  * drift r - c dt u/gamma -> r and the charge at r, and sorts.  Errors:
  * EINVAL (n <= 0, n > max_particles, non-finite input), ESTATE (after a
@@ -115,7 +210,10 @@ int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size_t arena_by
 int mithra_load_bunch(mithra_handle h, int64_t n, const double *xyz, const double *u,
                       double q_macro);
 
-/* Enqueue n_steps PIC steps on the stream and return without waiting.
+/* Enqueue n_steps PIC steps (ch. 3 "Methodology": field update, Mur
+ * boundaries, vertex fields, gather and Boris push in the total field,
+ * charge-conserving deposit; plus bin and sort) on the stream and return
+ * without waiting.
  * A non-finite value seen by the diagnostics is reported as ENUMERIC by
  * the next read.  Errors: ESTATE (no bunch loaded), EDEVICE. */
 int mithra_step(mithra_handle h, int64_t n_steps);
@@ -129,7 +227,8 @@ int mithra_step(mithra_handle h, int64_t n_steps);
  * nx*ny*nz*sizeof(dtype).  Errors: EINVAL, ENUMERIC, EDEVICE. */
 int mithra_read_fields(mithra_handle h, int field_id, int dtype, void *host_out, size_t bytes);
 
-/* Copy the particles in id order after synchronising the stream:
+/* Copy the particles in id order, in the six-column format of the
+ * manual's bunch output (ch. 4 BUNCH), after synchronising the stream:
  * xyz (n x 3, m) at t_{n+1/2}, u (n x 3) at t_n.  Optional (nullable):
  * cell[id] = linear node index of the cell corner (-1 outside the active
  * region 1 <= cell <= n-3 on every axis) and sort_perm[rank] = id of the
@@ -151,8 +250,36 @@ int mithra_radiated_power(mithra_handle h, int32_t k_plane, double *p_lab_W);
 int64_t mithra_power_history(mithra_handle h, double *out, int64_t n);
 
 /* |<exp(i k_r z)>| over particles in active cells, k_r = 2 pi gamma0
- * beta0 / lambda_u (resonant boosted wavenumber).  Synchronises. */
+ * beta0 / lambda_u (resonant boosted wavenumber; ch. 3 "Bunching
+ * factor").  Synchronises. */
 int mithra_bunching(mithra_handle h, double *b);
+
+/* Spectral radiated energy through the power plane (ch. 4 FEL-OUTPUT,
+ * radiation-power at normalized frequencies): running Fourier transforms
+ * over boosted time t_{n+1/2} of the lab-frame E'_x E'_y B'_x B'_y at the
+ * plane's interior nodes, F(omega) = sum_n F(t_n) exp(-i omega t_n) dt,
+ * omega = nu * 2 pi c / lambda*, give dW/domega = (1/pi) (dx dy / mu0)
+ * sum Re(E'_x B'_y* - E'_y B'_x*) (J s), whose integral over omega >= 0 is
+ * the time integral of the plane power.  Writes min(n, n_freq) values
+ * and returns that count (or a negative code).  Synchronises. */
+int64_t mithra_spectral_power(mithra_handle h, double *dW_domega, int64_t n);
+
+/* Undulator arrays, tapering and optical-undulator parameters (see
+ * mithra_undulator_desc); allowed before the first step.  Errors: EINVAL,
+ * ESTATE (after a step). */
+int mithra_set_undulator(mithra_handle h, const mithra_undulator_desc *u);
+
+/* TF/SF seed (see mithra_seed_desc); allowed before the first step.  A
+ * seeded run updates the x faces in the boundary kernel (after the
+ * injection), not inside the sweep.  Errors: EINVAL, ESTATE. */
+int mithra_set_seed(mithra_handle h, const mithra_seed_desc *s);
+
+/* Generate n macro-electrons on the device (see mithra_bunch_desc) and
+ * load them as mithra_load_bunch would (first current, charge, sort).
+ * q_macro as for mithra_load_bunch.  Errors: EINVAL (n outside
+ * 1..max_particles, bad description, shot-noise slices beyond the sort
+ * scratch), ESTATE (already loaded), EDEVICE. */
+int mithra_generate_bunch(mithra_handle h, const mithra_bunch_desc *b, int64_t n, double q_macro);
 
 /* Derived constants: out[0..7] = gamma0, beta0, dt, dt_b, NSFD A,
  * q_macro, steps done, particles. */

@@ -33,6 +33,10 @@ hipError_t launch_mur(const RunDev &R, hipStream_t st);
 int sweep_fuses_xfaces(const RunDev &R, int shape);
 hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStream_t st);
 hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st, int end_step = 0);
+hipError_t launch_plane_spectrum(const RunDev &R, hipStream_t st);
+hipError_t launch_spec_reduce(const RunDev &R, double *out, hipStream_t st);
+hipError_t launch_seed_inject(const RunDev &R, hipStream_t st);
+hipError_t launch_gen_bunch(const RunDev &R, const GenParams &P, int pass, double *zrange, hipStream_t st);
 hipError_t launch_push_deposit(const RunDev &R, hipStream_t st, bool box);
 hipError_t launch_load_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st);
@@ -100,7 +104,7 @@ static const int kPartials = 8192;  // per-block partial slots (>= persistent bl
 static const int kBunchBlocks = 256;
 
 struct Layout {
-    size_t ctl, pot, src, src_lo, eb, pr, pid, key_by_id, slot_of_id, cell_by_id, key_sorted, sk, sv, hist, boxpart,
+    size_t ctl, pot, src, src_lo, eb, spec, pr, pid, key_by_id, slot_of_id, cell_by_id, key_sorted, sk, sv, hist, boxpart,
         boxslot, ppart, power, scratch, tile_flag, ntiles, total;
 };
 
@@ -123,6 +127,7 @@ static Layout make_layout(const mithra_grid_desc *d, int64_t cap)
     L.src = take(8 * nn * pf);
     L.src_lo = (d->compensated && d->field_precision == 32) ? take(8 * nn * pf) : (size_t)-1;
     L.eb = take(8 * nn * pf);
+    L.spec = take((size_t)(d->n_freq > 0 ? d->n_freq : 0) * 8 * (size_t)d->nx * d->ny * 8);
     L.pr = take(12 * c * 8);
     L.pid = take(2 * c * 4);
     L.key_by_id = take(c * 4);
@@ -203,6 +208,15 @@ static double gamma0_of(const mithra_grid_desc *d)
     return d->und_type == 1 ? d->gamma / std::sqrt(1.0 + d->K * d->K) : d->gamma / std::sqrt(1.0 + 0.5 * d->K * d->K);
 }
 
+// field time step: dz / c for NSFD (dispersion-free along z); standard FD
+// cannot take it (eq. CFLcondition) and takes 0.99 of its stable step
+static double field_dt(const mithra_grid_desc *d)
+{
+    if (d->solver == 1)
+        return 0.99 / (kC * std::sqrt(1.0 / (d->dx * d->dx) + 1.0 / (d->dy * d->dy) + 1.0 / (d->dz * d->dz)));
+    return d->dz / kC;
+}
+
 static const char *validate(const mithra_grid_desc *d)
 {
     if (!d)
@@ -217,8 +231,8 @@ static const char *validate(const mithra_grid_desc *d)
         return "truncation_order must be 1 or 2";
     if (d->space_charge != 0 && d->space_charge != 1)
         return "space_charge must be 0 or 1";
-    if (d->solver != 0)
-        return "only the NSFD solver (0) is built";
+    if (d->solver != 0 && d->solver != 1)
+        return "solver must be 0 (NSFD) or 1 (FD)";
     if (d->n_sub < 1 || d->n_sub > 1024)
         return "n_sub must be in 1..1024";
     if (d->field_precision != 32 && d->field_precision != 64)
@@ -227,8 +241,12 @@ static const char *validate(const mithra_grid_desc *d)
         return "compensated must be 0 or 1";
     if (d->compensated && d->field_precision != 32)
         return "compensated accumulation applies to field_precision 32 only";
-    if (d->und_type != 0 && d->und_type != 1)
-        return "und_type must be 0 (planar) or 1 (helical)";
+    if (d->und_type < 0 || d->und_type > 3)
+        return "und_type must be 0 (planar), 1 (helical), 2 (optical plane wave) or 3 (optical Gaussian beam)";
+    if (d->n_freq < 0 || d->n_freq > 64)
+        return "n_freq must be in 0..64";
+    if (d->n_freq > 0 && !(std::isfinite(d->nu_min) && std::isfinite(d->nu_max)))
+        return "non-finite normalised frequency";
     if (d->n_periods < 1)
         return "n_periods must be >= 1";
     if (d->k_plane < 1 || d->k_plane > d->nz - 2)
@@ -246,8 +264,8 @@ static const char *validate(const mithra_grid_desc *d)
     if (!(d->dx > 0 && d->dy > 0 && d->dz > 0))
         return "mesh spacings must be positive";
     const double q = (d->dz / d->dx) * (d->dz / d->dx) + (d->dz / d->dy) * (d->dz / d->dy);
-    if (!(q < 1.0))
-        return "NSFD stability needs (dz/dx)^2 + (dz/dy)^2 < 1";
+    if (d->solver == 0 && !(q < 1.0))
+        return "NSFD stability needs (dz/dx)^2 + (dz/dy)^2 < 1 (mithra_adapt_mesh adjusts dx, dy)";
     if (!(d->gamma > 1.0 && d->K > 0.0 && d->lambda_u > 0.0))
         return "gamma > 1, K > 0 and lambda_u > 0 are required";
     if (!(gamma0_of(d) > 1.0))
@@ -315,8 +333,10 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.inv_dx = 1.0 / d->dx;
     R.inv_dy = 1.0 / d->dy;
     R.inv_dz = 1.0 / d->dz;
-    // Lorentz boost of mesh and time: dt = dz / c, dt_b = dt / N
-    R.dt = d->dz / kC;
+    // Lorentz boost of mesh and time: dt = dz / c (NSFD) or 0.99 of the
+    // stable step of eq. CFLcondition (FD), dt_b = dt / N
+    R.solver = d->solver;
+    R.dt = field_dt(d);
     R.dtb = R.dt / (double)d->n_sub;
     R.n_sub = d->n_sub;
     R.gamma0 = gamma0_of(d);
@@ -327,12 +347,17 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.z_ent = d->z_entrance;
     R.theta = d->pol_angle_deg * kPi / 180.0;
     R.und_type = d->und_type;
+    R.Kund = d->K;
+    R.lam_u = d->lambda_u;
+    R.n_modules = 1;
+    R.und_ext = d->und_type >= 2 ? 1 : 0;
     // NSFD: A = 0.25 (1 + 0.02 / ((dz/dx)^2 + (dz/dy)^2)); r_l = c dt / d_l
     const double cdt = kC * R.dt;
     const double rx2 = (cdt / d->dx) * (cdt / d->dx), ry2 = (cdt / d->dy) * (cdt / d->dy),
                  rz2 = (cdt / d->dz) * (cdt / d->dz);
     const double qq = (d->dz / d->dx) * (d->dz / d->dx) + (d->dz / d->dy) * (d->dz / d->dy);
-    R.A = 0.25 * (1.0 + 0.02 / qq);
+    // standard FD is the same update with no z average (A = 0)
+    R.A = d->solver == 0 ? 0.25 * (1.0 + 0.02 / qq) : 0.0;
     R.a1 = 2.0 * (1.0 - (1.0 - 2.0 * R.A) * rx2 - (1.0 - 2.0 * R.A) * ry2 - rz2);
     R.a2 = rx2;
     R.a4 = ry2;
@@ -390,6 +415,11 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.src = A + L.src;
     R.src_lo = L.src_lo == (size_t)-1 ? nullptr : A + L.src_lo;
     R.eb = A + L.eb;
+    R.nfreq = d->n_freq;
+    R.nu_min = d->nu_min;
+    R.nu_max = d->nu_max;
+    R.omega_r = 2.0 * kPi * kC * R.gamma0 * R.beta0 / d->lambda_u;
+    R.spec = d->n_freq > 0 ? (double *)(A + L.spec) : nullptr;
     for (int b = 0; b < 2; ++b)
         for (int a = 0; a < 6; ++a)
             R.pr[b][a] = (double *)(A + L.pr) + (size_t)(b * 6 + a) * c;
@@ -422,6 +452,8 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     if (R.src_lo)
         HIPCHK(h, hipMemsetAsync(R.src_lo, 0, 8 * nn * pf, h->stream));
     HIPCHK(h, hipMemsetAsync(R.eb, 0, 8 * nn * pf, h->stream));
+    if (R.spec)
+        HIPCHK(h, hipMemsetAsync(R.spec, 0, (size_t)R.nfreq * 8 * (size_t)d->nx * d->ny * 8, h->stream));
     HIPCHK(h, hipMemsetAsync(R.power_hist, 0, (size_t)kPowerCap * 8, h->stream));
     // no tile marked for any step (the load marks those of step 0)
     HIPCHK(h, hipMemsetAsync(R.tile_flag, 0xFF, L.ntiles * 4, h->stream));
@@ -462,6 +494,7 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
 }
 
 static int enqueue_sort_with_cells(mithra_handle h);
+static int finish_load(mithra_handle h, int64_t n, double q_macro);
 
 extern "C" int mithra_load_bunch(mithra_handle h, int64_t n, const double *xyz, const double *u, double q_macro)
 {
@@ -491,6 +524,14 @@ extern "C" int mithra_load_bunch(mithra_handle h, int64_t n, const double *xyz, 
     for (int64_t p = 0; p < n; ++p)
         ids[(size_t)p] = (int32_t)p;
     HIPCHK(h, hipMemcpy(R.pid[0], ids.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+    return finish_load(h, n, q_macro);
+}
+
+// The particles are in buffer 0 (ids 0..n-1 in slot order): first current
+// from the backward drift, charge, sort, boxes.
+static int finish_load(mithra_handle h, int64_t n, double q_macro)
+{
+    RunDev &R = h->R;
     R.np = n;
     R.q = q_macro;
     R.qV = q_macro / (h->d.dx * h->d.dy * h->d.dz);
@@ -545,6 +586,8 @@ static int enqueue_step_on(mithra_handle h, hipStream_t st, hipEvent_t *ev)
     auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
     HIPCHK(h, mark(0));
     HIPCHK(h, launch_sweep(R, h->sweep_shape, st));
+    if (R.seed_on)  // before Mur: the boundary kernel reads the corrected planes
+        HIPCHK(h, launch_seed_inject(R, st));
     HIPCHK(h, mark(1));
     HIPCHK(h, launch_mur(R, st));
     HIPCHK(h, mark(2));
@@ -554,6 +597,8 @@ static int enqueue_step_on(mithra_handle h, hipStream_t st, hipEvent_t *ev)
         HIPCHK(h, launch_vertex_power(R, st));
     else
         HIPCHK(h, launch_vertex_fields(R, 0, 0, st));
+    if (R.nfreq > 0)
+        HIPCHK(h, launch_plane_spectrum(R, st));
     HIPCHK(h, mark(3));
     HIPCHK(h, launch_push_deposit(R, st, !sort_ends_step(R)));
     HIPCHK(h, mark(4));
@@ -820,6 +865,219 @@ extern "C" int mithra_bunching(mithra_handle h, double *b)
     return MITHRA_OK;
 }
 
+extern "C" int64_t mithra_spectral_power(mithra_handle h, double *dW_domega, int64_t n)
+{
+    if (!h || !dW_domega || n < 0)
+        return MITHRA_EINVAL;
+    HIPCHK(h, sync_run(h));
+    const int64_t m = std::min<int64_t>(n, h->R.nfreq);
+    if (m <= 0)
+        return 0;
+    double *dev = (double *)(h->arena + h->L.scratch);  // nfreq <= 64 results
+    HIPCHK(h, launch_spec_reduce(h->R, dev, h->stream));
+    HIPCHK(h, sync_run(h));
+    HIPCHK(h, hipMemcpy(dW_domega, dev, (size_t)m * 8, hipMemcpyDeviceToHost));
+    return m;
+}
+
+static void drop_graphs(mithra_handle h)
+{
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    if (h->graph8) {
+        (void)hipGraphExecDestroy(h->graph8);
+        h->graph8 = nullptr;
+    }
+}
+
+extern "C" int mithra_set_undulator(mithra_handle h, const mithra_undulator_desc *u)
+{
+    if (!h || !u)
+        return MITHRA_EINVAL;
+    if (h->steps > 0)
+        return fail(h, MITHRA_ESTATE, "the undulator is fixed once the run has stepped");
+    if (h->batched)
+        return fail(h, MITHRA_ESTATE, "the run belongs to a batch");
+    const double v[] = {u->gap, u->dK, u->ctau, u->ct0, u->cep_deg, u->w0_par, u->w0_perp, u->z_focus};
+    for (double x : v)
+        if (!std::isfinite(x))
+            return fail(h, MITHRA_EINVAL, "non-finite undulator parameter");
+    if (u->n_modules < 1 || u->n_modules > 1000)
+        return fail(h, MITHRA_EINVAL, "n_modules must be in 1..1000");
+    if (u->n_modules > 1 && !(u->gap > 0.0))
+        return fail(h, MITHRA_EINVAL, "an undulator array needs gap > 0");
+    if (u->signal < 0 || u->signal > 3)
+        return fail(h, MITHRA_EINVAL, "signal must be 0..3");
+    if (h->d.und_type >= 2 && u->signal != 3 && !(u->ctau > 0.0))
+        return fail(h, MITHRA_EINVAL, "an optical pulse needs ctau > 0");
+    if (h->d.und_type == 3 && !(u->w0_par > 0.0 && u->w0_perp > 0.0))
+        return fail(h, MITHRA_EINVAL, "a Gaussian-beam undulator needs positive waists");
+    for (int m = 0; m < u->n_modules; ++m)
+        if (!(h->d.K + m * u->dK > 0.0))
+            return fail(h, MITHRA_EINVAL, "tapering makes K of module %d non-positive", m);
+    RunDev &R = h->R;
+    R.n_modules = u->n_modules;
+    R.gap = u->gap;
+    R.dK = u->dK;
+    R.opt_signal = u->signal;
+    R.opt_ctau = u->ctau;
+    R.opt_ct0 = u->ct0;
+    R.opt_cep = u->cep_deg * kPi / 180.0;
+    R.opt_w0[0] = u->w0_par;
+    R.opt_w0[1] = u->w0_perp;
+    R.opt_zf = u->z_focus;
+    R.und_ext = (h->d.und_type >= 2 || u->n_modules > 1) ? 1 : 0;
+    drop_graphs(h);
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_set_seed(mithra_handle h, const mithra_seed_desc *sd)
+{
+    if (!h || !sd)
+        return MITHRA_EINVAL;
+    if (h->steps > 0)
+        return fail(h, MITHRA_ESTATE, "the seed is fixed once the run has stepped");
+    if (h->batched)
+        return fail(h, MITHRA_ESTATE, "the run belongs to a batch");
+    const double v[] = {sd->a0, sd->wavelength, sd->ctau, sd->ct0, sd->cep_deg, sd->pol_deg, sd->w0, sd->z_focus};
+    for (double x : v)
+        if (!std::isfinite(x))
+            return fail(h, MITHRA_EINVAL, "non-finite seed parameter");
+    if (sd->type != 0 && sd->type != 1)
+        return fail(h, MITHRA_EINVAL, "seed type must be 0 (plane wave) or 1 (Gaussian beam)");
+    if (sd->signal < 0 || sd->signal > 3 || !(sd->wavelength > 0.0) || (sd->signal != 3 && !(sd->ctau > 0.0)))
+        return fail(h, MITHRA_EINVAL, "seed signal, wavelength or pulse length out of range");
+    if (sd->type == 1 && !(sd->w0 > 0.0))
+        return fail(h, MITHRA_EINVAL, "a Gaussian seed needs w0 > 0");
+    if (h->d.nz < 8)
+        return fail(h, MITHRA_EINVAL, "a seeded run needs nz >= 8");
+    RunDev &R = h->R;
+    R.seed_on = 1;
+    R.seed_type = sd->type;
+    R.seed_signal = sd->signal;
+    R.seed_a0 = sd->a0;
+    R.seed_lambda = sd->wavelength;
+    R.seed_ctau = sd->ctau;
+    R.seed_ct0 = sd->ct0;
+    R.seed_cep = sd->cep_deg * kPi / 180.0;
+    R.seed_pol = sd->pol_deg * kPi / 180.0;
+    R.seed_w0 = sd->w0;
+    R.seed_zf = sd->z_focus;
+    // the injection corrects planes 1 and 2 after the sweep: the x faces on
+    // those planes must then be updated by the boundary kernel, after it
+    if (sweep_fuses_xfaces(R, h->sweep_shape)) {
+        int sh = 0;
+        while (sh < sweep_shape_count() && sweep_fuses_xfaces(R, sh))
+            ++sh;
+        h->sweep_shape = sh;
+    }
+    R.xface_fused = sweep_fuses_xfaces(R, h->sweep_shape);
+    drop_graphs(h);
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_adapt_mesh(mithra_grid_desc *d, double bunch_time_step, int32_t *changed)
+{
+    if (!d || !(d->dx > 0 && d->dy > 0 && d->dz > 0) || !std::isfinite(bunch_time_step))
+        return MITHRA_EINVAL;
+    int32_t mask = 0;
+    if (d->solver == 0) {
+        const double q = (d->dz / d->dx) * (d->dz / d->dx) + (d->dz / d->dy) * (d->dz / d->dy);
+        if (!(q < 1.0)) {
+            // one common factor on dx and dy: q scales by 1/f^2
+            const double f = std::sqrt(q / 0.98);
+            d->dx *= f;
+            d->dy *= f;
+            mask |= 1;
+        }
+    }
+    if (bunch_time_step > 0.0) {
+        const double dt = field_dt(d);
+        int64_t nb = (int64_t)std::llround(dt / bunch_time_step);
+        if (nb < 1)
+            nb = 1;
+        if (nb > 1024)
+            nb = 1024;
+        if (nb != d->n_sub) {
+            d->n_sub = (int32_t)nb;
+            mask |= 2;
+        }
+    }
+    if (changed)
+        *changed = mask;
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_generate_bunch(mithra_handle h, const mithra_bunch_desc *b, int64_t n, double q_macro)
+{
+    if (!h || !b)
+        return MITHRA_EINVAL;
+    if (h->steps > 0 || h->loaded)
+        return fail(h, MITHRA_ESTATE, "the bunch is loaded once, before the first step");
+    if (n <= 0 || n > h->d.max_particles)
+        return fail(h, MITHRA_EINVAL, "n = %lld outside 1..max_particles (%lld)", (long long)n,
+                    (long long)h->d.max_particles);
+    const double v[] = {b->center[0], b->center[1], b->center[2], b->size[0], b->size[1], b->size[2],
+                        b->gamma, b->sigma_gamma_rel, b->sigma_u_perp, b->bunching, b->bunching_phase,
+                        b->n_electrons, q_macro};
+    for (double x : v)
+        if (!std::isfinite(x))
+            return fail(h, MITHRA_EINVAL, "non-finite bunch parameter");
+    if ((b->long_profile != 0 && b->long_profile != 1) || (b->trans_profile != 0 && b->trans_profile != 1) ||
+        (b->shot_noise != 0 && b->shot_noise != 1) || (b->tapers != 0 && b->tapers != 1))
+        return fail(h, MITHRA_EINVAL, "profile and flag fields must be 0 or 1");
+    if (!(b->gamma > 1.0) || b->size[2] < 0 || b->size[0] < 0 || b->size[1] < 0 || b->sigma_gamma_rel < 0 ||
+        b->sigma_u_perp < 0 || (b->shot_noise && !(b->n_electrons > 0)))
+        return fail(h, MITHRA_EINVAL, "bunch sizes, spreads, gamma or electron count out of range");
+    RunDev &R = h->R;
+    const double g0 = R.gamma0, b0 = R.beta0;
+    const double beta = std::sqrt(1.0 - 1.0 / (b->gamma * b->gamma));
+    const double kr = 2.0 * kPi * g0 * b0 / h->d.lambda_u;
+    GenParams P{};
+    P.long_profile = b->long_profile;
+    P.trans_profile = b->trans_profile;
+    P.shot_noise = b->shot_noise;
+    P.n = n;
+    P.cx = b->center[0];
+    P.cy = b->center[1];
+    P.cz = b->center[2];
+    P.sx = b->size[0];
+    P.sy = b->size[1];
+    P.L = b->size[2];
+    P.gamma = b->gamma;
+    P.sig_g = b->sigma_gamma_rel;
+    P.sig_u = b->sigma_u_perp;
+    P.bf = b->bunching;
+    P.bphase = b->bunching_phase;
+    P.n_e = b->n_electrons;
+    P.lz = 1.0 / (g0 * (1.0 - beta * b0));
+    P.k = kr * g0 * g0 * (1.0 - beta * b0) * b0 / beta;
+    P.sig_t = (2.0 * kPi / kr) / (g0 * (1.0 + b0));
+    P.n_flat = n;
+    if (b->long_profile == 0 && b->tapers == 1)
+        P.n_flat = (int64_t)std::llround((double)n * P.L / (P.L + std::sqrt(2.0 * kPi) * P.sig_t));
+    double *zr = (double *)(h->arena + h->L.scratch);
+    HIPCHK(h, launch_gen_bunch(R, P, 0, zr, h->stream));
+    if (b->shot_noise) {
+        double range[2];
+        HIPCHK(h, hipMemcpyAsync(range, zr, 16, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        P.zmin = range[0];
+        P.slice = 2.0 * kPi / P.k;
+        const double ns = std::floor((range[1] - range[0]) / P.slice) + 1.0;
+        const size_t cap = 2 * (size_t)(h->d.max_particles > 0 ? h->d.max_particles : 1);  // sort-key scratch
+        if (!(ns >= 1.0) || ns > (double)cap)
+            return fail(h, MITHRA_EINVAL, "%.0f shot-noise slices exceed the %zu of the sort scratch", ns, cap);
+        P.counts = (int32_t *)R.sk[0];
+        HIPCHK(h, hipMemsetAsync(P.counts, 0, (size_t)ns * 4, h->stream));
+        HIPCHK(h, launch_gen_bunch(R, P, 1, zr, h->stream));
+        HIPCHK(h, launch_gen_bunch(R, P, 2, zr, h->stream));
+    }
+    return finish_load(h, n, q_macro);
+}
+
 extern "C" int mithra_constants(mithra_handle h, double *o)
 {
     if (!h || !o)
@@ -862,6 +1120,8 @@ extern "C" int mithra_set_sweep_shape(mithra_handle h, int shape)
         return MITHRA_EINVAL;
     if (h->batched)
         return fail(h, MITHRA_ESTATE, "the run belongs to a batch: its sweep shape is fixed");
+    if (h->R.seed_on && sweep_fuses_xfaces(h->R, shape))
+        return fail(h, MITHRA_EINVAL, "a seeded run needs a sweep shape that leaves the x faces to the boundary kernel");
     h->sweep_shape = shape;
     h->R.xface_fused = sweep_fuses_xfaces(h->R, shape);
     if (h->graph) {
@@ -994,6 +1254,11 @@ extern "C" int mithra_autotune_sweep(mithra_handle h, int iters, int *best_shape
         return MITHRA_EINVAL;
     if (!h->loaded)
         return fail(h, MITHRA_ESTATE, "no bunch loaded");
+    if (h->R.seed_on) {  // seeded runs keep their non-fused shape
+        if (best_shape)
+            *best_shape = h->sweep_shape;
+        return MITHRA_OK;
+    }
     const TuneKey key{h->d.field_precision, h->d.compensated, h->d.space_charge, h->d.nx, h->d.ny, h->d.nz};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1285,6 +1550,9 @@ extern "C" int mithra_batch_create(const mithra_handle *runs, int32_t n_runs, vo
     for (int i = 0; i < n_runs; ++i) {
         if (!runs[i] || !runs[i]->loaded || runs[i]->batched)
             return MITHRA_ESTATE;
+        // the grouped stages carry the plain step only
+        if (runs[i]->R.seed_on || runs[i]->R.nfreq > 0 || runs[i]->R.und_ext)
+            return MITHRA_EINVAL;
         for (int j = 0; j < i; ++j)
             if (runs[j] == runs[i])
                 return MITHRA_EINVAL;

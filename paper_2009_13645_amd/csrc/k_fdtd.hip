@@ -1045,6 +1045,157 @@ struct VertexPower {
 };
 
 // ---------------------------------------------------------------------------
+// Spectral radiated power: running Fourier transforms over the boosted time
+// t_{s+1/2} of the lab-frame E'_x E'_y B'_x B'_y at every interior node of
+// the power plane, at omega_f = nu_f omega_r.  One thread per plane node
+// owns its accumulators (no atomics); the fields are those of the plane
+// power, from the potentials of step s.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ inline double spec_nu(const RunDev &R, int f)
+{
+    return R.nfreq == 1 ? R.nu_min : R.nu_min + (R.nu_max - R.nu_min) * f / (double)(R.nfreq - 1);
+}
+
+template <typename T>
+struct PlaneSpectrum {
+    static constexpr int kThreads = 256;
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        const int64_t s = R.ctl->step;
+        const int wx = R.nx - 2, wy = R.ny - 2;
+        const int t = (int)(blk.id * kThreads + threadIdx.x);
+        if (t >= wx * wy)
+            return;
+        const int i = 1 + t % wx, j = 1 + t / wx;
+        double E[3], B[3];
+        vertex_eb<T>(R, s, i, j, R.k_plane, E, B);
+        const double g0 = R.gamma0, b0 = R.beta0;
+        double F[4];
+        F[0] = g0 * (E[0] + b0 * kC * B[1]);
+        F[1] = g0 * (E[1] - b0 * kC * B[0]);
+        F[2] = g0 * (B[0] - b0 * E[1] / kC);
+        F[3] = g0 * (B[1] + b0 * E[0] / kC);
+        const double tt = ((double)s + 0.5) * R.dt;
+        const int64_t plane = (int64_t)R.nx * R.ny, pidx = (int64_t)j * R.nx + i;
+        for (int f = 0; f < R.nfreq; ++f) {
+            const double om = spec_nu(R, f) * R.omega_r;
+            const double c = cos(om * tt) * R.dt, sn = -sin(om * tt) * R.dt;
+            double *acc = R.spec + (int64_t)f * 8 * plane + pidx;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc[(2 * q) * plane] += F[q] * c;
+                acc[(2 * q + 1) * plane] += F[q] * sn;
+            }
+        }
+    }
+};
+
+// dW/domega of frequency f = blockIdx.x: (1/pi) (dx dy / mu0) sum over the
+// plane's interior nodes of Re(Ex' By'* - Ey' Bx'*), fixed-order tree sum
+__global__ __launch_bounds__(256) void k_spec_reduce(RunDev R, double *out)
+{
+    __shared__ double red[256];
+    const int f = blockIdx.x;
+    const int wx = R.nx - 2, wy = R.ny - 2;
+    const int64_t plane = (int64_t)R.nx * R.ny;
+    const double *acc = R.spec + (int64_t)f * 8 * plane;
+    double sum = 0.0;
+    for (int t = threadIdx.x; t < wx * wy; t += 256) {
+        const int64_t p = (int64_t)(1 + t / wx) * R.nx + 1 + t % wx;
+        sum += (acc[0 * plane + p] * acc[6 * plane + p] + acc[1 * plane + p] * acc[7 * plane + p]) -
+               (acc[2 * plane + p] * acc[4 * plane + p] + acc[3 * plane + p] * acc[5 * plane + p]);
+    }
+    red[threadIdx.x] = sum;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mu0 = 1.0 / (kEps0 * kC * kC);
+        out[f] = red[0] * R.dx * R.dy / (mu0 * kPi);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// TF/SF seed injection on the planes k = 1 (scattered-field boundary) and
+// k = 2 (total-field boundary): after the update of A_x and A_y, each node
+// gets back the incident-wave part of the terms through which it used the
+// other region's values, so that the total-field region holds +f.
+// Incident wave (boosted, along +z): A = A0 p s(t - (z - z_2)/c), the lab
+// signal Doppler-scaled by gamma0 (1 + beta0); Gaussian seeds add the
+// paraxial amplitude, curvature and Gouy phase.
+// ---------------------------------------------------------------------------
+
+__device__ inline double seed_signal(int type, double tau, double f, double tp, double t0, double ph)
+{
+    const double d = tau - t0;
+    const double car = cos(2.0 * kPi * f * d + ph);
+    const double ln2 = 0.69314718055994530942;
+    switch (type) {
+    case 0:
+        return -4.0 * ln2 * car * (d / tp) * exp(-2.0 * ln2 * d * d / (tp * tp));
+    case 1:
+        return car * exp(-2.0 * ln2 * d * d / (tp * tp));
+    case 2:
+        return car / cosh(d / tp);
+    default:
+        return d <= 0.0 ? car * exp(-2.0 * ln2 * d * d / (tp * tp)) : car;
+    }
+}
+
+__device__ inline double seed_incident(const RunDev &R, int comp, int i, int j, int k, double t)
+{
+    const double x = R.x0 + i * R.dx, y = R.y0 + j * R.dy, z = R.z0 + k * R.dz;
+    const double pc = comp == 0 ? cos(R.seed_pol) : sin(R.seed_pol);
+    const double D = R.gamma0 * (1.0 + R.beta0);
+    const double lam = R.seed_lambda * D;
+    const double f = kC / lam, tp = R.seed_ctau / kC * D, t0 = R.seed_ct0 / kC * D;
+    const double A0 = R.seed_a0 * kMe * kC / kQe;
+    const double z2 = R.z0 + 2.0 * R.dz;
+    const double tau = t - (z - z2) / kC;
+    double amp = 1.0, ph = R.seed_cep;
+    if (R.seed_type == 1) {
+        const double zR = kPi * R.seed_w0 * R.seed_w0 / lam;
+        const double l = z - R.seed_zf;
+        const double w = R.seed_w0 * sqrt(1.0 + (l / zR) * (l / zR));
+        const double r2 = x * x + y * y;
+        amp = (R.seed_w0 / w) * exp(-r2 / (w * w));
+        ph += -0.5 * (2.0 * kPi / lam) * r2 * l / (l * l + zR * zR) + atan(l / zR);
+    }
+    return pc * A0 * amp * seed_signal(R.seed_signal, tau, f, tp, t0, ph);
+}
+
+template <typename T>
+struct SeedInject {
+    static constexpr int kThreads = 256;
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        const int64_t s = R.ctl->step;
+        const int wx = R.nx - 2, wy = R.ny - 2;
+        const int64_t t = blk.id * kThreads + threadIdx.x;
+        if (t >= 2 * (int64_t)wx * wy)
+            return;
+        const int comp = (int)(t / ((int64_t)wx * wy));
+        const int r = (int)(t % ((int64_t)wx * wy));
+        const int i = 1 + r % wx, j = 1 + r / wx;
+        const double tt = (double)s * R.dt;  // time level n of the update
+        const double A = R.A;
+        auto F = [&](int ii, int jj, int kk) { return seed_incident(R, comp, ii, jj, kk, tt); };
+        const double c1 = A * (R.a2 * F(i + 1, j, 2) + R.a2 * F(i - 1, j, 2) + R.a4 * F(i, j + 1, 2) +
+                               R.a4 * F(i, j - 1, 2)) + R.a6 * F(i, j, 2);
+        const double c2 = A * (R.a2 * F(i + 1, j, 1) + R.a2 * F(i - 1, j, 1) + R.a4 * F(i, j + 1, 1) +
+                               R.a4 * F(i, j - 1, 1)) + R.a6 * F(i, j, 1);
+        T *pn = pot_ptr<T>(R, slot_next(s), comp);
+        const int64_t n1 = nid(R, i, j, 1), n2 = nid(R, i, j, 2);
+        pn[n1] = (T)((double)pn[n1] - c1);
+        pn[n2] = (T)((double)pn[n2] + c2);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 
@@ -1195,6 +1346,38 @@ hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStr
     else
         hipLaunchKernelGGL((k_run<VertexFields<double>, int, int>), dim3((unsigned)blocks), dim3(256), 0, st, R, step_bias,
                            full);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_spectrum(const RunDev &R, hipStream_t st)
+{
+    if (R.nfreq <= 0)
+        return hipSuccess;
+    const unsigned nb = (unsigned)(((int64_t)(R.nx - 2) * (R.ny - 2) + 255) / 256);
+    if (R.precision == 32)
+        hipLaunchKernelGGL((k_run<PlaneSpectrum<float>>), dim3(nb), dim3(256), 0, st, R);
+    else
+        hipLaunchKernelGGL((k_run<PlaneSpectrum<double>>), dim3(nb), dim3(256), 0, st, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_spec_reduce(const RunDev &R, double *out, hipStream_t st)
+{
+    if (R.nfreq <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_spec_reduce, dim3((unsigned)R.nfreq), dim3(256), 0, st, R, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_inject(const RunDev &R, hipStream_t st)
+{
+    if (!R.seed_on)
+        return hipSuccess;
+    const unsigned nb = (unsigned)((2 * (int64_t)(R.nx - 2) * (R.ny - 2) + 255) / 256);
+    if (R.precision == 32)
+        hipLaunchKernelGGL((k_run<SeedInject<float>>), dim3(nb), dim3(256), 0, st, R);
+    else
+        hipLaunchKernelGGL((k_run<SeedInject<double>>), dim3(nb), dim3(256), 0, st, R);
     return hipGetLastError();
 }
 

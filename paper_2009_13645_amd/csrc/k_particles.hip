@@ -1,9 +1,9 @@
-// k_particles.hip -- per-block particle step (used where a sort tile is too
-// large for the tile-owned kernel of k_tiles.hip), box reductions and the
-// bunching diagnostic.  Particles are processed in the order of the last
-// sort; each block sums its deposits in LDS over the node box its particles
-// touch and adds that box to HBM once, or adds directly when the box does
-// not fit.
+// k_particles.hip -- the particle step (gather, external field, Boris
+// push, deposit), box reductions, the bunching diagnostic and the Halton
+// bunch generator.  Particles are processed in the order of the last sort;
+// each block sums its deposits in LDS over the node box its particles touch
+// and adds that box to HBM once, or adds directly when the box does not
+// fit.
 #include "particle_dev.hpp"
 
 namespace mithra {
@@ -17,7 +17,9 @@ constexpr int kLdsNodes = 1536;  // node box capacity of the LDS stage (4 arrays
 // last bookkeeping kernel flips pbuf), so the sort never moves the state.
 // The block's deposits are summed in LDS over its node box when the box
 // fits, then added to HBM once per touched node; otherwise directly.
-template <typename T, bool COMP, int MODE>
+// EXT selects the general external field (undulator arrays, optical
+// undulators); the single static module keeps its own path.
+template <typename T, bool COMP, int MODE, bool EXT = false>
 struct PushDeposit {
     static constexpr int kThreads = kDepThreads;
     static constexpr int kWaves = 3;  // the LDS box allows 3 blocks per CU
@@ -95,7 +97,7 @@ struct PushDeposit {
                 const double t_half = ((double)s + 0.5) * R.dt;
                 for (int sub = 0; sub < R.n_sub; ++sub) {
                     double Ee[3], Be[3];
-                    undulator_field(R, r[0], r[1], r[2], t_half + (double)sub * R.dtb, Ee, Be);
+                    external_field<EXT>(R, r[0], r[1], r[2], t_half + (double)sub * R.dtb, Ee, Be);
                     for (int a = 0; a < 3; ++a) {
                         Ee[a] += Eg[a];
                         Be[a] += Bg[a];
@@ -303,6 +305,140 @@ __global__ __launch_bounds__(256) void k_bunching(RunDev R, double *part)
 }
 
 // ---------------------------------------------------------------------------
+// Halton bunch generation.  Element j of sequence i: 1 minus the radical
+// inverse of j in the base of the i-th prime.  One thread per particle;
+// the slices of the shot noise are counted in a second pass (integer
+// atomics: the counts do not depend on the order) and displaced in a
+// third.
+// ---------------------------------------------------------------------------
+
+__device__ inline double halton_dev(int i, uint64_t j)
+{
+    const uint64_t b = (uint64_t)(i == 0 ? 2 : i == 1 ? 3 : i == 2 ? 5 : i == 3 ? 7 : i == 4 ? 11 : i == 5 ? 13
+                                  : i == 6 ? 17 : i == 7 ? 19 : i == 8 ? 23 : 29);
+    double scale = 1.0, x = 0.0;
+    for (uint64_t k = j; k > 0; k /= b) {
+        scale /= (double)b;
+        x += (double)(k % b) * scale;
+    }
+    return 1.0 - x;
+}
+
+__device__ inline void halton_normal_dev(int ia, int ib, uint64_t j, double &c, double &s)
+{
+    const double r = sqrt(-2.0 * log(halton_dev(ia, j)));
+    const double a = 2.0 * kPi * halton_dev(ib, j);
+    c = r * cos(a);
+    s = r * sin(a);
+}
+
+// pass 0: quiet-start coordinates, momenta and the bunching displacement
+__global__ __launch_bounds__(256) void k_gen_bunch(RunDev R, GenParams P)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P.n)
+        return;
+    const uint64_t j = (uint64_t)q;
+    double x, y, zl, c, sn;
+    if (P.trans_profile == 0) {
+        x = P.sx * (halton_dev(0, j) - 0.5);
+        y = P.sy * (halton_dev(1, j) - 0.5);
+    } else {
+        halton_normal_dev(0, 1, j, c, sn);
+        x = P.sx * c;
+        y = P.sy * sn;
+    }
+    if (P.long_profile == 1) {
+        halton_normal_dev(2, 3, j, c, sn);
+        zl = P.L * c;
+    } else if (q < P.n_flat) {
+        zl = P.L * (halton_dev(2, j) - 0.5);
+    } else {
+        halton_normal_dev(2, 3, j, c, sn);
+        zl = (q & 1) ? 0.5 * P.L + P.sig_t * fabs(c) : -0.5 * P.L - P.sig_t * fabs(c);
+    }
+    halton_normal_dev(4, 5, j, c, sn);
+    const double ge = P.gamma * (1.0 + P.sig_g * c);
+    halton_normal_dev(6, 7, j, c, sn);
+    const double ux = P.sig_u * c, uy = P.sig_u * sn;
+    const double uzl = sqrt(ge * ge - 1.0 - ux * ux - uy * uy);
+    double z = P.cz + zl * P.lz;
+    if (P.bf != 0.0)
+        z = z - (2.0 * P.bf / P.k) * sin(P.k * z + P.bphase);
+    R.pr[0][0][q] = P.cx + x;
+    R.pr[0][1][q] = P.cy + y;
+    R.pr[0][2][q] = z;
+    R.pr[0][3][q] = ux;
+    R.pr[0][4][q] = uy;
+    R.pr[0][5][q] = R.gamma0 * (uzl - R.beta0 * ge);
+    R.pid[0][q] = (int32_t)q;
+}
+
+// smallest and largest z of the generated bunch (one block, fixed order)
+__global__ __launch_bounds__(1024) void k_gen_zrange(RunDev R, int64_t n, double *out)
+{
+    __shared__ double lo[1024], hi[1024];
+    double a = 1e300, b = -1e300;
+    for (int64_t q = threadIdx.x; q < n; q += 1024) {
+        const double z = R.pr[0][2][q];
+        a = fmin(a, z);
+        b = fmax(b, z);
+    }
+    lo[threadIdx.x] = a;
+    hi[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + w]);
+            hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = lo[0];
+        out[1] = hi[0];
+    }
+}
+
+// pass 1: particles per shot-noise slice
+__global__ __launch_bounds__(256) void k_gen_count(RunDev R, GenParams P)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P.n)
+        return;
+    const int64_t sl = (int64_t)floor((R.pr[0][2][q] - P.zmin) / P.slice);
+    atomicAdd(&P.counts[sl], 1);
+}
+
+// pass 2: the shot-noise displacement of each particle from its slice
+__global__ __launch_bounds__(256) void k_gen_noise(RunDev R, GenParams P)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= P.n)
+        return;
+    const double z = R.pr[0][2][q];
+    const int64_t sl = (int64_t)floor((z - P.zmin) / P.slice);
+    const double ne = fmax((double)P.counts[sl] * P.n_e / (double)P.n, 1.0);
+    const double bs = sqrt(-2.0 * log(halton_dev(8, (uint64_t)sl + 1))) / sqrt(ne);
+    const double ph = 2.0 * kPi * halton_dev(9, (uint64_t)sl + 1);
+    R.pr[0][2][q] = z + (-(2.0 * bs / P.k) * sin(P.k * z + ph));
+}
+
+hipError_t launch_gen_bunch(const RunDev &R, const GenParams &P, int pass, double *zrange, hipStream_t st)
+{
+    const unsigned nb = (unsigned)((P.n + 255) / 256);
+    if (pass == 0) {
+        hipLaunchKernelGGL(k_gen_bunch, dim3(nb), dim3(256), 0, st, R, P);
+        hipLaunchKernelGGL(k_gen_zrange, dim3(1), dim3(1024), 0, st, R, P.n, zrange);
+    } else if (pass == 1) {
+        hipLaunchKernelGGL(k_gen_count, dim3(nb), dim3(256), 0, st, R, P);
+    } else {
+        hipLaunchKernelGGL(k_gen_noise, dim3(nb), dim3(256), 0, st, R, P);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 
 template <int MODE>
 static hipError_t launch_dep(const RunDev &R, hipStream_t st)
@@ -310,6 +446,15 @@ static hipError_t launch_dep(const RunDev &R, hipStream_t st)
     if (R.np <= 0)
         return hipSuccess;
     const unsigned blocks = (unsigned)((R.np + kDepThreads - 1) / kDepThreads);
+    if (MODE == 0 && R.und_ext) {
+        if (R.precision == 64)
+            hipLaunchKernelGGL((k_run<PushDeposit<double, false, MODE, true>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
+        else if (R.compensated)
+            hipLaunchKernelGGL((k_run<PushDeposit<float, true, MODE, true>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
+        else
+            hipLaunchKernelGGL((k_run<PushDeposit<float, false, MODE, true>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
+        return hipGetLastError();
+    }
     if (R.precision == 64)
         hipLaunchKernelGGL((k_run<PushDeposit<double, false, MODE>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
     else if (R.compensated)

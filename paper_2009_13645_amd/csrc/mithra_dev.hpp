@@ -69,7 +69,21 @@ struct RunDev {
     // frame and undulator
     double gamma0, beta0;
     double ku, B0, Lu, z_ent, theta;
-    int und_type;
+    int und_type;     // 0 planar, 1 helical, 2 optical plane wave, 3 optical Gaussian beam
+    int und_ext;      // 1: the external field needs the general path (arrays or optical)
+    double Kund, lam_u; // undulator parameter (optical: a0) and period (optical: half the wavelength)
+    int n_modules;    // static array: modules, K_m = K + m dK, gaps between them
+    double gap, dK;
+    int opt_signal;   // optical pulse: signal type, length, offset (c t, lab), CEP (rad)
+    double opt_ctau, opt_ct0, opt_cep, opt_w0[2], opt_zf;
+    // TF/SF seed (planes k = 1 and 2)
+    int seed_on, seed_type, seed_signal;
+    double seed_a0, seed_lambda, seed_ctau, seed_ct0, seed_cep, seed_pol, seed_w0, seed_zf;
+    // spectral power: nfreq frequencies nu = nu_min + (nu_max - nu_min) f / (nfreq - 1) times omega_r
+    int nfreq;
+    double nu_min, nu_max, omega_r;
+    double *spec;     // [nfreq][8][nx*ny] running transforms (re/im of Ex' Ey' Bx' By')
+    int solver;       // 0 NSFD, 1 FD
     // NSFD interior update: next = a1 cur + a2 (bar_x+ + bar_x-) + a4 (bar_y+ + bar_y-)
     //                              + a6 (cur_k+ + cur_k-) - prev + S
     double A, a1, a2, a4, a6;
@@ -122,6 +136,18 @@ struct RunDev {
     int record_power;
     Ctl *ctl;
 };
+
+// Parameters of the Halton bunch generator (k_particles.hip), filled on the host.
+struct GenParams {
+    int long_profile, trans_profile, shot_noise;
+    int64_t n, n_flat;
+    double cx, cy, cz, sx, sy, L;
+    double gamma, sig_g, sig_u, bf, bphase, n_e;
+    double lz, k, sig_t;
+    double zmin, slice;  // shot noise: first z and slice length (third pass)
+    int32_t *counts;     // slice counts (second and third passes)
+};
+
 
 // Device address of a Ctl member, formed on the host without dereferencing.
 #define CTL_ADDR(ctl, member) ((int32_t *)((char *)(ctl) + offsetof(::mithra::Ctl, member)))

@@ -83,6 +83,174 @@ __device__ inline void undulator_field(const RunDev &R, double x, double y, doub
     B[2] = Bl[2];
 }
 
+// ---- general external field: undulator arrays and optical undulators ----
+
+// window of the gap fringes of an undulator array: 1 at the module edge,
+// ~6e-5 at the far end of the gap
+__device__ inline double gap_window(double dz, double g)
+{
+    const double t = kPi * dz / g;
+    return 0.35875 + 0.48829 * cos(t) + 0.14128 * cos(2.0 * t) + 0.01168 * cos(3.0 * t);
+}
+
+// longitudinal profile of the planar pattern of a module array at lab z'
+// (first entrance at 0), scaled by the module's B0 (K_m = K + m dK): body,
+// fringe before the first module and after the last, windowed fringes of
+// the two modules around a gap
+__device__ inline void array_profile(const RunDev &R, double zl, double &gB, double &hB)
+{
+    const int M = R.n_modules;
+    const double pitch = R.Lu + R.gap;
+    int m = (int)floor(zl / pitch);
+    m = m < 0 ? 0 : (m > M - 1 ? M - 1 : m);
+    const double ent = m * pitch, ext = ent + R.Lu;
+    const double b0 = 2.0 * kPi * kMe * kC * (R.Kund + m * R.dK) / (kQe * R.lam_u);
+    if (zl >= ent && zl <= ext) {
+        gB = b0 * sin(R.ku * (zl - ent));
+        hB = b0 * cos(R.ku * (zl - ent));
+        return;
+    }
+    if (zl < ent) {
+        const double a = R.ku * (zl - ent), e = exp(-0.5 * a * a);
+        gB = b0 * (a * e);
+        hB = b0 * e;
+        return;
+    }
+    const double a1 = R.ku * (zl - ext), e1 = exp(-0.5 * a1 * a1);
+    if (m == M - 1) {
+        gB = b0 * (a1 * e1);
+        hB = b0 * e1;
+        return;
+    }
+    const double ent2 = (m + 1) * pitch;
+    const double b1 = 2.0 * kPi * kMe * kC * (R.Kund + (m + 1) * R.dK) / (kQe * R.lam_u);
+    const double a2 = R.ku * (zl - ent2), e2 = exp(-0.5 * a2 * a2);
+    const double f1 = gap_window(zl - ext, R.gap), f2 = gap_window(ent2 - zl, R.gap);
+    gB = b0 * (a1 * e1) * f1 + b1 * (a2 * e2) * f2;
+    hB = b0 * e1 * f1 + b1 * e2 * f2;
+}
+
+__device__ inline void array_planar(const RunDev &R, double x, double y, double zl, double th, double Bl[3])
+{
+    double gB, hB, sth, cth;
+    array_profile(R, zl, gB, hB);
+    sincos(th, &sth, &cth);
+    const double eta = x * sth + y * cth;
+    const double Bperp = gB * cosh(R.ku * eta);
+    Bl[0] = Bperp * sth;
+    Bl[1] = Bperp * cth;
+    Bl[2] = hB * sinh(R.ku * eta);
+}
+
+// optical pulse signature with unit amplitude (modulated Neumann scaled by
+// the duration to be dimensionless, modulated Gaussian, modulated sech,
+// sinusoidal pulse with a Gaussian rise)
+__device__ inline double signal_value(int type, double tau, double f, double tp, double t0, double ph)
+{
+    const double d = tau - t0;
+    const double car = cos(2.0 * kPi * f * d + ph);
+    const double ln2 = 0.69314718055994530942;
+    switch (type) {
+    case 0:
+        return -4.0 * ln2 * car * (d / tp) * exp(-2.0 * ln2 * d * d / (tp * tp));
+    case 1:
+        return car * exp(-2.0 * ln2 * d * d / (tp * tp));
+    case 2:
+        return car / cosh(d / tp);
+    default:
+        return d <= 0.0 ? car * exp(-2.0 * ln2 * d * d / (tp * tp)) : car;
+    }
+}
+
+// lab fields of the optical undulator (strength a0 = K, wavelength
+// 2 lambda_u, propagating along -z; B along (sin th, cos th), E along
+// (-cos th, sin th)); plane wave or Gaussian beam
+__device__ inline void optical_lab(const RunDev &R, double x, double y, double zl, double tl, double El[3],
+                                   double Bl[3])
+{
+    const double lam = 2.0 * R.lam_u;
+    const double om = 2.0 * kPi * kC / lam;
+    const double E0 = R.Kund * kMe * kC * om / kQe;
+    const double f = kC / lam, tp = R.opt_ctau / kC, t0 = R.opt_ct0 / kC;
+    double sth, cth;
+    sincos(R.theta, &sth, &cth);
+    const double p[2] = {-cth, sth}, q[2] = {sth, cth};
+    if (R.und_type == 2) {
+        const double sv = signal_value(R.opt_signal, tl + zl / kC, f, tp, t0, R.opt_cep);
+        for (int a = 0; a < 2; ++a) {
+            El[a] = E0 * sv * p[a];
+            Bl[a] = (E0 / kC) * sv * q[a];
+        }
+        El[2] = 0.0;
+        Bl[2] = 0.0;
+        return;
+    }
+    const double k0 = 2.0 * kPi / lam;
+    const double l = R.opt_zf - zl;
+    const double rp = x * p[0] + y * p[1], rq = x * q[0] + y * q[1];
+    const double w0p = R.opt_w0[0], w0q = R.opt_w0[1];
+    const double zRp = kPi * w0p * w0p / lam, zRq = kPi * w0q * w0q / lam;
+    const double wp = w0p * sqrt(1.0 + (l / zRp) * (l / zRp)), wq = w0q * sqrt(1.0 + (l / zRq) * (l / zRq));
+    const double iRp = l / (l * l + zRp * zRp), iRq = l / (l * l + zRq * zRq);
+    const double amp = sqrt((w0p * w0q) / (wp * wq)) * exp(-rq * rq / (wq * wq) - rp * rp / (wp * wp));
+    const double curv = -0.5 * k0 * rp * rp * iRp - 0.5 * k0 * rq * rq * iRq;
+    const double Gp = atan(l / zRp), Gq = atan(l / zRq);
+    const double tau = tl - l / kC;
+    const double Epar = E0 * amp * signal_value(R.opt_signal, tau, f, tp, t0, R.opt_cep + curv - 0.5 * kPi + 0.5 * (Gp + Gq));
+    const double Elon = E0 * (rp * w0p / (zRp * wp)) * amp *
+                        signal_value(R.opt_signal, tau, f, tp, t0, R.opt_cep + curv + 0.5 * (3.0 * Gp + Gq));
+    const double Blon = (E0 / kC) * (rq * w0q / (zRq * wq)) * amp *
+                        signal_value(R.opt_signal, tau, f, tp, t0, R.opt_cep + curv + 0.5 * (Gp + 3.0 * Gq));
+    for (int a = 0; a < 2; ++a) {
+        El[a] = Epar * p[a];
+        Bl[a] = (Epar / kC) * q[a];
+    }
+    El[2] = -Elon;
+    Bl[2] = -Blon;
+}
+
+// the external field in the general case, boosted with E' != 0:
+// E = g0 (E' + c beta0 z x B') - (g0 - 1) E'_z z, B = g0 (B' - beta0 z x E' / c) - (g0 - 1) B'_z z
+__device__ inline void undulator_field_ext(const RunDev &R, double x, double y, double z, double t, double E[3],
+                                           double B[3])
+{
+    const double g0 = R.gamma0, b0 = R.beta0;
+    const double zl = g0 * (z - R.z_ent + b0 * kC * t);
+    double El[3] = {0.0, 0.0, 0.0}, Bl[3] = {0.0, 0.0, 0.0};
+    if (R.und_type >= 2) {
+        const double tl = g0 * (t + b0 * (z - R.z_ent) / kC);
+        optical_lab(R, x, y, zl, tl, El, Bl);
+    } else if (R.und_type == 1) {
+        double tmp[3];
+        array_planar(R, x, y, zl, 0.0, tmp);
+        for (int a = 0; a < 3; ++a)
+            Bl[a] += tmp[a];
+        array_planar(R, x, y, zl + 0.25 * R.lam_u, 0.5 * kPi, tmp);
+        for (int a = 0; a < 3; ++a)
+            Bl[a] += tmp[a];
+    } else {
+        array_planar(R, x, y, zl, R.theta, Bl);
+    }
+    E[0] = g0 * (El[0] + kC * b0 * (-Bl[1]));
+    E[1] = g0 * (El[1] + kC * b0 * (Bl[0]));
+    E[2] = g0 * El[2] - (g0 - 1.0) * El[2];
+    B[0] = g0 * (Bl[0] - b0 * (-El[1]) / kC);
+    B[1] = g0 * (Bl[1] - b0 * (El[0]) / kC);
+    B[2] = g0 * Bl[2] - (g0 - 1.0) * Bl[2];
+}
+
+// the external field of a run: the single static module on its own path
+// (EXT = false: the benchmark's push), arrays and optical undulators on the
+// general one
+template <bool EXT>
+__device__ inline void external_field(const RunDev &R, double x, double y, double z, double t, double E[3], double B[3])
+{
+    if constexpr (EXT)
+        undulator_field_ext(R, x, y, z, t, E, B);
+    else
+        undulator_field(R, x, y, z, t, E, B);
+}
+
 __device__ inline void boris(double u[3], const double E[3], const double B[3], double dtb)
 {
     const double ek = kQe * dtb / (2.0 * kMe * kC);

@@ -38,7 +38,45 @@ class GridDesc(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
                 ("gamma", C.c_double), ("K", C.c_double), ("lambda_u", C.c_double),
-                ("pol_angle_deg", C.c_double), ("z_entrance", C.c_double)]
+                ("pol_angle_deg", C.c_double), ("z_entrance", C.c_double),
+                ("n_freq", C.c_int32), ("pad_", C.c_int32), ("nu_min", C.c_double), ("nu_max", C.c_double)]
+
+
+class UndulatorDesc(C.Structure):
+    """ctypes mirror of `mithra_undulator_desc`."""
+    _fields_ = [("n_modules", C.c_int32), ("signal", C.c_int32), ("gap", C.c_double), ("dK", C.c_double),
+                ("ctau", C.c_double), ("ct0", C.c_double), ("cep_deg", C.c_double),
+                ("w0_par", C.c_double), ("w0_perp", C.c_double), ("z_focus", C.c_double)]
+
+
+class SeedDesc(C.Structure):
+    """ctypes mirror of `mithra_seed_desc`."""
+    _fields_ = [("type", C.c_int32), ("signal", C.c_int32), ("a0", C.c_double), ("wavelength", C.c_double),
+                ("ctau", C.c_double), ("ct0", C.c_double), ("cep_deg", C.c_double), ("pol_deg", C.c_double),
+                ("w0", C.c_double), ("z_focus", C.c_double)]
+
+
+class BunchDesc(C.Structure):
+    """ctypes mirror of `mithra_bunch_desc`."""
+    _fields_ = [("long_profile", C.c_int32), ("trans_profile", C.c_int32), ("shot_noise", C.c_int32),
+                ("tapers", C.c_int32), ("center", C.c_double * 3), ("size", C.c_double * 3),
+                ("gamma", C.c_double), ("sigma_gamma_rel", C.c_double), ("sigma_u_perp", C.c_double),
+                ("bunching", C.c_double), ("bunching_phase", C.c_double), ("n_electrons", C.c_double)]
+
+
+def _fill(struct, d: dict):
+    s = struct()
+    for name, typ in struct._fields_:
+        if name not in d:
+            continue
+        v = d[name]
+        if hasattr(typ, "_length_"):
+            arr = getattr(s, name)
+            for i, x in enumerate(v):
+                arr[i] = float(x)
+        else:
+            setattr(s, name, v)
+    return s
 
 
 _lib = None
@@ -86,6 +124,16 @@ def lib():
         L.mithra_time_sweep.restype = C.c_int
         L.mithra_step_timed.argtypes = [H, C.c_int64, dp, dp]
         L.mithra_step_timed.restype = C.c_int
+        L.mithra_spectral_power.argtypes = [H, dp, C.c_int64]
+        L.mithra_spectral_power.restype = C.c_int64
+        L.mithra_set_undulator.argtypes = [H, C.POINTER(UndulatorDesc)]
+        L.mithra_set_undulator.restype = C.c_int
+        L.mithra_set_seed.argtypes = [H, C.POINTER(SeedDesc)]
+        L.mithra_set_seed.restype = C.c_int
+        L.mithra_adapt_mesh.argtypes = [C.POINTER(GridDesc), C.c_double, C.POINTER(C.c_int32)]
+        L.mithra_adapt_mesh.restype = C.c_int
+        L.mithra_generate_bunch.argtypes = [H, C.POINTER(BunchDesc), C.c_int64, C.c_double]
+        L.mithra_generate_bunch.restype = C.c_int
         L.mithra_step_profile.argtypes = [H, C.c_int64, dp]
         L.mithra_step_profile.restype = C.c_int
         L.mithra_autotune_sweep.argtypes = [H, C.c_int, C.POINTER(C.c_int)]
@@ -121,7 +169,23 @@ def make_desc(d: dict, max_particles: int, record_power: int = 1) -> GridDesc:
     for k in ("dx", "dy", "dz", "x0", "y0", "z0", "gamma", "K", "lambda_u", "pol_angle_deg",
               "z_entrance"):
         setattr(g, k, float(d[k]))
+    g.n_freq = int(d.get("n_freq", 0))
+    g.nu_min = float(d.get("nu_min", 1.0))
+    g.nu_max = float(d.get("nu_max", 1.0))
     return g
+
+
+def adapt_mesh(d: dict, bunch_time_step: float = 0.0) -> Tuple[dict, int]:
+    """The MESH auto-adjustment: returns the adapted descriptor and the
+    mask of what changed (1: dx and dy, 2: n_sub)."""
+    g = make_desc(d, 1)
+    changed = C.c_int32(0)
+    rc = lib().mithra_adapt_mesh(C.byref(g), float(bunch_time_step), C.byref(changed))
+    if rc != 0:
+        raise MithraError(rc, "mesh adjustment refused")
+    out = dict(d)
+    out.update(dx=g.dx, dy=g.dy, n_sub=g.n_sub)
+    return out, int(changed.value)
 
 
 def footprint_bytes(d: dict, n_particles: int) -> int:
@@ -227,6 +291,33 @@ class Engine:
         out = C.c_double()
         self._check(self._L.mithra_bunching(self._h, C.byref(out)))
         return out.value
+
+    def spectral_power(self) -> np.ndarray:
+        """dW/domega at the descriptor's normalised frequencies (J s)."""
+        n = int(self.desc.get("n_freq", 0))
+        out = np.zeros(max(n, 1))
+        m = self._L.mithra_spectral_power(self._h, _dp(out), n)
+        if m < 0:
+            self._check(int(m))
+        return out[:m]
+
+    def set_undulator(self, params: dict):
+        """Undulator arrays / tapering / optical pulse (mithra_undulator_desc keys)."""
+        p = dict(params)
+        p.setdefault("n_modules", 1)
+        s = _fill(UndulatorDesc, p)
+        self._check(self._L.mithra_set_undulator(self._h, C.byref(s)))
+
+    def set_seed(self, params: dict):
+        """TF/SF seed (mithra_seed_desc keys)."""
+        s = _fill(SeedDesc, params)
+        self._check(self._L.mithra_set_seed(self._h, C.byref(s)))
+
+    def generate_bunch(self, params: dict, n: int, q_macro: float):
+        """Halton bunch generated and loaded on the device (mithra_bunch_desc keys)."""
+        s = _fill(BunchDesc, params)
+        self._check(self._L.mithra_generate_bunch(self._h, C.byref(s), int(n), float(q_macro)))
+        self.np = int(n)
 
     def constants(self) -> dict:
         out = np.zeros(8)

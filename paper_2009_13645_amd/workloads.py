@@ -386,3 +386,60 @@ def config5_requests(n_req: int = 1000, rate_hz: float = 20.0, seed: int = 5,
         w.name = f"cfg5-req{r:04d}-{w.nx}x{w.ny}x{w.nz}"
         out.append((float(t[r]), w))
     return out
+
+
+# ---------------------------------------------------------------------------
+# The manual's Example 1 (ch. 5 "Example 1: Infrared FEL", table example1,
+# and its job file): the run description and the bunch description.
+# ---------------------------------------------------------------------------
+
+EX1_GAMMA = 100.41            # 51.4 MeV
+EX1_K = 1.417                 # undulator-parameter of the job file
+EX1_LAMBDA_U = 0.03           # 3 cm
+EX1_CHARGE_C = 29.5e-12       # 29.5 pC (1.846e8 electrons)
+EX1_PARTICLES = 131072
+EX1_BUNCH_LAB = (260e-6, 260e-6, 100.5e-6)   # uniform 260 x 260 x 100.5 um (lab)
+EX1_MESH_LAB = (50e-6, 50e-6, 0.1e-6)        # mesh-resolution (lab)
+EX1_NODES = (64, 64, 2800)                   # mesh-lengths / mesh-resolution
+EX1_PLANE_LAB = 110e-6                       # power plane ahead of the bunch centre (lab)
+EX1_BUNCH_STEP_LAB = 1.6e-12                 # bunch-time-step (lab)
+
+
+def example1(solver: int = 0, field_precision: int = 64, plane_lab: float = EX1_PLANE_LAB) -> Tuple[dict, dict, int, float]:
+    """Example 1 in the boosted frame: the run descriptor, the device bunch
+    description (Halton quiet start, flat-top with tapers, uniform
+    transverse box, bunching factor 0.01, no shot noise), the particle
+    count and the macro-particle charge.
+
+    Lab lengths along z become boosted lengths times gamma0 (a mesh at rest
+    in the bunch frame); the transverse ones are unchanged.  The bunch centre
+    sits at the middle of the mesh, the undulator entrance two lab periods
+    ahead of the bunch head (distance-to-bunch-head default), the power
+    plane plane_lab (lab) ahead of the bunch centre.  Space charge off, Mur
+    second order, NSFD (or FD), as in the job file.  The bunch step of the
+    job file (1.6 ps lab) is turned into the sub-step count by the mesh
+    auto-adjustment (mithra_adapt_mesh).
+    """
+    g0 = EX1_GAMMA / math.sqrt(1.0 + 0.5 * EX1_K ** 2)
+    b0 = math.sqrt(1.0 - 1.0 / (g0 * g0))
+    nx, ny, nz = EX1_NODES
+    dx, dy = EX1_MESH_LAB[0], EX1_MESH_LAB[1]
+    dz = g0 * EX1_MESH_LAB[2]
+    beta = math.sqrt(1.0 - 1.0 / (EX1_GAMMA ** 2))
+    lz = 1.0 / (g0 * (1.0 - beta * b0))
+    zc = 0.5 * (nz - 1) * dz
+    kr = 2.0 * math.pi * g0 * b0 / EX1_LAMBDA_U
+    lam_lab = (2.0 * math.pi / kr) / (g0 * (1.0 + b0))
+    half = 0.5 * EX1_BUNCH_LAB[2] * lz + 3.0 * lam_lab * lz  # flat top plus the taper tails
+    z_head = zc + half
+    desc = dict(nx=nx, ny=ny, nz=nz, dx=dx, dy=dy, dz=dz,
+                x0=-0.5 * (nx - 1) * dx, y0=-0.5 * (ny - 1) * dy, z0=0.0,
+                truncation_order=2, space_charge=0, solver=solver, n_sub=1,
+                field_precision=field_precision, compensated=0, gamma=EX1_GAMMA, und_type=PLANAR,
+                K=EX1_K, lambda_u=EX1_LAMBDA_U, n_periods=300, pol_angle_deg=0.0,
+                z_entrance=z_head + 2.0 * EX1_LAMBDA_U / g0, tile=(4, 4, 4),
+                k_plane=int(round((zc + g0 * plane_lab) / dz)), n_freq=1, nu_min=1.0, nu_max=1.0)
+    bunch = dict(long_profile=0, trans_profile=0, shot_noise=0, tapers=1, center=(0.0, 0.0, zc),
+                 size=EX1_BUNCH_LAB, gamma=EX1_GAMMA, sigma_gamma_rel=1e-4, sigma_u_perp=0.0,
+                 bunching=0.01, bunching_phase=0.0, n_electrons=EX1_CHARGE_C / Q_E)
+    return desc, bunch, EX1_PARTICLES, -EX1_CHARGE_C / EX1_PARTICLES

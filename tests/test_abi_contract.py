@@ -48,8 +48,9 @@ def test_footprint_is_exact_monotone_and_zero_for_invalid():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(nx=5), dict(truncation_order=3), dict(space_charge=2), dict(solver=1), dict(n_sub=0),
-    dict(field_precision=16), dict(compensated=1, field_precision=64), dict(und_type=2),
+    dict(nx=5), dict(truncation_order=3), dict(space_charge=2), dict(solver=2), dict(n_sub=0),
+    dict(field_precision=16), dict(compensated=1, field_precision=64), dict(und_type=4), dict(n_freq=65),
+    dict(n_freq=2, nu_min=float("nan")),
     dict(n_periods=0), dict(k_plane=0), dict(k_plane=63), dict(tile=(0, 8, 8)),
     dict(tile=(8, 65, 8)), dict(dx=0.0), dict(gamma=1.0), dict(K=0.0), dict(lambda_u=-1.0),
     dict(dz=1.0), dict(z_entrance=float("nan")), dict(nx=(1 << 20) + 1),
@@ -88,3 +89,27 @@ def test_batch_workspace_and_argument_checks_without_device():
     assert L.mithra_batch_run(None, None) == -1
     assert L.mithra_batch_autotune_sweep(None, 3, None) == -1
     assert L.mithra_batch_destroy(None) == -1
+
+
+def test_adapt_mesh_meets_the_nsfd_condition_and_divides_the_field_step():
+    """MESH auto-adjustment (ch. 4 MESH): dx and dy scaled by one factor so
+    that (dz/dx)^2 + (dz/dy)^2 = 0.98 when the NSFD condition fails, and
+    n_sub = round(dt / bunch step) (at least 1); FD leaves the mesh."""
+    d = _desc()
+    d.update(dx=1.1 * d["dz"], dy=1.3 * d["dz"])
+    assert E.footprint_bytes(d, 16) == 0  # rejected as given
+    a, changed = E.adapt_mesh(d, bunch_time_step=0.0)
+    q = (a["dz"] / a["dx"]) ** 2 + (a["dz"] / a["dy"]) ** 2
+    assert changed == 1 and q == pytest.approx(0.98, rel=1e-14)
+    assert a["dx"] / a["dy"] == pytest.approx(1.1 / 1.3, rel=1e-14)
+    assert E.footprint_bytes(a, 16) > 0
+    dt = a["dz"] / 299792458.0
+    b, changed = E.adapt_mesh(a, bunch_time_step=dt / 3.3)
+    assert changed == 2 and b["n_sub"] == 3 and b["dx"] == a["dx"]
+    c, changed = E.adapt_mesh(b, bunch_time_step=10 * dt)
+    assert c["n_sub"] == 1
+    # FD: no NSFD condition; its field step is 0.99 of the stable step
+    f = dict(d, solver=1)
+    g, changed = E.adapt_mesh(f, bunch_time_step=0.0)
+    assert changed == 0 and g["dx"] == f["dx"]
+    assert E.footprint_bytes(f, 16) > 0
