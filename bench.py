@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--latency-runs", type=int, default=12)
     ap.add_argument("--workload", choices=["fel-amplifier", "batched-scan", "served-stream", "example1"],
                     default="fel-amplifier")
-    ap.add_argument("--ex1-steps", type=int, default=12000, help="example1: field steps per run")
+    ap.add_argument("--ex1-steps", type=int, default=16000, help="example1: field steps per run")
     ap.add_argument("--ex1-parity-steps", type=int, default=4, help="example1: oracle prefix steps")
     ap.add_argument("--requests", type=int, default=1000, help="served stream: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="served stream: Poisson arrival rate (1/s)")
@@ -304,12 +304,14 @@ def bench_served_stream(args) -> dict:
     }
 
 
-def _gain_fit(power, dt, g0, b0, steps_per_period):
+def _gain_fit(power, dt, g0, b0, steps_per_period, window_m=0.6):
     """Gain length and saturation power from a power history: the power
     averaged over one radiation period, the saturation power its maximum,
-    the gain length the inverse slope of ln P against the undulator length
-    z = gamma0 beta0 c t over the stretch where P rises from 1e-3 to 3e-2 of
-    its maximum (the exponential regime, well before saturation)."""
+    the gain length the inverse of the steepest slope of ln P against the
+    undulator length z = gamma0 beta0 c t over any stretch window_m long
+    before saturation (the exponential regime; a least-squares line per
+    window).  The stretch where P rises from 1e-3 to 3e-2 of its maximum is
+    fitted too, for comparison."""
     import numpy as np
     p = np.asarray(power, dtype=float)
     w = max(int(round(steps_per_period)), 1)
@@ -325,12 +327,27 @@ def _gain_fit(power, dt, g0, b0, steps_per_period):
     i0 = int(below[-1]) + 1 if len(below) else 0
     above = np.nonzero(ps[i0:i_sat] > hi)[0]
     i1 = i0 + int(above[0]) if len(above) else i_sat
-    if i1 - i0 < 4 * w:
-        return {"p_sat_W": p_sat, "z_sat_m": float(z[i_sat]), "gain_length_m": None}
-    sl, ic = np.polyfit(z[i0:i1], np.log(ps[i0:i1]), 1)
-    resid = np.log(ps[i0:i1]) - (sl * z[i0:i1] + ic)
-    return {"p_sat_W": p_sat, "z_sat_m": float(z[i_sat]), "gain_length_m": float(1.0 / sl),
-            "fit_z_m": [float(z[i0]), float(z[i1 - 1])], "fit_rms_ln": float(np.std(resid)),
+    lp = np.log(np.maximum(ps, 1e-300))
+    dz = z[1] - z[0]
+    m = max(int(round(window_m / dz)), 8)
+    best = (0.0, 0)
+    for a in range(0, max(i_sat - m, 0), max(m // 8, 1)):
+        sl_, _ = np.polyfit(z[a:a + m], lp[a:a + m], 1)
+        if sl_ > best[0]:
+            best = (sl_, a)
+    steep = None
+    if best[0] > 0:
+        a = best[1]
+        steep = {"gain_length_m": float(1.0 / best[0]), "z_m": [float(z[a]), float(z[a + m - 1])],
+                 "P_W": [float(ps[a]), float(ps[a + m - 1])]}
+    band = None
+    if i1 - i0 >= 4 * w:
+        sl, ic = np.polyfit(z[i0:i1], lp[i0:i1], 1)
+        band = {"gain_length_m": float(1.0 / sl), "z_m": [float(z[i0]), float(z[i1 - 1])],
+                "rms_ln": float(np.std(lp[i0:i1] - (sl * z[i0:i1] + ic)))}
+    return {"p_sat_W": p_sat, "z_sat_m": float(z[i_sat]),
+            "gain_length_m": steep["gain_length_m"] if steep else None,
+            "steepest_window": steep, "band_1e-3_3e-2": band,
             "curve_z_m": [float(v) for v in z[::max(len(z) // 200, 1)]],
             "curve_P_W": [float(v) for v in ps[::max(len(z) // 200, 1)]]}
 
@@ -356,6 +373,13 @@ def bench_example1(args) -> dict:
         e = Engine(d, max_particles=n)
         e.generate_bunch(b, n, q)
         c = e.constants()
+
+        def lab_gamma():
+            uu = e.read_particles()[1]
+            gb = np.sqrt(1.0 + np.sum(uu * uu, axis=1))
+            return float(np.mean(c["gamma0"] * (gb + c["beta0"] * uu[:, 2])))
+
+        gam0 = lab_gamma()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         done = 0
@@ -367,6 +391,11 @@ def bench_example1(args) -> dict:
             print(f"[example1] {name}: {done}/{args.ex1_steps} steps, {time.perf_counter() - t0:.1f} s",
                   file=sys.stderr, flush=True)
         wall = time.perf_counter() - t0
+        gam1 = lab_gamma()
+        planes = {}
+        for off in (0.0, 10e-6, 50e-6, 110e-6):
+            kk = int(round((0.5 * (W.EX1_NODES[2] - 1) * d["dz"] + c["gamma0"] * off) / d["dz"]))
+            planes[f"{off * 1e6:.0f}um"] = e.radiated_power(kk)
         pw = e.power_history(args.ex1_steps)
         spec = e.spectral_power()
         b_end = e.bunching()
@@ -375,6 +404,10 @@ def bench_example1(args) -> dict:
         out["runs"][name] = {"steps": args.ex1_steps, "ms_per_step": wall * 1e3 / args.ex1_steps,
                              "cell_updates_per_s": np.prod(W.EX1_NODES) * args.ex1_steps / wall,
                              "dt_s": c["dt"], "n_sub": d["n_sub"], "bunching_end": b_end,
+                             "lab_gamma_start": gam0, "lab_gamma_end": gam1,
+                             "electron_energy_lost_J": (gam0 - gam1) * W.EX1_CHARGE_C / 1.602176634e-19
+                             * 9.1093837015e-31 * 299792458.0 ** 2,
+                             "power_end_by_plane_W": planes,
                              "dW_domega_nu1_Js": float(spec[0]) if len(spec) else None, "fit": fit}
         e.close()
         del e

@@ -6,6 +6,13 @@ Two steps, each under its own profiler run:
   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_w> -- python3 -m paper_2009_13645_amd.counters run
   python3 -m paper_2009_13645_amd.counters summarize <dir_f> <dir_w>
 
+and for the particle kernel (push + gather + deposit), four runs, one per
+counter set (FETCH_SIZE; WRITE_SIZE TCC_ATOMIC_sum; eight SQ counters of
+instruction mix, LDS and waits; the FP64 instruction mix and VALU activity),
+then
+
+  python3 -m paper_2009_13645_amd.counters push <dir_1> <dir_2> <dir_3> <dir_4>
+
 `run` executes the benchmark workload (FEL amplifier, FP32) for a few
 steps, then 10 launches of the sweep alone, then a plain device-to-device
 copy of a known size (torch's copy kernel) used to calibrate what the
@@ -105,9 +112,81 @@ def summarize(dir_f, dir_w):
     print(json.dumps(rec))
 
 
+def _median(v):
+    v = sorted(v)
+    return v[len(v) // 2] if v else float("nan")
+
+
+def summarize_push(dirs):
+    """Per-launch counters of the benchmark's particle kernel, the median of
+    its last 10 dispatches in each run; bytes calibrated on the device copy
+    as for the sweep."""
+    rows = [_rows(d) for d in dirs]
+    name = "PushDeposit<float, false, 0"
+    vals = {}
+    calib = {}
+    for rr in rows:
+        counters = sorted({r["Counter_Name"] for r in rr})
+        for c in counters:
+            v = _per_dispatch(rr, name, c)
+            if v:
+                vals[c] = _median(v[-10:])
+            cp = _per_dispatch(rr, "copyBuffer", c)
+            if cp and c in ("FETCH_SIZE", "WRITE_SIZE"):
+                calib[c] = COPY_BYTES / (1024.0 * max(cp[-3:]))
+    fetch = vals.get("FETCH_SIZE", float("nan")) * 1024.0 * calib.get("FETCH_SIZE", float("nan"))
+    write = vals.get("WRITE_SIZE", float("nan")) * 1024.0 * calib.get("WRITE_SIZE", float("nan"))
+    waves = vals.get("SQ_WAVES", float("nan"))
+    f64 = 64.0 * (2.0 * vals.get("SQ_INSTS_VALU_FMA_F64", 0.0) + vals.get("SQ_INSTS_VALU_MUL_F64", 0.0)
+                  + vals.get("SQ_INSTS_VALU_ADD_F64", 0.0) + vals.get("SQ_INSTS_VALU_TRANS_F64", 0.0))
+    srcs = [os.path.join(ROOT, "paper_2009_13645_amd", "csrc", f) for f in ("k_particles.hip", "particle_dev.hpp")]
+    h = hashlib.sha256()
+    for f in srcs:
+        h.update(open(f, "rb").read())
+    rec = {
+        "kernel": "PushDeposit<float, false, 0> (gather + helical undulator + Boris + deposit; FEL amplifier, "
+                  "2^21 e-, FP32 fields)",
+        "counters_per_launch": vals,
+        "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+        "fp64_flops_per_launch": f64,
+        "per_wave": {k: vals[k] / waves for k in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM",
+                                                   "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64",
+                                                   "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_TRANS_F64")
+                     if k in vals and waves == waves and waves > 0},
+        "copy_calibration": calib,
+        "source_sha256": h.hexdigest(),
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_1> -- python3 -m paper_2009_13645_amd.counters run",
+            "rocprofv3 --pmc WRITE_SIZE TCC_ATOMIC_sum --output-format csv -d <dir_2> -- python3 -m "
+            "paper_2009_13645_amd.counters run",
+            "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE "
+            "SQ_WAIT_INST_ANY SQ_WAVE_CYCLES SQ_BUSY_CYCLES --output-format csv -d <dir_3> -- python3 -m "
+            "paper_2009_13645_amd.counters run",
+            "rocprofv3 --pmc SQ_ACTIVE_INST_VALU SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64 "
+            "SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VMEM GRBM_GUI_ACTIVE --output-format csv -d <dir_4> -- python3 -m "
+            "paper_2009_13645_amd.counters run",
+            "python3 -m paper_2009_13645_amd.counters push <dir_1> <dir_2> <dir_3> <dir_4>",
+        ],
+    }
+    with open(os.path.join(ROOT, "profiles", "push_counters.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    with open(os.path.join(ROOT, "profiles", "push_counters.md"), "w") as f:
+        f.write("# Hardware counters of the particle kernel (FEL amplifier, FP32 fields, 2^21 e-)\n\n")
+        for c in rec["commands"]:
+            f.write(f"    {c}\n")
+        f.write("\nMedian of the last 10 launches, per launch:\n\n| counter | value |\n|---|---:|\n")
+        for k in sorted(vals):
+            f.write(f"| {k} | {vals[k]:.4g} |\n")
+        f.write(f"\nFETCH {fetch / 1e6:.1f} MB, WRITE {write / 1e6:.1f} MB per launch (copy-calibrated); "
+                f"FP64 flops {f64 / 1e9:.2f} G per launch.\n")
+    print(json.dumps(rec))
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "run":
         run()
+    elif len(sys.argv) >= 6 and sys.argv[1] == "push":
+        summarize_push(sys.argv[2:6])
     elif len(sys.argv) >= 4 and sys.argv[1] == "summarize":
         summarize(sys.argv[2], sys.argv[3])
     else:

@@ -175,7 +175,9 @@ def test_device_bunch_generation_matches_the_oracle(variant):
     dr = np.max(np.abs((xg - xyz) / h))
     du = np.max(np.abs(ug - u)) / np.max(np.abs(u))
     print(f"[ext] generated bunch: max |dr| {dr:.2e} cells, max |du| {du:.2e}", flush=True)
-    assert dr < 1e-9 and du < 1e-12
+    # u_z = gamma0 (u'_z - beta0 gamma') cancels: an ulp of the two sides'
+    # log, cos or sqrt becomes ~gamma0 ulps of u
+    assert dr < 1e-9 and du < 1e-10
     # the generated bunch then steps like a loaded one
     o.load_bunch(xyz, u, -1e-12 / n)
     g.step(60)
