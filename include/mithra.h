@@ -254,6 +254,18 @@ int64_t mithra_power_history(mithra_handle h, double *out, int64_t n);
  * factor").  Synchronises. */
 int mithra_bunching(mithra_handle h, double *b);
 
+/* mithra_bunching for callers that cannot allocate device memory (code
+ * that must not call hipMalloc: graph-capturing or allocation-free serving
+ * loops).  Same result as mithra_bunching; its kernel's partial sums (3
+ * doubles for each of 256 blocks, whatever the particle count, so no input
+ * exceeds them) go to a library-held device array of 6 KiB, one per
+ * device, kept until the process ends, instead of the run's arena.  The
+ * run's device must be the current device (EINVAL otherwise).  Every call
+ * on a device shares that device's array: calls that overlap on one
+ * device (other threads or streams) race.  Synchronises.  Errors: EINVAL,
+ * ESTATE, EDEVICE. */
+int mithra_bunching_noalloc(mithra_handle h, double *b);
+
 /* Spectral radiated energy through the power plane (ch. 4 FEL-OUTPUT,
  * radiation-power at normalized frequencies): running Fourier transforms
  * over boosted time t_{n+1/2} of the lab-frame E'_x E'_y B'_x B'_y at the

@@ -865,6 +865,65 @@ extern "C" int mithra_bunching(mithra_handle h, double *b)
     return MITHRA_OK;
 }
 
+// ---- the allocation-free bunching call -------------------------------------
+//
+// Its kernel's partial sums (3 doubles for each of the kBunchBlocks blocks,
+// whatever the particle count) live in a file-scope device array, one copy
+// per device for the life of the process.  Host code never passes the
+// array's name to a kernel: the device address of each device's copy is
+// taken once (hipGetSymbolAddress, that device current) and kept.
+static __device__ __align__(256) double scratch[3 * kBunchBlocks];
+static constexpr int kMaxDevices = 64;
+static double *g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+static int scratch_address(mithra_handle h, double **out)
+{
+    int dev = -1;
+    HIPCHK(h, hipGetDevice(&dev));
+    hipPointerAttribute_t attr;
+    HIPCHK(h, hipPointerGetAttributes(&attr, h->arena));
+    if (attr.device != dev)
+        return fail(h, MITHRA_EINVAL, "the run's device (%d) must be the current device (%d)", attr.device, dev);
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(h, MITHRA_EINVAL, "device %d beyond the %d devices this call serves", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(h, MITHRA_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MITHRA_OK;
+}
+
+extern "C" int mithra_bunching_noalloc(mithra_handle h, double *b)
+{
+    if (!h || !b)
+        return MITHRA_EINVAL;
+    if (!h->loaded)
+        return fail(h, MITHRA_ESTATE, "no bunch loaded");
+    double *part = nullptr;
+    int rc = scratch_address(h, &part);
+    if (rc)
+        return rc;
+    // the partial sums are overwritten whole by the kernel: nothing to clear
+    HIPCHK(h, launch_bunching(h->R, part, kBunchBlocks, h->stream));
+    HIPCHK(h, sync_run(h));
+    double hp[3 * kBunchBlocks];
+    HIPCHK(h, hipMemcpy(hp, part, sizeof hp, hipMemcpyDeviceToHost));
+    double re = 0, im = 0, n = 0;
+    for (int i = 0; i < kBunchBlocks; ++i) {
+        re += hp[3 * i];
+        im += hp[3 * i + 1];
+        n += hp[3 * i + 2];
+    }
+    *b = n > 0 ? std::sqrt(re * re + im * im) / n : 0.0;
+    return MITHRA_OK;
+}
+
 extern "C" int64_t mithra_spectral_power(mithra_handle h, double *dW_domega, int64_t n)
 {
     if (!h || !dW_domega || n < 0)

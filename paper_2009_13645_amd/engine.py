@@ -124,6 +124,8 @@ def lib():
         L.mithra_time_sweep.restype = C.c_int
         L.mithra_step_timed.argtypes = [H, C.c_int64, dp, dp]
         L.mithra_step_timed.restype = C.c_int
+        L.mithra_bunching_noalloc.argtypes = [H, dp]
+        L.mithra_bunching_noalloc.restype = C.c_int
         L.mithra_spectral_power.argtypes = [H, dp, C.c_int64]
         L.mithra_spectral_power.restype = C.c_int64
         L.mithra_set_undulator.argtypes = [H, C.POINTER(UndulatorDesc)]
