@@ -151,7 +151,8 @@ typedef struct mithra_seed_desc {
  * (slices one load wavelength long, b_s = sqrt(-2 ln x_s)/sqrt(N_s), x_s
  * and phase / 2 pi from sequences 8 and 9) displace z by
  * -(2 b / k) sin(k z + phase), k the load wavenumber that the undulator
- * entrance compresses to the resonant one. */
+ * entrance compresses to the bunching wavenumber k_b = gamma0 k_u
+ * (1 + beta0) (see mithra_bunching). */
 typedef struct mithra_bunch_desc {
     int32_t long_profile;        /* 0 flat-top, 1 Gaussian */
     int32_t trans_profile;       /* 0 uniform, 1 Gaussian */
@@ -249,9 +250,13 @@ int mithra_radiated_power(mithra_handle h, int32_t k_plane, double *p_lab_W);
  * and returns the count (or a negative code). */
 int64_t mithra_power_history(mithra_handle h, double *out, int64_t n);
 
-/* |<exp(i k_r z)>| over particles in active cells, k_r = 2 pi gamma0
- * beta0 / lambda_u (resonant boosted wavenumber; ch. 3 "Bunching
- * factor").  Synchronises. */
+/* |<exp(i k_b z)>| over particles in active cells, k_b = 2 pi gamma0
+ * (1 + beta0) / lambda_u (ch. 3 "Bunching factor"): the wavenumber of the
+ * ponderomotive wave of the forward radiation and the backward undulator,
+ * i.e. the lab resonant wavenumber over gamma0 (microbunches are at rest in
+ * this frame, half a boosted radiation wavelength apart).  Instantaneous:
+ * in a planar undulator the figure-eight motion adds a modulation of order
+ * J1(K^2 / (4 + 2 K^2)).  Synchronises. */
 int mithra_bunching(mithra_handle h, double *b);
 
 /* mithra_bunching for callers that cannot allocate device memory (code

@@ -1243,9 +1243,11 @@ static void halton_normal(int ia, int ib, uint64_t j, double *c, double *s)
  * u_z = gamma0 (u'_z - beta0 gamma') (4-velocity boost).
  * Bunching (eq. bunchingFactor; reading of the garbled form): the
  * modulation that becomes resonant after the undulator entrance has, at
- * load, the wavenumber k = k_r gamma0^2 (1 - beta beta0) beta0 / beta
- * (k_r = 2 pi gamma0 beta0 / lambda_u; the entrance compresses the bunch
- * by that factor), and dz = -(2 b_f / k) sin(k z + phase) gives
+ * load, the wavenumber k = k_b gamma0^2 (1 - beta beta0) beta0 / beta, with
+ * k_b = gamma0 k_u (1 + beta0) the ponderomotive wavenumber (the lab
+ * resonant wavenumber over gamma0: microbunches at rest in this frame,
+ * half the boosted radiation wavelength apart), the entrance compressing
+ * the bunch by that factor; dz = -(2 b_f / k) sin(k z + phase) gives
  * <exp(i k z)> = b_f exp(-i phase) to first order.  Shot noise: slices
  * 2 pi / k long; slice s has b_s = sqrt(-2 ln x_s) / sqrt(N_s), x_s from
  * sequence 8, phase 2 pi y_s from sequence 9 (reading: the printed [0, pi]
@@ -1258,8 +1260,9 @@ void ora_generate_bunch(void *h, const double *p, int64_t n, double *xyz, double
     const double gam = p[8];
     const double beta = sqrt(1.0 - 1.0 / (gam * gam));
     const double lz = 1.0 / (g0 * (1.0 - beta * b0));
-    const double kr = 2.0 * PI_ * g0 * b0 / S->d.lambda_u;
-    const double k = kr * g0 * g0 * (1.0 - beta * b0) * b0 / beta;
+    const double kr = 2.0 * PI_ * g0 * b0 / S->d.lambda_u; /* boosted radiation */
+    const double kb = 2.0 * PI_ * g0 * (1.0 + b0) / S->d.lambda_u;
+    const double k = kb * g0 * g0 * (1.0 - beta * b0) * b0 / beta;
     const double lam_lab = (2.0 * PI_ / kr) / (g0 * (1.0 + b0));
     const double L = p[7];
     const double sig_t = lam_lab;
@@ -1441,12 +1444,15 @@ double ora_radiated_power(void *h, int k)
     return P * S->d.dx * S->d.dy / MU_0;
 }
 
-/* |<exp(i k_r z)>| over particles in active cells, k_r = 2 pi / lambda*,
- * lambda* = lambda_u / (gamma0 beta0). */
+/* |<exp(i k_b z)>| over particles in active cells (sec. "Bunching
+ * factor"; reading of the printed k_u): k_b = gamma0 k_u (1 + beta0), the
+ * wavenumber of the ponderomotive wave that the forward radiation
+ * (gamma0 beta0 k_u) and the backward undulator (gamma0 k_u) beat into,
+ * i.e. the lab resonant wavenumber k_u beta0 / (1 - beta0) over gamma0. */
 double ora_bunching(void *h)
 {
     ora_state *S = (ora_state *)h;
-    double kr = 2.0 * PI_ * S->gamma0 * S->beta0 / S->d.lambda_u;
+    double kr = 2.0 * PI_ * S->gamma0 * (1.0 + S->beta0) / S->d.lambda_u;
     double re = 0.0, im = 0.0;
     int64_t n = 0;
     for (int64_t p = 0; p < S->np; ++p) {

@@ -1093,7 +1093,11 @@ extern "C" int mithra_generate_bunch(mithra_handle h, const mithra_bunch_desc *b
     RunDev &R = h->R;
     const double g0 = R.gamma0, b0 = R.beta0;
     const double beta = std::sqrt(1.0 - 1.0 / (b->gamma * b->gamma));
+    // boosted radiation wavenumber, and the bunching (ponderomotive) one,
+    // gamma0 k_u (1 + beta0): microbunches at rest here, half a boosted
+    // radiation wavelength apart
     const double kr = 2.0 * kPi * g0 * b0 / h->d.lambda_u;
+    const double kb = 2.0 * kPi * g0 * (1.0 + b0) / h->d.lambda_u;
     GenParams P{};
     P.long_profile = b->long_profile;
     P.trans_profile = b->trans_profile;
@@ -1112,7 +1116,7 @@ extern "C" int mithra_generate_bunch(mithra_handle h, const mithra_bunch_desc *b
     P.bphase = b->bunching_phase;
     P.n_e = b->n_electrons;
     P.lz = 1.0 / (g0 * (1.0 - beta * b0));
-    P.k = kr * g0 * g0 * (1.0 - beta * b0) * b0 / beta;
+    P.k = kb * g0 * g0 * (1.0 - beta * b0) * b0 / beta;
     P.sig_t = (2.0 * kPi / kr) / (g0 * (1.0 + b0));
     P.n_flat = n;
     if (b->long_profile == 0 && b->tapers == 1)

@@ -267,12 +267,15 @@ struct PushDeposit {
     }
 };
 
-// |sum exp(i k_r z)| over active particles, in two partial sums per block
+// sum exp(i k_b z) and the count over active particles, three partial sums
+// per block; k_b = gamma0 k_u (1 + beta0), the ponderomotive wavenumber of
+// the forward radiation and the backward undulator (microbunches at rest in
+// this frame)
 __global__ __launch_bounds__(256) void k_bunching(RunDev R, double *part)
 {
     __shared__ double sr[256], si[256], sn[256];
     const int pb = R.ctl->pbuf;
-    const double kr = R.ku * R.gamma0 * R.beta0;
+    const double kr = R.ku * R.gamma0 * (1.0 + R.beta0);
     double re = 0, im = 0, n = 0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < R.np; p += (int64_t)gridDim.x * blockDim.x) {
         double r[3] = {R.pr[pb][0][p], R.pr[pb][1][p], R.pr[pb][2][p]}, g[3];

@@ -395,7 +395,8 @@ def test_generated_bunch_moments_bunching_and_quiet_start():
     beta = math.sqrt(1 - 1 / 100.0 ** 2)
     lz = 1 / (g0 * (1 - beta * b0))
     kr = 2 * math.pi * g0 * b0 / d["lambda_u"]
-    k = kr * g0 * g0 * (1 - beta * b0) * b0 / beta
+    kb = 2 * math.pi * g0 * (1 + b0) / d["lambda_u"]
+    k = kb * g0 * g0 * (1 - beta * b0) * b0 / beta
     L = 40 * (2 * math.pi / k) / lz  # lab length of 40 load wavelengths
     xyz, u = _gen(o, n, size_z=L)
     zc = 0.5 * d["nz"] * d["dz"]
@@ -441,7 +442,8 @@ def test_shot_noise_slices_have_the_shot_noise_bunching():
     xyz0, _ = _gen(o, n, size_z=2.5e-3)
     beta = math.sqrt(1 - 1 / 100.0 ** 2)
     kr = 2 * math.pi * g0 * b0 / d["lambda_u"]
-    k = kr * g0 * g0 * (1 - beta * b0) * b0 / beta
+    kb = 2 * math.pi * g0 * (1 + b0) / d["lambda_u"]
+    k = kb * g0 * g0 * (1 - beta * b0) * b0 / beta
     sl = 2 * math.pi / k
     z0 = xyz0[:, 2]
     s = np.floor((z0 - z0.min()) / sl).astype(int)
@@ -456,3 +458,109 @@ def test_shot_noise_slices_have_the_shot_noise_bunching():
     vals = np.array(vals)
     assert len(vals) > 100
     assert np.mean(vals) == pytest.approx(2.0, rel=0.1)
+
+
+# ---------------------------------------------------------------------------
+# The bunching wavenumber
+# ---------------------------------------------------------------------------
+
+def _helical_entry_setup(nz=260):
+    """A helical undulator (no figure-eight motion), a 4-wavelength lab
+    bunch loaded ahead of the entrance, a mesh of 40 cells per boosted
+    radiation wavelength, transverse cells 100 dz wide so that the
+    transverse faces stay far from the axis, negligible charge."""
+    lam_u, K, gam = 0.03, 1.0, 100.0
+    g0 = gam / math.sqrt(1 + K * K)
+    b0 = math.sqrt(1 - 1 / g0 ** 2)
+    ku = 2 * math.pi / lam_u
+    dz = (2 * math.pi / (g0 * b0 * ku)) / 40
+    d = desc(nx=10, ny=10, nz=nz, dz=dz, rx=100.0, ry=100.0, und_type=1, K=K, gamma=gam, lambda_u=lam_u,
+             n_periods=200, space_charge=0)
+    beta = math.sqrt(1 - 1 / gam ** 2)
+    lz = 1 / (g0 * (1 - beta * b0))
+    lam_lab = lam_u / (g0 * b0) / (g0 * (1 + b0))
+    L = 4 * lam_lab
+    zc = 115 * dz
+    d["z_entrance"] = zc + 0.5 * L * lz + 4.0 / (g0 * ku)
+    bunch = dict(long_profile=0, trans_profile=0, xc=0.0, yc=0.0, zc=zc, size_x=1e-6, size_y=1e-6, size_z=L,
+                 gamma=gam, sigma_gamma_rel=0.0, sigma_u_perp=0.0, bunching=0.0, bunching_phase=0.0,
+                 shot_noise=0, n_electrons=1.0, tapers=0)
+    return d, bunch, g0, b0, ku, dz, lam_lab
+
+
+def test_ponderomotive_response_peaks_at_the_bunching_wavenumber():
+    """Inside a helical undulator a weak forward seed at the resonant lab
+    wavelength changes u_z by a modulation along the bunch (the
+    ponderomotive wave of seed and undulator).  Its wavenumber, found from
+    the oracle's own dynamics (difference of a seeded and an unseeded run
+    of the same bunch), is gamma0 k_u (1 + beta0), the one the bunching
+    factor and the bunch generator use, not the boosted radiation
+    wavenumber gamma0 beta0 k_u."""
+    d, bunch, g0, b0, ku, dz, lam_lab = _helical_entry_setup()
+    kb = g0 * ku * (1 + b0)
+    kp = g0 * b0 * ku
+    runs = []
+    for a0 in (0.0, 1e-4):
+        o = Oracle(d)
+        xyz, u = o.generate_bunch(bunch, 2000)
+        if a0 > 0:
+            o.set_seed(dict(type=0, signal=3, a0=a0, wavelength=lam_lab, ctau=20 * dz / (g0 * (1 + b0)),
+                            ct0=60 * dz / (g0 * (1 + b0)), cep_deg=0.0, pol_deg=0.0))
+        o.load_bunch(xyz, u, -1e-30)
+        o.step(300)
+        x, uu, _, _ = o.particles()
+        runs.append((x, uu))
+    (x0, u0), (x1, u1) = runs
+    # the whole bunch is inside, past the entrance fringe, and at rest on
+    # average (the entrance moves along -z at beta0 c; dt = dz / c)
+    assert np.all(x0[:, 2] > d["z_entrance"] - 300 * b0 * dz + 4.0 / (g0 * ku))
+    assert abs(np.mean(u0[:, 2])) < 2e-3 and np.mean(np.hypot(u0[:, 0], u0[:, 1])) == pytest.approx(1.0, rel=2e-3)
+    du = u1[:, 2] - u0[:, 2]
+    assert np.max(np.abs(du)) > 1e-4
+    z = x1[:, 2]
+    ks = np.linspace(0.2, 1.6, 141) * kb
+    F = np.array([abs(np.sum(du * np.exp(1j * k * z))) for k in ks])
+    k_peak = ks[np.argmax(F)]
+    assert abs(k_peak / kb - 1.0) < 0.02
+    assert abs(np.sum(du * np.exp(1j * kb * z))) > 10 * abs(np.sum(du * np.exp(1j * kp * z)))
+    # the oracle's bunching factor measures that wavenumber: particles one
+    # found period apart are bunched, half a period apart are not
+    for spacing, want in ((2 * math.pi / k_peak, 1.0), (math.pi / k_peak, 0.0)):
+        o = Oracle(d)
+        zz = 20 * dz + spacing * np.arange(16)
+        o.load_bunch(np.stack([np.zeros(16), np.zeros(16), zz], axis=1), np.zeros((16, 3)), 0.0)
+        assert o.bunching() == pytest.approx(want, abs=0.05)
+
+
+def test_imposed_bunching_is_found_after_the_entrance():
+    """The generator imposes b_f at the load wavenumber; the undulator
+    entrance compresses the bunch, and the bunching factor of the oracle's
+    particles then reads b_f again (helical: no figure-eight modulation)."""
+    d, bunch, g0, b0, ku, dz, lam_lab = _helical_entry_setup()
+    o = Oracle(d)
+    bunch.update(bunching=0.05, bunching_phase=0.4)
+    xyz, u = o.generate_bunch(bunch, 4000)
+    o.load_bunch(xyz, u, -1e-30)
+    o.step(300)
+    assert o.bunching() == pytest.approx(0.05, rel=0.05)
+
+
+def test_bunching_period_is_the_lab_resonant_wavelength_contracted():
+    """Example 1 (planar, gamma 100.41, K 1.417, 3 cm period; its table
+    prints a 3 um radiation wavelength): the lab resonance
+    lambda_r = lambda_u (1 + K^2/2) / (2 gamma^2) gives 3 um to 1%, and
+    electrons at rest in the bunch frame spaced by gamma0 lambda_r (the lab
+    microbunch spacing, not contracted in the frame that moves with them)
+    are fully bunched; at half that spacing they are not bunched at all."""
+    gam, K, lam_u = 100.41, 1.417, 0.03
+    lam_r = lam_u * (1 + 0.5 * K * K) / (2 * gam * gam)
+    assert lam_r == pytest.approx(3e-6, rel=0.01)
+    g0 = gam / math.sqrt(1 + 0.5 * K * K)
+    dz = g0 * 0.1e-6
+    d = desc(nx=8, ny=8, nz=400, dz=dz, rx=50.0, ry=50.0, K=K, gamma=gam, lambda_u=lam_u)
+    M = 64
+    for spacing, want in ((g0 * lam_r, 1.0), (0.5 * g0 * lam_r, 0.0)):
+        o = Oracle(d)
+        z = 50 * dz + spacing * np.arange(M)
+        o.load_bunch(np.stack([np.zeros(M), np.zeros(M), z], axis=1), np.zeros((M, 3)), 0.0)
+        assert o.bunching() == pytest.approx(want, abs=2e-3)

@@ -577,7 +577,10 @@ def test_bunching_factor_closed_forms():
     w = W.config1()
     d = w.descriptor()
     o = Oracle(d)
-    lam = w.lambda_star
+    # one period of the bunching wavenumber: half the boosted radiation
+    # wavelength lambda* = lambda_u / (gamma0 beta0), up to (1 + beta0) / 2
+    c = o.consts()
+    lam = d["lambda_u"] / (c["gamma0"] * (1 + c["beta0"]))
     M = 64
     zc = d["z0"] + 30.0 * w.dz
     # uniform over whole wavelengths -> 0 ; all at the same phase -> 1
