@@ -44,6 +44,7 @@ def parse():
                     default="fel-amplifier")
     ap.add_argument("--ex1-steps", type=int, default=16000, help="example1: field steps per run")
     ap.add_argument("--ex1-parity-steps", type=int, default=4, help="example1: oracle prefix steps")
+    ap.add_argument("--ex1-history", default=None, help="example1: write the power histories (.npz) here")
     ap.add_argument("--requests", type=int, default=1000, help="served stream: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="served stream: Poisson arrival rate (1/s)")
     ap.add_argument("--tick", type=int, default=50, help="batched scan / served stream: steps per tick")
@@ -304,14 +305,17 @@ def bench_served_stream(args) -> dict:
     }
 
 
-def _gain_fit(power, dt, g0, b0, steps_per_period, window_m=0.6):
-    """Gain length and saturation power from a power history: the power
-    averaged over one radiation period, the saturation power its maximum,
-    the gain length the inverse of the steepest slope of ln P against the
-    undulator length z = gamma0 beta0 c t over any stretch window_m long
-    before saturation (the exponential regime; a least-squares line per
-    window).  The stretch where P rises from 1e-3 to 3e-2 of its maximum is
-    fitted too, for comparison."""
+def _gain_fit(power, dt, g0, b0, steps_per_period, window_m=0.4):
+    """Gain length and saturation power from a power history.
+
+    The power is averaged over one radiation period and set against the
+    undulator length z = gamma0 beta0 c t.  Saturation: the first local
+    maximum above a tenth of the overall maximum (the end of the
+    exponential regime), and the overall maximum.  Gain length: the inverse
+    of the steepest least-squares slope of ln P over any stretch window_m
+    long between the end of the start-up (P above 1e-4 of the maximum) and
+    the first maximum; the stretch where P rises from 1e-3 to 3e-2 of the
+    maximum is fitted too."""
     import numpy as np
     p = np.asarray(power, dtype=float)
     w = max(int(round(steps_per_period)), 1)
@@ -319,19 +323,22 @@ def _gain_fit(power, dt, g0, b0, steps_per_period, window_m=0.6):
         return None
     ps = np.convolve(p, np.ones(w) / w, mode="valid")
     z = g0 * b0 * 299792458.0 * dt * (np.arange(len(ps)) + 0.5 * w)
-    i_sat = int(np.argmax(ps))
-    p_sat = float(ps[i_sat])
-    lo, hi = 1e-3 * p_sat, 3e-2 * p_sat
-    # the last upward crossing of lo before saturation, then the first of hi
-    below = np.nonzero(ps[:i_sat] < lo)[0]
-    i0 = int(below[-1]) + 1 if len(below) else 0
-    above = np.nonzero(ps[i0:i_sat] > hi)[0]
-    i1 = i0 + int(above[0]) if len(above) else i_sat
-    lp = np.log(np.maximum(ps, 1e-300))
     dz = z[1] - z[0]
+    i_max = int(np.argmax(ps))
+    p_max = float(ps[i_max])
+    # first local maximum (over +-0.3 m) above a tenth of the maximum
+    r = max(int(round(0.3 / dz)), 1)
+    i_pk = i_max
+    for i in np.nonzero(ps > 0.1 * p_max)[0]:
+        if ps[i] >= np.max(ps[max(i - r, 0):i + r + 1]):
+            i_pk = int(i)
+            break
+    lp = np.log(np.maximum(ps, 1e-300))
     m = max(int(round(window_m / dz)), 8)
-    best = (0.0, 0)
-    for a in range(0, max(i_sat - m, 0), max(m // 8, 1)):
+    started = np.nonzero(ps[:i_pk] > 1e-4 * p_max)[0]
+    a0 = int(started[0]) if len(started) else 0
+    best = (0.0, a0)
+    for a in range(a0, max(i_pk - m, a0), max(m // 8, 1)):
         sl_, _ = np.polyfit(z[a:a + m], lp[a:a + m], 1)
         if sl_ > best[0]:
             best = (sl_, a)
@@ -340,16 +347,23 @@ def _gain_fit(power, dt, g0, b0, steps_per_period, window_m=0.6):
         a = best[1]
         steep = {"gain_length_m": float(1.0 / best[0]), "z_m": [float(z[a]), float(z[a + m - 1])],
                  "P_W": [float(ps[a]), float(ps[a + m - 1])]}
+    lo, hi = 1e-3 * p_max, 3e-2 * p_max
+    below = np.nonzero(ps[:i_pk] < lo)[0]
+    i0 = int(below[-1]) + 1 if len(below) else 0
+    above = np.nonzero(ps[i0:i_pk] > hi)[0]
+    i1 = i0 + int(above[0]) if len(above) else i_pk
     band = None
     if i1 - i0 >= 4 * w:
         sl, ic = np.polyfit(z[i0:i1], lp[i0:i1], 1)
         band = {"gain_length_m": float(1.0 / sl), "z_m": [float(z[i0]), float(z[i1 - 1])],
                 "rms_ln": float(np.std(lp[i0:i1] - (sl * z[i0:i1] + ic)))}
-    return {"p_sat_W": p_sat, "z_sat_m": float(z[i_sat]),
+    k = max(len(z) // 100, 1)
+    return {"p_first_peak_W": float(ps[i_pk]), "z_first_peak_m": float(z[i_pk]),
+            "p_max_W": p_max, "z_max_m": float(z[i_max]),
             "gain_length_m": steep["gain_length_m"] if steep else None,
             "steepest_window": steep, "band_1e-3_3e-2": band,
-            "curve_z_m": [float(v) for v in z[::max(len(z) // 200, 1)]],
-            "curve_P_W": [float(v) for v in ps[::max(len(z) // 200, 1)]]}
+            "curve_z_m": [round(float(v), 4) for v in z[::k]],
+            "curve_P_W": [float("%.4g" % v) for v in ps[::k]]}
 
 
 def bench_example1(args) -> dict:
@@ -358,14 +372,17 @@ def bench_example1(args) -> dict:
     charge, FP64 as the paper's code) run through the undulator on the GPU
     with NSFD and with standard FD; the gain length and saturation power
     are fitted from the plane power and set against the manual's numbers
-    (MITHRA 22 cm and 2.6 GW; 1-D theory 22.4 cm and 2.7 GW).  The oracle
-    checks a prefix of steps of the same run."""
+    (MITHRA 22 cm and 2.6 GW as printed; 1-D theory 22.4 cm, and 2.7 GW
+    printed for rho P_beam = 0.006 x 4.55 GW = 27 MW) and against Xie's 3-D
+    estimate for this beam.  The oracle checks a prefix of steps of the
+    same run."""
     import math
     import numpy as np
     import torch
     from paper_2009_13645_amd import workloads as W
     from paper_2009_13645_amd.engine import Engine, adapt_mesh
     out = {"metric": "Example 1 gain length and saturation power", "runs": {}}
+    hist = {}
     for solver, name in ((0, "NSFD"), (1, "FD")):
         d, b, n, q = W.example1(solver=solver)
         g0 = W.EX1_GAMMA / math.sqrt(1.0 + 0.5 * W.EX1_K ** 2)
@@ -397,6 +414,8 @@ def bench_example1(args) -> dict:
             kk = int(round((0.5 * (W.EX1_NODES[2] - 1) * d["dz"] + c["gamma0"] * off) / d["dz"]))
             planes[f"{off * 1e6:.0f}um"] = e.radiated_power(kk)
         pw = e.power_history(args.ex1_steps)
+        hist[name] = pw
+        hist["dt_" + name] = c["dt"]
         spec = e.spectral_power()
         b_end = e.bunching()
         lam_star = W.EX1_LAMBDA_U / (c["gamma0"] * c["beta0"])
@@ -412,16 +431,24 @@ def bench_example1(args) -> dict:
         e.close()
         del e
         torch.cuda.empty_cache()
-    # 1-D theory from the table's density (the same formula pinned against the table)
-    rho = W.fel_rho_1d(W.EX1_GAMMA, W.EX1_K, W.EX1_LAMBDA_U, 2.72e19, helical=False)
-    lg_1d = W.EX1_LAMBDA_U / (4.0 * math.pi * math.sqrt(3.0) * rho)
-    out["theory_1d"] = {"rho": rho, "gain_length_m": lg_1d, "manual_gain_length_m": 0.224,
-                        "manual_p_sat_W": 2.7e9, "mithra_gain_length_m": 0.22, "mithra_p_sat_W": 2.6e9}
+    if args.ex1_history:
+        np.savez(args.ex1_history, gamma0=c["gamma0"], beta0=c["beta0"], **hist)
+    # yardsticks: the manual's numbers, its own product rho P_beam, and the
+    # 3-D estimate of Xie's fitting formula for this beam
+    p_beam = W.EX1_GAMMA * 9.1093837015e-31 * 299792458.0 ** 3 * W.EX1_CHARGE_C / 1.602176634e-19 \
+        / W.EX1_BUNCH_LAB[2]
+    est = W.xie_estimate(W.EX1_GAMMA, W.EX1_K, W.EX1_LAMBDA_U, W.EX1_CHARGE_C, W.EX1_BUNCH_LAB, 1e-4)
+    out["yardsticks"] = {
+        "manual": {"gain_length_1d_m": 0.224, "rho": 0.006, "p_sat_1d_W_printed": 2.7e9,
+                   "mithra_gain_length_m": 0.22, "mithra_p_sat_W_printed": 2.6e9},
+        "p_beam_W": p_beam, "manual_rho_times_p_beam_W": 0.006 * p_beam,
+        "xie_3d": est}
     f = out["runs"]["NSFD"]["fit"] or {}
     if f.get("gain_length_m"):
-        out["gain_length_rel_to_1d"] = f["gain_length_m"] / 0.224 - 1.0
-    if f.get("p_sat_W"):
-        out["p_sat_rel_to_1d"] = f["p_sat_W"] / 2.7e9 - 1.0
+        out["gain_length_rel_to_manual"] = f["gain_length_m"] / 0.22 - 1.0
+        out["gain_length_rel_to_xie"] = f["gain_length_m"] / est["gain_length_3d_m"] - 1.0
+    if f.get("p_max_W"):
+        out["p_max_rel_to_rho_p_beam"] = f["p_max_W"] / (0.006 * p_beam) - 1.0
     # prefix parity against the oracle (same device-generated bunch, FP64)
     if args.ex1_parity_steps > 0 and not args.no_cpu_baseline:
         from oracle.oracle import Oracle

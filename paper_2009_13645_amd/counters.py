@@ -2,16 +2,16 @@
 
 Two steps, each under its own profiler run:
 
-  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_f> -- python3 -m paper_2009_13645_amd.counters run
-  rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_w> -- python3 -m paper_2009_13645_amd.counters run
-  python3 -m paper_2009_13645_amd.counters summarize <dir_f> <dir_w>
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_f> -- python3 <repo>/paper_2009_13645_amd/counters.py run
+  rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_w> -- python3 <repo>/paper_2009_13645_amd/counters.py run
+  python3 <repo>/paper_2009_13645_amd/counters.py summarize <dir_f> <dir_w>
 
 and for the particle kernel (push + gather + deposit), four runs, one per
 counter set (FETCH_SIZE; WRITE_SIZE TCC_ATOMIC_sum; eight SQ counters of
 instruction mix, LDS and waits; the FP64 instruction mix and VALU activity),
 then
 
-  python3 -m paper_2009_13645_amd.counters push <dir_1> <dir_2> <dir_3> <dir_4>
+  python3 <repo>/paper_2009_13645_amd/counters.py push <dir_1> <dir_2> <dir_3> <dir_4>
 
 `run` executes the benchmark workload (FEL amplifier, FP32) for a few
 steps, then 10 launches of the sweep alone, then a plain device-to-device
@@ -94,9 +94,9 @@ def summarize(dir_f, dir_w):
         "copy_calibration": {"fetch_factor": cf, "write_factor": cw, "copy_bytes": COPY_BYTES},
         "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
         "commands": [
-            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_f> -- python3 -m paper_2009_13645_amd.counters run",
-            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_w> -- python3 -m paper_2009_13645_amd.counters run",
-            "python3 -m paper_2009_13645_amd.counters summarize <dir_f> <dir_w>",
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_f> -- python3 <repo>/paper_2009_13645_amd/counters.py run",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_w> -- python3 <repo>/paper_2009_13645_amd/counters.py run",
+            "python3 <repo>/paper_2009_13645_amd/counters.py summarize <dir_f> <dir_w>",
         ],
     }
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
@@ -156,7 +156,7 @@ def summarize_push(dirs):
         "copy_calibration": calib,
         "source_sha256": h.hexdigest(),
         "commands": [
-            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_1> -- python3 -m paper_2009_13645_amd.counters run",
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_1> -- python3 <repo>/paper_2009_13645_amd/counters.py run",
             "rocprofv3 --pmc WRITE_SIZE TCC_ATOMIC_sum --output-format csv -d <dir_2> -- python3 -m "
             "paper_2009_13645_amd.counters run",
             "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE "
@@ -165,7 +165,7 @@ def summarize_push(dirs):
             "rocprofv3 --pmc SQ_ACTIVE_INST_VALU SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64 "
             "SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VMEM GRBM_GUI_ACTIVE --output-format csv -d <dir_4> -- python3 -m "
             "paper_2009_13645_amd.counters run",
-            "python3 -m paper_2009_13645_amd.counters push <dir_1> <dir_2> <dir_3> <dir_4>",
+            "python3 <repo>/paper_2009_13645_amd/counters.py push <dir_1> <dir_2> <dir_3> <dir_4>",
         ],
     }
     with open(os.path.join(ROOT, "profiles", "push_counters.json"), "w") as f:

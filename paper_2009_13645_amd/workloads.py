@@ -216,6 +216,36 @@ def fel_rho_1d(gamma: float, K: float, lambda_u: float, n_e: float, helical: boo
     return (1.0 / (2.0 * gamma)) * (kjj * wp / (4.0 * C_LIGHT * ku)) ** (2.0 / 3.0)
 
 
+def xie_estimate(gamma: float, K: float, lambda_u: float, charge: float, box_lab, sigma_gamma_rel: float) -> dict:
+    """3-D gain length and saturation power of a planar-undulator FEL with a
+    uniform, zero-emittance beam in a lab box, from M. Xie's fitting formula
+    (Proc. PAC 1995): L_G = L_G1D (1 + Lambda(eta_d, eta_eps, eta_gamma)),
+    with the 1-D parameter rho = (1/gamma) (a_w [JJ] omega_p / (4 c k_u))^(2/3),
+    a_w = K / sqrt(2), L_G1D = lambda_u / (4 pi sqrt(3) rho), the rms beam
+    size of the box (width / sqrt(12)) in eta_d = L_G1D / (2 k_r sigma^2),
+    eta_eps = 0, eta_gamma = 4 pi (L_G1D / lambda_u) sigma_gamma, and
+    P_sat = 1.6 rho P_beam (L_G1D / L_G)^2.  An estimate for sizing and for
+    comparison, not part of the method."""
+    from scipy.special import j0, j1
+    ku = 2.0 * math.pi / lambda_u
+    n_e = charge / Q_E / (box_lab[0] * box_lab[1] * box_lab[2])
+    wp = math.sqrt(n_e * Q_E * Q_E / (EPS_0 * M_E))
+    xi = K * K / (4.0 + 2.0 * K * K)
+    jj = j0(xi) - j1(xi)
+    rho = (1.0 / gamma) * ((K / math.sqrt(2.0)) * jj * wp / (4.0 * C_LIGHT * ku)) ** (2.0 / 3.0)
+    lg1 = lambda_u / (4.0 * math.pi * math.sqrt(3.0) * rho)
+    lam_r = lambda_u * (1.0 + 0.5 * K * K) / (2.0 * gamma * gamma)
+    kr = 2.0 * math.pi / lam_r
+    sig = math.sqrt(box_lab[0] * box_lab[1] / 12.0)
+    eta_d = lg1 / (2.0 * kr * sig * sig)
+    eta_g = 4.0 * math.pi * (lg1 / lambda_u) * sigma_gamma_rel
+    lam = 0.45 * eta_d ** 0.57 + 3.0 * eta_g ** 2 + 51.0 * eta_d ** 0.95 * eta_g ** 3
+    lg3 = lg1 * (1.0 + lam)
+    p_beam = gamma * M_E * C_LIGHT ** 3 * charge / Q_E / box_lab[2]
+    return {"rho_1d": rho, "gain_length_1d_m": lg1, "eta_d": eta_d, "eta_gamma": eta_g,
+            "gain_length_3d_m": lg3, "p_beam_W": p_beam, "p_sat_3d_W": 1.6 * rho * p_beam * (lg1 / lg3) ** 2}
+
+
 def make_bunch(w: Workload, n: Optional[int] = None, seed: Optional[int] = None
                ) -> Tuple[np.ndarray, np.ndarray, float]:
     """Draw the bunch of workload `w`.
