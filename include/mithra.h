@@ -233,7 +233,8 @@ int mithra_read_fields(mithra_handle h, int field_id, int dtype, void *host_out,
  * xyz (n x 3, m) at t_{n+1/2}, u (n x 3) at t_n.  Optional (nullable):
  * cell[id] = linear node index of the cell corner (-1 outside the active
  * region 1 <= cell <= n-3 on every axis) and sort_perm[rank] = id of the
- * current sort order (ascending tile-major key, ties by id).  Any pointer
+ * current sort order (ascending tile-major key, ties in the previous
+ * order: a stable sort; before the first sort, by id).  Any pointer
  * may be NULL.  Errors: ESTATE, ENUMERIC, EDEVICE. */
 int mithra_read_particles(mithra_handle h, double *xyz, double *u, int32_t *cell,
                           int32_t *sort_perm);

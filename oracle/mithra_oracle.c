@@ -73,6 +73,7 @@ typedef struct {
     double q;                           /* macro-particle charge (C) */
     uint32_t *key;                      /* per id */
     int32_t *perm;                      /* perm[rank] = id */
+    int32_t *prev_rank;                 /* prev_rank[id]: rank in the last order */
     int32_t *cell;                      /* per id: linear node index of the cell corner, -1 inactive */
     int64_t step;
     int loaded;
@@ -183,6 +184,7 @@ void ora_destroy(void *h)
     free(S->spec);
     free(S->key);
     free(S->perm);
+    free(S->prev_rank);
     free(S->cell);
     free(S);
 }
@@ -781,7 +783,8 @@ static void push_particles(ora_state *S)
 /* ------------------------------------------------------------------ */
 /* Cell index and sort order.  key = tile-major cell index for an       */
 /* active cell, 0xFFFFFFFF otherwise; the order is ascending key, ties  */
-/* by particle id.                                                      */
+/* in the previous order (the last sort's ranks; before the first sort, */
+/* the particle ids): a stable sort of the previous order by key.       */
 /* ------------------------------------------------------------------ */
 
 static uint32_t cell_key(const ora_state *S, const double r[3], int32_t *cell_lin)
@@ -802,24 +805,28 @@ static uint32_t cell_key(const ora_state *S, const double r[3], int32_t *cell_li
 }
 
 static const uint32_t *g_sort_keys;
-static int cmp_key_id(const void *a, const void *b)
+static const int32_t *g_prev_rank;
+static int cmp_key_rank(const void *a, const void *b)
 {
     int32_t ia = *(const int32_t *)a, ib = *(const int32_t *)b;
     uint32_t ka = g_sort_keys[ia], kb = g_sort_keys[ib];
     if (ka != kb)
         return ka < kb ? -1 : 1;
-    return ia < ib ? -1 : (ia > ib ? 1 : 0);
+    int32_t ra = g_prev_rank[ia], rb = g_prev_rank[ib];
+    return ra < rb ? -1 : (ra > rb ? 1 : 0);
 }
 
 static void sort_particles(ora_state *S)
 {
+    for (int64_t rank = 0; rank < S->np; ++rank)
+        S->prev_rank[S->perm[rank]] = (int32_t)rank;
     for (int64_t p = 0; p < S->np; ++p) {
         double r[3] = {S->r[0][p], S->r[1][p], S->r[2][p]};
         S->key[p] = cell_key(S, r, &S->cell[p]);
-        S->perm[p] = (int32_t)p;
     }
     g_sort_keys = S->key;
-    qsort(S->perm, (size_t)S->np, sizeof(int32_t), cmp_key_id);
+    g_prev_rank = S->prev_rank;
+    qsort(S->perm, (size_t)S->np, sizeof(int32_t), cmp_key_rank);
 }
 
 /* ------------------------------------------------------------------ */
@@ -940,10 +947,14 @@ int ora_load_bunch(void *h, int64_t n, const double *xyz, const double *u, doubl
     }
     free(S->key);
     free(S->perm);
+    free(S->prev_rank);
     free(S->cell);
     S->key = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
     S->perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    S->prev_rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     S->cell = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    for (int64_t p = 0; p < n; ++p) /* the order before the first sort: by id */
+        S->perm[p] = (int32_t)p;
     for (int64_t p = 0; p < n; ++p)
         for (int a = 0; a < 3; ++a) {
             S->r[a][p] = xyz[3 * p + a];

@@ -104,7 +104,7 @@ static const int kPartials = 8192;  // per-block partial slots (>= persistent bl
 static const int kBunchBlocks = 256;
 
 struct Layout {
-    size_t ctl, pot, src, src_lo, eb, spec, pr, pid, key_by_id, slot_of_id, cell_by_id, key_sorted, sk, sv, hist, boxpart,
+    size_t ctl, pot, src, src_lo, eb, spec, pr, pid, key_in, slot_in, cell_by_id, key_sorted, sk, sv, hist, boxpart,
         boxslot, ppart, power, scratch, tile_flag, ntiles, total;
 };
 
@@ -130,8 +130,8 @@ static Layout make_layout(const mithra_grid_desc *d, int64_t cap)
     L.spec = take((size_t)(d->n_freq > 0 ? d->n_freq : 0) * 8 * (size_t)d->nx * d->ny * 8);
     L.pr = take(12 * c * 8);
     L.pid = take(2 * c * 4);
-    L.key_by_id = take(c * 4);
-    L.slot_of_id = take(c * 4);
+    L.key_in = take(c * 4);
+    L.slot_in = take(c * 4);
     L.cell_by_id = take(c * 4);
     L.key_sorted = take(c * 4);
     L.sk = take(2 * c * 4);
@@ -425,8 +425,8 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
             R.pr[b][a] = (double *)(A + L.pr) + (size_t)(b * 6 + a) * c;
     R.pid[0] = (int32_t *)(A + L.pid);
     R.pid[1] = R.pid[0] + c;
-    R.key_by_id = (uint32_t *)(A + L.key_by_id);
-    R.slot_of_id = (int32_t *)(A + L.slot_of_id);
+    R.key_in = (uint32_t *)(A + L.key_in);
+    R.slot_in = (int32_t *)(A + L.slot_in);
     h->cell_by_id = (int32_t *)(A + L.cell_by_id);
     R.key_sorted = (uint32_t *)(A + L.key_sorted);
     R.tile_flag = (uint32_t *)(A + L.tile_flag);

@@ -21,11 +21,16 @@ constexpr int kLdsNodes = 1536;  // node box capacity of the LDS stage (4 arrays
 // undulators); the single static module keeps its own path.
 template <typename T, bool COMP, int MODE, bool EXT = false>
 struct PushDeposit {
+    // The block's box accumulates in FP64 LDS whatever the source precision
+    // (an FP32 box measured 367 against 225 us per launch at the FEL
+    // amplifier).  Three waves per SIMD: the push needs about 160 VGPRs (at
+    // 128 it spills), and the box allows three blocks per CU.
+    using LT = double;
     static constexpr int kThreads = kDepThreads;
-    static constexpr int kWaves = 3;  // the LDS box allows 3 blocks per CU
+    static constexpr int kWaves = 3;
     static __device__ void run(const RunDev &R, Blk blk)
     {
-        __shared__ double lds[4 * kLdsNodes];
+        __shared__ LT lds[4 * kLdsNodes];
         __shared__ int bb[6];
         const int64_t s = R.ctl->step;
         const int pb = R.ctl->pbuf;
@@ -117,9 +122,10 @@ struct PushDeposit {
                 const bool act2 = cell_of(R, r, g2, c2);
                 dep_j = act1 && act2;
                 dep_q = act2;
-                // sort key of the new position, in id order, for this step's sort
-                R.key_by_id[id] = act2 ? key_of_cell(R, c2) : R.key_inactive;
-                R.slot_of_id[id] = (int32_t)p;
+                // sort key of the new position at rank p: the sort is stable,
+                // so ties keep this step's order
+                R.key_in[p] = act2 ? key_of_cell(R, c2) : R.key_inactive;
+                R.slot_in[p] = (int32_t)p;
                 if (act2)  // the next step's vertex fields are needed around this cell
                     R.tile_flag[tile_of_cell(R, c2)] = (uint32_t)(s + 1);
             }
@@ -209,12 +215,12 @@ struct PushDeposit {
         // together (so that the returning atomics of the compensated mode are
         // in flight together), the node's (i, j, k) decoded once for the four.
         // first / stride: this thread's share; sync orders the three phases.
-        auto lds_deposit = [&](double *base, int B0, int B1, int B2, int bx, int by, int bv, int first, int stride,
+        auto lds_deposit = [&](LT *base, int B0, int B1, int B2, int bx, int by, int bv, int first, int stride,
                                auto sync) {
             for (int e = first; e < 4 * bv; e += stride)
-                base[e] = 0.0;
+                base[e] = (LT)0;
             sync();
-            const LdsAcc<double> acc{base, B0, B1, B2, bx, by, bv};
+            const LdsAcc<LT> acc{base, B0, B1, B2, bx, by, bv};
             if (dep_j)
                 deposit_move(R, acc, g1, c1, g2, c2);
             if (dep_q)
@@ -227,7 +233,7 @@ struct PushDeposit {
                 int idx[4][4];
     #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    v[q] = base[q * bv + e];
+                    v[q] = (double)base[q * bv + e];
                     idx[q][0] = q;
                     idx[q][1] = B0 + i;
                     idx[q][2] = B1 + j;

@@ -7,13 +7,14 @@
 //   local_lin = ((k%Tz) Ty + j%Ty) Tx + i%Tx,
 // and particles outside the active region (cell outside 1..n-3 on some
 // axis) get the key one past the largest tile-major index.  The order is
-// ascending key with ties broken by particle id; it is unique, so the
-// result is bit-exact whatever the previous order was.
+// ascending key with ties in the previous order: a stable sort of the
+// previous order (the last sort's ranks; at load, the buffer order, which
+// is the particle ids).
 //
-// Method: keys are scattered to id order, then an LSD radix sort with
-// 8-bit digits and stable passes runs on (key, slot) pairs starting from id
-// order, which makes ties come out in id order.  The value carried is the
-// particle's slot in the buffer the next push reads (slot_of_id), so the
+// Method: the keys are written in the previous order (the push writes the
+// key of rank p at p, coalesced), then an LSD radix sort with 8-bit digits
+// and stable passes runs on (key, slot) pairs.  The value carried is the
+// particle's slot in the buffer the next push reads (slot_in), so the
 // push reaches the state without looking the slot up.  Each pass is a
 // per-block digit histogram, 256 independent per-digit scans over the
 // blocks, and a stable scatter that ranks equal digits within a wavefront
@@ -57,7 +58,7 @@ __device__ inline int wmax(int v)
     return v;
 }
 
-// keys to id order, slot of every id, box of active cells, active count
+// keys and slots in buffer order, box of active cells, active count
 __global__ __launch_bounds__(256) void k_sort_keys(RunDev R)
 {
     const int pb = R.ctl->pbuf;
@@ -67,9 +68,8 @@ __global__ __launch_bounds__(256) void k_sort_keys(RunDev R)
     if (p < R.np) {
         int c[3];
         const uint32_t key = particle_key(R, R.pr[pb][0][p], R.pr[pb][1][p], R.pr[pb][2][p], c, act);
-        const int32_t id = R.pid[pb][p];
-        R.key_by_id[id] = key;
-        R.slot_of_id[id] = (int32_t)p;
+        R.key_in[p] = key;
+        R.slot_in[p] = (int32_t)p;
         if (act)
             for (int a = 0; a < 3; ++a)
                 lo[a] = hi[a] = c[a];
@@ -372,8 +372,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_sort_small(RunDev R, int step
     const int npass = ctl->npass;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     for (int i = t; i < n; i += kSmallThreads) {
-        skey[0][i] = R.key_by_id[i];
-        sval[0][i] = R.slot_of_id[i];
+        skey[0][i] = R.key_in[i];
+        sval[0][i] = R.slot_in[i];
     }
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     const int wbase = wave * (kSmallChunk / kWaves);
@@ -488,7 +488,7 @@ struct RadixHistRun {
     {
         if (ps >= R.ctl->npass || R.np <= 0)
             return;
-        const uint32_t *kin = ps == 0 ? R.key_by_id : R.sk[(ps - 1) & 1];
+        const uint32_t *kin = ps == 0 ? R.key_in : R.sk[(ps - 1) & 1];
         radix_hist_blk(kin, R.np, 8 * ps, R.hist, R.sort_blocks, blk.id, R.ctl, R.key_inactive);
     }
 };
@@ -509,8 +509,8 @@ struct RadixScatterRun {
     {
         if (ps >= R.ctl->npass || R.np <= 0)
             return;
-        const uint32_t *kin = ps == 0 ? R.key_by_id : R.sk[(ps - 1) & 1];
-        const int32_t *vin = ps == 0 ? R.slot_of_id : R.sv[(ps - 1) & 1];
+        const uint32_t *kin = ps == 0 ? R.key_in : R.sk[(ps - 1) & 1];
+        const int32_t *vin = ps == 0 ? R.slot_in : R.sv[(ps - 1) & 1];
         radix_scatter_blk(kin, vin, R.sk[ps & 1], R.sv[ps & 1], R.np, 8 * ps, R.hist, R.sort_blocks,
                           R.hist + 256 * R.sort_blocks, blk.id, R.ctl, R.key_inactive);
     }
@@ -550,8 +550,8 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int ste
         // range does not need return at once
         const int passes = sort_passes(R.key_inactive);
         const int64_t nb = R.sort_blocks;
-        const uint32_t *kin = R.key_by_id;
-        const int32_t *vin = R.slot_of_id;
+        const uint32_t *kin = R.key_in;
+        const int32_t *vin = R.slot_in;
         for (int ps = 0; ps < passes; ++ps) {
             uint32_t *kout = R.sk[ps & 1];
             int32_t *vout = R.sv[ps & 1];

@@ -118,8 +118,8 @@ struct RunDev {
     void *eb;         // [6: Ex Ey Ez Bx By Bz][nn]
     double *pr[2][6]; // particle buffers: x y z ux uy uz
     int32_t *pid[2];
-    uint32_t *key_by_id;
-    int32_t *slot_of_id;
+    uint32_t *key_in;     // sort input: key of rank p of the previous order
+    int32_t *slot_in;     // sort input: the slot that holds it
     uint32_t *key_sorted;
     uint32_t *tile_flag;  // per sort tile: the step whose vertex fields the tile's particles gather
     uint32_t *sk[2];

@@ -430,12 +430,15 @@ EX1_CHARGE_C = 29.5e-12       # 29.5 pC (1.846e8 electrons)
 EX1_PARTICLES = 131072
 EX1_BUNCH_LAB = (260e-6, 260e-6, 100.5e-6)   # uniform 260 x 260 x 100.5 um (lab)
 EX1_MESH_LAB = (50e-6, 50e-6, 0.1e-6)        # mesh-resolution (lab)
+EX1_MESH_LENGTHS_LAB = (3200e-6, 3200e-6, 280e-6)  # mesh-lengths (lab)
 EX1_NODES = (64, 64, 2800)                   # mesh-lengths / mesh-resolution
 EX1_PLANE_LAB = 110e-6                       # power plane ahead of the bunch centre (lab)
 EX1_BUNCH_STEP_LAB = 1.6e-12                 # bunch-time-step (lab)
 
 
-def example1(solver: int = 0, field_precision: int = 64, plane_lab: float = EX1_PLANE_LAB) -> Tuple[dict, dict, int, float]:
+def example1(solver: int = 0, field_precision: int = 64, plane_lab: float = EX1_PLANE_LAB,
+             mesh_lab=EX1_MESH_LAB, lengths_lab=EX1_MESH_LENGTHS_LAB,
+             n_particles: int = EX1_PARTICLES) -> Tuple[dict, dict, int, float]:
     """Example 1 in the boosted frame: the run descriptor, the device bunch
     description (Halton quiet start, flat-top with tapers, uniform
     transverse box, bunching factor 0.01, no shot noise), the particle
@@ -448,13 +451,16 @@ def example1(solver: int = 0, field_precision: int = 64, plane_lab: float = EX1_
     plane plane_lab (lab) ahead of the bunch centre.  Space charge off, Mur
     second order, NSFD (or FD), as in the job file.  The bunch step of the
     job file (1.6 ps lab) is turned into the sub-step count by the mesh
-    auto-adjustment (mithra_adapt_mesh).
+    auto-adjustment (mithra_adapt_mesh).  mesh_lab, lengths_lab and
+    n_particles vary the job's mesh-resolution, mesh-lengths and
+    number-of-particles (the manual's convergence study); node counts are
+    lengths over resolution.
     """
     g0 = EX1_GAMMA / math.sqrt(1.0 + 0.5 * EX1_K ** 2)
     b0 = math.sqrt(1.0 - 1.0 / (g0 * g0))
-    nx, ny, nz = EX1_NODES
-    dx, dy = EX1_MESH_LAB[0], EX1_MESH_LAB[1]
-    dz = g0 * EX1_MESH_LAB[2]
+    nx, ny, nz = (int(round(lengths_lab[a] / mesh_lab[a])) for a in range(3))
+    dx, dy = mesh_lab[0], mesh_lab[1]
+    dz = g0 * mesh_lab[2]
     beta = math.sqrt(1.0 - 1.0 / (EX1_GAMMA ** 2))
     lz = 1.0 / (g0 * (1.0 - beta * b0))
     zc = 0.5 * (nz - 1) * dz
@@ -472,4 +478,4 @@ def example1(solver: int = 0, field_precision: int = 64, plane_lab: float = EX1_
     bunch = dict(long_profile=0, trans_profile=0, shot_noise=0, tapers=1, center=(0.0, 0.0, zc),
                  size=EX1_BUNCH_LAB, gamma=EX1_GAMMA, sigma_gamma_rel=1e-4, sigma_u_perp=0.0,
                  bunching=0.01, bunching_phase=0.0, n_electrons=EX1_CHARGE_C / Q_E)
-    return desc, bunch, EX1_PARTICLES, -EX1_CHARGE_C / EX1_PARTICLES
+    return desc, bunch, n_particles, -EX1_CHARGE_C / n_particles

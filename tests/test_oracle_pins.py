@@ -542,10 +542,40 @@ def test_cell_index_and_sort_order_properties():
     assert np.all(ti * Tx + li == ci[act])
     assert np.all(tj * Ty + lj == cj[act])
     assert np.all(tk * Tz + lk == ck[act])
-    # perm is a permutation sorted by (key, id)
+    # perm is a permutation sorted by (key, id): before the first sort the
+    # order is by id
     assert np.array_equal(np.sort(perm), np.arange(n))
     kp = keys[perm].astype(np.int64)
     assert np.all((np.diff(kp) > 0) | ((np.diff(kp) == 0) & (np.diff(perm) > 0)))
+
+
+def test_sort_is_stable_in_the_previous_order():
+    """After a step the order is a stable sort of the previous order by the
+    new keys: ties keep their previous ranks, not their ids."""
+    d = small_desc(nx=16, ny=16, nz=20, tile=(2, 2, 2), space_charge=0)
+    o = Oracle(d)
+    rng = np.random.default_rng(8)
+    n = 2000
+    # few cells, many ties; momenta large enough that particles change cells
+    g = np.stack([rng.uniform(5, 8, n), rng.uniform(5, 8, n), rng.uniform(6, 10, n)], axis=1)
+    xyz = np.stack([d["x0"] + g[:, 0] * d["dx"], d["y0"] + g[:, 1] * d["dy"], d["z0"] + g[:, 2] * d["dz"]], axis=1)
+    u = rng.normal(0.0, 0.3, (n, 3))
+    o.load_bunch(xyz, u, 0.0)
+    prev = o.particles()[3]
+    moved = 0
+    for _ in range(3):
+        o.step(1)
+        perm = o.particles()[3]
+        keys = o.keys().astype(np.int64)
+        rank = np.empty(n, dtype=np.int64)
+        rank[prev] = np.arange(n)
+        kp, rp = keys[perm], rank[perm]
+        assert np.array_equal(np.sort(perm), np.arange(n))
+        assert np.all((np.diff(kp) > 0) | ((np.diff(kp) == 0) & (np.diff(rp) > 0)))
+        # ties whose previous ranks disagree with their ids do occur
+        moved += int(np.sum((np.diff(kp) == 0) & (np.diff(rp) > 0) & (np.diff(perm) < 0)))
+        prev = perm
+    assert moved > 0
 
 
 # ---------------------------------------------------------------------------
