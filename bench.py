@@ -40,11 +40,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--latency-runs", type=int, default=12)
-    ap.add_argument("--workload", choices=["fel-amplifier", "batched-scan", "served-stream", "example1"],
+    ap.add_argument("--workload", choices=["fel-amplifier", "batched-scan", "served-stream", "example1",
+                                           "example1-convergence"],
                     default="fel-amplifier")
+    ap.add_argument("--sort-every", type=int, default=4,
+                    help="fel-amplifier: sort the particles after every N-th push (same on the oracle side)")
     ap.add_argument("--ex1-steps", type=int, default=16000, help="example1: field steps per run")
     ap.add_argument("--ex1-parity-steps", type=int, default=4, help="example1: oracle prefix steps")
     ap.add_argument("--ex1-history", default=None, help="example1: write the power histories (.npz) here")
+    ap.add_argument("--ex1-length", type=float, default=5.5, help="example1-convergence: undulator length (m)")
     ap.add_argument("--requests", type=int, default=1000, help="served stream: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="served stream: Poisson arrival rate (1/s)")
     ap.add_argument("--tick", type=int, default=50, help="batched scan / served stream: steps per tick")
@@ -101,7 +105,7 @@ def _oracle_steps(o, seconds: float, max_steps: int):
     return steps, t
 
 
-def cpu_baseline(w, seconds: float):
+def cpu_baseline(w, seconds: float, sort_every: int = 1):
     """The FP64 oracle on the same workload, timed on the host cores for a
     bounded number of steps (load excluded): once on one thread, then on all
     the host's threads, continuing the same run.  Returns the record and
@@ -109,6 +113,7 @@ def cpu_baseline(w, seconds: float):
     from oracle.oracle import Oracle, set_threads, threads
     from paper_2009_13645_amd import workloads as W
     d = w.descriptor()
+    d["sort_every"] = sort_every
     xyz, u, q = W.make_bunch(w)
     n_all = threads()
     o = Oracle(d)
@@ -366,6 +371,98 @@ def _gain_fit(power, dt, g0, b0, steps_per_period, window_m=0.4):
             "curve_P_W": [float("%.4g" % v) for v in ps[::k]]}
 
 
+def _ex1_curve(d, b, n, q, bunch_step_lab, z_end, label):
+    """One Example 1 run on the GPU up to undulator length z_end: the power
+    averaged over one radiation period against z, and the gain fit."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2009_13645_amd import workloads as W
+    from paper_2009_13645_amd.engine import Engine, adapt_mesh
+    g0 = W.EX1_GAMMA / math.sqrt(1.0 + 0.5 * W.EX1_K ** 2)
+    d, _ = adapt_mesh(d, bunch_step_lab / g0)
+    e = Engine(d, max_particles=n)
+    e.generate_bunch(b, n, q)
+    c = e.constants()
+    steps = int(math.ceil(z_end / (c["gamma0"] * c["beta0"] * 299792458.0 * c["dt"])))
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(2000, steps - done)
+        e.step(k)
+        torch.cuda.synchronize()
+        done += k
+    wall = time.perf_counter() - t0
+    print(f"[example1-convergence] {label}: {d['nx']}x{d['ny']}x{d['nz']} nodes, {n} e-, n_sub {d['n_sub']}, "
+          f"{steps} steps, {wall:.1f} s", file=sys.stderr, flush=True)
+    pw = e.power_history(steps)
+    e.close()
+    del e
+    torch.cuda.empty_cache()
+    lam_star = W.EX1_LAMBDA_U / (c["gamma0"] * c["beta0"])
+    w = max(int(round(lam_star / (299792458.0 * c["dt"]))), 1)
+    ps = np.convolve(pw, np.ones(w) / w, mode="valid")
+    z = c["gamma0"] * c["beta0"] * 299792458.0 * c["dt"] * (np.arange(len(ps)) + 0.5 * w)
+    fit = _gain_fit(pw, c["dt"], c["gamma0"], c["beta0"], lam_star / (299792458.0 * c["dt"]))
+    info = {"nodes": [d["nx"], d["ny"], d["nz"]], "particles": n, "n_sub": d["n_sub"], "steps": steps,
+            "ms_per_step": wall * 1e3 / steps, "gain_length_m": fit["gain_length_m"] if fit else None,
+            "p_first_peak_W": fit["p_first_peak_W"] if fit else None,
+            "z_first_peak_m": fit["z_first_peak_m"] if fit else None}
+    return z, ps, info
+
+
+def bench_example1_convergence(args) -> dict:
+    """The manual's convergence study of Example 1 (ch. 5, Convergence
+    Analysis, eq. errorDefinition): the job's suggested values against a
+    finer value of each of the six numerical parameters (macro-particle
+    count, bunch time step, mesh length along z, transverse mesh length,
+    dz, dx = dy), one at a time; error = integral of |P - P_0| over integral
+    of P_0 along the 5 m undulator, P_0 the finer run's power."""
+    import numpy as np
+    from paper_2009_13645_amd import workloads as W
+    z_end = args.ex1_length
+    L = W.EX1_MESH_LENGTHS_LAB
+    M = W.EX1_MESH_LAB
+    variants = [
+        ("suggested", {}, W.EX1_BUNCH_STEP_LAB),
+        ("n x4", {"n_particles": 4 * W.EX1_PARTICLES}, W.EX1_BUNCH_STEP_LAB),
+        ("dt_b / 4", {}, W.EX1_BUNCH_STEP_LAB / 4),
+        ("l_z 380 um", {"lengths_lab": (L[0], L[1], 380e-6)}, W.EX1_BUNCH_STEP_LAB),
+        ("l_x = l_y 4800 um", {"lengths_lab": (4800e-6, 4800e-6, L[2])}, W.EX1_BUNCH_STEP_LAB),
+        ("dz / 2", {"mesh_lab": (M[0], M[1], 0.5 * M[2])}, W.EX1_BUNCH_STEP_LAB),
+        ("dx = dy / 2", {"mesh_lab": (0.5 * M[0], 0.5 * M[1], M[2])}, W.EX1_BUNCH_STEP_LAB),
+        # the manual's space-charge comparison (Example 1, "Space-charge
+        # effect"), and the l_z step again with space charge
+        ("space charge", {"space_charge": 1}, W.EX1_BUNCH_STEP_LAB),
+        ("space charge, l_z 380 um", {"space_charge": 1, "lengths_lab": (L[0], L[1], 380e-6)},
+         W.EX1_BUNCH_STEP_LAB),
+    ]
+    pairs = [(v[0], "suggested") for v in variants[1:7]] + [("space charge", "suggested"),
+                                                            ("space charge, l_z 380 um", "space charge")]
+    curves = {}
+    out = {"metric": "Example 1 convergence (error of the suggested values against a finer run)",
+           "undulator_length_m": 5.0, "runs": {}, "error": {}}
+    for label, kw, dtb in variants:
+        kw = dict(kw)
+        sc = kw.pop("space_charge", 0)
+        d, b, n, q = W.example1(**kw)
+        d["space_charge"] = sc
+        z, ps, info = _ex1_curve(d, b, n, q, dtb, z_end, label)
+        curves[label] = (z, ps)
+        out["runs"][label] = info
+    zz = np.linspace(0.0, 5.0, 2001)
+    for label, against in pairs:
+        base = np.interp(zz, *curves[against])
+        ref = np.interp(zz, *curves[label])
+        key = label if against == "suggested" else f"{label} vs {against}"
+        out["error"][key] = float(np.trapezoid(np.abs(base - ref), zz) / np.trapezoid(ref, zz))
+    if args.ex1_history:
+        np.savez(args.ex1_history, **{k.replace(" ", "_").replace("/", "over") + "_z": v[0]
+                                      for k, v in curves.items()},
+                 **{k.replace(" ", "_").replace("/", "over") + "_P": v[1] for k, v in curves.items()})
+    return out
+
+
 def bench_example1(args) -> dict:
     """The manual's Example 1 (infrared FEL, 64 x 64 x 2800 nodes, 131072
     e-, uniform bunch with bunching factor 0.01, NSFD, Mur-2, no space
@@ -499,6 +596,9 @@ def main():
     if args.workload == "example1":
         print(json.dumps(bench_example1(args)))
         return
+    if args.workload == "example1-convergence":
+        print(json.dumps(bench_example1_convergence(args)))
+        return
 
     import numpy as np
     import torch
@@ -507,6 +607,7 @@ def main():
 
     w = W.config2(field_precision=32, compensated=0)
     d = w.descriptor()
+    d["sort_every"] = args.sort_every
     xyz, u, q = W.make_bunch(w)
     eng = Engine(d, max_particles=len(xyz))
     eng.load_bunch(xyz, u, q)
@@ -553,6 +654,7 @@ def main():
 
     # the same run with FP64 fields (the paper's precision)
     d64 = W.config2(field_precision=64, compensated=0).descriptor()
+    d64["sort_every"] = args.sort_every
     e64 = Engine(d64, max_particles=len(xyz))
     e64.load_bunch(xyz, u, q)
     e64.step(args.warmup)
@@ -580,7 +682,7 @@ def main():
     cpu = None
     err = None
     if not args.no_cpu_baseline:
-        cpu, ora, n_ora, bunch = cpu_baseline(w, args.cpu_seconds)
+        cpu, ora, n_ora, bunch = cpu_baseline(w, args.cpu_seconds, args.sort_every)
         err = error_vs_oracle(d, bunch, ora, n_ora)
         ora.close()
 
@@ -602,6 +704,7 @@ def main():
             "workload": "FEL amplifier: 128x128x1024 nodes, 2^21 macro-electrons, helical K=1.4, "
                         "gamma=200, FP32 fields and sources, FP64 particles, NSFD + Mur-2, space charge",
             "nodes": w.n_nodes, "particles": w.n_particles, "parallelism": "single GPU",
+            "sort_every": args.sort_every,
         },
         "roofline": {
             "bound": "hbm", "kernel": "NSFD sweep (A_x, A_y, A_z, phi)",

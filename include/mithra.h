@@ -90,7 +90,8 @@ typedef struct mithra_grid_desc {
     double pol_angle_deg;        /* field direction (sin, cos, 0) of this angle: 0 = along y, > 0 toward +x */
     double z_entrance;           /* boosted-frame z of the undulator entrance at t = 0 (m) */
     int32_t n_freq;              /* spectral power: number of normalised frequencies (0: none, <= 64) */
-    int32_t pad_;
+    int32_t sort_every;          /* sort by cell after every sort_every-th push (0 or 1: every push,
+                                    <= 1024); in between the particles keep their order */
     double nu_min, nu_max;       /* normalised frequencies nu_min..nu_max (equally spaced; one: nu_min) */
 } mithra_grid_desc;
 

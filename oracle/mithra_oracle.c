@@ -46,7 +46,7 @@ typedef struct {
     int32_t n_periods;        /* undulator length in periods */
     int32_t k_plane;          /* radiated-power plane (node index along z) */
     int32_t tile[3];          /* sort tile dimensions (cells) */
-    int32_t pad_;
+    int32_t sort_every;       /* sort after every sort_every-th push (0, 1: every push) */
     double dx, dy, dz;
     double x0, y0, z0;
     double gamma;             /* beam Lorentz factor (lab) */
@@ -816,6 +816,16 @@ static int cmp_key_rank(const void *a, const void *b)
     return ra < rb ? -1 : (ra > rb ? 1 : 0);
 }
 
+/* Cells and keys of the current positions, the order unchanged (a step
+ * without a sort). */
+static void update_cells(ora_state *S)
+{
+    for (int64_t p = 0; p < S->np; ++p) {
+        double r[3] = {S->r[0][p], S->r[1][p], S->r[2][p]};
+        S->key[p] = cell_key(S, r, &S->cell[p]);
+    }
+}
+
 static void sort_particles(ora_state *S)
 {
     for (int64_t rank = 0; rank < S->np; ++rank)
@@ -1177,7 +1187,14 @@ void ora_step(void *h, int64_t nsteps)
         spectrum_accumulate(S);
         if (S->np > 0) {
             push_particles(S);
-            sort_particles(S);
+            /* the order is refreshed after every sort_every-th push (the
+             * push of step n is the (n+1)-th); in between the particles keep
+             * their order, which the deposit follows */
+            const int se = S->d.sort_every > 1 ? S->d.sort_every : 1;
+            if ((S->step + 1) % se == 0)
+                sort_particles(S);
+            else
+                update_cells(S);
             deposit_all(S);
         }
         rotate_levels(S);

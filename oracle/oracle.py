@@ -36,7 +36,7 @@ class _Desc(C.Structure):
                 ("truncation_order", C.c_int32), ("space_charge", C.c_int32),
                 ("solver", C.c_int32), ("n_sub", C.c_int32), ("und_type", C.c_int32),
                 ("n_periods", C.c_int32), ("k_plane", C.c_int32),
-                ("tile", C.c_int32 * 3), ("pad_", C.c_int32),
+                ("tile", C.c_int32 * 3), ("sort_every", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
                 ("gamma", C.c_double), ("K", C.c_double), ("lambda_u", C.c_double),
@@ -144,6 +144,7 @@ class Oracle:
             setattr(d, k, int(desc[k]))
         for a in range(3):
             d.tile[a] = int(desc["tile"][a])
+        d.sort_every = int(desc.get("sort_every", 1))
         for k in ("dx", "dy", "dz", "x0", "y0", "z0", "gamma", "K", "lambda_u",
                   "pol_angle_deg", "z_entrance"):
             setattr(d, k, float(desc[k]))

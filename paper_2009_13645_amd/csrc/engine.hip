@@ -235,6 +235,8 @@ static const char *validate(const mithra_grid_desc *d)
         return "solver must be 0 (NSFD) or 1 (FD)";
     if (d->n_sub < 1 || d->n_sub > 1024)
         return "n_sub must be in 1..1024";
+    if (d->sort_every < 0 || d->sort_every > 1024)
+        return "sort_every must be in 0..1024";
     if (d->field_precision != 32 && d->field_precision != 64)
         return "field_precision must be 32 or 64";
     if (d->compensated != 0 && d->compensated != 1)
@@ -339,6 +341,7 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.dt = field_dt(d);
     R.dtb = R.dt / (double)d->n_sub;
     R.n_sub = d->n_sub;
+    R.sort_every = d->sort_every > 1 ? d->sort_every : 1;
     R.gamma0 = gamma0_of(d);
     R.beta0 = std::sqrt(1.0 - 1.0 / (R.gamma0 * R.gamma0));
     R.ku = 2.0 * kPi / d->lambda_u;
@@ -789,7 +792,11 @@ extern "C" int mithra_read_particles(mithra_handle h, double *xyz, double *u, in
         int32_t sb = 0;
         HIPCHK(h, hipMemcpy(&sb, &R.ctl->sorted_buf, 4, hipMemcpyDeviceToHost));
         std::vector<int32_t> slots((size_t)n);
-        HIPCHK(h, hipMemcpy(slots.data(), R.sv[sb], (size_t)n * 4, hipMemcpyDeviceToHost));
+        if (sb < 0)  // no sort after the last push: the buffer order
+            for (int64_t r = 0; r < n; ++r)
+                slots[(size_t)r] = (int32_t)r;
+        else
+            HIPCHK(h, hipMemcpy(slots.data(), R.sv[sb], (size_t)n * 4, hipMemcpyDeviceToHost));
         for (int64_t r = 0; r < n; ++r)
             sort_perm[r] = ids[(size_t)slots[(size_t)r]];
     }

@@ -47,7 +47,8 @@ struct PushDeposit {
         if (p < R.np) {
             // rank p of the last sort: the slot where the previous push (or
             // the load) left the particle, and its id
-            const int32_t src = R.sv[R.ctl->sorted_buf][p];
+            const int sb = R.ctl->sorted_buf;
+            const int32_t src = sb < 0 ? (int32_t)p : R.sv[sb][p];
             const int32_t id = R.pid[pb][src];
             double r[3], u[3];
             for (int a = 0; a < 3; ++a) {

@@ -467,7 +467,7 @@ bool sort_ends_step(const RunDev &R) { return R.np > 0 && R.np <= kSmallChunk; }
 // the sort range as a kernel of its own (after a generic box reduction)
 struct SortRange {
     static constexpr int kThreads = 1;
-    static __device__ void run(const RunDev &R, Blk) { sort_range(R); }
+    static __device__ void run(const RunDev &R, Blk) { sort_range(R, false); }
 };
 
 // The same passes with every pointer derived from the run, for grouped

@@ -41,7 +41,8 @@ struct Ctl {
     uint32_t key_base;     // sort keys of the current sort are offset by this (active keys >= it)
     uint32_t key_span;     // active keys lie in [key_base, key_base + key_span); inactive sort as key_span
     int32_t npass;         // radix passes the current sort needs (8-bit digits of key_span)
-    int32_t sorted_buf;    // sv[sorted_buf] holds the particles' slots in the order of the last sort
+    int32_t sorted_buf;    // sv[sorted_buf] holds the particles' slots in the order of the last sort;
+                           // -1: no sort after the last push, the order is the buffer order
 };
 
 constexpr int kMaxBatch = 1;  // one run per RunDev
@@ -66,6 +67,7 @@ struct RunDev {
     // time
     double dt, dtb;
     int n_sub;
+    int sort_every;  // sort after every sort_every-th push (>= 1)
     // frame and undulator
     double gamma0, beta0;
     double ku, B0, Lu, z_ent, theta;
@@ -400,9 +402,18 @@ __device__ inline uint32_t key_of_cell(const RunDev &R, const int c[3])
 // the key of the box's high corner (the key is increasing in each tile
 // coordinate and in each offset inside a tile).  Inactive particles sort as
 // one past that range.  One thread.
-__device__ inline void sort_range(const RunDev &R)
+// may_skip: the sort after the push of step ctl->step, which runs only
+// after every sort_every-th push; a skipped sort leaves the order as it is
+// (no passes, and the push reads the state in buffer order).  The sort at
+// load always runs.
+__device__ inline void sort_range(const RunDev &R, bool may_skip)
 {
     Ctl *c = R.ctl;
+    if (may_skip && R.sort_every > 1 && (c->step + 1) % R.sort_every != 0) {
+        c->npass = 0;
+        c->sorted_buf = -1;
+        return;
+    }
     uint32_t base = 0, span = 0;
     if (c->cell_hi[0] >= c->cell_lo[0] && c->cell_hi[1] >= c->cell_lo[1] && c->cell_hi[2] >= c->cell_lo[2]) {
         const uint32_t vol = (uint32_t)(R.tile[0] * R.tile[1] * R.tile[2]);
@@ -480,7 +491,7 @@ struct BoxReduceStep {
                 }
                 c->n_active = v[12];
                 c->n_items = 0;
-                sort_range(R);  // the offset and pass count of this step's sort
+                sort_range(R, true);  // the offset and pass count of this step's sort
             }
         }
         __syncthreads();

@@ -39,7 +39,7 @@ class GridDesc(C.Structure):
                 ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
                 ("gamma", C.c_double), ("K", C.c_double), ("lambda_u", C.c_double),
                 ("pol_angle_deg", C.c_double), ("z_entrance", C.c_double),
-                ("n_freq", C.c_int32), ("pad_", C.c_int32), ("nu_min", C.c_double), ("nu_max", C.c_double)]
+                ("n_freq", C.c_int32), ("sort_every", C.c_int32), ("nu_min", C.c_double), ("nu_max", C.c_double)]
 
 
 class UndulatorDesc(C.Structure):
@@ -172,6 +172,7 @@ def make_desc(d: dict, max_particles: int, record_power: int = 1) -> GridDesc:
               "z_entrance"):
         setattr(g, k, float(d[k]))
     g.n_freq = int(d.get("n_freq", 0))
+    g.sort_every = int(d.get("sort_every", 1))
     g.nu_min = float(d.get("nu_min", 1.0))
     g.nu_max = float(d.get("nu_max", 1.0))
     return g

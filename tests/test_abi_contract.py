@@ -53,7 +53,8 @@ def test_footprint_is_exact_monotone_and_zero_for_invalid():
     dict(n_freq=2, nu_min=float("nan")),
     dict(n_periods=0), dict(k_plane=0), dict(k_plane=63), dict(tile=(0, 8, 8)),
     dict(tile=(8, 65, 8)), dict(dx=0.0), dict(gamma=1.0), dict(K=0.0), dict(lambda_u=-1.0),
-    dict(dz=1.0), dict(z_entrance=float("nan")), dict(nx=(1 << 20) + 1),
+    dict(dz=1.0), dict(z_entrance=float("nan")), dict(nx=(1 << 20) + 1), dict(sort_every=-1),
+    dict(sort_every=1025),
 ])
 def test_invalid_descriptors_are_rejected_without_device(bad):
     g = E.make_desc(_desc(**bad), 4096)

@@ -80,6 +80,22 @@ def test_config1_fp64_parity_200_steps():
     assert g.bunching() == pytest.approx(o.bunching(), rel=1e-10)
 
 
+@pytest.mark.parametrize("which,every,steps", [("tiny", 3, 200), ("tiny", 3, 202), ("small", 4, 41),
+                                                ("small", 4, 43)])
+def test_sort_every_few_steps_matches_the_oracle(which, every, steps):
+    """Sorting after every few pushes only (the order kept in between) on
+    both sides: fields, momenta, cells and the order itself, ending after a
+    push with and without a sort; the one-workgroup and the multi-block
+    sort paths."""
+    w = W.config1() if which == "tiny" else W.config2_small(field_precision=64)
+    d, o, g = run_both(w, steps, d_over=dict(sort_every=every))
+    cg, co, pg, po = compare(d, o, g, 1e-10)
+    mism = int(np.sum(cg != co)) + int(np.sum(pg != po))
+    print(f"[parity] sort every {every}: cell/perm mismatches after {steps} steps:", mism, flush=True)
+    assert mism == 0
+    assert g.bunching() == pytest.approx(o.bunching(), rel=1e-10)
+
+
 @pytest.mark.parametrize("which", ["tiny", "small"])
 def test_power_history_matches_oracle_each_step(which):
     """The power recorded inside each step (partial sums in the vertex-field
