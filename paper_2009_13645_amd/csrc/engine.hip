@@ -105,7 +105,7 @@ static const int kBunchBlocks = 256;
 
 struct Layout {
     size_t ctl, pot, src, src_lo, eb, spec, pr, pid, key_in, slot_in, cell_by_id, key_sorted, sk, sv, hist, boxpart,
-        boxslot, ppart, power, scratch, tile_flag, ntiles, total;
+        boxslot, ppart, power, scratch, tile_flag, srow, ntiles, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -150,6 +150,7 @@ static Layout make_layout(const mithra_grid_desc *d, int64_t cap)
     L.scratch = take((size_t)(3 * kBunchBlocks + 8) * 8);
     L.ntiles = ntiles;
     L.tile_flag = take(ntiles * 4);
+    L.srow = take(4 * (size_t)d->ny * d->nz * 4);
     L.total = off;
     return L;
 }
@@ -433,6 +434,8 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     h->cell_by_id = (int32_t *)(A + L.cell_by_id);
     R.key_sorted = (uint32_t *)(A + L.key_sorted);
     R.tile_flag = (uint32_t *)(A + L.tile_flag);
+    R.srow_lo = (int32_t *)(A + L.srow);
+    R.srow_hi = R.srow_lo + 2 * (size_t)d->ny * d->nz;
     R.sk[0] = (uint32_t *)(A + L.sk);
     R.sk[1] = R.sk[0] + c;
     R.sv[0] = (int32_t *)(A + L.sv);
@@ -460,6 +463,9 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     HIPCHK(h, hipMemsetAsync(R.power_hist, 0, (size_t)kPowerCap * 8, h->stream));
     // no tile marked for any step (the load marks those of step 0)
     HIPCHK(h, hipMemsetAsync(R.tile_flag, 0xFF, L.ntiles * 4, h->stream));
+    // source row ranges empty: lo = 0x7f7f7f7f, hi = -1
+    HIPCHK(h, hipMemsetAsync(R.srow_lo, 0x7F, 2 * (size_t)d->ny * d->nz * 4, h->stream));
+    HIPCHK(h, hipMemsetAsync(R.srow_hi, 0xFF, 2 * (size_t)d->ny * d->nz * 4, h->stream));
     Ctl c0;
     memset(&c0, 0, sizeof c0);
     for (int s = 0; s < 2; ++s)

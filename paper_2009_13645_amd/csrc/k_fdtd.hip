@@ -262,6 +262,8 @@ struct SweepVec {
         __attribute__((aligned(16))) T sbc[kDiffForm<T> ? 2 : 1][kDiffForm<T> ? TY + 2 : 1][ROW];
         // psi^n at the two outermost nodes of each row end (x-face update)
         T rawe[2][TY + 2][4];
+        // source row ranges of the tile's rows for the chunk's planes
+        int2 sr[TZ][TY];
     };
 
     static __device__ __attribute__((always_inline)) void run(const RunDev &R, Blk blk)
@@ -345,6 +347,19 @@ struct SweepVec {
         const int *rhi = R.ctl->dep_hi[set_r];
         const bool src_col = work && i0 + V - 1 >= rlo[0] && i0 <= rhi[0] + 1 && j >= rlo[1] && j <= rhi[1] + 1;
         const int sk_lo = rlo[2], sk_hi = rhi[2] + 1;
+        // the source row ranges of the set for the tile's rows and the
+        // chunk's planes, through LDS (rows and planes clamped into the grid;
+        // a clamped entry is never used for a stored node)
+        {
+            const int32_t *srl = R.srow_lo + (size_t)set_r * R.nz * R.ny;
+            const int32_t *srh = R.srow_hi + (size_t)set_r * R.nz * R.ny;
+            for (int e = threadIdx.x; e < TZ * TY; e += kThreads) {
+                const int pz = e / TY, py = e - pz * TY;
+                const int64_t row = (int64_t)min(kb + pz, R.nz - 1) * R.ny + min(tile_y * TY + py, R.ny - 1);
+                L.sr[pz][py] = make_int2(srl[row], srh[row]);
+            }
+            __syncthreads();
+        }
         const T *J = src_ptr<T>(R, set_r, COMP);
         const T *Jl = LO ? srclo_ptr<T>(R, set_r, COMP) : nullptr;
         const ST sfac = (ST)(COMP < 3 ? 0.5 * R.sfac_A : R.sfac_phi);
@@ -368,7 +383,9 @@ struct SweepVec {
         auto fetch = [&](int kk, const PlaneSrc<T, V, LO> &prv, PlaneSrc<T, V, LO> &r) {
             const int64_t c = (int64_t)kk * plane + col;
             r.pm = vload_nt<T, V>(prev + c);
-            const bool in = src_col && kk >= sk_lo && kk <= sk_hi;
+            // planes at or beyond ke are not stored: no source needed
+            const int2 rg = L.sr[min(kk - kb, TZ - 1)][ly];
+            const bool in = src_col && kk >= sk_lo && kk <= sk_hi && kk < ke && i0 + V - 1 >= rg.x && i0 <= rg.y;
             const int64_t ca = in ? c : 0;
             r.a = vload<T, V>(J + ca);
             if constexpr (LO)
@@ -682,6 +699,18 @@ __device__ inline void clear_next_sources(const RunDev &R, int64_t b, int64_t nb
     const int ex = hi[0] - l0 + 1, ey = hi[1] - l1 + 1, ez = hi[2] - l2 + 1;
     if (ex <= 0 || ey <= 0 || ez <= 0)
         return;
+    // the set's source row ranges, on the rows the deposit's boxes may have
+    // grown them to (one more node along y and z)
+    {
+        int32_t *slo = R.srow_lo + (size_t)set_c * R.nz * R.ny;
+        int32_t *shi = R.srow_hi + (size_t)set_c * R.nz * R.ny;
+        const int ry = ey + 1, nr = ry * (ez + 1);
+        for (int64_t r = b * blockDim.x + threadIdx.x; r < nr; r += nb * blockDim.x) {
+            const int64_t row = (int64_t)(l2 + (int)(r / ry)) * R.ny + (l1 + (int)(r % ry));
+            slo[row] = 0x7f7f7f7f;
+            shi[row] = -1;
+        }
+    }
     const uint32_t rows = (uint32_t)ey * (uint32_t)ez;
     const uint32_t nw = (uint32_t)nb * (blockDim.x / 64);
     const uint32_t w0 = __builtin_amdgcn_readfirstlane((uint32_t)b * (blockDim.x / 64) + (threadIdx.x >> 6));

@@ -208,6 +208,18 @@ struct PushDeposit {
         const int L0 = bb[0], L1 = bb[1], L2 = bb[2];
         if (bb[3] < 0)
             return;  // nothing deposited by this block (uniform)
+        // the rows of this block's node box, grown by one node along every
+        // axis, join the source row ranges of the set (read by the sweep)
+        {
+            const int ry = bb[4] - L1 + 2, rz = bb[5] - L2 + 2;
+            int32_t *slo = R.srow_lo + (size_t)set * R.nz * R.ny;
+            int32_t *shi = R.srow_hi + (size_t)set * R.nz * R.ny;
+            for (int r = threadIdx.x; r < ry * rz; r += kDepThreads) {
+                const int64_t row = (int64_t)(L2 + r / ry) * R.ny + (L1 + r % ry);
+                atomicMin(&slo[row], L0);
+                atomicMax(&shi[row], bb[3] + 1);
+            }
+        }
         const int ex = bb[3] - L0 + 1, ey = bb[4] - L1 + 1, ez = bb[5] - L2 + 1;
         const int vol = ex * ey * ez;
         const GlobalAcc<T, COMP> gacc = make_gacc<T, COMP>(R, set);

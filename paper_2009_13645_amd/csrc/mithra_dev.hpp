@@ -124,6 +124,11 @@ struct RunDev {
     int32_t *slot_in;     // sort input: the slot that holds it
     uint32_t *key_sorted;
     uint32_t *tile_flag;  // per sort tile: the step whose vertex fields the tile's particles gather
+    // per source set and (z plane, y row), [2][nz][ny]: the x range of nodes
+    // whose sources the last deposit into the set may have made nonzero,
+    // grown by one node along every axis (so that it also covers the
+    // neighbour each node-averaged source reads); empty when lo > hi
+    int32_t *srow_lo, *srow_hi;
     uint32_t *sk[2];
     int32_t *sv[2];
     uint32_t *hist;
