@@ -123,10 +123,13 @@ struct PushDeposit {
                 const bool act2 = cell_of(R, r, g2, c2);
                 dep_j = act1 && act2;
                 dep_q = act2;
-                // sort key of the new position at rank p: the sort is stable,
-                // so ties keep this step's order
-                R.key_in[p] = act2 ? key_of_cell(R, c2) : R.key_inactive;
-                R.slot_in[p] = (int32_t)p;
+                // sort key of the new position at rank p, for the sort after
+                // this push (when there is one): the sort is stable, so ties
+                // keep this step's order
+                if (R.sort_every == 1 || (s + 1) % R.sort_every == 0) {
+                    R.key_in[p] = act2 ? key_of_cell(R, c2) : R.key_inactive;
+                    R.slot_in[p] = (int32_t)p;
+                }
                 if (act2)  // the next step's vertex fields are needed around this cell
                     R.tile_flag[tile_of_cell(R, c2)] = (uint32_t)(s + 1);
             }
