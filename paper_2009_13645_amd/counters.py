@@ -40,6 +40,7 @@ def run():
     from paper_2009_13645_amd.engine import Engine
     w = W.config2(field_precision=32, compensated=0)
     d = w.descriptor()
+    d["sort_every"] = 4  # as the benchmark runs it
     xyz, u, q = W.make_bunch(w)
     e = Engine(d, max_particles=len(xyz))
     e.load_bunch(xyz, u, q)
@@ -157,14 +158,14 @@ def summarize_push(dirs):
         "source_sha256": h.hexdigest(),
         "commands": [
             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_1> -- python3 <repo>/paper_2009_13645_amd/counters.py run",
-            "rocprofv3 --pmc WRITE_SIZE TCC_ATOMIC_sum --output-format csv -d <dir_2> -- python3 -m "
-            "paper_2009_13645_amd.counters run",
+            "rocprofv3 --pmc WRITE_SIZE TCC_ATOMIC_sum --output-format csv -d <dir_2> -- python3 "
+            "<repo>/paper_2009_13645_amd/counters.py run",
             "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE "
-            "SQ_WAIT_INST_ANY SQ_WAVE_CYCLES SQ_BUSY_CYCLES --output-format csv -d <dir_3> -- python3 -m "
-            "paper_2009_13645_amd.counters run",
+            "SQ_WAIT_INST_ANY SQ_WAVE_CYCLES SQ_BUSY_CYCLES --output-format csv -d <dir_3> -- python3 "
+            "<repo>/paper_2009_13645_amd/counters.py run",
             "rocprofv3 --pmc SQ_ACTIVE_INST_VALU SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64 "
-            "SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VMEM GRBM_GUI_ACTIVE --output-format csv -d <dir_4> -- python3 -m "
-            "paper_2009_13645_amd.counters run",
+            "SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VMEM GRBM_GUI_ACTIVE --output-format csv -d <dir_4> -- python3 "
+            "<repo>/paper_2009_13645_amd/counters.py run",
             "python3 <repo>/paper_2009_13645_amd/counters.py push <dir_1> <dir_2> <dir_3> <dir_4>",
         ],
     }

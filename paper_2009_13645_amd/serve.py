@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import dataclasses
 import time
+from concurrent.futures import ThreadPoolExecutor
 from typing import Callable, Dict, List, Optional, Sequence
 
 import numpy as np
@@ -76,11 +77,13 @@ class Server:
         for the run's precision class.
     tune_min: batch size at which the batch-level shape tuner runs (once);
         0 disables it.
+    prepare_workers: host threads that draw the bunches of arrived requests
+        while the device works on a tick (0: drawn at admission).
     """
 
     def __init__(self, cap_bytes: float = 250e9, max_active: int = 64, tick_steps: int = 50,
                  autotune: bool = True, device: str = "cuda:0", clock: Optional[Callable[[], float]] = None,
-                 backend=None, tune_min: int = 16):
+                 backend=None, tune_min: int = 16, prepare_workers: int = 2):
         if backend is None:
             from . import engine as backend
         self.backend = backend  # provides Engine, Batch, footprint_bytes
@@ -89,13 +92,18 @@ class Server:
         self.tick_steps = int(tick_steps)
         self.autotune = autotune
         self.tune_min = int(tune_min)
+        self.prepare_workers = int(prepare_workers)
         self.class_shape: Dict[tuple, int] = {}  # (precision, compensated) -> tuned sweep shape
         self.device = device
         self.clock = clock or time.perf_counter
-        self.stats = {"ticks": 0, "rebuilds": 0, "peak_active": 0, "peak_bytes": 0}
+        # counts, and host seconds spent admitting (bunch, arena, load),
+        # building batches, in ticks (device work and the wait for it) and
+        # retiring
+        self.stats = {"ticks": 0, "rebuilds": 0, "peak_active": 0, "peak_bytes": 0,
+                      "t_admit_s": 0.0, "t_rebuild_s": 0.0, "t_tick_s": 0.0, "t_retire_s": 0.0}
 
-    def _admit(self, req: Request, now: float):
-        xyz, u, q = req.bunch()
+    def _admit(self, req: Request, now: float, ready=None):
+        xyz, u, q = ready.result() if ready is not None else req.bunch()
         eng = self.backend.Engine(req.desc, max_particles=len(xyz), device=self.device)
         eng.load_bunch(xyz, u, q)
         shape = self.class_shape.get(self._class(req))
@@ -129,6 +137,20 @@ class Server:
         results: List[Result] = []
         batch = None
         used = 0
+        # bunches of arrived requests drawn on host threads while a tick runs
+        # (the device wait releases the interpreter); at most max_active ahead
+        pool = ThreadPoolExecutor(self.prepare_workers) if self.prepare_workers > 0 else None
+        ready: Dict[int, object] = {}
+
+        def prepare(now: float):
+            if pool is None:
+                return
+            for r in pending[qi:qi + self.max_active]:
+                if realtime and r.arrival > now:
+                    break
+                if r.rid not in ready:
+                    ready[r.rid] = pool.submit(r.bunch)
+
         t0 = self.clock()
         while qi < len(pending) or active:
             now = self.clock() - t0
@@ -146,7 +168,9 @@ class Server:
                 if batch is not None:
                     batch.close()
                     batch = None
-                active.append(self._admit(r, now))
+                ta = self.clock()
+                active.append(self._admit(r, now, ready.pop(r.rid, None)))
+                self.stats["t_admit_s"] += self.clock() - ta
                 used += fp
                 qi += 1
                 changed = True
@@ -159,6 +183,7 @@ class Server:
             self.stats["peak_active"] = max(self.stats["peak_active"], len(active))
             self.stats["peak_bytes"] = max(self.stats["peak_bytes"], used)
             if batch is None or changed:
+                tb = self.clock()
                 batch = Batch([a.eng for a in active])
                 self.stats["rebuilds"] += 1
                 if self.tune_min > 0 and not self.class_shape and len(active) >= self.tune_min:
@@ -166,23 +191,31 @@ class Server:
                     for a, sh in zip(active, shapes):
                         self.class_shape[self._class(a.req)] = int(sh)
                     self.stats["tuned_shapes"] = dict((str(k), v) for k, v in self.class_shape.items())
+                self.stats["t_rebuild_s"] += self.clock() - tb
             n = [min(self.tick_steps, a.req.steps - a.done) for a in active]
+            tt = self.clock()
             batch.run(n)
+            prepare(self.clock() - t0)
             batch.sync()
+            self.stats["t_tick_s"] += self.clock() - tt
             self.stats["ticks"] += 1
             for a, k in zip(active, n):
                 a.done += k
             now = self.clock() - t0
             fin = [a for a in active if a.done >= a.req.steps]
             if fin:
+                tr = self.clock()
                 batch.close()
                 batch = None
                 for a in fin:
                     results.append(self._retire(a, now))
                     used -= a.footprint
+                self.stats["t_retire_s"] += self.clock() - tr
                 active = [a for a in active if a.done < a.req.steps]
         if batch is not None:
             batch.close()
+        if pool is not None:
+            pool.shutdown(wait=True)
         return results
 
 

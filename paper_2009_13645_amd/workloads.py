@@ -78,6 +78,7 @@ class Workload:
     shot_noise: bool = False
     seed: int = 1
     tile: Tuple[int, int, int] = (8, 8, 8)
+    sort_every: int = 1  # sort after every sort_every-th push
     k_plane: int = -1  # radiated-power plane (node index), -1: 3/4 of nz
 
     # ---- derived geometry (recipe only) ----
@@ -160,6 +161,7 @@ class Workload:
             z_entrance=self.z_entrance,
             tile=tuple(self.tile),
             k_plane=self.plane_k,
+            sort_every=self.sort_every,
         )
 
     def footprint_guess_bytes(self) -> int:
@@ -376,7 +378,8 @@ def config4_runs(n_runs: int = 64, base_seed: int = 4000, steps_cap: Optional[in
     n_x, n_y ~ U{32, 40, ..., 96}, n_z ~ U{32, 40, ..., 256},
     N_p ~ U[1e4, 5e5], gamma ~ U[50, 300], K ~ U[0.5, 2.0], planar,
     40 periods, Gaussian sigma = (n_x/16, n_y/16, n_z/32) cells, precision
-    FP64-all or FP32 fields with probability 1/2, steps ~ U{500, ..., 3000}.
+    FP64-all or FP32 fields with probability 1/2, steps ~ U{500, ..., 3000};
+    particles sorted after every fourth push.
     `scale` < 1 shrinks particle counts (used by CPU-side tests).
     """
     runs = []
@@ -398,7 +401,7 @@ def config4_runs(n_runs: int = 64, base_seed: int = 4000, steps_cap: Optional[in
                      steps=steps, n_particles=npart, charge_C=1e-12,
                      bunch="gaussian", sigma_cells=(nx / 16.0, ny / 16.0, nz / 32.0),
                      sigma_gamma_rel=1e-4, seed=base_seed + r, field_precision=prec,
-                     tile=(8, 8, 8))
+                     tile=(8, 8, 8), sort_every=4)
         runs.append(w)
     return runs
 
