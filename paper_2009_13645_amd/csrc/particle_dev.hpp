@@ -1,5 +1,4 @@
-// particle_dev.hpp -- device functions of the particle phase shared by the
-// per-block and the tile-owned push/deposit kernels:
+// particle_dev.hpp -- device functions of the particle phase:
 //  * external static undulator field: lab-frame field at the position
 //    z' = gamma0 (z - z_entrance + beta0 c t) with entrance and exit fringes,
 //    boosted with E' = 0 (MITHRA 2.0 manual, eqs. undulatorField,
