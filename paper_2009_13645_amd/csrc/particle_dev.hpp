@@ -475,18 +475,29 @@ __device__ inline void deposit_charge(const RunDev &R, const Acc &acc, const dou
     }
 }
 
+// Minimum / maximum over the 64 lanes of a wavefront (every lane active):
+// prefix reductions inside each row of 16 lanes with DPP row shifts (a lane
+// whose source lies outside its row keeps its own value), then the rows'
+// last lanes combined through readlane.  No LDS crossbar traffic, unlike a
+// shuffle, which the deposit's atomics compete with.
 __device__ inline int wave_min(int v)
 {
-    for (int o = 32; o > 0; o >>= 1)
-        v = min(v, __shfl_xor(v, o));
-    return v;
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    return min(min(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+               min(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
 }
 
 __device__ inline int wave_max(int v)
 {
-    for (int o = 32; o > 0; o >>= 1)
-        v = max(v, __shfl_xor(v, o));
-    return v;
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xf, 0xf, false));
+    return max(max(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+               max(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
 }
 
 }  // namespace mithra
