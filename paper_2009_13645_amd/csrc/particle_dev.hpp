@@ -337,9 +337,15 @@ struct GlobalAcc {
             }
         }
     }
-    __device__ inline void add(int comp, int i, int j, int k, double v) const
+    // index of node (i, j, k) in one array; add_at takes a node's index
+    // and the offsets (0 or 1) of a corner along x, y, z
+    __device__ inline int64_t base(const int c[3]) const { return (int64_t)c[2] * nxy + (int64_t)c[1] * nx + c[0]; }
+    __device__ inline void add_at(int comp, int64_t b, int di, int dj, int dk, double v) const
     {
-        const int64_t idx = (int64_t)k * nxy + (int64_t)j * nx + i;
+        add_idx(comp, b + di + (dj ? (int64_t)nx : 0) + (dk ? nxy : 0), v);
+    }
+    __device__ inline void add_idx(int comp, int64_t idx, double v) const
+    {
         if constexpr (sizeof(T) == 8) {
             atomicAdd(reinterpret_cast<double *>(A0) + comp * nn + idx, v);
         } else {
@@ -373,22 +379,27 @@ template <typename AccT = double>
 struct LdsAcc {
     AccT *s;
     int lo0, lo1, lo2, ex, ey, vol;
-    __device__ inline void add(int comp, int i, int j, int k, double v) const
+    // index of node (i, j, k) in the box; add_at takes a node's index and the
+    // offsets (0 or 1) of a corner along x, y, z, so that a particle's adds
+    // need one multiply-add chain, not one per add
+    __device__ inline int base(const int c[3]) const { return ((c[2] - lo2) * ey + (c[1] - lo1)) * ex + (c[0] - lo0); }
+    __device__ inline void add_at(int comp, int b, int di, int dj, int dk, double v) const
     {
-        atomicAdd(&s[comp * vol + ((k - lo2) * ey + (j - lo1)) * ex + (i - lo0)], (AccT)v);
+        atomicAdd(&s[comp * vol + b + di + (dj ? ex : 0) + (dk ? ex * ey : 0)], (AccT)v);
     }
 };
 
 // current of the straight segment a -> b (grid units) inside cell c
 template <class Acc>
-__device__ inline void segment_current(const RunDev &R, const Acc &acc, const double a[3], const double b[3],
+__device__ inline void segment_current(const RunDev &R, const Acc &acc, const double a[3], const double bp[3],
                                        const int c[3])
 {
     double d[3], W[3];
     for (int l = 0; l < 3; ++l) {
-        d[l] = b[l] - a[l];
-        W[l] = 0.5 * (a[l] + b[l]) - (double)c[l];
+        d[l] = bp[l] - a[l];
+        W[l] = 0.5 * (a[l] + bp[l]) - (double)c[l];
     }
+    const auto b = acc.base(c);
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
@@ -396,14 +407,12 @@ __device__ inline void segment_current(const RunDev &R, const Acc &acc, const do
         const double F = d[l] * R.qvh_dt[l];
         const double x = d[m1] * d[m2] * (1.0 / 12.0);
         const double u1 = W[m1], u2 = W[m2];
-        int q[3] = {c[0], c[1], c[2]};
-        acc.add(l, q[0], q[1], q[2], F * ((1.0 - u1) * (1.0 - u2) + x));
-        q[m1] += 1;
-        acc.add(l, q[0], q[1], q[2], F * (u1 * (1.0 - u2) - x));
-        q[m2] += 1;
-        acc.add(l, q[0], q[1], q[2], F * (u1 * u2 + x));
-        q[m1] -= 1;
-        acc.add(l, q[0], q[1], q[2], F * ((1.0 - u1) * u2 - x));
+        // corner offsets along (x, y, z) of the edges (0,0), (1,0), (1,1), (0,1) in (m1, m2)
+        const int o1[3] = {m1 == 0, m1 == 1, m1 == 2}, o2[3] = {m2 == 0, m2 == 1, m2 == 2};
+        acc.add_at(l, b, 0, 0, 0, F * ((1.0 - u1) * (1.0 - u2) + x));
+        acc.add_at(l, b, o1[0], o1[1], o1[2], F * (u1 * (1.0 - u2) - x));
+        acc.add_at(l, b, o1[0] | o2[0], o1[1] | o2[1], o1[2] | o2[2], F * (u1 * u2 + x));
+        acc.add_at(l, b, o2[0], o2[1], o2[2], F * ((1.0 - u1) * u2 - x));
     }
 }
 
@@ -415,6 +424,7 @@ __device__ inline void deposit_move(const RunDev &R, const Acc &acc, const doubl
     // deposit onto the same 12 edges; their values are formed exactly as for
     // two segments and summed in registers, so one set of 12 adds is issued.
     if (c1[0] == c2[0] && c1[1] == c2[1] && c1[2] == c2[2]) {
+        const auto b1c = acc.base(c1);
         double d1[3], d2[3], W1[3], W2[3];
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
@@ -441,10 +451,9 @@ __device__ inline void deposit_move(const RunDev &R, const Acc &acc, const doubl
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int q4 = (e + rot) & 3;
-                int q[3] = {c1[0], c1[1], c1[2]};
-                q[m1] += (q4 == 1 || q4 == 2) ? 1 : 0;
-                q[m2] += (q4 >= 2) ? 1 : 0;
-                acc.add(l, q[0], q[1], q[2], w[q4]);
+                const int s1 = (q4 == 1 || q4 == 2) ? 1 : 0, s2 = (q4 >= 2) ? 1 : 0;
+                acc.add_at(l, b1c, (m1 == 0) ? s1 : ((m2 == 0) ? s2 : 0), (m1 == 1) ? s1 : ((m2 == 1) ? s2 : 0),
+                           (m1 == 2) ? s1 : ((m2 == 2) ? s2 : 0), w[q4]);
             }
         }
         return;
@@ -467,11 +476,12 @@ __device__ inline void deposit_charge(const RunDev &R, const Acc &acc, const dou
     // the eight corners in an order rotated by the lane (lanes of the same
     // cell add to different nodes at once); each value is formed as before
     const int rot = (int)(threadIdx.x & 7);
+    const auto b = acc.base(c);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int q8 = (e + rot) & 7;
         const int I = q8 & 1, J = (q8 >> 1) & 1, K = q8 >> 2;
-        acc.add(3, c[0] + I, c[1] + J, c[2] + K, R.qV * wx[I] * wy[J] * wz[K]);
+        acc.add_at(3, b, I, J, K, R.qV * wx[I] * wy[J] * wz[K]);
     }
 }
 
