@@ -165,8 +165,10 @@ struct mithra_engine {
     bool loaded = false;
     int sweep_shape = 0;
     int32_t *cell_by_id = nullptr;
-    hipGraphExec_t graph = nullptr;   // one step
-    hipGraphExec_t graph8 = nullptr;  // kGraphSteps steps
+    // captured steps: one step without and with the sort launches; a run of
+    // steps starting at each sort phase (step mod sort_every)
+    hipGraphExec_t g1[2] = {nullptr, nullptr};
+    std::vector<hipGraphExec_t> gl;
     int use_graph = 1;
     bool batched = false;              // the run belongs to a batch
     hipStream_t ext_stream = nullptr;  // that batch's stream
@@ -589,7 +591,29 @@ static int enqueue_sort_with_cells(mithra_handle h)
 // events), ev[i] is recorded before stage i and ev[6] after the last one:
 // stages 0 sweep, 1 Mur, 2 vertex fields, 3 push + deposit, 4 sort (with
 // the box reductions), 5 step tail (power sum, bookkeeping).
-static int enqueue_step_on(mithra_handle h, hipStream_t st, hipEvent_t *ev)
+static void drop_graphs(mithra_handle h)
+{
+    for (auto &g : h->g1)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    for (auto &g : h->gl)
+        if (g)
+            (void)hipGraphExecDestroy(g);
+    h->gl.clear();
+}
+
+// Step s sorts after its push when (s + 1) is a multiple of sort_every; the
+// multi-workgroup sort's launches are left out of the other steps (their
+// box reduction sets no passes anyway).  A one-workgroup sort also ends the
+// step, so it is always launched.
+static bool step_sorts(const mithra_handle h, int64_t s)
+{
+    return h->R.sort_every <= 1 || (s + 1) % h->R.sort_every == 0 || sort_ends_step(h->R);
+}
+
+static int enqueue_step_on(mithra_handle h, hipStream_t st, hipEvent_t *ev, int64_t s)
 {
     RunDev &R = h->R;
     auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
@@ -611,7 +635,8 @@ static int enqueue_step_on(mithra_handle h, hipStream_t st, hipEvent_t *ev)
     HIPCHK(h, mark(3));
     HIPCHK(h, launch_push_deposit(R, st, !sort_ends_step(R)));
     HIPCHK(h, mark(4));
-    HIPCHK(h, launch_sort(R, st, true, 1));
+    if (step_sorts(h, s))
+        HIPCHK(h, launch_sort(R, st, true, 1));
     HIPCHK(h, mark(5));
     if (sort_ends_step(R))
         ;  // the small sort ended the step
@@ -624,7 +649,7 @@ static int enqueue_step_on(mithra_handle h, hipStream_t st, hipEvent_t *ev)
     return MITHRA_OK;
 }
 
-static int enqueue_step(mithra_handle h) { return enqueue_step_on(h, h->stream, nullptr); }
+static int enqueue_step(mithra_handle h, int64_t s) { return enqueue_step_on(h, h->stream, nullptr, s); }
 
 // Capture one step on a private stream (the caller's stream may be the
 // legacy default stream, which cannot be captured); the graph is then
@@ -632,7 +657,8 @@ static int enqueue_step(mithra_handle h) { return enqueue_step_on(h, h->stream, 
 // steps per graph of the long replay (fewer graph launches per step)
 static const int kGraphSteps = 8;
 
-static int build_graph(mithra_handle h, int nsteps, hipGraphExec_t *out)
+// the steps s0 .. s0 + nsteps - 1 (only their sort phases matter)
+static int build_graph(mithra_handle h, int nsteps, int64_t s0, hipGraphExec_t *out)
 {
     hipStream_t cap = nullptr;
     HIPCHK(h, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -643,7 +669,7 @@ static int build_graph(mithra_handle h, int nsteps, hipGraphExec_t *out)
     if (e == hipSuccess) {
         h->stream = cap;
         for (int i = 0; i < nsteps && rc == MITHRA_OK; ++i)
-            rc = enqueue_step(h);
+            rc = enqueue_step(h, s0 + i);
         h->stream = user;
         e = hipStreamEndCapture(cap, &g);
     }
@@ -673,28 +699,35 @@ extern "C" int mithra_step(mithra_handle h, int64_t n_steps)
     if (h->batched)
         return fail(h, MITHRA_ESTATE, "the run belongs to a batch: step it with mithra_batch_run");
     int64_t i = 0;
-    if (h->use_graph && n_steps >= kGraphSteps) {
-        // replays of a graph of kGraphSteps steps, then single steps
-        if (!h->graph8) {
-            int rc = build_graph(h, kGraphSteps, &h->graph8);
-            if (rc)
-                return rc;
-        }
-        for (; i + kGraphSteps <= n_steps; i += kGraphSteps) {
-            HIPCHK(h, hipGraphLaunch(h->graph8, h->stream));
-            h->steps += kGraphSteps;
+    // replays of a graph of at least kGraphSteps steps, a whole number of
+    // sort periods (for periods up to 64 steps), then single steps
+    const int64_t se = h->R.sort_every > 1 ? h->R.sort_every : 1;
+    const int64_t L = se <= 64 ? se * ((kGraphSteps + se - 1) / se) : 0;
+    if (h->use_graph && L > 0 && n_steps >= L) {
+        if ((int64_t)h->gl.size() < se)
+            h->gl.resize((size_t)se, nullptr);
+        for (; i + L <= n_steps; i += L) {
+            hipGraphExec_t &g = h->gl[(size_t)(h->steps % se)];
+            if (!g) {
+                int rc = build_graph(h, (int)L, h->steps, &g);
+                if (rc)
+                    return rc;
+            }
+            HIPCHK(h, hipGraphLaunch(g, h->stream));
+            h->steps += L;
         }
     }
     for (; i < n_steps; ++i) {
         if (h->use_graph) {
-            if (!h->graph) {
-                int rc = build_graph(h, 1, &h->graph);
+            hipGraphExec_t &g = h->g1[step_sorts(h, h->steps) ? 1 : 0];
+            if (!g) {
+                int rc = build_graph(h, 1, h->steps, &g);
                 if (rc)
                     return rc;
             }
-            HIPCHK(h, hipGraphLaunch(h->graph, h->stream));
+            HIPCHK(h, hipGraphLaunch(g, h->stream));
         } else {
-            int rc = enqueue_step(h);
+            int rc = enqueue_step(h, h->steps);
             if (rc)
                 return rc;
         }
@@ -952,18 +985,6 @@ extern "C" int64_t mithra_spectral_power(mithra_handle h, double *dW_domega, int
     return m;
 }
 
-static void drop_graphs(mithra_handle h)
-{
-    if (h->graph) {
-        (void)hipGraphExecDestroy(h->graph);
-        h->graph = nullptr;
-    }
-    if (h->graph8) {
-        (void)hipGraphExecDestroy(h->graph8);
-        h->graph8 = nullptr;
-    }
-}
-
 extern "C" int mithra_set_undulator(mithra_handle h, const mithra_undulator_desc *u)
 {
     if (!h || !u)
@@ -1180,10 +1201,7 @@ extern "C" int mithra_destroy(mithra_handle h)
 {
     if (!h)
         return MITHRA_EINVAL;
-    if (h->graph)
-        (void)hipGraphExecDestroy(h->graph);
-    if (h->graph8)
-        (void)hipGraphExecDestroy(h->graph8);
+    drop_graphs(h);
     delete h;
     return MITHRA_OK;
 }
@@ -1200,14 +1218,7 @@ extern "C" int mithra_set_sweep_shape(mithra_handle h, int shape)
         return fail(h, MITHRA_EINVAL, "a seeded run needs a sweep shape that leaves the x faces to the boundary kernel");
     h->sweep_shape = shape;
     h->R.xface_fused = sweep_fuses_xfaces(h->R, shape);
-    if (h->graph) {
-        (void)hipGraphExecDestroy(h->graph);
-        h->graph = nullptr;
-    }
-    if (h->graph8) {
-        (void)hipGraphExecDestroy(h->graph8);
-        h->graph8 = nullptr;
-    }
+    drop_graphs(h);
     return MITHRA_OK;
 }
 
@@ -1230,7 +1241,7 @@ static int step_profile(mithra_handle h, int64_t n, double *stage_ms)
         HIPCHK(h, hipEventCreate(&e));
     int rc = MITHRA_OK;
     for (int64_t i = 0; i < n && rc == MITHRA_OK; ++i) {
-        rc = enqueue_step_on(h, h->stream, &ev[(size_t)(7 * i)]);
+        rc = enqueue_step_on(h, h->stream, &ev[(size_t)(7 * i)], h->steps);
         if (rc == MITHRA_OK)
             h->steps += 1;
     }
@@ -1667,14 +1678,7 @@ static void member_set_shape(mithra_handle h, int shape)
 {
     h->sweep_shape = shape;
     h->R.xface_fused = sweep_fuses_xfaces(h->R, shape);
-    if (h->graph) {
-        (void)hipGraphExecDestroy(h->graph);
-        h->graph = nullptr;
-    }
-    if (h->graph8) {
-        (void)hipGraphExecDestroy(h->graph8);
-        h->graph8 = nullptr;
-    }
+    drop_graphs(h);
 }
 
 static int rebuild_tables(mithra_batch b)
