@@ -218,19 +218,26 @@ def fel_rho_1d(gamma: float, K: float, lambda_u: float, n_e: float, helical: boo
     return (1.0 / (2.0 * gamma)) * (kjj * wp / (4.0 * C_LIGHT * ku)) ** (2.0 / 3.0)
 
 
-def xie_estimate(gamma: float, K: float, lambda_u: float, charge: float, box_lab, sigma_gamma_rel: float) -> dict:
+def xie_estimate(gamma: float, K: float, lambda_u: float, charge: float, box_lab, sigma_gamma_rel: float,
+                 transverse: str = "box") -> dict:
     """3-D gain length and saturation power of a planar-undulator FEL with a
-    uniform, zero-emittance beam in a lab box, from M. Xie's fitting formula
+    zero-emittance beam, uniform over its lab length box_lab[2] and either
+    uniform over a transverse box (transverse="box") or Gaussian with rms
+    box_lab[0], box_lab[1] across (transverse="gaussian", on-axis density),
+    from M. Xie's fitting formula
     (Proc. PAC 1995): L_G = L_G1D (1 + Lambda(eta_d, eta_eps, eta_gamma)),
     with the 1-D parameter rho = (1/gamma) (a_w [JJ] omega_p / (4 c k_u))^(2/3),
     a_w = K / sqrt(2), L_G1D = lambda_u / (4 pi sqrt(3) rho), the rms beam
-    size of the box (width / sqrt(12)) in eta_d = L_G1D / (2 k_r sigma^2),
+    size (a box's width / sqrt(12)) in eta_d = L_G1D / (2 k_r sigma^2),
     eta_eps = 0, eta_gamma = 4 pi (L_G1D / lambda_u) sigma_gamma, and
     P_sat = 1.6 rho P_beam (L_G1D / L_G)^2.  An estimate for sizing and for
     comparison, not part of the method."""
     from scipy.special import j0, j1
     ku = 2.0 * math.pi / lambda_u
-    n_e = charge / Q_E / (box_lab[0] * box_lab[1] * box_lab[2])
+    if transverse == "gaussian":
+        n_e = charge / Q_E / (2.0 * math.pi * box_lab[0] * box_lab[1] * box_lab[2])
+    else:
+        n_e = charge / Q_E / (box_lab[0] * box_lab[1] * box_lab[2])
     wp = math.sqrt(n_e * Q_E * Q_E / (EPS_0 * M_E))
     xi = K * K / (4.0 + 2.0 * K * K)
     jj = j0(xi) - j1(xi)
@@ -238,7 +245,7 @@ def xie_estimate(gamma: float, K: float, lambda_u: float, charge: float, box_lab
     lg1 = lambda_u / (4.0 * math.pi * math.sqrt(3.0) * rho)
     lam_r = lambda_u * (1.0 + 0.5 * K * K) / (2.0 * gamma * gamma)
     kr = 2.0 * math.pi / lam_r
-    sig = math.sqrt(box_lab[0] * box_lab[1] / 12.0)
+    sig = math.sqrt(box_lab[0] * box_lab[1] / (1.0 if transverse == "gaussian" else 12.0))
     eta_d = lg1 / (2.0 * kr * sig * sig)
     eta_g = 4.0 * math.pi * (lg1 / lambda_u) * sigma_gamma_rel
     lam = 0.45 * eta_d ** 0.57 + 3.0 * eta_g ** 2 + 51.0 * eta_d ** 0.95 * eta_g ** 3
@@ -431,7 +438,7 @@ EX1_K = 1.417                 # undulator-parameter of the job file
 EX1_LAMBDA_U = 0.03           # 3 cm
 EX1_CHARGE_C = 29.5e-12       # 29.5 pC (1.846e8 electrons)
 EX1_PARTICLES = 131072
-EX1_BUNCH_LAB = (260e-6, 260e-6, 100.5e-6)   # uniform 260 x 260 x 100.5 um (lab)
+EX1_BUNCH_LAB = (260e-6, 260e-6, 100.5e-6)   # sigma-position: rms 260 um across (Gaussian), 100.5 um long (lab)
 EX1_MESH_LAB = (50e-6, 50e-6, 0.1e-6)        # mesh-resolution (lab)
 EX1_MESH_LENGTHS_LAB = (3200e-6, 3200e-6, 280e-6)  # mesh-lengths (lab)
 EX1_NODES = (64, 64, 2800)                   # mesh-lengths / mesh-resolution
@@ -441,11 +448,11 @@ EX1_BUNCH_STEP_LAB = 1.6e-12                 # bunch-time-step (lab)
 
 def example1(solver: int = 0, field_precision: int = 64, plane_lab: float = EX1_PLANE_LAB,
              mesh_lab=EX1_MESH_LAB, lengths_lab=EX1_MESH_LENGTHS_LAB,
-             n_particles: int = EX1_PARTICLES) -> Tuple[dict, dict, int, float]:
+             n_particles: int = EX1_PARTICLES, transverse: str = "gaussian") -> Tuple[dict, dict, int, float]:
     """Example 1 in the boosted frame: the run descriptor, the device bunch
-    description (Halton quiet start, flat-top with tapers, uniform
-    transverse box, bunching factor 0.01, no shot noise), the particle
-    count and the macro-particle charge.
+    description (Halton quiet start, flat-top with tapers, Gaussian rms
+    260 um across, bunching factor 0.01, no shot noise), the particle count
+    and the macro-particle charge.
 
     Lab lengths along z become boosted lengths times gamma0 (a mesh at rest
     in the bunch frame); the transverse ones are unchanged.  The bunch centre
@@ -457,7 +464,10 @@ def example1(solver: int = 0, field_precision: int = 64, plane_lab: float = EX1_
     auto-adjustment (mithra_adapt_mesh).  mesh_lab, lengths_lab and
     n_particles vary the job's mesh-resolution, mesh-lengths and
     number-of-particles (the manual's convergence study); node counts are
-    lengths over resolution.
+    lengths over resolution.  transverse: "gaussian" (the job file: MITHRA's
+    transverse profiles are always Gaussian, sigma-position their rms) or
+    "box" (the uniform 260 x 260 um box that the table's electron density
+    corresponds to).
     """
     g0 = EX1_GAMMA / math.sqrt(1.0 + 0.5 * EX1_K ** 2)
     b0 = math.sqrt(1.0 - 1.0 / (g0 * g0))
@@ -478,7 +488,10 @@ def example1(solver: int = 0, field_precision: int = 64, plane_lab: float = EX1_
                 K=EX1_K, lambda_u=EX1_LAMBDA_U, n_periods=300, pol_angle_deg=0.0,
                 z_entrance=z_head + 2.0 * EX1_LAMBDA_U / g0, tile=(4, 4, 4),
                 k_plane=int(round((zc + g0 * plane_lab) / dz)), n_freq=1, nu_min=1.0, nu_max=1.0)
-    bunch = dict(long_profile=0, trans_profile=0, shot_noise=0, tapers=1, center=(0.0, 0.0, zc),
+    if transverse not in ("gaussian", "box"):
+        raise ValueError("transverse must be 'gaussian' or 'box'")
+    bunch = dict(long_profile=0, trans_profile=1 if transverse == "gaussian" else 0, shot_noise=0, tapers=1,
+                 center=(0.0, 0.0, zc),
                  size=EX1_BUNCH_LAB, gamma=EX1_GAMMA, sigma_gamma_rel=1e-4, sigma_u_perp=0.0,
                  bunching=0.01, bunching_phase=0.0, n_electrons=EX1_CHARGE_C / Q_E)
     return desc, bunch, n_particles, -EX1_CHARGE_C / n_particles
