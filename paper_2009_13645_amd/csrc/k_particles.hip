@@ -24,14 +24,16 @@ struct PushDeposit {
     // The block's box accumulates in FP64 LDS whatever the source precision
     // (an FP32 box measured 367 against 225 us per launch at the FEL
     // amplifier).  Three waves per SIMD: the push needs about 160 VGPRs (at
-    // 128 it spills), and the box allows three blocks per CU.
+    // 128 it spills), and the box allows three blocks per CU.  The general
+    // external field (arrays, optical undulators) needs about 210: two
+    // waves, where three spilled about 50 registers per lane.
     using LT = double;
     static constexpr int kThreads = kDepThreads;
-    static constexpr int kWaves = 3;
+    static constexpr int kWaves = EXT ? 2 : 3;
     static __device__ void run(const RunDev &R, Blk blk)
     {
         __shared__ LT lds[4 * kLdsNodes];
-        __shared__ int bb[6];
+        __shared__ int bb[7];  // node box lo[3], hi[3]; active count
         const int64_t s = R.ctl->step;
         const int pb = R.ctl->pbuf;
         const int set = MODE == 0 ? (int)((s + 1) & 1) : 0;
@@ -40,6 +42,8 @@ struct PushDeposit {
             bb[threadIdx.x] = 0x7fffffff;
             bb[3 + threadIdx.x] = -1;
         }
+        if (threadIdx.x == 3)
+            bb[6] = 0;
 
         double g1[3] = {0, 0, 0}, g2[3] = {0, 0, 0};
         int c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0};
@@ -134,45 +138,6 @@ struct PushDeposit {
                     R.tile_flag[tile_of_cell(R, c2)] = (uint32_t)(s + 1);
             }
         }
-        if (MODE == 0) {
-            // per-block box of the active cells after the push (sort statistics)
-            __shared__ int32_t cw[4][7];
-            int clo[3], chi[3];
-            for (int l = 0; l < 3; ++l) {
-                clo[l] = dep_q ? c2[l] : 0x7fffffff;
-                chi[l] = dep_q ? c2[l] : -1;
-                clo[l] = wave_min(clo[l]);
-                chi[l] = wave_max(chi[l]);
-            }
-            const int nact = __popcll(__ballot(dep_q));
-            const int wave = threadIdx.x >> 6;
-            if ((threadIdx.x & 63) == 0) {
-                for (int l = 0; l < 3; ++l) {
-                    cw[wave][l] = clo[l];
-                    cw[wave][3 + l] = chi[l];
-                }
-                cw[wave][6] = nact;
-            }
-            __syncthreads();
-            if (threadIdx.x < 7) {
-                int32_t v = cw[0][threadIdx.x];
-                for (int w = 1; w < kDepThreads / 64; ++w) {
-                    const int32_t x = cw[w][threadIdx.x];
-                    v = threadIdx.x < 3 ? min(v, x) : (threadIdx.x < 6 ? max(v, x) : v + x);
-                }
-                // into this block's slot (cell box at words 6-11, count at 12)
-                int32_t *slot = R.boxslot + 16 * (blk.id & (kBoxSlots - 1));
-                if (threadIdx.x < 3) {
-                    if (v != 0x7fffffff)
-                        atomicMin(&slot[6 + threadIdx.x], v);
-                } else if (threadIdx.x < 6) {
-                    if (v >= 0)
-                        atomicMax(&slot[6 + threadIdx.x], v);
-                } else if (v != 0) {
-                    atomicAdd(&slot[12], v);
-                }
-            }
-        }
         // node box of this thread's deposits
         int lo[3], hi[3];
         for (int l = 0; l < 3; ++l) {
@@ -188,22 +153,30 @@ struct PushDeposit {
             lo[l] = wave_min(lo[l]);
             hi[l] = wave_max(hi[l]);
         }
+        // active particles after the push (sort statistics)
+        const int nact = MODE == 0 ? (int)__popcll(__ballot(dep_q)) : 0;
         __syncthreads();
-        if ((threadIdx.x & 63) == 0 && hi[0] >= 0)
-            for (int l = 0; l < 3; ++l) {
-                atomicMin(&bb[l], lo[l]);
-                atomicMax(&bb[3 + l], hi[l]);
-            }
+        if ((threadIdx.x & 63) == 0) {
+            if (hi[0] >= 0)
+                for (int l = 0; l < 3; ++l) {
+                    atomicMin(&bb[l], lo[l]);
+                    atomicMax(&bb[3 + l], hi[l]);
+                }
+            if (nact != 0)
+                atomicAdd(&bb[6], nact);
+        }
         __syncthreads();
         // this block's box: the push reduces it into its slot (BoxReduceStep),
         // the load deposit writes its partial (k_box_reduce)
         if (MODE == 0) {
+            int32_t *slot = R.boxslot + 16 * (blk.id & (kBoxSlots - 1));
             if (threadIdx.x < 6 && bb[3] >= 0) {
-                int32_t *slot = R.boxslot + 16 * (blk.id & (kBoxSlots - 1));
                 if (threadIdx.x < 3)
                     atomicMin(&slot[threadIdx.x], bb[threadIdx.x]);
                 else
                     atomicMax(&slot[threadIdx.x], bb[threadIdx.x]);
+            } else if (threadIdx.x == 6 && bb[6] != 0) {
+                atomicAdd(&slot[12], bb[6]);
             }
         } else if (threadIdx.x < 7) {
             R.boxpart[8 * (int64_t)blk.id + threadIdx.x] = threadIdx.x < 6 ? bb[threadIdx.x] : 0;
@@ -217,8 +190,10 @@ struct PushDeposit {
             const int ry = bb[4] - L1 + 2, rz = bb[5] - L2 + 2;
             int32_t *slo = R.srow_lo + (size_t)set * R.nz * R.ny;
             int32_t *shi = R.srow_hi + (size_t)set * R.nz * R.ny;
-            for (int r = threadIdx.x; r < ry * rz; r += kDepThreads) {
-                const int64_t row = (int64_t)(L2 + r / ry) * R.ny + (L1 + r % ry);
+            const double iry = 1.0 / (double)ry;
+            for (int64_t r = threadIdx.x; r < (int64_t)ry * rz; r += kDepThreads) {
+                const int64_t rk = small_div(r, iry), rj = r - rk * ry;
+                const int64_t row = (L2 + rk) * R.ny + (L1 + rj);
                 atomicMin(&slo[row], L0);
                 atomicMax(&shi[row], bb[3] + 1);
             }
@@ -242,9 +217,10 @@ struct PushDeposit {
             if (dep_q)
                 deposit_charge(R, acc, g2, c2);
             sync();
+            const double ibx = 1.0 / (double)bx, iby = 1.0 / (double)by;
             for (int e = first; e < bv; e += stride) {
-                const int i = e % bx, jk = e / bx;
-                const int j = jk % by, k = jk / by;
+                const int jk = (int)small_div((int64_t)e, ibx), i = e - jk * bx;
+                const int k = (int)small_div((int64_t)jk, iby), j = jk - k * by;
                 double v[4];
                 int idx[4][4];
     #pragma unroll

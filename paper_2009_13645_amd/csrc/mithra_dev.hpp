@@ -385,21 +385,26 @@ __device__ inline void plane_power_final(const RunDev &R, int64_t s, double *out
 }
 
 // Linear index of the sort tile of an active cell c (tile-major order).
+// (cells are non-negative; the tile divisions are exact multiply-highs)
 __device__ inline uint32_t tile_of_cell(const RunDev &R, const int c[3])
 {
-    return ((uint32_t)(c[2] / R.tile[2]) * (uint32_t)R.ntile[1] + (uint32_t)(c[1] / R.tile[1])) *
+    return (fdiv((uint32_t)c[2], R.tdiv[2]) * (uint32_t)R.ntile[1] + fdiv((uint32_t)c[1], R.tdiv[1])) *
                (uint32_t)R.ntile[0] +
-           (uint32_t)(c[0] / R.tile[0]);
+           fdiv((uint32_t)c[0], R.tdiv[0]);
 }
 
 // Tile-major sort key of an active cell c (see k_sort.hip for the order).
 __device__ inline uint32_t key_of_cell(const RunDev &R, const int c[3])
 {
-    const int Tx = R.tile[0], Ty = R.tile[1], Tz = R.tile[2];
-    const uint32_t tl = ((uint32_t)(c[2] / Tz) * (uint32_t)R.ntile[1] + (uint32_t)(c[1] / Ty)) * (uint32_t)R.ntile[0] +
-                        (uint32_t)(c[0] / Tx);
-    const uint32_t loc = ((uint32_t)(c[2] % Tz) * Ty + (uint32_t)(c[1] % Ty)) * Tx + (uint32_t)(c[0] % Tx);
-    return tl * (uint32_t)(Tx * Ty * Tz) + loc;
+    const uint32_t Tx = (uint32_t)R.tile[0], Ty = (uint32_t)R.tile[1], Tz = (uint32_t)R.tile[2];
+    uint32_t q[3], m[3];
+    for (int a = 0; a < 3; ++a) {
+        q[a] = fdiv((uint32_t)c[a], R.tdiv[a]);
+        m[a] = (uint32_t)c[a] - q[a] * (uint32_t)R.tile[a];
+    }
+    const uint32_t tl = (q[2] * (uint32_t)R.ntile[1] + q[1]) * (uint32_t)R.ntile[0] + q[0];
+    const uint32_t loc = (m[2] * Ty + m[1]) * Tx + m[0];
+    return tl * (Tx * Ty * Tz) + loc;
 }
 
 // Offset and pass count of the current sort, from the box of the active
@@ -447,12 +452,13 @@ constexpr int kDepThreads = 256;
 __host__ __device__ inline int64_t dep_blocks_dev(int64_t np) { return (np + kDepThreads - 1) / kDepThreads; }
 
 // After a per-block push: the deposit box of set (s+1)&1, the active-cell
-// box and the active count, then the key range of the sort that follows;
+// box (from the deposit box) and the active count, then the key range of
+// the sort that follows;
 // the tile work item counter is reset.  The push's workgroups reduce their
 // boxes into kBoxSlots slots with integer atomics (min, max, add: the order
 // does not change the result); here the first wavefront reduces the slots,
 // leaves them empty for the next push, and one thread stores the result.
-// Slot layout (16 words): dep lo[3], dep hi[3], cell lo[3], cell hi[3],
+// Slot layout (16 words): dep lo[3], dep hi[3], unused[6] (left empty),
 // active count, pad[3].  Every thread of the block must call it (barriers).
 constexpr int kBoxSlots = 64;
 
@@ -488,11 +494,15 @@ struct BoxReduceStep {
                 }
             }
             if (threadIdx.x == 0) {
+                // the box of the active cells after the push is taken as the
+                // node box of the deposits less its upper layer: it holds
+                // every active cell, and the cells it adds (those left by
+                // the push) lie within one cell of it
                 for (int a = 0; a < 3; ++a) {
                     c->dep_lo[set][a] = v[a];
                     c->dep_hi[set][a] = v[3 + a];
-                    c->cell_lo[a] = v[6 + a];
-                    c->cell_hi[a] = v[9 + a];
+                    c->cell_lo[a] = v[a];
+                    c->cell_hi[a] = v[3 + a] - 1;
                 }
                 c->n_active = v[12];
                 c->n_items = 0;

@@ -389,83 +389,66 @@ struct LdsAcc {
     }
 };
 
-// current of the straight segment a -> b (grid units) inside cell c
-template <class Acc>
-__device__ inline void segment_current(const RunDev &R, const Acc &acc, const double a[3], const double bp[3],
-                                       const int c[3])
-{
-    double d[3], W[3];
-    for (int l = 0; l < 3; ++l) {
-        d[l] = bp[l] - a[l];
-        W[l] = 0.5 * (a[l] + bp[l]) - (double)c[l];
-    }
-    const auto b = acc.base(c);
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
-        // J_l = q (displacement in metres) / (dt V) times the edge weights
-        const double F = d[l] * R.qvh_dt[l];
-        const double x = d[m1] * d[m2] * (1.0 / 12.0);
-        const double u1 = W[m1], u2 = W[m2];
-        // corner offsets along (x, y, z) of the edges (0,0), (1,0), (1,1), (0,1) in (m1, m2)
-        const int o1[3] = {m1 == 0, m1 == 1, m1 == 2}, o2[3] = {m2 == 0, m2 == 1, m2 == 2};
-        acc.add_at(l, b, 0, 0, 0, F * ((1.0 - u1) * (1.0 - u2) + x));
-        acc.add_at(l, b, o1[0], o1[1], o1[2], F * (u1 * (1.0 - u2) - x));
-        acc.add_at(l, b, o1[0] | o2[0], o1[1] | o2[1], o1[2] | o2[2], F * (u1 * u2 + x));
-        acc.add_at(l, b, o2[0], o2[1], o2[2], F * ((1.0 - u1) * u2 - x));
-    }
-}
-
+// Current of the move g1 (cell c1) -> g2 (cell c2), grid units: the zigzag
+// splits it at the relay point gr (the crossed cell face on an axis whose
+// cell changes, the midpoint on the others) into segment A (g1 -> gr, in c1)
+// and segment B (gr -> g2, in c2); each carries the exact current of a
+// straight move inside its cell under linear weights, on the four edges of
+// each component.  Every lane runs the same code: when the move stays in
+// one cell, B's values ride on A's adds (12 adds instead of 24); otherwise
+// B adds on its own edges.  Lanes take a component's four edges in an order
+// rotated by the lane, so that lanes of one cell add to different edges at
+// once.
 template <class Acc>
 __device__ inline void deposit_move(const RunDev &R, const Acc &acc, const double g1[3], const int c1[3],
                                     const double g2[3], const int c2[3])
 {
-    // Same cell before and after: both zigzag halves (relay at the midpoint)
-    // deposit onto the same 12 edges; their values are formed exactly as for
-    // two segments and summed in registers, so one set of 12 adds is issued.
-    if (c1[0] == c2[0] && c1[1] == c2[1] && c1[2] == c2[2]) {
-        const auto b1c = acc.base(c1);
-        double d1[3], d2[3], W1[3], W2[3];
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            const double gm = fmin((double)c1[l] + 1.0, fmax((double)c1[l], 0.5 * (g1[l] + g2[l])));
-            d1[l] = gm - g1[l];
-            d2[l] = g2[l] - gm;
-            W1[l] = 0.5 * (g1[l] + gm) - (double)c1[l];
-            W2[l] = 0.5 * (gm + g2[l]) - (double)c1[l];
-        }
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
-            const double F1 = d1[l] * R.qvh_dt[l], F2 = d2[l] * R.qvh_dt[l];
-            const double x1 = d1[m1] * d1[m2] * (1.0 / 12.0), x2 = d2[m1] * d2[m2] * (1.0 / 12.0);
-            const double a1 = W1[m1], b1 = W1[m2], a2 = W2[m1], b2 = W2[m2];
-            // the four edges of component l: (0,0), (1,0), (1,1), (0,1) in
-            // (m1, m2); lanes take them in an order rotated by the lane, so
-            // that lanes of the same cell add to different edges at once
-            const double w[4] = {F1 * ((1.0 - a1) * (1.0 - b1) + x1) + F2 * ((1.0 - a2) * (1.0 - b2) + x2),
-                                 F1 * (a1 * (1.0 - b1) - x1) + F2 * (a2 * (1.0 - b2) - x2),
-                                 F1 * (a1 * b1 + x1) + F2 * (a2 * b2 + x2),
-                                 F1 * ((1.0 - a1) * b1 - x1) + F2 * ((1.0 - a2) * b2 - x2)};
-            const int rot = (int)(threadIdx.x & 3);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int q4 = (e + rot) & 3;
-                const int s1 = (q4 == 1 || q4 == 2) ? 1 : 0, s2 = (q4 >= 2) ? 1 : 0;
-                acc.add_at(l, b1c, (m1 == 0) ? s1 : ((m2 == 0) ? s2 : 0), (m1 == 1) ? s1 : ((m2 == 1) ? s2 : 0),
-                           (m1 == 2) ? s1 : ((m2 == 2) ? s2 : 0), w[q4]);
-            }
-        }
-        return;
-    }
     double gr[3];
     for (int l = 0; l < 3; ++l) {
         const double lo = (double)min(c1[l], c2[l]) + 1.0;
         const double hi = (double)max(c1[l], c2[l]);
         gr[l] = fmin(lo, fmax(hi, 0.5 * (g1[l] + g2[l])));
     }
-    segment_current(R, acc, g1, gr, c1);
-    segment_current(R, acc, gr, g2, c2);
+    const bool same = c1[0] == c2[0] && c1[1] == c2[1] && c1[2] == c2[2];
+    const auto b1 = acc.base(c1), b2 = acc.base(c2);
+    double dA[3], dB[3], WA[3], WB[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        dA[l] = gr[l] - g1[l];
+        dB[l] = g2[l] - gr[l];
+        WA[l] = 0.5 * (g1[l] + gr[l]) - (double)c1[l];
+        WB[l] = 0.5 * (gr[l] + g2[l]) - (double)c2[l];
+    }
+    const int rot = (int)(threadIdx.x & 3);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
+        // J_l = q (displacement in metres) / (dt V) times the edge weights
+        const double FA = dA[l] * R.qvh_dt[l], FB = dB[l] * R.qvh_dt[l];
+        const double xA = dA[m1] * dA[m2] * (1.0 / 12.0), xB = dB[m1] * dB[m2] * (1.0 / 12.0);
+        const double a1 = WA[m1], b1v = WA[m2], a2 = WB[m1], b2v = WB[m2];
+        const double wA[4] = {FA * ((1.0 - a1) * (1.0 - b1v) + xA), FA * (a1 * (1.0 - b1v) - xA), FA * (a1 * b1v + xA),
+                              FA * ((1.0 - a1) * b1v - xA)};
+        const double wB[4] = {FB * ((1.0 - a2) * (1.0 - b2v) + xB), FB * (a2 * (1.0 - b2v) - xB), FB * (a2 * b2v + xB),
+                              FB * ((1.0 - a2) * b2v - xB)};
+        // edges (0,0), (1,0), (1,1), (0,1) in (m1, m2)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int q4 = (e + rot) & 3;
+            const int s1 = (q4 == 1 || q4 == 2) ? 1 : 0, s2 = (q4 >= 2) ? 1 : 0;
+            acc.add_at(l, b1, (m1 == 0) ? s1 : ((m2 == 0) ? s2 : 0), (m1 == 1) ? s1 : ((m2 == 1) ? s2 : 0),
+                       (m1 == 2) ? s1 : ((m2 == 2) ? s2 : 0), same ? wA[q4] + wB[q4] : wA[q4]);
+        }
+        if (!same) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int q4 = (e + rot) & 3;
+                const int s1 = (q4 == 1 || q4 == 2) ? 1 : 0, s2 = (q4 >= 2) ? 1 : 0;
+                acc.add_at(l, b2, (m1 == 0) ? s1 : ((m2 == 0) ? s2 : 0), (m1 == 1) ? s1 : ((m2 == 1) ? s2 : 0),
+                           (m1 == 2) ? s1 : ((m2 == 2) ? s2 : 0), wB[q4]);
+            }
+        }
+    }
 }
 
 template <class Acc>
@@ -483,6 +466,15 @@ __device__ inline void deposit_charge(const RunDev &R, const Acc &acc, const dou
         const int I = q8 & 1, J = (q8 >> 1) & 1, K = q8 >> 2;
         acc.add_at(3, b, I, J, K, R.qV * wx[I] * wy[J] * wz[K]);
     }
+}
+
+// floor(n / d) for 0 <= n < 2^52 and d >= 1, from inv_d = 1 / d rounded to
+// FP64: (n + 1/2) / d lies at least 1/(2d) from an integer, and the two
+// roundings move it by less than 2.3e-16 (n + 1/2) / d, which is smaller
+// for every n here; three instructions instead of an integer division.
+__device__ inline int64_t small_div(int64_t n, double inv_d)
+{
+    return (int64_t)(((double)n + 0.5) * inv_d);
 }
 
 // Minimum / maximum over the 64 lanes of a wavefront (every lane active):
