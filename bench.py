@@ -6,6 +6,9 @@ deposit, bin + sort, radiated-power diagnostic): the FEL-amplifier
 configuration, 128 x 128 x 1024 nodes, 2^21 macro-electrons, helical
 undulator K = 1.4, gamma = 200, FP32 fields and sources, FP64 particles.
 Inputs are synthetic (seeded) and resident in HBM before timing starts.
+By default the timed steps are the whole 4000-step run after its first 20
+steps (which build the step graphs), timed in 500-step segments and in two
+phases: until the whole bunch is inside the undulator, and after.
 
 Prints one JSON line: cell-updates/s of the whole step (value), particle-
 steps/s, the sweep's HBM roofline, the per-stage times and the particle
@@ -14,7 +17,7 @@ run-latency percentiles of the small undulator run, the FP64 CPU oracle
 timed on a bounded sample (1 thread and all threads) and the error of the
 GPU run against that oracle after the same steps.
 
-    python bench.py [--gpus 1] [--steps 200] [--warmup 20]
+    python bench.py [--gpus 1] [--steps 3980] [--warmup 20]
 """
 from __future__ import annotations
 
@@ -35,8 +38,9 @@ FP64_PEAK_TFLOPS = 78.6
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=3980,
+                    help="timed steps (default: the rest of the 4000-step FEL-amplifier run)")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed steps after the load (graph builds)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--latency-runs", type=int, default=12)
@@ -619,25 +623,104 @@ def main():
     d = w.descriptor()
     d["sort_every"] = args.sort_every
     xyz, u, q = W.make_bunch(w)
-    eng = Engine(d, max_particles=len(xyz))
-    eng.load_bunch(xyz, u, q)
-    eng.step(args.warmup)
-    torch.cuda.synchronize()
-
-    # timed region: K whole steps (graph replay), inputs already in HBM
-    t0 = time.perf_counter()
-    eng.step(args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_step = elapsed * 1e3 / args.steps
-
-    # same run continued: K steps by direct launches with HIP events between
-    # the stages of every step, on the engine's stream
-    prof = eng.step_profile(args.steps)
-    stage_us = {k: v / args.steps * 1e3 for k, v in prof.items()}
-
-    f_occ = source_occupancy(eng, d)
+    # the entrance, moving at -beta0 c, has passed the bunch tail after
+    # `inside` steps: the two phases of the run are reported apart
+    inside = w.steps_bunch_inside()
     C = 4
+
+    def run_timed(desc, k, seg=500):
+        """Load, W untimed steps, then k graph-replayed steps timed in
+        segments (500 steps, and a cut where the bunch is inside); returns
+        the engine and [(first step, end step, seconds)]."""
+        e = Engine(desc, max_particles=len(xyz))
+        e.load_bunch(xyz, u, q)
+        e.step(args.warmup)
+        torch.cuda.synchronize()
+        end = args.warmup + k
+        cuts = set(range(args.warmup + seg, end, seg)) | {end}
+        if args.warmup < inside < end:
+            cuts.add(inside)
+        segs, at = [], args.warmup
+        t_prev = time.perf_counter()
+        for b in sorted(cuts):
+            e.step(b - at)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            segs.append((at, b, t - t_prev))
+            at, t_prev = b, t
+        return e, segs
+
+    def phases(segs):
+        n = sum(b - a for a, b, _ in segs)
+        tot = sum(t for _, _, t in segs)
+        out = {"elapsed_s": tot, "ms_per_step": tot * 1e3 / n}
+        for name, part in (("entrance_phase", [x for x in segs if x[1] <= inside]),
+                           ("inside_phase", [x for x in segs if x[0] >= inside])):
+            if part:
+                out[name] = {"steps": [part[0][0], part[-1][1]],
+                             "ms_per_step": sum(x[2] for x in part) * 1e3 / sum(x[1] - x[0] for x in part)}
+        merged = {}
+        for a, b, t in segs:
+            m = merged.setdefault(args.warmup + (a - args.warmup) // 500 * 500, [a, b, 0.0])
+            m[1] = b
+            m[2] += t
+        out["segments"] = [{"steps": [a, b], "ms_per_step": t * 1e3 / (b - a)} for a, b, t in merged.values()]
+        return out
+
+    def stages(desc, k):
+        """The same steps on a new engine, launched one by one with HIP
+        events between the stages; average microseconds per step."""
+        e = Engine(desc, max_particles=len(xyz))
+        e.load_bunch(xyz, u, q)
+        e.step(args.warmup)
+        torch.cuda.synchronize()
+        prof = e.step_profile(k)
+        torch.cuda.synchronize()
+        f = source_occupancy(e, desc)
+        e.close()
+        torch.cuda.empty_cache()
+        return {key: v / k * 1e3 for key, v in prof.items()}, f
+
+    # the same run with FP64 fields (the paper's precision)
+    d64 = W.config2(field_precision=64, compensated=0).descriptor()
+    d64["sort_every"] = args.sort_every
+    e64, segs64 = run_timed(d64, args.steps)
+    e64.close()
+    torch.cuda.empty_cache()
+    t64 = phases(segs64)
+    st64, f_occ64 = stages(d64, args.steps)
+    alg64 = C * 8 * (3.0 + f_occ64) * w.n_nodes
+    sw64 = st64["sweep"] * 1e-6
+    fp64 = {"ms_per_step": t64["ms_per_step"], "value": w.n_nodes * args.steps / t64["elapsed_s"],
+            "particle_steps_per_s": w.n_particles * args.steps / t64["elapsed_s"], "steps": args.steps,
+            "phases": {k: v for k, v in t64.items() if k.endswith("_phase")},
+            "stages_us": st64,
+            "roofline": {"bound": "hbm", "kernel": "NSFD sweep, FP64 words", "achieved": alg64 / sw64 / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg64 / sw64 / 1e9 / HBM_PEAK_GBS,
+                         "alg_bytes_per_launch": alg64, "f_occ": f_occ64, "avg_launch_us": sw64 * 1e6}}
+
+    lat = run_latency(args.latency_runs)
+
+    # the oracle on the host from the load, and the GPU stepped as far from
+    # the same inputs (a full-size oracle step takes seconds)
+    cpu = None
+    err = None
+    if not args.no_cpu_baseline:
+        cpu, ora, n_ora, bunch = cpu_baseline(w, args.cpu_seconds, args.sort_every)
+        err = error_vs_oracle(d, bunch, ora, n_ora)
+        ora.close()
+
+    # the headline: K steps from step W, graph-replayed; then the same steps
+    # on a new engine with events between the stages (the last FP32 steps
+    # of the process, so that a kernel trace takes both as its final window)
+    eng, segs = run_timed(d, args.steps)
+    eng.close()
+    torch.cuda.empty_cache()
+    timing = phases(segs)
+    elapsed = timing["elapsed_s"]
+    ms_step = timing["ms_per_step"]
+    stage_us, f_occ = stages(d, args.steps)
+
     alg_sweep = C * 4 * (3.0 + f_occ) * w.n_nodes          # bytes per sweep launch (FP32 words)
     alg_part = 96.0 * w.n_particles                         # FP64 r and u read and written
     flops_part = 600.0 * w.n_particles                      # estimated FP64 flops per particle-step
@@ -659,42 +742,6 @@ def main():
                            "alg_bytes_per_step": alg_sweep + alg_part,
                            "what": "sweep algorithmic bytes + 96 B per particle over the whole step"},
     }
-    del eng
-    torch.cuda.empty_cache()
-
-    # the same run with FP64 fields (the paper's precision)
-    d64 = W.config2(field_precision=64, compensated=0).descriptor()
-    d64["sort_every"] = args.sort_every
-    e64 = Engine(d64, max_particles=len(xyz))
-    e64.load_bunch(xyz, u, q)
-    e64.step(args.warmup)
-    torch.cuda.synchronize()
-    k64 = max(args.steps // 2, 1)
-    t0 = time.perf_counter()
-    e64.step(k64)
-    torch.cuda.synchronize()
-    el64 = time.perf_counter() - t0
-    prof64 = e64.step_profile(k64)
-    f_occ64 = source_occupancy(e64, d64)
-    alg64 = C * 8 * (3.0 + f_occ64) * w.n_nodes
-    sw64 = prof64["sweep"] / k64 * 1e-3
-    fp64 = {"ms_per_step": el64 * 1e3 / k64, "value": w.n_nodes * k64 / el64,
-            "particle_steps_per_s": w.n_particles * k64 / el64, "steps": k64,
-            "stages_us": {k: v / k64 * 1e3 for k, v in prof64.items()},
-            "roofline": {"bound": "hbm", "kernel": "NSFD sweep, FP64 words", "achieved": alg64 / sw64 / 1e9,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg64 / sw64 / 1e9 / HBM_PEAK_GBS,
-                         "alg_bytes_per_launch": alg64, "f_occ": f_occ64, "avg_launch_us": sw64 * 1e6}}
-    del e64
-    torch.cuda.empty_cache()
-
-    lat = run_latency(args.latency_runs)
-
-    cpu = None
-    err = None
-    if not args.no_cpu_baseline:
-        cpu, ora, n_ora, bunch = cpu_baseline(w, args.cpu_seconds, args.sort_every)
-        err = error_vs_oracle(d, bunch, ora, n_ora)
-        ora.close()
 
     out = {
         "metric": "cell-updates/s + particle-steps/s per GPU (% HBM roofline); p50/p99 run latency",
@@ -714,7 +761,7 @@ def main():
             "workload": "FEL amplifier: 128x128x1024 nodes, 2^21 macro-electrons, helical K=1.4, "
                         "gamma=200, FP32 fields and sources, FP64 particles, NSFD + Mur-2, space charge",
             "nodes": w.n_nodes, "particles": w.n_particles, "parallelism": "single GPU",
-            "sort_every": args.sort_every,
+            "sort_every": args.sort_every, "run_steps": w.steps, "timed_steps": [args.warmup, args.warmup + args.steps],
         },
         "roofline": {
             "bound": "hbm", "kernel": "NSFD sweep (A_x, A_y, A_z, phi)",
@@ -725,6 +772,8 @@ def main():
         },
         "rooflines": rooflines,
         "stages_us": stage_us,
+        "phases": {k: v for k, v in timing.items() if k.endswith("_phase")},
+        "segments": timing["segments"],
         "fp64": fp64,
         "latency": lat,
         "error_vs_oracle": err,

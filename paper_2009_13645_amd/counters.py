@@ -13,8 +13,17 @@ then
 
   python3 <repo>/paper_2009_13645_amd/counters.py push <dir_1> <dir_2> <dir_3> <dir_4>
 
-`run` executes the benchmark workload (FEL amplifier, FP32) for a few
-steps, then 10 launches of the sweep alone, then a plain device-to-device
+and for the kernel time of a benchmark run, one kernel trace, then
+
+  python3 <repo>/paper_2009_13645_amd/counters.py kstats <dir> <n_steps>
+
+which writes profiles/bench_fel_amplifier_fp32_kernel_stats.md: kernel
+time over the run's last n_steps FP32 steps (the bench's timed steps and
+its per-stage profile) beside the profiler's whole-process statistics.
+
+`run` executes the benchmark workload (FEL amplifier, FP32) until the
+whole bunch is inside the undulator and 20 steps more, as the benchmark
+times it, then 10 launches of the sweep alone, then a plain device-to-device
 copy of a known size (torch's copy kernel) used to calibrate what the
 counters read per byte.  `summarize` writes profiles/sweep_traffic.json
 (bytes per sweep launch, tagged with the hash of the sweep's source file)
@@ -44,7 +53,7 @@ def run():
     xyz, u, q = W.make_bunch(w)
     e = Engine(d, max_particles=len(xyz))
     e.load_bunch(xyz, u, q)
-    e.step(20)
+    e.step(w.steps_bunch_inside() + 20)
     torch.cuda.synchronize()
     e.time_sweep(-1, 10)
     torch.cuda.synchronize()
@@ -61,7 +70,8 @@ def _rows(d):
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not files:
         raise SystemExit(f"no counter_collection.csv under {d}")
-    with open(files[0]) as f:
+    # the newest file: a folder reused by several runs keeps the older ones
+    with open(max(files, key=os.path.getmtime)) as f:
         return list(csv.DictReader(f))
 
 
@@ -183,11 +193,63 @@ def summarize_push(dirs):
     print(json.dumps(rec))
 
 
+def kstats(trace_dir, n_steps):
+    """Kernel time over the last n_steps steps of the FEL amplifier in a
+    kernel trace of bench.py: the window opens at the n_steps-th last
+    dispatch of the FP32 sweep and holds every dispatch from there on."""
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_trace.csv under {trace_dir}")
+    with open(max(files, key=os.path.getmtime)) as f:
+        rows = list(csv.DictReader(f))
+    sweeps = sorted((r for r in rows if "SweepVec<float" in r["Kernel_Name"]), key=lambda r: int(r["Start_Timestamp"]))
+    if len(sweeps) < n_steps:
+        raise SystemExit(f"only {len(sweeps)} FP32 sweeps in the trace")
+    t_open = int(sweeps[-n_steps]["Start_Timestamp"])
+    win = {}
+    for r in rows:
+        if int(r["Start_Timestamp"]) < t_open:
+            continue
+        v = win.setdefault(r["Kernel_Name"], [0, 0.0])
+        v[0] += 1
+        v[1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+    tot = sum(v[1] for v in win.values())
+    L = ["# Kernel time of the benchmark's timed steps (FEL amplifier, FP32 fields, 128x128x1024 nodes, "
+         "2^21 e-, whole bunch inside the undulator)", "",
+         "Commands (from the repository root):", "",
+         "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- python3 -u bench.py "
+         "--steps 100 --warmup 10 --no-cpu-baseline --latency-runs 2 --no-full-run",
+         f"    python3 paper_2009_13645_amd/counters.py kstats <dir> {n_steps}", "",
+         f"Window: every dispatch from the {n_steps}-th last FP32 sweep on (the bench's {n_steps // 2} graph-replayed "
+         f"timed steps, then as many steps launched one by one with events between the stages).", "",
+         "| kernel | calls | average us | share |", "|---|---:|---:|---:|"]
+    for name, (n, t) in sorted(win.items(), key=lambda kv: -kv[1][1])[:14]:
+        L.append(f"| `{name[:90].replace('|', '/')}` | {n} | {t / n:.1f} | {100 * t / tot:.1f}% |")
+    L.append("")
+    L.append(f"Kernel time in the window: {tot / 1e3:.2f} ms over {n_steps} steps, {tot / n_steps:.1f} us per step.")
+    st = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if st:
+        with open(max(st, key=os.path.getmtime)) as f:
+            srows = sorted(csv.DictReader(f), key=lambda r: -float(r["TotalDurationNs"]))
+        stot = sum(float(r["TotalDurationNs"]) for r in srows)
+        L += ["", "The profiler's own statistics over the whole process (all legs of the bench: the FP32 steps "
+              "from the load, the FP64 run, the latency runs):", "",
+              "| kernel | calls | average us | share |", "|---|---:|---:|---:|"]
+        for r in srows[:14]:
+            L.append(f"| `{r['Name'][:90].replace('|', '/')}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{100 * float(r['TotalDurationNs']) / stot:.1f}% |")
+    with open(os.path.join(ROOT, "profiles", "bench_fel_amplifier_fp32_kernel_stats.md"), "w") as f:
+        f.write("\n".join(L) + "\n")
+    print("\n".join(L))
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "run":
         run()
     elif len(sys.argv) >= 6 and sys.argv[1] == "push":
         summarize_push(sys.argv[2:6])
+    elif len(sys.argv) >= 4 and sys.argv[1] == "kstats":
+        kstats(sys.argv[2], int(sys.argv[3]))
     elif len(sys.argv) >= 4 and sys.argv[1] == "summarize":
         summarize(sys.argv[2], sys.argv[3])
     else:

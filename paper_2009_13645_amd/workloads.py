@@ -130,6 +130,23 @@ class Workload:
         return self.center_z_cells + 4.0 * sz
 
     @property
+    def tail_z_cells(self) -> float:
+        sz = self.sigma_cells[2]
+        if self.bunch == "flattop":
+            return self.center_z_cells - 0.5 * self.flat_len_cells - 3.0 * self.cells_per_wavelength
+        return self.center_z_cells - 4.0 * sz
+
+    def steps_bunch_inside(self) -> int:
+        """NSFD steps (dt = dz/c) after which the undulator entrance, moving
+        at -beta0 c, lies two boosted periods behind the bunch tail.  Taking
+        the particles at rest makes it an upper bound on the steps until the
+        whole bunch is inside the undulator (they drift forward until they
+        enter)."""
+        z_tail = self.origin[2] + self.tail_z_cells * self.dz
+        dist = self.z_entrance - z_tail + 2.0 * self.lambda_u / self.gamma0
+        return int(math.ceil(dist / (self.beta0 * self.dz)))
+
+    @property
     def z_entrance(self) -> float:
         """Boosted-frame z of the undulator entrance at t = 0 (metres)."""
         z_head = self.origin[2] + self.head_z_cells * self.dz
