@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--workload", choices=["fel-amplifier", "batched-scan", "served-stream", "example1",
                                            "example1-convergence"],
                     default="fel-amplifier")
-    ap.add_argument("--sort-every", type=int, default=8,
+    ap.add_argument("--sort-every", type=int, default=16,
                     help="fel-amplifier: sort the particles after every N-th push (same on the oracle side)")
     ap.add_argument("--ex1-steps", type=int, default=16000, help="example1: field steps per run")
     ap.add_argument("--ex1-parity-steps", type=int, default=4, help="example1: oracle prefix steps")

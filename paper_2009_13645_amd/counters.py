@@ -49,7 +49,7 @@ def run():
     from paper_2009_13645_amd.engine import Engine
     w = W.config2(field_precision=32, compensated=0)
     d = w.descriptor()
-    d["sort_every"] = 8  # as the benchmark runs it
+    d["sort_every"] = 16  # as the benchmark runs it
     xyz, u, q = W.make_bunch(w)
     e = Engine(d, max_particles=len(xyz))
     e.load_bunch(xyz, u, q)

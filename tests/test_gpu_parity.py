@@ -81,7 +81,7 @@ def test_config1_fp64_parity_200_steps():
 
 
 @pytest.mark.parametrize("which,every,steps", [("tiny", 3, 200), ("tiny", 3, 202), ("small", 4, 41),
-                                                ("small", 4, 43), ("small", 8, 47)])
+                                                ("small", 4, 43), ("small", 8, 47), ("small", 16, 49)])
 def test_sort_every_few_steps_matches_the_oracle(which, every, steps):
     """Sorting after every few pushes only (the order kept in between) on
     both sides: fields, momenta, cells and the order itself, ending after a
