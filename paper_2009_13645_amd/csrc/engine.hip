@@ -37,7 +37,7 @@ hipError_t launch_plane_spectrum(const RunDev &R, hipStream_t st);
 hipError_t launch_spec_reduce(const RunDev &R, double *out, hipStream_t st);
 hipError_t launch_seed_inject(const RunDev &R, hipStream_t st);
 hipError_t launch_gen_bunch(const RunDev &R, const GenParams &P, int pass, double *zrange, hipStream_t st);
-hipError_t launch_push_deposit(const RunDev &R, hipStream_t st, bool box);
+hipError_t launch_push_deposit(const RunDev &R, hipStream_t st, bool box, bool end_step);
 hipError_t launch_load_deposit(const RunDev &R, hipStream_t st);
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st);
 hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int step_tail = 0);
@@ -60,7 +60,6 @@ int64_t power_blocks();
 hipError_t launch_power_group(const Group &g, int64_t total, const Group &gf, int64_t total_f, int precision,
                               hipStream_t st);
 hipError_t launch_vertex_power(const RunDev &R, hipStream_t st);
-hipError_t launch_power_final(const RunDev &R, hipStream_t st, int end_step);
 hipError_t launch_push_group(const Group &g, int64_t total, int precision, int compensated, hipStream_t st);
 hipError_t launch_box_group(const Group &g, int64_t total, hipStream_t st);
 hipError_t launch_sort_group(const Group &gs, int64_t total_s, const Group &gd, int64_t total_d, const Group &gp,
@@ -78,8 +77,6 @@ __device__ inline void book_end(Ctl *ctl, int advance)
     if (advance)
         ctl->step += 1;
 }
-
-__global__ void k_book_end(Ctl *ctl, int advance) { book_end(ctl, advance); }
 
 struct BookEnd {
     static constexpr int kThreads = 1;
@@ -633,17 +630,16 @@ static int enqueue_step_on(mithra_handle h, hipStream_t st, hipEvent_t *ev, int6
     if (R.nfreq > 0)
         HIPCHK(h, launch_plane_spectrum(R, st));
     HIPCHK(h, mark(3));
-    HIPCHK(h, launch_push_deposit(R, st, !sort_ends_step(R)));
+    // a small run's one-workgroup sort reduces the boxes and ends the step;
+    // otherwise the box reduction after the push ends it (the power of the
+    // step from the vertex launch's partial sums, then the bookkeeping), and
+    // the sort passes, when the step sorts, follow
+    const bool small = sort_ends_step(R);
+    HIPCHK(h, launch_push_deposit(R, st, !small, !small));
     HIPCHK(h, mark(4));
     if (step_sorts(h, s))
         HIPCHK(h, launch_sort(R, st, true, 1));
     HIPCHK(h, mark(5));
-    if (sort_ends_step(R))
-        ;  // the small sort ended the step
-    else if (R.record_power)
-        HIPCHK(h, launch_power_final(R, st, 1));  // sums the partials of the vertex launch; ends the step
-    else
-        hipLaunchKernelGGL(k_book_end, dim3(1), dim3(1), 0, st, R.ctl, 1);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, mark(6));
     return MITHRA_OK;

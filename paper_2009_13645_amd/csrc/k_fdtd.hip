@@ -1359,13 +1359,6 @@ hipError_t launch_vertex_power(const RunDev &R, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_power_final(const RunDev &R, hipStream_t st, int end_step)
-{
-    hipLaunchKernelGGL((k_run<PlanePowerFinal, int, double *, int>), dim3(1), dim3(64), 0, st, R, 0, (double *)nullptr,
-                       end_step);
-    return hipGetLastError();
-}
-
 hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStream_t st)
 {
     const int64_t blocks = vertex_blocks(R);

@@ -559,14 +559,17 @@ hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *pa
 
 int64_t dep_blocks(int64_t np) { return (np + kDepThreads - 1) / kDepThreads; }
 
-hipError_t launch_push_deposit(const RunDev &R, hipStream_t st, bool box)
+hipError_t launch_push_deposit(const RunDev &R, hipStream_t st, bool box, bool end_step)
 {
     hipError_t e = launch_dep<0>(R, st);
-    if (e != hipSuccess || R.np <= 0 || !box)  // !box: the small sort's workgroup reduces the boxes
+    if (e != hipSuccess || !box)  // !box: the small sort's workgroup reduces the boxes
         return e;
     // the boxes are written by a kernel that reads the step number on the
     // device, like every other stage
-    hipLaunchKernelGGL((k_run<BoxReduceStep>), dim3(1), dim3(BoxReduceStep::kThreads), 0, st, R);
+    if (end_step)
+        hipLaunchKernelGGL((k_run<BoxReduceEndStep>), dim3(1), dim3(BoxReduceEndStep::kThreads), 0, st, R);
+    else if (R.np > 0)
+        hipLaunchKernelGGL((k_run<BoxReduceStep>), dim3(1), dim3(BoxReduceStep::kThreads), 0, st, R);
     return hipGetLastError();
 }
 

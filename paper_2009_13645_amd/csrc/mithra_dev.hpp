@@ -513,4 +513,27 @@ struct BoxReduceStep {
     }
 };
 
+// The box reductions, then the end of the step: the step's radiated power
+// from the vertex launch's partial sums (when the run records it) and the
+// bookkeeping (particle buffer, step counter).  For a single run whose sort,
+// when the step has one, runs as separate pass kernels: those read the sort
+// range and the slots, not the step counter or the buffer index, so the
+// step may end before them and no launch follows the sort.  Grouped steps
+// keep the separate end: there a member on its last step skips the stages
+// that come after its step counter has reached the target.
+struct BoxReduceEndStep {
+    static constexpr int kThreads = 64;
+    static __device__ void run(const RunDev &R, Blk blk)
+    {
+        BoxReduceStep::run(R, blk);
+        if (R.record_power) {
+            plane_power_final(R, R.ctl->step, nullptr, 1);
+        } else if (threadIdx.x == 0) {
+            R.ctl->pbuf ^= 1;
+            R.ctl->nsort += 1;
+            R.ctl->step += 1;
+        }
+    }
+};
+
 }  // namespace mithra
