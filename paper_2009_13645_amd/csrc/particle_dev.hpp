@@ -337,13 +337,10 @@ struct GlobalAcc {
             }
         }
     }
-    // index of node (i, j, k) in one array; add_at takes a node's index
-    // and the offsets (0 or 1) of a corner along x, y, z
+    // index of node (i, j, k) in one array, the index steps along x, y, z,
+    // and the add at an index
     __device__ inline int64_t base(const int c[3]) const { return (int64_t)c[2] * nxy + (int64_t)c[1] * nx + c[0]; }
-    __device__ inline void add_at(int comp, int64_t b, int di, int dj, int dk, double v) const
-    {
-        add_idx(comp, b + di + (dj ? (int64_t)nx : 0) + (dk ? nxy : 0), v);
-    }
+    __device__ inline int64_t stride(int axis) const { return axis == 0 ? 1 : (axis == 1 ? (int64_t)nx : nxy); }
     __device__ inline void add_idx(int comp, int64_t idx, double v) const
     {
         if constexpr (sizeof(T) == 8) {
@@ -379,26 +376,33 @@ template <typename AccT = double>
 struct LdsAcc {
     AccT *s;
     int lo0, lo1, lo2, ex, ey, vol;
-    // index of node (i, j, k) in the box; add_at takes a node's index and the
-    // offsets (0 or 1) of a corner along x, y, z, so that a particle's adds
-    // need one multiply-add chain, not one per add
+    // index of node (i, j, k) in the box, the index steps along x, y, z,
+    // and the add at an index
     __device__ inline int base(const int c[3]) const { return ((c[2] - lo2) * ey + (c[1] - lo1)) * ex + (c[0] - lo0); }
-    __device__ inline void add_at(int comp, int b, int di, int dj, int dk, double v) const
-    {
-        atomicAdd(&s[comp * vol + b + di + (dj ? ex : 0) + (dk ? ex * ey : 0)], (AccT)v);
-    }
+    __device__ inline int stride(int axis) const { return axis == 0 ? 1 : (axis == 1 ? ex : ex * ey); }
+    __device__ inline void add_idx(int comp, int idx, double v) const { atomicAdd(&s[comp * vol + idx], (AccT)v); }
 };
+
+// Lane order of a particle's adds: lanes of one cell would add to the same
+// node at once, and same-address atomics serialize.  So the add that the
+// code issues as corner e goes, on lane l, to corner e XOR r (r = l mod 8
+// for the eight charge corners, l mod 4 for the four edges of a current
+// component): along each axis whose bit of r is set, the corner's two
+// weights and its two index offsets trade places.  A lane pays that once per
+// particle (a few selects), where an additive rotation picked the value and
+// the offsets of every add from all of them.
 
 // Current of the move g1 (cell c1) -> g2 (cell c2), grid units: the zigzag
 // splits it at the relay point gr (the crossed cell face on an axis whose
 // cell changes, the midpoint on the others) into segment A (g1 -> gr, in c1)
 // and segment B (gr -> g2, in c2); each carries the exact current of a
-// straight move inside its cell under linear weights, on the four edges of
-// each component.  Every lane runs the same code: when the move stays in
-// one cell, B's values ride on A's adds (12 adds instead of 24); otherwise
-// B adds on its own edges.  Lanes take a component's four edges in an order
-// rotated by the lane, so that lanes of one cell add to different edges at
-// once.
+// straight move inside its cell under linear weights.  For component l, the
+// edge at offsets (s1, s2) along the two other axes (m1, m2) gets
+// F (p1[s1] p2[s2] + x) when s1 == s2 and F (p1[s1] p2[s2] - x) otherwise,
+// with p[0] = 1 - u, p[1] = u (u: the segment's mean offset along that
+// axis), x = d_m1 d_m2 / 12 and F = q d_l / (dt V).  Every lane runs the
+// same code: when the move stays in one cell, B's values ride on A's adds
+// (12 adds instead of 24); otherwise B adds on its own edges.
 template <class Acc>
 __device__ inline void deposit_move(const RunDev &R, const Acc &acc, const double g1[3], const int c1[3],
                                     const double g2[3], const int c2[3])
@@ -410,6 +414,7 @@ __device__ inline void deposit_move(const RunDev &R, const Acc &acc, const doubl
         gr[l] = fmin(lo, fmax(hi, 0.5 * (g1[l] + g2[l])));
     }
     const bool same = c1[0] == c2[0] && c1[1] == c2[1] && c1[2] == c2[2];
+    const double sm = same ? 1.0 : 0.0;
     const auto b1 = acc.base(c1), b2 = acc.base(c2);
     double dA[3], dB[3], WA[3], WB[3];
 #pragma unroll
@@ -419,53 +424,61 @@ __device__ inline void deposit_move(const RunDev &R, const Acc &acc, const doubl
         WA[l] = 0.5 * (g1[l] + gr[l]) - (double)c1[l];
         WB[l] = 0.5 * (gr[l] + g2[l]) - (double)c2[l];
     }
-    const int rot = (int)(threadIdx.x & 3);
+    const bool r0 = (threadIdx.x & 1) != 0, r1 = (threadIdx.x & 2) != 0;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         const int m1 = (l + 1) % 3, m2 = (l + 2) % 3;
-        // J_l = q (displacement in metres) / (dt V) times the edge weights
         const double FA = dA[l] * R.qvh_dt[l], FB = dB[l] * R.qvh_dt[l];
-        const double xA = dA[m1] * dA[m2] * (1.0 / 12.0), xB = dB[m1] * dB[m2] * (1.0 / 12.0);
-        const double a1 = WA[m1], b1v = WA[m2], a2 = WB[m1], b2v = WB[m2];
-        const double wA[4] = {FA * ((1.0 - a1) * (1.0 - b1v) + xA), FA * (a1 * (1.0 - b1v) - xA), FA * (a1 * b1v + xA),
-                              FA * ((1.0 - a1) * b1v - xA)};
-        const double wB[4] = {FB * ((1.0 - a2) * (1.0 - b2v) + xB), FB * (a2 * (1.0 - b2v) - xB), FB * (a2 * b2v + xB),
-                              FB * ((1.0 - a2) * b2v - xB)};
-        // edges (0,0), (1,0), (1,1), (0,1) in (m1, m2)
+        // x with the sign of the edges whose issued offsets are equal
+        const double xA = (r0 == r1 ? 1.0 : -1.0) * (dA[m1] * dA[m2] * (1.0 / 12.0));
+        const double xB = (r0 == r1 ? 1.0 : -1.0) * (dB[m1] * dB[m2] * (1.0 / 12.0));
+        // p[e ^ r] for issued offset e
+        const double pA1[2] = {r0 ? WA[m1] : 1.0 - WA[m1], r0 ? 1.0 - WA[m1] : WA[m1]};
+        const double pA2[2] = {r1 ? WA[m2] : 1.0 - WA[m2], r1 ? 1.0 - WA[m2] : WA[m2]};
+        const double pB1[2] = {r0 ? WB[m1] : 1.0 - WB[m1], r0 ? 1.0 - WB[m1] : WB[m1]};
+        const double pB2[2] = {r1 ? WB[m2] : 1.0 - WB[m2], r1 ? 1.0 - WB[m2] : WB[m2]};
+        const auto st1 = acc.stride(m1), st2 = acc.stride(m2);
+        const decltype(st1) o1[2] = {r0 ? st1 : 0, r0 ? 0 : st1}, o2[2] = {r1 ? st2 : 0, r1 ? 0 : st2};
+        double wB[2][2];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int q4 = (e + rot) & 3;
-            const int s1 = (q4 == 1 || q4 == 2) ? 1 : 0, s2 = (q4 >= 2) ? 1 : 0;
-            acc.add_at(l, b1, (m1 == 0) ? s1 : ((m2 == 0) ? s2 : 0), (m1 == 1) ? s1 : ((m2 == 1) ? s2 : 0),
-                       (m1 == 2) ? s1 : ((m2 == 2) ? s2 : 0), same ? wA[q4] + wB[q4] : wA[q4]);
-        }
+        for (int e1 = 0; e1 < 2; ++e1)
+#pragma unroll
+            for (int e2 = 0; e2 < 2; ++e2) {
+                const double wA = FA * (pA1[e1] * pA2[e2] + (e1 == e2 ? xA : -xA));
+                wB[e1][e2] = FB * (pB1[e1] * pB2[e2] + (e1 == e2 ? xB : -xB));
+                acc.add_idx(l, b1 + o1[e1] + o2[e2], wA + sm * wB[e1][e2]);
+            }
         if (!same) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int q4 = (e + rot) & 3;
-                const int s1 = (q4 == 1 || q4 == 2) ? 1 : 0, s2 = (q4 >= 2) ? 1 : 0;
-                acc.add_at(l, b2, (m1 == 0) ? s1 : ((m2 == 0) ? s2 : 0), (m1 == 1) ? s1 : ((m2 == 1) ? s2 : 0),
-                           (m1 == 2) ? s1 : ((m2 == 2) ? s2 : 0), wB[q4]);
-            }
+            for (int e1 = 0; e1 < 2; ++e1)
+#pragma unroll
+                for (int e2 = 0; e2 < 2; ++e2)
+                    acc.add_idx(l, b2 + o1[e1] + o2[e2], wB[e1][e2]);
         }
     }
 }
 
+// Cloud-in-cell charge on the eight corners of cell c.
 template <class Acc>
 __device__ inline void deposit_charge(const RunDev &R, const Acc &acc, const double g[3], const int c[3])
 {
     const double dx = g[0] - c[0], dy = g[1] - c[1], dz = g[2] - c[2];
-    const double wx[2] = {1.0 - dx, dx}, wy[2] = {1.0 - dy, dy}, wz[2] = {1.0 - dz, dz};
-    // the eight corners in an order rotated by the lane (lanes of the same
-    // cell add to different nodes at once); each value is formed as before
-    const int rot = (int)(threadIdx.x & 7);
+    const bool r0 = (threadIdx.x & 1) != 0, r1 = (threadIdx.x & 2) != 0, r2 = (threadIdx.x & 4) != 0;
+    // weight and index offset of issued offset e along each axis: those of e ^ r
+    const double wx[2] = {r0 ? dx : 1.0 - dx, r0 ? 1.0 - dx : dx};
+    const double wy[2] = {r1 ? dy : 1.0 - dy, r1 ? 1.0 - dy : dy};
+    const double wz[2] = {r2 ? dz : 1.0 - dz, r2 ? 1.0 - dz : dz};
+    const auto sy = acc.stride(1), sz = acc.stride(2);
+    const decltype(sy) ox[2] = {r0 ? 1 : 0, r0 ? 0 : 1}, oy[2] = {r1 ? sy : 0, r1 ? 0 : sy},
+                       oz[2] = {r2 ? sz : 0, r2 ? 0 : sz};
     const auto b = acc.base(c);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int q8 = (e + rot) & 7;
-        const int I = q8 & 1, J = (q8 >> 1) & 1, K = q8 >> 2;
-        acc.add_at(3, b, I, J, K, R.qV * wx[I] * wy[J] * wz[K]);
-    }
+    for (int K = 0; K < 2; ++K)
+#pragma unroll
+        for (int J = 0; J < 2; ++J)
+#pragma unroll
+            for (int I = 0; I < 2; ++I)
+                acc.add_idx(3, b + ox[I] + oy[J] + oz[K], R.qV * wx[I] * wy[J] * wz[K]);
 }
 
 // floor(n / d) for 0 <= n < 2^52 and d >= 1, from inv_d = 1 / d rounded to
