@@ -8,7 +8,11 @@
 
 namespace mithra {
 
-constexpr int kLdsNodes = 1536;  // node box capacity of the LDS stage (4 arrays, FP64: 48 KiB)
+// node box capacity of the LDS stage (4 arrays, FP64: 51.6 KiB): the most
+// that lets three workgroups share a CU's 160 KiB of LDS (1536 nodes: the
+// widest phase of the FEL amplifier's envelope ran 195 against 186 us, its
+// blocks' boxes overflowing more often)
+constexpr int kLdsNodes = 1650;
 
 // Gather + undulator + N_b Boris sub-steps + deposit (MODE 0), or the load
 // deposit of the backward-drift move (MODE 1, set 0).  Rank p handles the
