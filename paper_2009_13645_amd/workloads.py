@@ -403,7 +403,7 @@ def config4_runs(n_runs: int = 64, base_seed: int = 4000, steps_cap: Optional[in
     N_p ~ U[1e4, 5e5], gamma ~ U[50, 300], K ~ U[0.5, 2.0], planar,
     40 periods, Gaussian sigma = (n_x/16, n_y/16, n_z/32) cells, precision
     FP64-all or FP32 fields with probability 1/2, steps ~ U{500, ..., 3000};
-    particles sorted after every fourth push.
+    particles sorted after every 16th push.
     `scale` < 1 shrinks particle counts (used by CPU-side tests).
     """
     runs = []
@@ -425,7 +425,7 @@ def config4_runs(n_runs: int = 64, base_seed: int = 4000, steps_cap: Optional[in
                      steps=steps, n_particles=npart, charge_C=1e-12,
                      bunch="gaussian", sigma_cells=(nx / 16.0, ny / 16.0, nz / 32.0),
                      sigma_gamma_rel=1e-4, seed=base_seed + r, field_precision=prec,
-                     tile=(8, 8, 8), sort_every=4)
+                     tile=(8, 8, 8), sort_every=16)
         runs.append(w)
     return runs
 
