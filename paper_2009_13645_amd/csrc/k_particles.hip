@@ -223,19 +223,14 @@ struct PushDeposit {
             sync();
             const double ibx = 1.0 / (double)bx, iby = 1.0 / (double)by;
             for (int e = first; e < bv; e += stride) {
-                const int jk = (int)small_div((int64_t)e, ibx), i = e - jk * bx;
-                const int k = (int)small_div((int64_t)jk, iby), j = jk - k * by;
+                const int jk = small_div(e, ibx), i = e - jk * bx;
+                const int k = small_div(jk, iby), j = jk - k * by;
                 double v[4];
-                int idx[4][4];
     #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 4; ++q)
                     v[q] = (double)base[q * bv + e];
-                    idx[q][0] = q;
-                    idx[q][1] = B0 + i;
-                    idx[q][2] = B1 + j;
-                    idx[q][3] = B2 + k;
-                }
-                gacc.add4(v, idx);
+                const int c[3] = {B0 + i, B1 + j, B2 + k};
+                gacc.add4(v, gacc.base(c));
             }
         };
         if (vol <= kLdsNodes) {

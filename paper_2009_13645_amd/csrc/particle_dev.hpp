@@ -299,24 +299,22 @@ struct GlobalAcc {
     int64_t nn;
     int nx;
     int64_t nxy;
-    // four independent adds (zeros skipped); in the compensated mode all the
-    // returning adds are issued before their errors are added
-    __device__ inline void add4(const double v[4], const int idx[4][4]) const
+    // the four components of node `at` (one index for all four: each add is
+    // one address add from its array's start); zeros skipped; in the
+    // compensated mode all the returning adds are issued before their errors
+    // are added
+    __device__ inline void add4(const double v[4], int64_t at) const
     {
-        int64_t at[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            at[q] = (int64_t)idx[q][3] * nxy + (int64_t)idx[q][2] * nx + idx[q][1];
         if constexpr (sizeof(T) == 8) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (v[q] != 0.0)
-                    atomicAdd(reinterpret_cast<double *>(A0) + idx[q][0] * nn + at[q], v[q]);
+                    atomicAdd(reinterpret_cast<double *>(A0) + q * nn + at, v[q]);
         } else if (!COMP) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (v[q] != 0.0)
-                    atomicAdd(reinterpret_cast<float *>(A0) + idx[q][0] * nn + at[q], (float)v[q]);
+                    atomicAdd(reinterpret_cast<float *>(A0) + q * nn + at, (float)v[q]);
         } else {
             float vf[4], old[4];
 #pragma unroll
@@ -324,7 +322,7 @@ struct GlobalAcc {
                 vf[q] = (float)v[q];
                 old[q] = 0.0f;
                 if (v[q] != 0.0)
-                    old[q] = atomicAdd(reinterpret_cast<float *>(A0) + idx[q][0] * nn + at[q], vf[q]);
+                    old[q] = atomicAdd(reinterpret_cast<float *>(A0) + q * nn + at, vf[q]);
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -332,7 +330,7 @@ struct GlobalAcc {
                     const float sm = old[q] + vf[q];
                     const float bv = sm - old[q];
                     const float err = (old[q] - (sm - bv)) + (vf[q] - bv);
-                    atomicAdd(reinterpret_cast<float *>(Lo0) + idx[q][0] * nn + at[q], err + (float)(v[q] - (double)vf[q]));
+                    atomicAdd(reinterpret_cast<float *>(Lo0) + q * nn + at, err + (float)(v[q] - (double)vf[q]));
                 }
             }
         }
@@ -488,6 +486,12 @@ __device__ inline void deposit_charge(const RunDev &R, const Acc &acc, const dou
 __device__ inline int64_t small_div(int64_t n, double inv_d)
 {
     return (int64_t)(((double)n + 0.5) * inv_d);
+}
+
+// the same for 0 <= n < 2^31 in 32-bit registers (four instructions)
+__device__ inline int small_div(int n, double inv_d)
+{
+    return (int)(((double)n + 0.5) * inv_d);
 }
 
 // Minimum / maximum over the 64 lanes of a wavefront (every lane active):
