@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--ex1-length", type=float, default=5.5, help="example1-convergence: undulator length (m)")
     ap.add_argument("--requests", type=int, default=1000, help="served stream: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="served stream: Poisson arrival rate (1/s)")
-    ap.add_argument("--tick", type=int, default=50, help="batched scan / served stream: steps per tick")
+    ap.add_argument("--tick", type=int, default=48,
+                    help="batched scan / served stream: steps per tick (a multiple of the runs' sort interval)")
     return ap.parse_args()
 
 

@@ -1421,7 +1421,8 @@ struct mithra_batch_s {
     std::vector<SweepCls> sweep;
     GroupTab mur[2], mur_edge[2], vertex[2], power[2], power_final[2], push[3], one, sort_s, sort_d, sort_p;
     int max_passes = 0;
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr;         // one batched step
+    hipGraphExec_t graph_nosort = nullptr;  // the same without the sort passes (captured on first use)
     std::vector<int64_t> host_targets;
     std::string err;
 };
@@ -1572,7 +1573,7 @@ static int build_tables(mithra_batch b)
     return MITHRA_OK;
 }
 
-static int enqueue_batch_step(mithra_batch b, hipStream_t st)
+static int enqueue_batch_step(mithra_batch b, hipStream_t st, bool sort)
 {
     for (auto &c : b->sweep)
         BHIPCHK(b, launch_sweep_group(c.t.g, c.t.total, c.precision, c.comp, c.shape, st));
@@ -1584,8 +1585,9 @@ static int enqueue_batch_step(mithra_batch b, hipStream_t st)
     for (int ci = 0; ci < 3; ++ci)
         BHIPCHK(b, launch_push_group(b->push[ci].g, b->push[ci].total, ci == 0 ? 64 : 32, ci == 2, st));
     BHIPCHK(b, launch_box_group(b->one.g, b->one.total, st));
-    BHIPCHK(b, launch_sort_group(b->sort_s.g, b->sort_s.total, b->sort_d.g, b->sort_d.total, b->sort_p.g,
-                                 b->sort_p.total, b->max_passes, st));
+    if (sort)
+        BHIPCHK(b, launch_sort_group(b->sort_s.g, b->sort_s.total, b->sort_d.g, b->sort_d.total, b->sort_p.g,
+                                     b->sort_p.total, b->max_passes, st));
     for (int pi = 0; pi < 2; ++pi)
         BHIPCHK(b, launch_power_group(b->power[pi].g, b->power[pi].total, b->power_final[pi].g,
                                       b->power_final[pi].total, pi == 0 ? 32 : 64, st));
@@ -1594,15 +1596,16 @@ static int enqueue_batch_step(mithra_batch b, hipStream_t st)
     return MITHRA_OK;
 }
 
-static int build_batch_graph(mithra_batch b)
+static int build_batch_graph(mithra_batch b, bool sort = true)
 {
+    hipGraphExec_t *out = sort ? &b->graph : &b->graph_nosort;
     hipStream_t cap = nullptr;
     BHIPCHK(b, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     int rc = MITHRA_OK;
     if (e == hipSuccess) {
-        rc = enqueue_batch_step(b, cap);
+        rc = enqueue_batch_step(b, cap, sort);
         e = hipStreamEndCapture(cap, &g);
     }
     (void)hipStreamDestroy(cap);
@@ -1613,7 +1616,7 @@ static int build_batch_graph(mithra_batch b)
     }
     if (e != hipSuccess)
         return bfail(b, MITHRA_EDEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess)
         return bfail(b, MITHRA_EDEVICE, "batch graph instantiate failed: %s", hipGetErrorString(e));
@@ -1757,10 +1760,11 @@ extern "C" int mithra_batch_autotune_sweep(mithra_batch b, int iters, int32_t *s
     if (!rc)
         rc = rebuild_tables(b);
     if (!rc) {
-        if (b->graph) {
-            (void)hipGraphExecDestroy(b->graph);
-            b->graph = nullptr;
-        }
+        for (hipGraphExec_t *gx : {&b->graph, &b->graph_nosort})
+            if (*gx) {
+                (void)hipGraphExecDestroy(*gx);
+                *gx = nullptr;
+            }
         rc = build_batch_graph(b);
     }
     if (rc)
@@ -1790,8 +1794,35 @@ extern "C" int mithra_batch_run(mithra_batch b, const int64_t *n_steps)
         b->host_targets[i] = h->steps + n_steps[i];
         BHIPCHK(b, hipMemcpy(&h->R.ctl->target, &b->host_targets[i], sizeof(int64_t), hipMemcpyHostToDevice));
     }
-    for (int64_t k = 0; k < most; ++k)
-        BHIPCHK(b, hipGraphLaunch(b->graph, b->stream));
+    // When every member that steps in this call sorts after the same pushes
+    // (one sort interval, one step phase), the steps after which none sorts
+    // replay the graph without the sort passes; otherwise every step carries
+    // them and a member whose step does not sort skips them on the device.
+    int se = 0;
+    int64_t phase = -1;
+    bool uniform = true;
+    for (size_t i = 0; i < n; ++i) {
+        if (n_steps[i] == 0)
+            continue;
+        const int e = b->runs[i]->R.sort_every > 1 ? b->runs[i]->R.sort_every : 1;
+        const int64_t p = b->runs[i]->steps % e;
+        if (phase < 0) {
+            se = e;
+            phase = p;
+        } else if (e != se || p != phase) {
+            uniform = false;
+        }
+    }
+    uniform = uniform && se > 1;
+    if (uniform && !b->graph_nosort) {
+        const int rc = build_batch_graph(b, false);
+        if (rc)
+            return rc;
+    }
+    for (int64_t k = 0; k < most; ++k) {
+        const bool sorts = !uniform || (phase + k + 1) % se == 0;
+        BHIPCHK(b, hipGraphLaunch(sorts ? b->graph : b->graph_nosort, b->stream));
+    }
     for (size_t i = 0; i < n; ++i)
         b->runs[i]->steps += n_steps[i];
     return MITHRA_OK;
@@ -1821,6 +1852,8 @@ extern "C" int mithra_batch_destroy(mithra_batch b)
     }
     if (b->graph)
         (void)hipGraphExecDestroy(b->graph);
+    if (b->graph_nosort)
+        (void)hipGraphExecDestroy(b->graph_nosort);
     delete b;
     return MITHRA_OK;
 }

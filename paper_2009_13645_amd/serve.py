@@ -72,6 +72,9 @@ class Server:
     cap_bytes: admission limit on the sum of active arena sizes.
     max_active: slot limit (runs per batch).
     tick_steps: steps per tick (the granularity of admission and retirement).
+        A multiple of the runs' sort interval keeps every member's sorts on
+        the same steps (members join at tick boundaries), so the batch
+        replays its step without the sort passes on the other steps.
     autotune: pick each run's sweep tile shape with the library's autotuner
         (runs timed alone), until the batch-level tuner has chosen a shape
         for the run's precision class.
@@ -81,7 +84,7 @@ class Server:
         while the device works on a tick (0: drawn at admission).
     """
 
-    def __init__(self, cap_bytes: float = 250e9, max_active: int = 64, tick_steps: int = 50,
+    def __init__(self, cap_bytes: float = 250e9, max_active: int = 64, tick_steps: int = 48,
                  autotune: bool = True, device: str = "cuda:0", clock: Optional[Callable[[], float]] = None,
                  backend=None, tune_min: int = 16, prepare_workers: int = 2):
         if backend is None:
