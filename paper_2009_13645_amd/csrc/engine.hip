@@ -1412,6 +1412,10 @@ struct GroupTab {
 struct mithra_batch_s {
     std::vector<mithra_handle> runs;
     hipStream_t stream = nullptr;
+    // the FP64 members' stages run on a second stream (fork and join by
+    // events), beside the FP32 members' stages on the batch stream
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0, ws_used = 0;
     struct SweepCls {
@@ -1573,24 +1577,49 @@ static int build_tables(mithra_batch b)
     return MITHRA_OK;
 }
 
+// One batched step.  The members of the two precisions share no memory, so
+// their stages up to the push form two independent chains: the FP64
+// members' on the side stream, the FP32 members' on st; each chain's
+// grouped launches then fill the tails of the other's.  The box reductions,
+// the sort and the bookkeeping run over all members after the join.
+static void batch_free_streams(mithra_batch b)
+{
+    if (b->side)
+        (void)hipStreamDestroy(b->side);
+    if (b->fork)
+        (void)hipEventDestroy(b->fork);
+    if (b->join)
+        (void)hipEventDestroy(b->join);
+    b->side = nullptr;
+    b->fork = b->join = nullptr;
+}
+
 static int enqueue_batch_step(mithra_batch b, hipStream_t st, bool sort)
 {
-    for (auto &c : b->sweep)
-        BHIPCHK(b, launch_sweep_group(c.t.g, c.t.total, c.precision, c.comp, c.shape, st));
-    for (int pi = 0; pi < 2; ++pi)
-        BHIPCHK(b, launch_mur_group(b->mur[pi].g, b->mur[pi].total, b->mur_edge[pi].g, b->mur_edge[pi].total,
-                                    pi == 0 ? 32 : 64, st));
-    for (int pi = 0; pi < 2; ++pi)
-        BHIPCHK(b, launch_vertex_group(b->vertex[pi].g, b->vertex[pi].total, pi == 0 ? 32 : 64, st));
-    for (int ci = 0; ci < 3; ++ci)
-        BHIPCHK(b, launch_push_group(b->push[ci].g, b->push[ci].total, ci == 0 ? 64 : 32, ci == 2, st));
+    BHIPCHK(b, hipEventRecord(b->fork, st));
+    BHIPCHK(b, hipStreamWaitEvent(b->side, b->fork, 0));
+    for (int chain = 0; chain < 2; ++chain) {
+        hipStream_t cs = chain == 0 ? b->side : st;
+        const int prec = chain == 0 ? 64 : 32, pi = chain == 0 ? 1 : 0;
+        for (auto &c : b->sweep)
+            if (c.precision == prec)
+                BHIPCHK(b, launch_sweep_group(c.t.g, c.t.total, c.precision, c.comp, c.shape, cs));
+        BHIPCHK(b, launch_mur_group(b->mur[pi].g, b->mur[pi].total, b->mur_edge[pi].g, b->mur_edge[pi].total, prec,
+                                    cs));
+        BHIPCHK(b, launch_vertex_group(b->vertex[pi].g, b->vertex[pi].total, prec, cs));
+        // the plane power reads the potentials of this step only
+        BHIPCHK(b, launch_power_group(b->power[pi].g, b->power[pi].total, b->power_final[pi].g,
+                                      b->power_final[pi].total, prec, cs));
+        for (int ci = 0; ci < 3; ++ci)
+            if ((ci == 0) == (chain == 0))
+                BHIPCHK(b, launch_push_group(b->push[ci].g, b->push[ci].total, ci == 0 ? 64 : 32, ci == 2, cs));
+    }
+    BHIPCHK(b, hipEventRecord(b->join, b->side));
+    BHIPCHK(b, hipStreamWaitEvent(st, b->join, 0));
     BHIPCHK(b, launch_box_group(b->one.g, b->one.total, st));
     if (sort)
         BHIPCHK(b, launch_sort_group(b->sort_s.g, b->sort_s.total, b->sort_d.g, b->sort_d.total, b->sort_p.g,
                                      b->sort_p.total, b->max_passes, st));
-    for (int pi = 0; pi < 2; ++pi)
-        BHIPCHK(b, launch_power_group(b->power[pi].g, b->power[pi].total, b->power_final[pi].g,
-                                      b->power_final[pi].total, pi == 0 ? 32 : 64, st));
     hipLaunchKernelGGL((k_group<BookEnd>), dim3((unsigned)b->one.total), dim3(1), 0, st, b->one.g);
     BHIPCHK(b, hipGetLastError());
     return MITHRA_OK;
@@ -1646,10 +1675,18 @@ extern "C" int mithra_batch_create(const mithra_handle *runs, int32_t n_runs, vo
     mithra_batch b = new mithra_batch_s;
     b->runs.assign(runs, runs + n_runs);
     b->stream = (hipStream_t)hip_stream;
+    if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess) {
+        batch_free_streams(b);
+        delete b;
+        return MITHRA_EDEVICE;
+    }
     b->ws = (char *)dev_workspace;
     b->ws_bytes = workspace_bytes;
     for (auto h : b->runs) {
         if (hipStreamSynchronize(h->stream) != hipSuccess) {
+            batch_free_streams(b);
             delete b;
             return MITHRA_EDEVICE;
         }
@@ -1660,6 +1697,7 @@ extern "C" int mithra_batch_create(const mithra_handle *runs, int32_t n_runs, vo
     if (rc) {
         if (b->graph)
             (void)hipGraphExecDestroy(b->graph);
+        batch_free_streams(b);
         delete b;
         return rc;
     }
@@ -1854,6 +1892,7 @@ extern "C" int mithra_batch_destroy(mithra_batch b)
         (void)hipGraphExecDestroy(b->graph);
     if (b->graph_nosort)
         (void)hipGraphExecDestroy(b->graph_nosort);
+    batch_free_streams(b);
     delete b;
     return MITHRA_OK;
 }
