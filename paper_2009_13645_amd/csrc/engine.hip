@@ -45,8 +45,7 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int ste
 // ends the step after it, in one workgroup, when this holds
 bool sort_ends_step(const RunDev &R);
 hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
-                             int32_t *count, hipStream_t st, int32_t *zero);
-hipError_t launch_box_reduce_set(const RunDev &R, int64_t nblocks, hipStream_t st);
+                             int32_t *count, hipStream_t st);
 int64_t sweep_blocks(const RunDev &R, int shape);
 hipError_t launch_sweep_group(const Group &g, int64_t total, int precision, int compensated, int shape,
                               hipStream_t st);
@@ -101,7 +100,7 @@ static const int kPartials = 8192;  // per-block partial slots (>= persistent bl
 static const int kBunchBlocks = 256;
 
 struct Layout {
-    size_t ctl, pot, src, src_lo, eb, spec, pr, pid, key_in, slot_in, cell_by_id, key_sorted, sk, sv, hist, boxpart,
+    size_t ctl, pot, src, src_lo, eb, spec, pr, pid, key_in, slot_in, cell_by_id, sk, sv, hist, boxpart,
         boxslot, ppart, power, scratch, tile_flag, srow, ntiles, total;
 };
 
@@ -130,7 +129,6 @@ static Layout make_layout(const mithra_grid_desc *d, int64_t cap)
     L.key_in = take(c * 4);
     L.slot_in = take(c * 4);
     L.cell_by_id = take(c * 4);
-    L.key_sorted = take(c * 4);
     L.sk = take(2 * c * 4);
     L.sv = take(2 * c * 4);
     L.hist = take((256 * (size_t)sort_blocks((int64_t)c) + 256) * 4);
@@ -431,7 +429,6 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     R.key_in = (uint32_t *)(A + L.key_in);
     R.slot_in = (int32_t *)(A + L.slot_in);
     h->cell_by_id = (int32_t *)(A + L.cell_by_id);
-    R.key_sorted = (uint32_t *)(A + L.key_sorted);
     R.tile_flag = (uint32_t *)(A + L.tile_flag);
     R.srow_lo = (int32_t *)(A + L.srow);
     R.srow_hi = R.srow_lo + 2 * (size_t)d->ny * d->nz;

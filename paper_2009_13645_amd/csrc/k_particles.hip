@@ -466,11 +466,8 @@ static hipError_t launch_dep(const RunDev &R, hipStream_t st)
 
 // Reduce the per-block partial boxes (and counts) of `nblocks` blocks into
 // lo/hi (and *count if non-null): one block, fixed order.
-__device__ inline void box_reduce_blk(const int32_t *part, int64_t nblocks, int32_t *lo, int32_t *hi, int32_t *count,
-                                      int32_t *zero)
+__device__ inline void box_reduce_blk(const int32_t *part, int64_t nblocks, int32_t *lo, int32_t *hi, int32_t *count)
 {
-    if (zero && threadIdx.x == 0)
-        *zero = 0;
     __shared__ int32_t sh[7][1024];
     int32_t v[7] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1, 0};
     for (int64_t b = threadIdx.x; b < nblocks; b += 1024) {
@@ -505,54 +502,15 @@ __device__ inline void box_reduce_blk(const int32_t *part, int64_t nblocks, int3
 }
 
 __global__ __launch_bounds__(1024) void k_box_reduce(const int32_t *part, int64_t nblocks, int32_t *lo, int32_t *hi,
-                                                    int32_t *count, int32_t *zero)
+                                                    int32_t *count)
 {
-    box_reduce_blk(part, nblocks, lo, hi, count, zero);
-}
-
-struct BoxReduceSet {
-    static constexpr int kThreads = 1024;
-    static __device__ void run(const RunDev &R, Blk blk, int64_t nblocks_arg)
-    {
-        const int64_t nblocks = nblocks_arg < 0 ? dep_blocks_dev(R.np) : nblocks_arg;
-        const int set = (int)((R.ctl->step + 1) & 1);
-        __shared__ int32_t sh[6][1024];
-        int32_t v[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
-        for (int64_t b = threadIdx.x; b < nblocks; b += 1024) {
-            const int32_t *q = R.boxpart + 8 * b;
-            for (int a = 0; a < 3; ++a) {
-                v[a] = min(v[a], q[a]);
-                v[3 + a] = max(v[3 + a], q[3 + a]);
-            }
-        }
-        for (int a = 0; a < 6; ++a)
-            sh[a][threadIdx.x] = v[a];
-        __syncthreads();
-        for (int w = 512; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w)
-                for (int a = 0; a < 3; ++a) {
-                    sh[a][threadIdx.x] = min(sh[a][threadIdx.x], sh[a][threadIdx.x + w]);
-                    sh[3 + a][threadIdx.x] = max(sh[3 + a][threadIdx.x], sh[3 + a][threadIdx.x + w]);
-                }
-            __syncthreads();
-        }
-        if (threadIdx.x < 3) {
-            R.ctl->dep_lo[set][threadIdx.x] = sh[threadIdx.x][0];
-            R.ctl->dep_hi[set][threadIdx.x] = sh[3 + threadIdx.x][0];
-        }
-    }
-};
-
-hipError_t launch_box_reduce_set(const RunDev &R, int64_t nblocks, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_run<BoxReduceSet, int64_t>), dim3(1), dim3(1024), 0, st, R, nblocks);
-    return hipGetLastError();
+    box_reduce_blk(part, nblocks, lo, hi, count);
 }
 
 hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
-                             int32_t *count, hipStream_t st, int32_t *zero)
+                             int32_t *count, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_box_reduce, dim3(1), dim3(1024), 0, st, part, nblocks, lo, hi, count, zero);
+    hipLaunchKernelGGL(k_box_reduce, dim3(1), dim3(1024), 0, st, part, nblocks, lo, hi, count);
     return hipGetLastError();
 }
 
@@ -578,7 +536,7 @@ hipError_t launch_load_deposit(const RunDev &R, hipStream_t st)
     if (e != hipSuccess)
         return e;
     return launch_box_reduce(R, dep_blocks(R.np), R.boxpart, CTL_ADDR(R.ctl, dep_lo), CTL_ADDR(R.ctl, dep_hi), nullptr,
-                             st, nullptr);
+                             st);
 }
 
 hipError_t launch_bunching(const RunDev &R, double *part, int blocks, hipStream_t st)

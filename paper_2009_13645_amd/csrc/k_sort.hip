@@ -519,7 +519,7 @@ struct RadixScatterRun {
 // ---------------------------------------------------------------------------
 
 hipError_t launch_box_reduce(const RunDev &R, int64_t nblocks, const int32_t *part, int32_t *lo, int32_t *hi,
-                             int32_t *count, hipStream_t st, int32_t *zero);
+                             int32_t *count, hipStream_t st);
 
 int sort_passes(uint32_t key_inactive) { return sort_passes_of(key_inactive); }
 
@@ -538,7 +538,7 @@ hipError_t launch_sort(const RunDev &R, hipStream_t st, bool keys_ready, int ste
         hipLaunchKernelGGL(k_sort_keys, dim3(pblocks), dim3(256), 0, st, R);
     if (!keys_ready) {
         hipError_t e = launch_box_reduce(R, pblocks, R.boxpart, CTL_ADDR(R.ctl, cell_lo), CTL_ADDR(R.ctl, cell_hi),
-                                         CTL_ADDR(R.ctl, n_active), st, CTL_ADDR(R.ctl, n_items));
+                                         CTL_ADDR(R.ctl, n_active), st);
         if (e != hipSuccess)
             return e;
         hipLaunchKernelGGL((k_run<SortRange>), dim3(1), dim3(1), 0, st, R);

@@ -32,11 +32,7 @@ struct Ctl {
     int32_t cell_lo[3];    // bounding box of active particle cells at the last sort
     int32_t cell_hi[3];
     int32_t nan_flag;      // set when a diagnostic sees a non-finite value
-    int32_t n_active;      // particles in active cells at the last sort
-    int32_t sorted_active; // n_active of the sort the current push works on
-    int32_t n_items;       // tile work items built after the last sort
-    int32_t item_next;     // next work item to take (persistent push)
-    int32_t pad_;
+    int32_t n_active;      // particles in active cells after the last push (or the load)
     int64_t target;        // step count at which a batched run stops (grouped launches only)
     uint32_t key_base;     // sort keys of the current sort are offset by this (active keys >= it)
     uint32_t key_span;     // active keys lie in [key_base, key_base + key_span); inactive sort as key_span
@@ -122,7 +118,6 @@ struct RunDev {
     int32_t *pid[2];
     uint32_t *key_in;     // sort input: key of rank p of the previous order
     int32_t *slot_in;     // sort input: the slot that holds it
-    uint32_t *key_sorted;
     uint32_t *tile_flag;  // per sort tile: the step whose vertex fields the tile's particles gather
     // per source set and (z plane, y row), [2][nz][ny]: the x range of nodes
     // whose sources the last deposit into the set may have made nonzero,
@@ -505,7 +500,6 @@ struct BoxReduceStep {
                     c->cell_hi[a] = v[3 + a] - 1;
                 }
                 c->n_active = v[12];
-                c->n_items = 0;
                 sort_range(R, true);  // the offset and pass count of this step's sort
             }
         }
