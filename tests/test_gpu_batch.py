@@ -88,6 +88,36 @@ def test_batch_equals_solo_runs_over_two_calls():
     batched[0][0].step(1)
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+def test_single_precision_batch_equals_solo_runs(prec):
+    """A batch whose members all have one precision (one of the step graph's
+    two precision branches is empty), over the steps after which no member
+    sorts (the sort-free graph) and a sort step."""
+    from paper_2009_13645_amd.engine import Batch
+    runs = W.config4_runs(2, base_seed=4100, scale=0.03)
+    for w in runs:
+        w.field_precision, w.compensated = prec, 0
+    n = 20  # the recipe sorts after every 16th push
+    batched = [make(w) for w in runs]
+    b = Batch([e for e, _, _ in batched])
+    b.run([n, n])
+    b.sync()
+    for (e, d, _), w in zip(batched, runs):
+        s, _, _ = make(w)
+        s.step(n)
+        worst = {f: rel_l2(e.read_field(f), s.read_field(f)) for f in FIELDS}
+        print(f"[batch] single precision FP{prec} {w.name}:", {k: f"{v:.1e}" for k, v in worst.items()}, flush=True)
+        for k, v in worst.items():
+            assert v < tol(w), (w.name, k, v)
+        xb, ub, cb, pb = e.read_particles()
+        xs, us, cs, ps = s.read_particles()
+        assert rel_l2(ub, us) < tol(w)
+        if prec == 64:
+            assert int(np.sum(cb != cs)) == 0 and int(np.sum(pb != ps)) == 0
+        s.close()
+    b.close()
+
+
 def test_batched_fp64_members_match_the_oracle():
     from paper_2009_13645_amd.engine import Batch
     runs = [w for w in members() if w.field_precision == 64][:2]
