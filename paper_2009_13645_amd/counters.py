@@ -19,7 +19,14 @@ and for the kernel time of a benchmark run, one kernel trace, then
 
 which writes profiles/bench_fel_amplifier_fp32_kernel_stats.md: kernel
 time over the run's last n_steps FP32 steps (the bench's timed steps and
-its per-stage profile) beside the profiler's whole-process statistics.
+its per-stage profile) beside the profiler's whole-process statistics;
+and for the batched scan, one kernel trace of
+`bench.py --workload batched-scan`, then
+
+  python3 <repo>/paper_2009_13645_amd/counters.py bstats <dir>
+
+which writes profiles/bench_batched_scan_kernel_stats.md: kernel time of
+the grouped launches from the batch's first push on (the timed scan).
 
 `run` executes the benchmark workload (FEL amplifier, FP32) until the
 whole bunch is inside the undulator and 20 steps more, as the benchmark
@@ -243,11 +250,74 @@ def kstats(trace_dir, n_steps):
     print("\n".join(L))
 
 
+def bstats(trace_dir):
+    """Kernel time of the batched scan in a kernel trace of bench.py
+    --workload batched-scan: every dispatch from the first grouped push on
+    (the batch-level sweep tuner before it launches sweeps and boundaries
+    only; the runs stepped alone come before the batch is created)."""
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_trace.csv under {trace_dir}")
+    with open(max(files, key=os.path.getmtime)) as f:
+        rows = list(csv.DictReader(f))
+    pushes = [int(r["Start_Timestamp"]) for r in rows
+              if "k_group" in r["Kernel_Name"] and "PushDeposit" in r["Kernel_Name"]]
+    if not pushes:
+        raise SystemExit("no grouped push in the trace")
+    t_open = min(pushes)
+    win, t_end = {}, t_open
+    for r in rows:
+        t0 = int(r["Start_Timestamp"])
+        if t0 < t_open:
+            continue
+        t_end = max(t_end, int(r["End_Timestamp"]))
+        v = win.setdefault(r["Kernel_Name"], [0, 0.0])
+        v[0] += 1
+        v[1] += (int(r["End_Timestamp"]) - t0) * 1e-3
+    tot = sum(v[1] for v in win.values())
+    span = (t_end - t_open) * 1e-3
+    n_push = sum(v[0] for k, v in win.items() if "PushDeposit" in k)
+    L = ["# Kernel time of the batched scan (64 uneven runs as one batch, grouped launches in captured graphs)", "",
+         "Commands (from the repository root):", "",
+         "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bscan -- python3 -u bench.py "
+         "--workload batched-scan",
+         "    python3 paper_2009_13645_amd/counters.py bstats <dir>", "",
+         "Window: every dispatch from the batch's first grouped push to the end of the scan. Grouped launches "
+         "are split by kernel variant (precision, compensation, sweep shape), so one batched step holds one "
+         "launch per variant and stage; the FP64 and FP32 members run as two graph branches, so their kernels "
+         "overlap and the shares are of summed kernel time, not of wall time.", "",
+         "| kernel | calls | average us | share |", "|---|---:|---:|---:|"]
+    groups = {}
+    for name, (n, t) in sorted(win.items(), key=lambda kv: -kv[1][1]):
+        if len(L) < 40:
+            L.append(f"| `{name[:110].replace('|', '/')}` | {n} | {t / n:.1f} | {100 * t / tot:.1f}% |")
+        low = name.lower()
+        for stage, keys in (("sweep", ("sweep",)), ("push and deposit", ("pushdeposit",)), ("Mur", ("mur",)),
+                            ("vertex fields", ("vertex",)), ("power", ("power",)),
+                            ("sort", ("radix", "digit", "sort")), ("box reduction", ("box",)),
+                            ("bookkeeping", ("book",))):
+            if any(k in low for k in keys):
+                groups[stage] = groups.get(stage, 0.0) + t
+                break
+        else:
+            groups["other"] = groups.get("other", 0.0) + t
+    L += ["", f"Summed kernel time {tot / 1e3:.1f} ms; first grouped push to last kernel end {span / 1e3:.1f} ms "
+              f"({n_push} grouped push launches).", "",
+          "| stage | summed kernel time ms | share |", "|---|---:|---:|"]
+    for k, t in sorted(groups.items(), key=lambda kv: -kv[1]):
+        L.append(f"| {k} | {t / 1e3:.1f} | {100 * t / tot:.1f}% |")
+    with open(os.path.join(ROOT, "profiles", "bench_batched_scan_kernel_stats.md"), "w") as f:
+        f.write("\n".join(L) + "\n")
+    print("\n".join(L))
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "run":
         run()
     elif len(sys.argv) >= 6 and sys.argv[1] == "push":
         summarize_push(sys.argv[2:6])
+    elif len(sys.argv) >= 3 and sys.argv[1] == "bstats":
+        bstats(sys.argv[2])
     elif len(sys.argv) >= 4 and sys.argv[1] == "kstats":
         kstats(sys.argv[2], int(sys.argv[3]))
     elif len(sys.argv) >= 4 and sys.argv[1] == "summarize":

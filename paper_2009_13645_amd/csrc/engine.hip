@@ -53,7 +53,7 @@ int64_t mur_blocks(const RunDev &R);
 int64_t mur_edge_blocks(const RunDev &R);
 hipError_t launch_mur_group(const Group &g, int64_t total, const Group &ge, int64_t total_e, int precision,
                             hipStream_t st);
-int64_t vertex_blocks(const RunDev &R);
+int64_t vertex_group_blocks(const RunDev &R);
 hipError_t launch_vertex_group(const Group &g, int64_t total, int precision, hipStream_t st);
 int64_t power_blocks();
 hipError_t launch_power_group(const Group &g, int64_t total, const Group &gf, int64_t total_f, int precision,
@@ -1539,7 +1539,7 @@ static int build_tables(mithra_batch b)
         if (!rc)
             rc = make_tab(b, mem, [](const RunDev &R) { return mur_edge_blocks(R); }, &b->mur_edge[pi]);
         if (!rc)
-            rc = make_tab(b, mem, [](const RunDev &R) { return vertex_blocks(R); }, &b->vertex[pi]);
+            rc = make_tab(b, mem, [](const RunDev &R) { return vertex_group_blocks(R); }, &b->vertex[pi]);
         if (!rc)
             rc = make_tab(b, memp, [](const RunDev &) { return power_blocks(); }, &b->power[pi]);
         if (!rc)
