@@ -598,7 +598,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+        print("bench.py: the benchmark runs on one GPU only; --gpus must be 1 "
               "(multi-GPU sharding is a design note, not a benchmark here)", file=sys.stderr)
         sys.exit(2)
 
