@@ -194,7 +194,10 @@ int mithra_adapt_mesh(mithra_grid_desc *d, double bunch_time_step, int32_t *chan
  * FD; dt_b = dt/n_sub), the update coefficients (eqs. NSFDCoefficient and
  * updateEquation) and the Mur coefficients (sec. "Boundary Truncation"),
  * carve `dev_arena` and zero the fields.  `hip_stream` is a hipStream_t (NULL = default
- * stream).  On success *out is a new handle.  Errors: EINVAL (bad
+ * stream).  On success *out is a new handle.  On an error *out is a
+ * handle that holds only the message (read it with `mithra_last_error`,
+ * then pass it to `mithra_destroy`), or NULL when `out` itself is
+ * NULL.  Errors: EINVAL (bad
  * descriptor: sizes, NSFD condition, precision, tiles, key range),
  * ENOMEM (arena_bytes < footprint or misaligned), EDEVICE. */
 int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size_t arena_bytes,

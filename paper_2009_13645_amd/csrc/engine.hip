@@ -315,6 +315,9 @@ extern "C" int mithra_init_grid(const mithra_grid_desc *d, void *dev_arena, size
     }
     h->arena = (char *)dev_arena;
     h->stream = (hipStream_t)hip_stream;
+    // from here on a failure returns the handle too, so that its message
+    // can be read; the caller destroys it
+    *out = h;
     const char *env = getenv("MITHRA_NO_GRAPH");
     h->use_graph = (env && env[0] == '1') ? 0 : 1;
 

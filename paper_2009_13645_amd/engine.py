@@ -89,6 +89,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2009_13645_amd.build` (no CPU fallback exists)")
+        # torch first: its HIP runtime must be in the process before the
+        # library binds its own HIP dependency.  Loaded before torch, the
+        # library's HIP calls failed with "no ROCm-capable device is
+        # detected" on a machine with a GPU (footprint_bytes, host code
+        # only, can be the first call of a program).
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         H = C.c_void_p
         dp = C.POINTER(C.c_double)

@@ -77,6 +77,23 @@ def test_small_arena_is_enomem_and_null_handle_calls_fail():
     assert E.lib().mithra_last_error(None) == b"null handle"
 
 
+def test_library_loads_after_torch_whatever_the_first_call():
+    """A program whose first call is host-only (footprint_bytes) still gets
+    torch, and with it torch's HIP runtime, into the process before the
+    library is loaded (loaded first, the library's HIP calls found no
+    device)."""
+    import subprocess
+    import sys
+    code = ("import sys\n"
+            "from paper_2009_13645_amd import engine as E, workloads as W\n"
+            "assert 'torch' not in sys.modules\n"
+            "w = W.config1()\n"
+            "assert E.footprint_bytes(w.descriptor(), w.n_particles) > 0\n"
+            "assert 'torch' in sys.modules\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+
+
 def test_batch_workspace_and_argument_checks_without_device():
     L = E.lib()
     assert L.mithra_batch_workspace_bytes(0) == 0
