@@ -53,7 +53,7 @@ int64_t mur_blocks(const RunDev &R);
 int64_t mur_edge_blocks(const RunDev &R);
 hipError_t launch_mur_group(const Group &g, int64_t total, const Group &ge, int64_t total_e, int precision,
                             hipStream_t st);
-int64_t vertex_group_blocks(const RunDev &R);
+int64_t vertex_blocks(const RunDev &R);
 hipError_t launch_vertex_group(const Group &g, int64_t total, int precision, hipStream_t st);
 int64_t power_blocks();
 hipError_t launch_power_group(const Group &g, int64_t total, const Group &gf, int64_t total_f, int precision,
@@ -1403,6 +1403,19 @@ extern "C" int mithra_autotune_sweep(mithra_handle h, int iters, int *best_shape
 // batched step is captured into a graph.  Each member stops at its own
 // target step: its kernels return at once after that, so runs of different
 // lengths share the replays.
+
+// Workgroups of a member in a grouped vertex-field launch: an eighth of the
+// single run's count.  A member's particle box is a small part of its grid
+// (the grid holds the radiation around the bunch), and the workgroups past
+// the box find no node to do and return, but in a launch over many members
+// they fill the dispatch and the CU slots that the working ones wait for.
+// The grid-stride loop still covers a box as large as the grid (eight nodes
+// per thread then).
+static int64_t vertex_group_blocks(const RunDev &R)
+{
+    const int64_t b = vertex_blocks(R) / 8;
+    return b < 1 ? 1 : b;
+}
 
 struct GroupTab {
     Group g{};

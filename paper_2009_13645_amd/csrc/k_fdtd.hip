@@ -1349,19 +1349,6 @@ hipError_t launch_mur(const RunDev &R, hipStream_t st)
 // workgroups of the vertex fields (a grid-stride loop over the box)
 int64_t vertex_blocks(const RunDev &R) { return vertex_blocks_of(R); }
 
-// Workgroups of a member in a grouped vertex-field launch: an eighth of the
-// single run's count.  A member's particle box is a small part of its grid
-// (the grid holds the radiation around the bunch), and the workgroups past
-// the box find no node to do and return, but in a launch over many members
-// they fill the dispatch and the CU slots that the working ones wait for.
-// The grid-stride loop still covers a box as large as the grid (eight
-// nodes per thread then).
-int64_t vertex_group_blocks(const RunDev &R)
-{
-    const int64_t b = vertex_blocks_of(R) / 8;
-    return b < 1 ? 1 : b;
-}
-
 hipError_t launch_vertex_power(const RunDev &R, hipStream_t st)
 {
     const int64_t blocks = vertex_blocks_of(R) + kPowerBlocks;
