@@ -225,7 +225,7 @@ def kstats(trace_dir, n_steps):
          "2^21 e-, whole bunch inside the undulator)", "",
          "Commands (from the repository root):", "",
          "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o bench -- python3 -u bench.py "
-         "--steps 100 --warmup 10 --no-cpu-baseline --latency-runs 2 --no-full-run",
+         "--no-cpu-baseline --latency-runs 2",
          f"    python3 paper_2009_13645_amd/counters.py kstats <dir> {n_steps}", "",
          f"Window: every dispatch from the {n_steps}-th last FP32 sweep on (the bench's {n_steps // 2} graph-replayed "
          f"timed steps, then as many steps launched one by one with events between the stages).", "",

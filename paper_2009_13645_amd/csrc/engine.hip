@@ -24,12 +24,14 @@
 
 #include "mithra.h"
 #include "mithra_dev.hpp"
+#include "mur_dev.hpp"
 
 namespace mithra {
 hipError_t launch_sweep(const RunDev &R, int shape, hipStream_t st);
 int sweep_shape_count();
 void sweep_shape_dims(int shape, int *tx, int *ty, int *tz);
 hipError_t launch_mur(const RunDev &R, hipStream_t st);
+hipError_t launch_mur_faces(const RunDev &R, hipStream_t st);
 int sweep_fuses_xfaces(const RunDev &R, int shape);
 hipError_t launch_vertex_fields(const RunDev &R, int step_bias, int full, hipStream_t st);
 hipError_t launch_plane_power(const RunDev &R, int step_bias, int kp, double *out, hipStream_t st, int end_step = 0);
@@ -619,7 +621,10 @@ static int enqueue_step_on(mithra_handle h, hipStream_t st, hipEvent_t *ev, int6
     if (R.seed_on)  // before Mur: the boundary kernel reads the corrected planes
         HIPCHK(h, launch_seed_inject(R, st));
     HIPCHK(h, mark(1));
-    HIPCHK(h, launch_mur(R, st));
+    if (push_carries_mur_edges(R))  // the push launch runs the edge workgroups
+        HIPCHK(h, launch_mur_faces(R, st));
+    else
+        HIPCHK(h, launch_mur(R, st));
     HIPCHK(h, mark(2));
     // no mid-step bookkeeping: the box reductions after the push rewrite the
     // deposit box, the active-cell box and the active count whole
