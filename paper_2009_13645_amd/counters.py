@@ -162,7 +162,7 @@ def summarize_push(dirs):
     for f in srcs:
         h.update(open(f, "rb").read())
     rec = {
-        "kernel": "PushDeposit<float, false, 0> (gather + helical undulator + Boris + deposit; FEL amplifier, "
+        "kernel": "PushDeposit<float, false, 0> with the Mur edge workgroups at the end of its launch (gather + helical undulator + Boris + deposit; FEL amplifier, "
                   "2^21 e-, FP32 fields)",
         "counters_per_launch": vals,
         "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
