@@ -1,23 +1,24 @@
 // k_fdtd.hip -- field kernels of the boosted-frame PIC step.
 //
-//  * k_sweep: NSFD update of A_x, A_y, A_z and phi at interior nodes
-//    (MITHRA 2.0 manual, sec. "FDTD for Wave Equation", eqs. NSFDtrick and
-//    updateEquation; sec. "FDTD for Scalar Potential").  HBM-bound 15-point
-//    stencil: each thread owns one (i,j) column of a TX x TY tile and marches
-//    along z with a register queue of psi^n(k-1..k+1); the z-averaged value
-//    psi-bar of every column (plus a one-column halo ring) goes through a
-//    double-buffered LDS plane, so psi^n is read from HBM about once.  The
-//    source of the step (node-averaged edge current, or rho) is read only
-//    inside the bounding box of the last deposit.
-//  * k_mur: Mur absorbing boundaries (sec. "Boundary Truncation"), one
-//    thread per boundary node, in two launches.  Faces use the printed
-//    first/second-order updates with permuted axes; further workgroups of
-//    the face launch clear the other source set inside its own box for the
-//    coming deposit.  Then edges and corners solve the sum of the first-order
-//    conditions of their faces discretised at the centre of the 2x2 (2x2x2)
-//    node stencil, reading the new face values (a corner recomputes its edge
-//    neighbours).  Three time levels make all reads race-free.
-//  * k_vertex_fields: E and B at vertices (sec. "Field Evaluation"):
+//  * Sweep / SweepVec: NSFD update of A_x, A_y, A_z and phi at interior
+//    nodes (MITHRA 2.0 manual, sec. "FDTD for Wave Equation", eqs. NSFDtrick
+//    and updateEquation; sec. "FDTD for Scalar Potential").  HBM-bound
+//    15-point stencil: each thread owns one (i,j) column of a TX x TY tile
+//    and marches along z with a register queue of psi^n(k-1..k+1); the
+//    z-averaged value psi-bar of every column (plus a one-column halo ring)
+//    goes through a double-buffered LDS plane, so psi^n is read from HBM
+//    about once.  The source of the step (node-averaged edge current, or
+//    rho) is read only inside the bounding box of the last deposit.
+//  * Mur: Mur absorbing boundaries (sec. "Boundary Truncation"), one thread
+//    per boundary face node.  Faces use the printed first/second-order
+//    updates with permuted axes; further workgroups of the face launch clear
+//    the other source set inside its own box for the coming deposit.  Edges
+//    and corners (MurEdge, mur_dev.hpp) follow in a later launch: they solve
+//    the sum of the first-order conditions of their faces discretised at the
+//    centre of the 2x2 (2x2x2) node stencil, reading the new face values (a
+//    corner recomputes its edge neighbours).  Three time levels make all
+//    reads race-free.
+//  * VertexFields: E and B at vertices (sec. "Field Evaluation"):
 //    E = -(A^{n+1} - A^n)/dt - grad phi, B = mean of curl A^n and curl A^{n+1}.
 #include "mithra_dev.hpp"
 #include "mur_dev.hpp"
