@@ -495,6 +495,42 @@ def test_straight_move_inside_a_cell_matches_line_integral_current():
         assert np.count_nonzero(J) == 4
 
 
+def test_zigzag_current_jumps_when_the_end_point_crosses_a_face():
+    """The zigzag split (sec. "Current Deposition") puts the relay point at
+    the midpoint of a move that stays in its cell, but on the face (along the
+    crossing axis) for a move that crosses it.  The deposited current is
+    therefore discontinuous in the end point: a move ending just inside a
+    face and the same move ending just past it differ by the current of a
+    small loop, while the cloud-in-cell charge is continuous.  A particle
+    that ends a step within rounding distance of a face can so deposit
+    either current; FP64 runs of the GPU path meet this after about a
+    thousand steps of the FEL amplifier, when rounding differences have
+    moved the positions by about 1e-10 cells."""
+    d = small_desc(nx=12, ny=12, nz=12, z_entrance=10.0)
+    h = np.array([d["dx"], d["dy"], d["dz"]])
+    org = np.array([d["x0"], d["y0"], d["z0"]])
+    u = np.array([0.9, -0.6, 0.5])
+    q = -3e-15
+
+    def deposit(x_end):
+        o = Oracle(d)
+        r2 = org + np.array([x_end, 6.38, 4.61]) * h
+        o.load_bunch(r2[None, :], u[None, :], q)
+        out = {f: o.field(f).copy() for f in ("Jx", "Jy", "Jz", "Q")}
+        o.close()
+        return out
+
+    eps = 1e-9
+    inside, inside2, past = deposit(6.0 - eps), deposit(6.0 - 2 * eps), deposit(6.0 + eps)
+    jmax = max(np.abs(inside[f]).max() for f in ("Jx", "Jy", "Jz"))
+    jump = max(np.abs(past[f] - inside[f]).max() for f in ("Jx", "Jy", "Jz"))
+    drift = max(np.abs(inside2[f] - inside[f]).max() for f in ("Jx", "Jy", "Jz"))
+    assert jump > 1e-3 * jmax          # a finite jump across the face
+    assert drift < 1e-6 * jmax         # continuous on one side of it
+    qmax = np.abs(inside["Q"]).max()
+    assert np.abs(past["Q"] - inside["Q"]).max() < 1e-6 * qmax
+
+
 def test_particle_at_rest_deposits_no_current():
     d = small_desc(nx=12, ny=12, nz=12, z_entrance=10.0)
     o = Oracle(d)
