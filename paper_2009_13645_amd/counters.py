@@ -28,6 +28,13 @@ and for the batched scan, one kernel trace of
 which writes profiles/bench_batched_scan_kernel_stats.md: kernel time of
 the grouped launches from the batch's first push on (the timed scan).
 
+and for the manual's Example 1, from bench.py's output lines and power
+histories,
+
+  python3 <repo>/paper_2009_13645_amd/counters.py ex1 <example1.json> <hist.npz> [<convergence.json> <conv_hist.npz>]
+
+which writes profiles/example1_gain_curve.md (and example1_convergence.md).
+
 `run` executes the benchmark workload (FEL amplifier, FP32) until the
 whole bunch is inside the undulator and 20 steps more, as the benchmark
 times it, then 10 launches of the sweep alone, then a plain device-to-device
@@ -311,11 +318,84 @@ def bstats(trace_dir):
     print("\n".join(L))
 
 
+def ex1(j_path, h_path, c_path=None, cz_path=None):
+    """Example 1 summaries from bench.py's JSON lines and power histories:
+    profiles/example1_gain_curve.md (the three 8 m runs, gain-length fits,
+    yardsticks, the oracle prefix parity, the power table) and, given the
+    convergence run's line and histories, profiles/example1_convergence.md."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    j = json.loads(open(j_path).read().strip().splitlines()[-1])
+    h = np.load(h_path)
+    g0 = float(h["gamma0"]); b0 = float(h["beta0"])
+    names = ("NSFD", "FD", "NSFD box")
+    fits = {}
+    for n in names:
+        dt = float(h["dt_" + n]); fits[n] = bench._gain_fit(h[n], dt, g0, b0, 0.03 / (g0 * b0) / (299792458.0 * dt))
+    y = j["yardsticks"]; par = j["oracle_prefix_parity"]
+    L = ["# Example 1 (infrared FEL) on the GPU: gain curves", "",
+         "Commands (from the repository root):", "", "    python3 bench.py --workload example1 --ex1-history <hist.npz> > <example1.json>",
+         "    python3 paper_2009_13645_amd/counters.py ex1 <example1.json> <hist.npz>", "",
+         "64 x 64 x 2800 nodes (lab mesh 50 x 50 x 0.1 um, boosted dz = gamma0 x 0.1 um), 131072 macro-electrons generated on the device (Halton quiet start, uniform 100.5 um along z with tapers, b_f = 0.01 at the bunching wavenumber, energy spread 1e-4), 29.5 pC, planar K = 1.417, 3 cm period, gamma = 100.41, Mur-2, no space charge, FP64 fields and particles, 16000 field steps (8 m). Power: lab-frame Poynting flux through the plane 110 um (lab) ahead of the bunch centre, averaged over one radiation period, against z = gamma0 beta0 c t.", "",
+         "Transverse profile: 'Gaussian' follows the job file (the manual: MITHRA's transverse distributions are always Gaussian and sigma-position is their rms, 260 um; the job's 4-sigma truncation and 3.2 mm mesh fit this); 'box' is the uniform 260 x 260 um box whose N / volume is the table's 2.72e13 cm^-3.", "",
+         "| | NSFD, Gaussian | FD, Gaussian | NSFD, box |", "|---|---:|---:|---:|"]
+    def row(t, f): L.append(f"| {t} | " + " | ".join(f(n) for n in names) + " |")
+    row("ms per step", lambda n: f"{j['runs'][n]['ms_per_step']:.3f}")
+    row("gain length, steepest 0.4 m (m)", lambda n: f"{fits[n]['gain_length_m']:.3f} (z {fits[n]['steepest_window']['z_m'][0]:.2f}-{fits[n]['steepest_window']['z_m'][1]:.2f})")
+    row("first power maximum (MW at m)", lambda n: f"{fits[n]['p_first_peak_W']/1e6:.2f} at {fits[n]['z_first_peak_m']:.2f}")
+    row("largest power in 8 m (MW at m)", lambda n: f"{fits[n]['p_max_W']/1e6:.2f} at {fits[n]['z_max_m']:.2f}")
+    row("bunching factor at 8 m", lambda n: f"{j['runs'][n]['bunching_end']:.3f}")
+    row("lab gamma, start -> 8 m", lambda n: f"{j['runs'][n]['lab_gamma_start']:.3f} -> {j['runs'][n]['lab_gamma_end']:.3f}")
+    xg = y["xie_3d"]; xb = y["xie_3d_box"]
+    dz = 100 * (fits['FD']['z_first_peak_m'] - fits['NSFD']['z_first_peak_m'])
+    L += ["", "Yardsticks:", "",
+          f"- the manual: MITHRA 0.22 m and \"2.6 GW\"; its table: 1-D gain length 0.224 m from rho = 0.006, with the electron density N / (sigma_x sigma_y L) = 2.72e13 cm^-3 (2 pi above the Gaussian beam's peak density), and \"2.7 GW\" printed for rho P_beam, which is 0.006 x {y['p_beam_W']/1e9:.2f} GW = {y['manual_rho_times_p_beam_W']/1e6:.1f} MW;",
+          f"- Xie's 3-D fit (a_w = K/sqrt 2): Gaussian beam, on-axis density: rho_1D = {xg['rho_1d']:.4f}, gain length {xg['gain_length_3d_m']:.3f} m, saturation {xg['p_sat_3d_W']/1e6:.1f} MW; box beam: rho_1D = {xb['rho_1d']:.4f}, {xb['gain_length_3d_m']:.3f} m, {xb['p_sat_3d_W']/1e6:.1f} MW.", "",
+          f"With the job file's beam the gain length is {fits['NSFD']['gain_length_m']:.2f} m, {100*(fits['NSFD']['gain_length_m']/xg['gain_length_3d_m']-1):+.0f}% against Xie's estimate for that beam and {fits['NSFD']['gain_length_m']/0.22:.1f}x the manual's 0.22 m; with the table's box density it is {fits['NSFD box']['gain_length_m']:.3f} m ({100*(fits['NSFD box']['gain_length_m']/0.22-1):+.0f}% against 0.22 m). NSFD and FD agree: FD {100*(fits['FD']['gain_length_m']/fits['NSFD']['gain_length_m']-1):+.0f}% in gain length, first maximum {abs(dz):.0f} cm {'later' if dz > 0 else 'earlier'}.", "",
+          f"Oracle prefix parity (the Gaussian NSFD run, same device-generated bunch, {par['steps']} steps, FP64; each component against the norm of its vector field): positions {par['bunch_max_dz_cells']:.1e} cells; A {max(par[k] for k in par if k.startswith('rel_l2_A')):.1e}, J {max(par[k] for k in par if k.startswith('rel_l2_J')):.1e}, rho {par['rel_l2_Q']:.1e}, E {max(par[k] for k in par if k.startswith('rel_l2_E')):.1e}, B {max(par[k] for k in par if k.startswith('rel_l2_B')):.1e}, momenta {par['rel_l2_u']:.1e} (relative L2).", "",
+          "Power (MW, one-period average):", "", "| z (m) | NSFD, Gaussian | FD, Gaussian | NSFD, box |", "|---:|---:|---:|---:|"]
+    for zz in np.arange(0.5, 8.01, 0.5):
+        vals = [np.interp(zz, np.array(fits[n]["curve_z_m"]), np.array(fits[n]["curve_P_W"])) / 1e6 for n in names]
+        L.append(f"| {zz:.1f} | " + " | ".join(f"{v:.4g}" for v in vals) + " |")
+    open(os.path.join(ROOT, "profiles", "example1_gain_curve.md"), "w").write("\n".join(L) + "\n")
+    # convergence
+    if c_path:
+        c = json.loads(open(c_path).read().strip().splitlines()[-1])
+        cz = np.load(cz_path)
+        M = ["# Example 1 convergence study on the GPU (the manual's error of eq. errorDefinition)", "",
+             "Commands (from the repository root):", "", "    python3 bench.py --workload example1-convergence --ex1-history <conv_hist.npz> > <convergence.json>",
+             "    python3 paper_2009_13645_amd/counters.py ex1 <example1.json> <hist.npz> <convergence.json> <conv_hist.npz>", "",
+             "Each row runs Example 1 (the job file's Gaussian beam, NSFD, Mur-2, FP64, device-generated bunch with b_f = 0.01, sorted every push) to 5.5 m of undulator with one numerical parameter changed from the job file's value. error = integral of |P - P_0| over integral of P_0 along the 5 m undulator, P_0 being the finer run's power (one-period average at the plane 110 um ahead of the bunch centre). The last row compares two space-charge runs. Gain length: steepest 0.4 m of ln P after the entrance transient.", "",
+             "| run | nodes | particles | n_sub | ms/step | gain length (m) | first power maximum (MW at m) | error against the job's values |",
+             "|---|---|---:|---:|---:|---:|---:|---:|"]
+        for k, v in c["runs"].items():
+            if k == "space charge, l_z 380 um":
+                errs = f"{c['error']['space charge, l_z 380 um vs space charge']:.3f} (against the space-charge run)"
+            else:
+                e = c["error"].get(k); errs = "reference" if e is None else f"{e:.3f}"
+            key = k.replace(" ", "_").replace("/", "over")
+            z = cz[key + "_z"]; P = cz[key + "_P"]
+            lp = np.log(np.maximum(P, 1e-300)); dz_ = z[1] - z[0]; m = int(round(0.4 / dz_))
+            ipk = int(np.argmax(P[: np.searchsorted(z, 5.4)]))
+            st = np.nonzero(P[:ipk] > 1e-3 * P[ipk])[0]; a0 = int(st[0]) if len(st) else 0
+            best = 0.0
+            for a in range(a0, max(ipk - m, a0), max(m // 8, 1)):
+                best = max(best, np.polyfit(z[a:a + m], lp[a:a + m], 1)[0])
+            lg = 1 / best if best > 0 else float("nan")
+            M.append(f"| {k} | {'x'.join(map(str, v['nodes']))} | {v['particles']} | {v['n_sub']} | {v['ms_per_step']:.3f} | {lg:.3f} | {P[ipk]/1e6:.2f} at {z[ipk]:.2f} | {errs} |")
+        open(os.path.join(ROOT, "profiles", "example1_convergence.md"), "w").write("\n".join(M) + "\n")
+        print("\n".join(M))
+    print("\n".join(L[:26]))
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "run":
         run()
     elif len(sys.argv) >= 6 and sys.argv[1] == "push":
         summarize_push(sys.argv[2:6])
+    elif len(sys.argv) >= 4 and sys.argv[1] == "ex1":
+        ex1(*sys.argv[2:6])
     elif len(sys.argv) >= 3 and sys.argv[1] == "bstats":
         bstats(sys.argv[2])
     elif len(sys.argv) >= 4 and sys.argv[1] == "kstats":
