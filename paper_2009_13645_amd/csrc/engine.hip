@@ -621,10 +621,7 @@ static int enqueue_step_on(mithra_handle h, hipStream_t st, hipEvent_t *ev, int6
     if (R.seed_on)  // before Mur: the boundary kernel reads the corrected planes
         HIPCHK(h, launch_seed_inject(R, st));
     HIPCHK(h, mark(1));
-    if (push_carries_mur_edges(R))  // the push launch runs the edge workgroups
-        HIPCHK(h, launch_mur_faces(R, st));
-    else
-        HIPCHK(h, launch_mur(R, st));
+    HIPCHK(h, launch_mur_faces(R, st));  // the push launch runs the edge workgroups
     HIPCHK(h, mark(2));
     // no mid-step bookkeeping: the box reductions after the push rewrite the
     // deposit box, the active-cell box and the active count whole

@@ -468,39 +468,42 @@ template <int MODE>
 static hipError_t launch_dep(const RunDev &R, hipStream_t st)
 {
     if constexpr (MODE == 0) {
-        if (push_carries_mur_edges(R)) {
-            const unsigned blocks = (unsigned)((R.np + kDepThreads - 1) / kDepThreads + mur_edge_blocks_of(R));
+        // a step's push, then the Mur edge and corner workgroups
+        const unsigned blocks = (unsigned)((R.np + kDepThreads - 1) / kDepThreads + mur_edge_blocks_of(R));
+        if (R.und_ext) {
             if (R.precision == 64)
-                hipLaunchKernelGGL((k_run<PushThenEdges<PushDeposit<double, false, 0>, double>>), dim3(blocks),
+                hipLaunchKernelGGL((k_run<PushThenEdges<PushDeposit<double, false, 0, true>, double>>), dim3(blocks),
                                    dim3(kDepThreads), 0, st, R);
             else if (R.compensated)
-                hipLaunchKernelGGL((k_run<PushThenEdges<PushDeposit<float, true, 0>, float>>), dim3(blocks),
+                hipLaunchKernelGGL((k_run<PushThenEdges<PushDeposit<float, true, 0, true>, float>>), dim3(blocks),
                                    dim3(kDepThreads), 0, st, R);
             else
-                hipLaunchKernelGGL((k_run<PushThenEdges<PushDeposit<float, false, 0>, float>>), dim3(blocks),
+                hipLaunchKernelGGL((k_run<PushThenEdges<PushDeposit<float, false, 0, true>, float>>), dim3(blocks),
                                    dim3(kDepThreads), 0, st, R);
-            return hipGetLastError();
+        } else if (R.precision == 64) {
+            hipLaunchKernelGGL((k_run<PushThenEdges<PushDeposit<double, false, 0>, double>>), dim3(blocks),
+                               dim3(kDepThreads), 0, st, R);
+        } else if (R.compensated) {
+            hipLaunchKernelGGL((k_run<PushThenEdges<PushDeposit<float, true, 0>, float>>), dim3(blocks),
+                               dim3(kDepThreads), 0, st, R);
+        } else {
+            hipLaunchKernelGGL((k_run<PushThenEdges<PushDeposit<float, false, 0>, float>>), dim3(blocks),
+                               dim3(kDepThreads), 0, st, R);
         }
-    }
-    if (R.np <= 0)
-        return hipSuccess;
-    const unsigned blocks = (unsigned)((R.np + kDepThreads - 1) / kDepThreads);
-    if (MODE == 0 && R.und_ext) {
+        return hipGetLastError();
+    } else {
+        // the load's deposit (no push, no boundary)
+        if (R.np <= 0)
+            return hipSuccess;
+        const unsigned blocks = (unsigned)((R.np + kDepThreads - 1) / kDepThreads);
         if (R.precision == 64)
-            hipLaunchKernelGGL((k_run<PushDeposit<double, false, MODE, true>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
+            hipLaunchKernelGGL((k_run<PushDeposit<double, false, MODE>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
         else if (R.compensated)
-            hipLaunchKernelGGL((k_run<PushDeposit<float, true, MODE, true>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
+            hipLaunchKernelGGL((k_run<PushDeposit<float, true, MODE>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
         else
-            hipLaunchKernelGGL((k_run<PushDeposit<float, false, MODE, true>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
+            hipLaunchKernelGGL((k_run<PushDeposit<float, false, MODE>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
         return hipGetLastError();
     }
-    if (R.precision == 64)
-        hipLaunchKernelGGL((k_run<PushDeposit<double, false, MODE>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
-    else if (R.compensated)
-        hipLaunchKernelGGL((k_run<PushDeposit<float, true, MODE>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
-    else
-        hipLaunchKernelGGL((k_run<PushDeposit<float, false, MODE>>), dim3(blocks), dim3(kDepThreads), 0, st, R);
-    return hipGetLastError();
 }
 
 // Reduce the per-block partial boxes (and counts) of `nblocks` blocks into

@@ -105,8 +105,8 @@ __device__ double corner_np1(const RunDev &R, const Lv<T> &L, const int p[3], co
 // three edge neighbours.  Not in the face kernel: this path needs far more
 // registers than the face path, and in one kernel it set the face threads'
 // occupancy too.  A single run's step carries these workgroups at the end
-// of the push launch (PushThenEdges); grouped steps and the general
-// external field launch them on their own after the face kernel.
+// of the push launch (PushThenEdges); grouped steps and the sweep-shape
+// tuners launch them on their own after the face kernel.
 template <typename T>
 struct MurEdge {
     static constexpr int kThreads = 256;
@@ -167,10 +167,5 @@ __host__ __device__ inline int64_t mur_edge_blocks_of(const RunDev &R)
     const int64_t nodes = 4LL * R.nx + 4LL * (R.ny - 2) + 4LL * (R.nz - 2);
     return ((nodes + 255) / 256) * (R.space_charge ? 4 : 3);
 }
-
-// Does the push launch of a single run's step carry the edge workgroups?
-// (Not for the general external field: that push runs at two waves per
-// SIMD and keeps the separate launch.)
-__host__ __device__ inline bool push_carries_mur_edges(const RunDev &R) { return !R.und_ext; }
 
 }  // namespace mithra
